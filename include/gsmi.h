@@ -1,0 +1,169 @@
+/*
+ * gsmi.h -- C ABI of the MI355X (gfx950) 3D Gaussian Splatting forward
+ * rasterizer.
+ *
+ * The library renders one image of a set of 3D Gaussians (Sec. 3.1 of
+ * "Rendering 3D Gaussians on a Graph Processor"): it culls and projects every
+ * Gaussian (EWA splatting, Sigma' = J W Sigma W^T J^T, SH colour), bins each
+ * one into 64-bit (tile << 32 | depth) keys over 16x16-pixel screen tiles
+ * using the 3-sigma square bound of Sec. 4.4, sorts the keys, and composites
+ * every pixel front to back with Eq. 1 and early termination.
+ *
+ * Conventions
+ *   - Every array pointer in this header is a DEVICE pointer (HIP device
+ *     memory of the context's device) owned by the caller, unless a comment
+ *     says otherwise.  Structures themselves are read on the host.
+ *   - Arrays are structure-of-arrays, channel-major: element (c, i) of an
+ *     array declared [C][n] lives at index c*n + i.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All work is enqueued on it; gs_render blocks the host once per call to
+ *     read the pair count (see pair_capacity).
+ *   - A context is not thread-safe: use one per host thread / stream.
+ *   - Errors: every argument is checked on the host before anything is
+ *     enqueued; on an error return no output has been written.
+ *     gs_last_error() gives a message for the last failing call on a context
+ *     (or on the calling thread when the context pointer was NULL).
+ */
+#ifndef GSMI_H
+#define GSMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARGUMENT = 1, /* bad pointer, size, degree, camera, option */
+    GS_ERR_OUT_OF_MEMORY = 2,    /* device allocation of the workspace failed */
+    GS_ERR_CAPACITY = 3,         /* more (Gaussian, tile) pairs than allowed */
+    GS_ERR_HIP = 4,              /* a HIP runtime call failed (message says which) */
+    GS_ERR_UNSUPPORTED = 5       /* valid request outside what this build handles */
+} gs_status;
+
+typedef enum { GS_F32 = 0, GS_BF16 = 1, GS_F16 = 2 } gs_dtype;
+
+typedef struct gs_context gs_context;
+
+/* Gaussians of the scene (Sec. 3.1: mean, rotation and scale of the
+ * covariance Sigma = R S S^T R^T, opacity, SH colour; the record of Sec. 4.6
+ * stores scale in log space and rotation as a quaternion).
+ *   n               number of Gaussians, 0 <= n < 2^31
+ *   sh_degree       0..3; (sh_degree+1)^2 coefficients per colour channel
+ *   attr_dtype      storage type of log_scales, quats, opacity_logits and sh
+ *                   (means are always float32)
+ *   means           float [3][n]  world-space centres
+ *   log_scales      [3][n]        per-axis log standard deviation
+ *   quats           [4][n]        rotation quaternion (w, x, y, z); it is
+ *                                 normalised by the renderer; a zero
+ *                                 quaternion culls the Gaussian
+ *   opacity_logits  [n]           opacity before the logistic sigmoid
+ *   sh              [(deg+1)^2][3][n]  real SH coefficients, index
+ *                                 k = l*l + l + m (m = -l..l), then channel */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;
+    int32_t attr_dtype;
+    const float* means;
+    const void* log_scales;
+    const void* quats;
+    const void* opacity_logits;
+    const void* sh;
+} gs_gaussians;
+
+/* Pinhole camera.  R (row-major) and t map world to camera coordinates,
+ * x right, y down, z forward; a camera-space point (x, y, z) lands on the
+ * image point (fx x/z + cx, fy y/z + cy), and pixel (px, py) samples the
+ * image point (px, py).  Gaussians with camera-space z <= near_plane are
+ * culled (Sec. 4.5).  All values must be finite; fx, fy, near_plane > 0. */
+typedef struct {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    float near_plane;
+} gs_camera;
+
+/* Render options.
+ *   background     colour added with the final transmittance
+ *   tile_size      must be 16
+ *   pair_capacity  0: the library reads the pair count back to the host
+ *                  and grows its buffers (one host sync per render);
+ *                  > 0: fixed upper bound on (Gaussian, tile) pairs, no
+ *                  sync; a larger count returns GS_ERR_CAPACITY
+ *   flags          reserved, must be 0 */
+typedef struct {
+    float background[3];
+    int32_t tile_size;
+    uint64_t pair_capacity;
+    uint32_t flags;
+} gs_render_opts;
+
+/* Creates a context on HIP device `device`; *out receives it. */
+gs_status gs_create(int device, gs_context** out);
+
+/* Frees the context and its workspace; NULL is allowed. */
+void gs_destroy(gs_context* ctx);
+
+/* Message of the last failing call on ctx (NULL: on this thread).  The
+ * string is owned by the library and valid until the next call. */
+const char* gs_last_error(const gs_context* ctx);
+
+/* Checks every argument of gs_render without touching a device; returns
+ * the status gs_render would return for them before enqueuing anything. */
+gs_status gs_validate(const gs_gaussians* g, const gs_camera* cam, int32_t width, int32_t height,
+                      const gs_render_opts* opts, const float* out_rgb);
+
+/* Renders one image (Sec. 3.1 stages 1-4, Eq. 1).
+ *   width, height   image size in pixels, 1..32768 each
+ *   out_rgb         float [3][height][width]; colour C + T * background,
+ *                   not clamped
+ *   out_final_T     float [height][width] final transmittance, or NULL
+ *   out_n_contrib   uint32 [height][width], or NULL: one past the position
+ *                   (within the pixel's tile list) of the last Gaussian that
+ *                   contributed to the pixel, 0 if none
+ * The per-tile lists and the projected Gaussians of this render stay in the
+ * context until the next gs_render or gs_destroy (see below). */
+gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam,
+                    int32_t width, int32_t height, const gs_render_opts* opts,
+                    float* out_rgb, float* out_final_T, uint32_t* out_n_contrib, void* stream);
+
+/* Sizes of the last render's per-tile lists (host values; synchronises the
+ * context's last stream). */
+typedef struct {
+    uint64_t num_pairs;   /* K, total (Gaussian, tile) pairs */
+    int32_t tiles_x, tiles_y;
+    int64_t n_visible;    /* Gaussians overlapping at least one tile */
+} gs_list_info;
+
+gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out);
+
+/* Copies the last render's per-tile lists into caller memory.
+ *   values        uint32 [K]: Gaussian indices; tile t's list is
+ *                 values[offsets[t] .. offsets[t+1]), front to back, i.e.
+ *                 all K pairs sorted by key (tile << 32 | depth bits), ties
+ *                 by Gaussian index
+ *   tile_offsets  uint32 [tiles+1], or NULL
+ *   keys          uint64 [K], or NULL: key of each sorted pair, where depth
+ *                 bits are the IEEE float32 bits of the camera-space depth */
+gs_status gs_copy_lists(gs_context* ctx, uint32_t* values, uint32_t* tile_offsets, uint64_t* keys,
+                        void* stream);
+
+/* Projected Gaussians of the last render (any pointer may be NULL).
+ *   splats         float [n][12]: u_hi, v_hi, u_lo, v_lo, conic A, B, C,
+ *                  opacity, r, g, b, depth, where the 2D centre is
+ *                  u = u_hi + u_lo (float32 pair of the double value) and
+ *                  the EWA falloff is exp(-0.5(A dx^2 + C dy^2) - B dx dy)
+ *   depth_key      uint32 [n] float32 bits of depth; 0xFFFFFFFF for a
+ *                  Gaussian that overlaps no tile
+ *   radius         int32 [n] 3-sigma radius in pixels, 0 if no tile
+ *   tiles_touched  uint32 [n]
+ *   rect           uint16 [n][4] tile rectangle x0, y0, x1, y1 (exclusive) */
+gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key, int32_t* radius,
+                             uint32_t* tiles_touched, uint16_t* rect, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSMI_H */

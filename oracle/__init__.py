@@ -22,12 +22,11 @@ _SRC = os.path.join(_HERE, "gs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 TILE = 16
 
-# Default thresholds of the relative decision margins under which a pixel is
-# treated as ambiguous (float32 evaluation may take the other branch); derived
-# from the float32 error analysis of the blend (alpha within ~2e-6 relative,
-# transmittance within ~1e-4 relative).
-ALPHA_MARGIN = 1e-5
-T_MARGIN = 1e-3
+# Decision margins are reported in units of a float32 error bound (see
+# composite_pixel in gs_oracle.c): below 1, a float32 evaluation of the same
+# step may take the other branch of the alpha or the termination test.
+ALPHA_MARGIN = 1.0
+T_MARGIN = 1.0
 
 
 def build(force: bool = True) -> str:

@@ -415,31 +415,49 @@ int64_t or_tile_list(int64_t n, const int32_t* rect, const uint32_t* tiles_touch
  * below 1e-4.
  *   out5 = (r, g, b, final T, n_contrib) where n_contrib is one past the list
  *   position of the last entry that contributed (0 if none).
- *   margins2 = smallest relative distance of any alpha (to 1/255) and of any
- *   candidate transmittance (to 1e-4) met on the walk.
+ *   margins2 = how far the two kinds of threshold decision met on the walk
+ *   sit from their thresholds, in units of a float32 error bound (a value
+ *   below 1 means a float32 evaluation may take the other branch):
+ *     alpha:  |255 a - 1| / e_a with e_a = 16u (1 + S), u = 2^-24 and
+ *             S = (|A| dx^2 + |C| dy^2)/2 + |B dx dy|, the size of the terms
+ *             of the quadratic form (it bounds the cancellation error); a
+ *             float32 evaluation with relative error 2u in dx, dy, 3u in the
+ *             conic and opacity and 2u in exp2 stays within half of e_a;
+ *             an alpha clamped to 0.99 carries only the 2u of that constant;
+ *     T:      |T' / 1e-4 - 1| / e_T with e_T the accumulated relative error
+ *             bound of T' (each factor 1 - a contributes e_a a / (1 - a) + 3u).
  * ------------------------------------------------------------------------- */
 static void composite_pixel(double px, double py, const uint32_t* list, int64_t len, int64_t n,
                             const double* mean2d, const double* conic, const double* opacity,
                             const double* rgb, const double bg[3], double out5[5], double margins2[2])
 {
+    const double u = 1.0 / 16777216.0;
     double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+    double eT = 0.0;
     double m_alpha = INFINITY, m_T = INFINITY;
     int64_t last = 0;
     for (int64_t j = 0; j < len; ++j) {
         int64_t i = list[j];
         double dx = mean2d[i] - px, dy = mean2d[n + i] - py;
-        double power = -0.5 * (conic[i] * dx * dx + conic[2 * n + i] * dy * dy) - conic[n + i] * dx * dy;
+        double qa = conic[i] * dx * dx, qc = conic[2 * n + i] * dy * dy, qb = conic[n + i] * dx * dy;
+        double power = -0.5 * (qa + qc) - qb;
         double a = opacity[i] * exp(power);
-        if (a > 0.99) a = 0.99;
-        double ma = fabs(a - 1.0 / 255.0) * 255.0;
+        double ea = 16.0 * u * (1.0 + 0.5 * (fabs(qa) + fabs(qc)) + fabs(qb));
+        if (a > 0.99) {
+            if (a > 0.99 * (1.0 + ea)) ea = 2.0 * u;
+            a = 0.99;
+        }
+        double ma = fabs(255.0 * a - 1.0) / ea;
         if (ma < m_alpha) m_alpha = ma;
         if (a < 1.0 / 255.0) continue;
         double Tn = T * (1.0 - a);
-        double mt = fabs(Tn - 1e-4) * 1e4;
+        double eTn = eT + ea * a / (1.0 - a) + 3.0 * u;
+        double mt = fabs(Tn * 1e4 - 1.0) / eTn;
         if (mt < m_T) m_T = mt;
         if (Tn < 1e-4) break;
         for (int ch = 0; ch < 3; ++ch) C[ch] += a * T * rgb[ch * n + i];
         T = Tn;
+        eT = eTn;
         last = j + 1;
     }
     for (int ch = 0; ch < 3; ++ch) out5[ch] = C[ch] + T * bg[ch];

@@ -1,0 +1,238 @@
+"""Python binding of the MI355X Gaussian-splatting rasterizer (``libgsmi.so``).
+
+Argument marshalling only: every step of the render runs in the HIP kernels
+behind the C ABI of ``include/gsmi.h``.  PyTorch provides device memory and
+the current stream.  The library must be built first
+(``python -m paper_2607_15951_amd.build``); importing this module without it
+raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgsmi.so")
+
+GS_OK, GS_ERR_INVALID_ARGUMENT, GS_ERR_OUT_OF_MEMORY, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = range(6)
+GS_F32, GS_BF16, GS_F16 = 0, 1, 2
+TILE = 16
+
+EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
+            "gs_copy_lists", "gs_copy_projection"]
+
+
+class GsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"gsmi status {status}: {message}")
+        self.status = status
+
+
+class gs_gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("attr_dtype", C.c_int32),
+                ("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logits", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class gs_camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("near_plane", C.c_float)]
+
+
+class gs_render_opts(C.Structure):
+    _fields_ = [("background", C.c_float * 3), ("tile_size", C.c_int32), ("pair_capacity", C.c_uint64),
+                ("flags", C.c_uint32)]
+
+
+class gs_list_info(C.Structure):
+    _fields_ = [("num_pairs", C.c_uint64), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
+                ("n_visible", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libgsmi.so and declares its C signatures (no device call)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2607_15951_amd.build`")
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.gs_create.argtypes = [C.c_int, C.POINTER(P)]
+    L.gs_create.restype = C.c_int
+    L.gs_destroy.argtypes = [P]
+    L.gs_destroy.restype = None
+    L.gs_last_error.argtypes = [P]
+    L.gs_last_error.restype = C.c_char_p
+    L.gs_validate.argtypes = [C.POINTER(gs_gaussians), C.POINTER(gs_camera), C.c_int32, C.c_int32,
+                              C.POINTER(gs_render_opts), P]
+    L.gs_validate.restype = C.c_int
+    L.gs_render.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(gs_camera), C.c_int32, C.c_int32,
+                            C.POINTER(gs_render_opts), P, P, P, P]
+    L.gs_render.restype = C.c_int
+    L.gs_get_list_info.argtypes = [P, C.POINTER(gs_list_info)]
+    L.gs_get_list_info.restype = C.c_int
+    L.gs_copy_lists.argtypes = [P, P, P, P, P]
+    L.gs_copy_lists.restype = C.c_int
+    L.gs_copy_projection.argtypes = [P, P, P, P, P, P, P]
+    L.gs_copy_projection.restype = C.c_int
+    _lib = L
+    return L
+
+
+def make_camera(cam: dict) -> gs_camera:
+    c = gs_camera()
+    R = np.asarray(cam["R"], np.float32).reshape(9)
+    t = np.asarray(cam["t"], np.float32).reshape(3)
+    for k in range(9):
+        c.R[k] = float(R[k])
+    for k in range(3):
+        c.t[k] = float(t[k])
+    c.fx, c.fy, c.cx, c.cy = (float(np.float32(cam[k])) for k in ("fx", "fy", "cx", "cy"))
+    c.near_plane = float(np.float32(cam["near"]))
+    return c
+
+
+def make_opts(background=(0.0, 0.0, 0.0), pair_capacity: int = 0) -> gs_render_opts:
+    o = gs_render_opts()
+    for k in range(3):
+        o.background[k] = float(background[k])
+    o.tile_size = TILE
+    o.pair_capacity = int(pair_capacity)
+    o.flags = 0
+    return o
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def scene_to_device(scene: dict, dtype: int = GS_F32, device="cuda"):
+    """Uploads a scenes.make_scene() dict; non-mean attributes in ``dtype``."""
+    torch = _torch()
+    tdt = {GS_F32: torch.float32, GS_BF16: torch.bfloat16, GS_F16: torch.float16}[dtype]
+    out = {"sh_degree": int(scene["sh_degree"]), "attr_dtype": dtype,
+           "means": torch.from_numpy(np.ascontiguousarray(scene["means"], np.float32)).to(device)}
+    for k in ("log_scales", "quats", "opacity_logits", "sh"):
+        t = torch.from_numpy(np.ascontiguousarray(scene[k], np.float32))
+        out[k] = t.to(tdt).contiguous().to(device)
+    return out
+
+
+def make_gaussians(dev_scene: dict) -> gs_gaussians:
+    g = gs_gaussians()
+    g.n = int(dev_scene["means"].shape[1])
+    g.sh_degree = int(dev_scene["sh_degree"])
+    g.attr_dtype = int(dev_scene.get("attr_dtype", GS_F32))
+    g.means = dev_scene["means"].data_ptr()
+    g.log_scales = dev_scene["log_scales"].data_ptr()
+    g.quats = dev_scene["quats"].data_ptr()
+    g.opacity_logits = dev_scene["opacity_logits"].data_ptr()
+    g.sh = dev_scene["sh"].data_ptr()
+    return g
+
+
+def validate(gaussians: gs_gaussians, camera: gs_camera, width: int, height: int,
+             opts: gs_render_opts | None, out_rgb_ptr) -> int:
+    """Host-only argument check (no device touched); returns the status code."""
+    L = load_library()
+    return int(L.gs_validate(C.byref(gaussians), C.byref(camera), int(width), int(height),
+                             C.byref(opts) if opts is not None else None, out_rgb_ptr))
+
+
+class Renderer:
+    """One gs_context on one device.  Not thread-safe."""
+
+    def __init__(self, device: int = 0):
+        self._L = load_library()
+        self._ctx = C.c_void_p()
+        st = self._L.gs_create(int(device), C.byref(self._ctx))
+        if st != GS_OK:
+            raise GsError(st, self._L.gs_last_error(None).decode())
+        self.device = device
+        self._last = None
+
+    def close(self):
+        if self._ctx:
+            self._L.gs_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != GS_OK:
+            raise GsError(st, self._L.gs_last_error(self._ctx).decode())
+
+    def render(self, dev_scene: dict, camera: dict, width: int, height: int, background=(0.0, 0.0, 0.0),
+               pair_capacity: int = 0, out=None, want_T: bool = True, want_n_contrib: bool = True,
+               stream=None):
+        """Renders into (new or given) tensors: rgb [3,H,W], final_T [H,W], n_contrib [H,W]."""
+        torch = _torch()
+        dev = dev_scene["means"].device
+        if out is None:
+            out = {"image": torch.empty((3, height, width), dtype=torch.float32, device=dev),
+                   "final_T": torch.empty((height, width), dtype=torch.float32, device=dev) if want_T else None,
+                   "n_contrib": torch.empty((height, width), dtype=torch.int32, device=dev)
+                   if want_n_contrib else None}
+        g = make_gaussians(dev_scene)
+        cam = make_camera(camera)
+        opts = make_opts(background, pair_capacity)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        st = self._L.gs_render(self._ctx, C.byref(g), C.byref(cam), int(width), int(height), C.byref(opts),
+                               _ptr(out["image"]), _ptr(out.get("final_T")), _ptr(out.get("n_contrib")),
+                               C.c_void_p(s))
+        self._check(st)
+        self._last = (dev, int(g.n))
+        return out
+
+    def list_info(self) -> dict:
+        info = gs_list_info()
+        self._check(self._L.gs_get_list_info(self._ctx, C.byref(info)))
+        return dict(num_pairs=int(info.num_pairs), tiles_x=info.tiles_x, tiles_y=info.tiles_y,
+                    n_visible=int(info.n_visible))
+
+    def lists(self, keys: bool = False) -> dict:
+        """Sorted per-tile lists of the last render as device tensors."""
+        torch = _torch()
+        info = self.list_info()
+        dev = self._last[0]
+        K = info["num_pairs"]
+        T = info["tiles_x"] * info["tiles_y"]
+        values = torch.empty(max(K, 1), dtype=torch.int32, device=dev)
+        offsets = torch.empty(T + 1, dtype=torch.int32, device=dev)
+        kt = torch.empty(max(K, 1), dtype=torch.int64, device=dev) if keys else None
+        s = torch.cuda.current_stream(dev).cuda_stream
+        self._check(self._L.gs_copy_lists(self._ctx, _ptr(values), _ptr(offsets), _ptr(kt), C.c_void_p(s)))
+        res = dict(values=values[:K], tile_offsets=offsets, **info)
+        if keys:
+            res["keys"] = kt[:K]
+        return res
+
+    def projection(self) -> dict:
+        torch = _torch()
+        dev, n = self._last
+        n1 = max(n, 1)
+        out = dict(splats=torch.empty((n1, 12), dtype=torch.float32, device=dev),
+                   depth_key=torch.empty(n1, dtype=torch.int32, device=dev),
+                   radius=torch.empty(n1, dtype=torch.int32, device=dev),
+                   tiles_touched=torch.empty(n1, dtype=torch.int32, device=dev),
+                   rect=torch.empty((n1, 4), dtype=torch.int16, device=dev))
+        s = torch.cuda.current_stream(dev).cuda_stream
+        self._check(self._L.gs_copy_projection(self._ctx, *[_ptr(out[k]) for k in
+                                                            ("splats", "depth_key", "radius", "tiles_touched",
+                                                             "rect")], C.c_void_p(s)))
+        return {k: v[:n] for k, v in out.items()}

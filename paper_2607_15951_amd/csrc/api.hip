@@ -1,0 +1,362 @@
+// api.hip -- host side of the C ABI declared in include/gsmi.h: argument
+// validation, the context's device workspace and the launch sequence of one
+// render (project -> depth sort -> tile count/offsets -> scatter -> blend).
+#include "gsmi.h"
+#include "gs_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+using namespace gsmi;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct gs_context {
+    int device = 0;
+    std::string err;
+    DevBuf splats, depth_key, radius, tiles_touched, rect;
+    DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist;
+    DevBuf counters;   // [0] n_visible, [1] overflow, [2..3] K as u64
+    DevBuf counts, totals, tile_offsets, values;
+    uint64_t* host_k = nullptr;   // pinned readback slot
+    // last render
+    bool have_render = false;
+    int64_t n = 0;
+    int tiles_x = 0, tiles_y = 0;
+    uint64_t capacity = 0;
+    int sorted_in_b = 1;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+gs_status fail(gs_context* ctx, gs_status st, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    else g_thread_error = msg;
+    return st;
+}
+
+gs_status hip_fail(gs_context* ctx, hipError_t e, const char* what)
+{
+    return fail(ctx, GS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+gs_status ensure(gs_context* ctx, DevBuf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return GS_OK;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    const size_t want = bytes + bytes / 4;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(ctx, GS_ERR_OUT_OF_MEMORY,
+                    "hipMalloc of " + std::to_string(want) + " bytes failed: " + hipGetErrorString(e));
+    }
+    b.bytes = want;
+    return GS_OK;
+}
+
+bool finite_all(const float* v, int k)
+{
+    for (int i = 0; i < k; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+gs_status validate(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam, int32_t width, int32_t height,
+                   const gs_render_opts* opts, const float* out_rgb)
+{
+    if (!g) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "gaussians is NULL");
+    if (!cam) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    if (!out_rgb) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "out_rgb is NULL");
+    if (g->n < 0 || g->n >= (int64_t(1) << 31))
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "n must lie in [0, 2^31)");
+    if (g->sh_degree < 0 || g->sh_degree > 3) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "sh_degree must be 0..3");
+    if (g->attr_dtype < GS_F32 || g->attr_dtype > GS_F16)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "attr_dtype must be GS_F32, GS_BF16 or GS_F16");
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "a Gaussian attribute pointer is NULL");
+    if (width < 1 || height < 1 || width > 32768 || height > 32768)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "width and height must lie in [1, 32768]");
+    const int tiles_x = (width + kTile - 1) / kTile;
+    if (tiles_x > kMaxBandTiles) return fail(ctx, GS_ERR_UNSUPPORTED, "image wider than 32768 pixels");
+    if (!finite_all(cam->R, 9) || !finite_all(cam->t, 3) || !std::isfinite(cam->fx) || !std::isfinite(cam->fy) ||
+        !std::isfinite(cam->cx) || !std::isfinite(cam->cy) || !std::isfinite(cam->near_plane))
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "camera holds a non-finite value");
+    if (!(cam->fx > 0.f) || !(cam->fy > 0.f) || !(cam->near_plane > 0.f))
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "camera fx, fy and near_plane must be positive");
+    if (opts) {
+        if (opts->tile_size != kTile) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "tile_size must be 16");
+        if (opts->flags != 0) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "flags must be 0");
+        if (!finite_all(opts->background, 3))
+            return fail(ctx, GS_ERR_INVALID_ARGUMENT, "background holds a non-finite value");
+    }
+    return GS_OK;
+}
+
+#define HIP_TRY(expr, what)                                   \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+gs_status gs_create(int device, gs_context** out)
+{
+    if (!out) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "no such device");
+    gs_context* ctx = new gs_context();
+    ctx->device = device;
+    e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->host_k), sizeof(uint64_t));
+    if (e != hipSuccess) {
+        delete ctx;
+        return hip_fail(nullptr, e, "context set-up");
+    }
+    *out = ctx;
+    return GS_OK;
+}
+
+void gs_destroy(gs_context* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    DevBuf* bufs[] = {&ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
+                      &ctx->sort_ka, &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb, &ctx->hist,
+                      &ctx->counters, &ctx->counts, &ctx->totals, &ctx->tile_offsets, &ctx->values};
+    for (DevBuf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (ctx->host_k) (void)hipHostFree(ctx->host_k);
+    delete ctx;
+}
+
+const char* gs_last_error(const gs_context* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_thread_error.c_str();
+}
+
+gs_status gs_validate(const gs_gaussians* g, const gs_camera* cam, int32_t width, int32_t height,
+                      const gs_render_opts* opts, const float* out_rgb)
+{
+    return validate(nullptr, g, cam, width, height, opts, out_rgb);
+}
+
+gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam, int32_t width, int32_t height,
+                    const gs_render_opts* opts, float* out_rgb, float* out_final_T, uint32_t* out_n_contrib,
+                    void* stream)
+{
+    if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
+    gs_status st = validate(ctx, g, cam, width, height, opts, out_rgb);
+    if (st != GS_OK) return st;
+    gs_render_opts o{};
+    o.tile_size = kTile;
+    if (opts) o = *opts;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+
+    const int64_t n = g->n;
+    const int tiles_x = (width + kTile - 1) / kTile, tiles_y = (height + kTile - 1) / kTile;
+    const int64_t T = (int64_t)tiles_x * tiles_y;
+    const int band_rows = kMaxBandTiles / tiles_x;
+    const int num_bands = (tiles_y + band_rows - 1) / band_rows;
+    const int num_chunks = (int)((n + kBinChunk - 1) / kBinChunk);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+
+    if ((st = ensure(ctx, ctx->splats, nn * sizeof(Splat))) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->depth_key, nn * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->radius, nn * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->tiles_touched, nn * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->rect, nn * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->sort_ka, nn * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->sort_va, nn * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->sort_kb, nn * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->sort_vb, nn * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->hist, depth_sort_hist_elems(n) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->counters, 64)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->counts, (size_t)(num_chunks > 0 ? num_chunks : 1) * (size_t)T * 4)) != GS_OK)
+        return st;
+    if ((st = ensure(ctx, ctx->totals, (size_t)T * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
+
+    uint32_t* counters = static_cast<uint32_t*>(ctx->counters.p);
+    uint64_t* k_total = reinterpret_cast<uint64_t*>(counters + 2);
+    HIP_TRY(launch_fill_u32(counters, 0u, 4, s), "clear counters");
+
+    ProjectArgs pa{};
+    pa.n = n;
+    pa.sh_degree = g->sh_degree;
+    pa.dtype = g->attr_dtype;
+    pa.means = g->means;
+    pa.log_scales = g->log_scales;
+    pa.quats = g->quats;
+    pa.logits = g->opacity_logits;
+    pa.sh = g->sh;
+    for (int k = 0; k < 9; ++k) pa.R[k] = cam->R[k];
+    for (int k = 0; k < 3; ++k) pa.t[k] = cam->t[k];
+    pa.fx = cam->fx;
+    pa.fy = cam->fy;
+    pa.cx = cam->cx;
+    pa.cy = cam->cy;
+    pa.near_plane = cam->near_plane;
+    for (int k = 0; k < 3; ++k)   // camera centre -R^T t
+        pa.campos[k] = (float)-(pa.R[k] * pa.t[0] + pa.R[3 + k] * pa.t[1] + pa.R[6 + k] * pa.t[2]);
+    pa.width = width;
+    pa.height = height;
+    pa.tiles_x = tiles_x;
+    pa.tiles_y = tiles_y;
+    pa.splats = static_cast<Splat*>(ctx->splats.p);
+    pa.depth_key = static_cast<uint32_t*>(ctx->depth_key.p);
+    pa.radius = static_cast<int32_t*>(ctx->radius.p);
+    pa.tiles_touched = static_cast<uint32_t*>(ctx->tiles_touched.p);
+    pa.rect = static_cast<ushort4*>(ctx->rect.p);
+    pa.n_visible = counters;
+    HIP_TRY(launch_project(pa, s), "project");
+
+    int in_b = 1;
+    HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
+                              static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
+                              static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p), n,
+                              &in_b, s),
+            "depth sort");
+
+    BinArgs ba{};
+    ba.sorted_idx = static_cast<const uint32_t*>(in_b ? ctx->sort_vb.p : ctx->sort_va.p);
+    ba.n_visible = counters;
+    ba.rect = pa.rect;
+    ba.n = n;
+    ba.tiles_x = tiles_x;
+    ba.tiles_y = tiles_y;
+    ba.band_rows = band_rows;
+    ba.num_bands = num_bands;
+    ba.num_chunks = num_chunks;
+    ba.counts = static_cast<uint32_t*>(ctx->counts.p);
+    ba.totals = static_cast<uint32_t*>(ctx->totals.p);
+    ba.tile_offsets = static_cast<uint32_t*>(ctx->tile_offsets.p);
+    ba.overflow = counters + 1;
+    ba.capacity = o.pair_capacity ? o.pair_capacity : ~0ull;
+    HIP_TRY(launch_bin_count(ba, s), "bin count");
+    HIP_TRY(launch_bin_offsets(ba, s, k_total), "bin offsets");
+
+    uint64_t capacity = o.pair_capacity;
+    if (capacity == 0) {
+        HIP_TRY(hipMemcpyAsync(ctx->host_k, k_total, sizeof(uint64_t), hipMemcpyDeviceToHost, s), "read K");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        const uint64_t K = *ctx->host_k;
+        if (K > 0xFFFFFFFFull) {
+            ctx->have_render = false;
+            return fail(ctx, GS_ERR_CAPACITY, "more than 2^32-1 (Gaussian, tile) pairs");
+        }
+        capacity = K;
+    }
+    if ((st = ensure(ctx, ctx->values, (size_t)(capacity > 0 ? capacity : 1) * 4)) != GS_OK) return st;
+    ba.values = static_cast<uint32_t*>(ctx->values.p);
+    ba.capacity = capacity;
+    HIP_TRY(launch_bin_scatter(ba, s), "bin scatter");
+
+    BlendArgs bl{};
+    bl.splats = pa.splats;
+    bl.values = ba.values;
+    bl.tile_offsets = ba.tile_offsets;
+    bl.width = width;
+    bl.height = height;
+    bl.tiles_x = tiles_x;
+    bl.tiles_y = tiles_y;
+    const float zero_bg[3] = {0.f, 0.f, 0.f};
+    const float* bg = opts ? o.background : zero_bg;
+    for (int k = 0; k < 3; ++k) bl.bg[k] = bg[k];
+    bl.out_rgb = out_rgb;
+    bl.out_T = out_final_T;
+    bl.out_nc = out_n_contrib;
+    HIP_TRY(launch_blend(bl, capacity, s), "blend");
+
+    ctx->have_render = true;
+    ctx->n = n;
+    ctx->tiles_x = tiles_x;
+    ctx->tiles_y = tiles_y;
+    ctx->capacity = capacity;
+    ctx->sorted_in_b = in_b;
+    ctx->stream = s;
+    return GS_OK;
+}
+
+gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out)
+{
+    if (!ctx || !out) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (!ctx->have_render) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "no render on this context yet");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    uint32_t c[4];
+    HIP_TRY(hipMemcpyAsync(c, ctx->counters.p, sizeof c, hipMemcpyDeviceToHost, ctx->stream), "read counters");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    uint64_t K;
+    std::memcpy(&K, c + 2, 8);
+    out->num_pairs = K;
+    out->tiles_x = ctx->tiles_x;
+    out->tiles_y = ctx->tiles_y;
+    out->n_visible = c[0];
+    if (c[1] != 0 || K > ctx->capacity)
+        return fail(ctx, GS_ERR_CAPACITY, "the last render produced more pairs than pair_capacity");
+    return GS_OK;
+}
+
+gs_status gs_copy_lists(gs_context* ctx, uint32_t* values, uint32_t* tile_offsets, uint64_t* keys, void* stream)
+{
+    gs_list_info info;
+    gs_status st = gs_get_list_info(ctx, &info);
+    if (st != GS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t T = (int64_t)ctx->tiles_x * ctx->tiles_y;
+    if (values && info.num_pairs)
+        HIP_TRY(hipMemcpyAsync(values, ctx->values.p, info.num_pairs * 4, hipMemcpyDeviceToDevice, s), "copy values");
+    if (tile_offsets)
+        HIP_TRY(hipMemcpyAsync(tile_offsets, ctx->tile_offsets.p, (size_t)(T + 1) * 4, hipMemcpyDeviceToDevice, s),
+                "copy offsets");
+    if (keys)
+        HIP_TRY(launch_write_keys(static_cast<const uint32_t*>(ctx->values.p),
+                                  static_cast<const uint32_t*>(ctx->tile_offsets.p),
+                                  static_cast<const uint32_t*>(ctx->depth_key.p), T, keys, s),
+                "write keys");
+    return GS_OK;
+}
+
+gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key, int32_t* radius,
+                             uint32_t* tiles_touched, uint16_t* rect, void* stream)
+{
+    if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (!ctx->have_render) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "no render on this context yet");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t n = (size_t)ctx->n;
+    if (n == 0) return GS_OK;
+    if (splats) HIP_TRY(hipMemcpyAsync(splats, ctx->splats.p, n * sizeof(Splat), hipMemcpyDeviceToDevice, s), "copy");
+    if (depth_key) HIP_TRY(hipMemcpyAsync(depth_key, ctx->depth_key.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
+    if (radius) HIP_TRY(hipMemcpyAsync(radius, ctx->radius.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
+    if (tiles_touched)
+        HIP_TRY(hipMemcpyAsync(tiles_touched, ctx->tiles_touched.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
+    if (rect) HIP_TRY(hipMemcpyAsync(rect, ctx->rect.p, n * 8, hipMemcpyDeviceToDevice, s), "copy");
+    return GS_OK;
+}
+
+}  // extern "C"

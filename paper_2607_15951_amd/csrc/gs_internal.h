@@ -1,0 +1,91 @@
+// gs_internal.h -- shared declarations of the gfx950 render kernels (not part
+// of the public C ABI; see include/gsmi.h for that).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsmi {
+
+constexpr int kTile = 16;                 // screen tile edge in pixels
+constexpr int kTilePixels = kTile * kTile;
+constexpr int kMaxBandTiles = 2048;       // LDS cursors per binning wave
+constexpr int kSortBlock = 256;           // threads of a depth-sort block
+constexpr int kSortItems = 8;             // keys per thread per depth-sort block
+constexpr int kSortTile = kSortBlock * kSortItems;
+constexpr int kBinChunk = 8192;           // depth-sorted Gaussians per binning wave
+
+// One projected Gaussian as the blend reads it: 3 x float4 = 48 bytes.
+//   a = (u_hi, v_hi, u_lo, v_lo)   2D centre as a float pair of the double
+//   b = (A, B, C, opacity)         conic and sigmoid(opacity logit)
+//   c = (r, g, b, depth)
+struct Splat {
+    float4 a, b, c;
+};
+
+struct ProjectArgs {
+    int64_t n;
+    int sh_degree;
+    int dtype;                // 0 f32, 1 bf16, 2 f16 (all but means)
+    const float* means;
+    const void* log_scales;
+    const void* quats;
+    const void* logits;
+    const void* sh;
+    double R[9], t[3];
+    double fx, fy, cx, cy, near_plane;
+    float campos[3];
+    int width, height, tiles_x, tiles_y;
+    Splat* splats;
+    uint32_t* depth_key;
+    int32_t* radius;
+    uint32_t* tiles_touched;
+    ushort4* rect;
+    uint32_t* n_visible;
+};
+
+hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
+
+// Stable LSD radix sort of n 32-bit keys with values 0..n-1, four 8-bit
+// passes; *result_in_b tells which ping-pong buffer pair holds the result.
+size_t depth_sort_hist_elems(int64_t n);
+hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a,
+                             uint32_t* keys_b, uint32_t* vals_b, uint32_t* hist, int64_t n,
+                             int* result_in_b, hipStream_t s);
+
+struct BinArgs {
+    const uint32_t* sorted_idx;   // depth-sorted Gaussian indices
+    const uint32_t* n_visible;    // device counter
+    const ushort4* rect;
+    int64_t n;                    // upper bound of n_visible
+    int tiles_x, tiles_y, band_rows, num_bands, num_chunks;
+    uint32_t* counts;             // [num_chunks][tiles] -> column prefix in place
+    uint32_t* totals;             // [tiles]
+    uint32_t* tile_offsets;       // [tiles + 1]
+    uint32_t* values;             // [capacity] sorted pair values
+    uint64_t capacity;
+    uint32_t* overflow;           // set to 1 when K > capacity
+};
+
+hipError_t launch_bin_count(const BinArgs& a, hipStream_t s);
+hipError_t launch_bin_offsets(const BinArgs& a, hipStream_t s, uint64_t* k_total);
+hipError_t launch_bin_scatter(const BinArgs& a, hipStream_t s);
+
+struct BlendArgs {
+    const Splat* splats;
+    const uint32_t* values;
+    const uint32_t* tile_offsets;
+    int width, height, tiles_x, tiles_y;
+    float bg[3];
+    float* out_rgb;
+    float* out_T;        // may be null
+    uint32_t* out_nc;    // may be null
+};
+
+hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_write_keys(const uint32_t* values, const uint32_t* tile_offsets,
+                             const uint32_t* depth_key, int64_t tiles, uint64_t* keys, hipStream_t s);
+
+}  // namespace gsmi

@@ -1,0 +1,264 @@
+// project.hip -- per-Gaussian cull + EWA projection + SH colour (gfx950).
+//
+// Stages 1-2 of the four-stage render (Sec. 3.1): frustum (near-plane) cull,
+// projection to a 2D centre and conic, the 3-sigma square bound of Sec. 4.4,
+// opacity sigma(alpha) of Eq. 1 and view-dependent SH colour.  One lane per
+// Gaussian; structure-of-arrays inputs make every load a coalesced stream.
+//
+// Precision.  The geometry that decides integers -- culling, the bounding
+// radius, the tile rectangle -- and the sort key's depth are evaluated in IEEE
+// double precision in a fixed operation order with FMA contraction disabled,
+// so that they are reproducible bit for bit on any IEEE machine that follows
+// the same order.  On gfx950 the FP64 vector rate is half the FP32 rate and
+// this kernel is bound by HBM reads (up to 236 B per Gaussian), so the double
+// arithmetic costs no frame time.  Colour and opacity are FP32.
+#include "gs_internal.h"
+
+#include <hip/hip_fp16.h>
+
+namespace gsmi {
+namespace {
+
+template <int DT>
+__device__ __forceinline__ float load_attr(const void* p, int64_t idx)
+{
+    if constexpr (DT == 0) {
+        return static_cast<const float*>(p)[idx];
+    } else if constexpr (DT == 1) {
+        uint32_t b = static_cast<const uint16_t*>(p)[idx];
+        return __uint_as_float(b << 16);
+    } else {
+        return __half2float(static_cast<const __half*>(p)[idx]);
+    }
+}
+
+// Real SH basis to degree 3 in Cartesian form (unit direction x, y, z), index
+// k = l*l + l + m; the sign convention carries the Condon-Shortley phase.
+__device__ __forceinline__ void sh_basis(float x, float y, float z, int degree, float Y[16])
+{
+    Y[0] = 0.28209479177387814f;
+    if (degree < 1) return;
+    const float c1 = 0.48860251190291992f;
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    if (degree < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float xy = x * y, yz = y * z, xz = x * z;
+    Y[4] = 1.0925484305920792f * xy;
+    Y[5] = -1.0925484305920792f * yz;
+    Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+    Y[7] = -1.0925484305920792f * xz;
+    Y[8] = 0.54627421529603959f * (xx - yy);
+    if (degree < 3) return;
+    Y[9] = -0.59004358992664352f * y * (3.0f * xx - yy);
+    Y[10] = 2.8906114426405538f * xy * z;
+    Y[11] = -0.45704579946446572f * y * (4.0f * zz - xx - yy);
+    Y[12] = 0.37317633259011540f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -0.45704579946446572f * x * (4.0f * zz - xx - yy);
+    Y[14] = 1.4453057213202769f * z * (xx - yy);
+    Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
+}
+
+struct Geometry {
+    double tz, u, v;
+    double A, B, C;
+    int32_t radius;
+};
+
+// Culling and projection in double precision.  Returns false for a culled
+// Gaussian.  The expression shapes below fix the rounding order.
+__device__ __forceinline__ bool project_geometry(const ProjectArgs& a, double mx, double my, double mz,
+                                                 double l0, double l1, double l2, double qw, double qx,
+                                                 double qy, double qz, Geometry& g)
+{
+#pragma clang fp contract(off)
+    const double* W = a.R;
+    const double tx = ((W[0] * mx + W[1] * my) + W[2] * mz) + a.t[0];
+    const double ty = ((W[3] * mx + W[4] * my) + W[5] * mz) + a.t[1];
+    const double tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + a.t[2];
+    if (!(tz > a.near_plane) || !isfinite(tx) || !isfinite(ty) || !isfinite(tz)) return false;
+
+    const double n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    if (!(n2 > 0.0) || !isfinite(n2)) return false;
+    const double qn = sqrt(n2);
+    const double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+    // rotation matrix of the unit quaternion, row-major
+    double Q[9];
+    Q[0] = 1.0 - 2.0 * (y * y + z * z);
+    Q[1] = 2.0 * (x * y - w * z);
+    Q[2] = 2.0 * (x * z + w * y);
+    Q[3] = 2.0 * (x * y + w * z);
+    Q[4] = 1.0 - 2.0 * (x * x + z * z);
+    Q[5] = 2.0 * (y * z - w * x);
+    Q[6] = 2.0 * (x * z - w * y);
+    Q[7] = 2.0 * (y * z + w * x);
+    Q[8] = 1.0 - 2.0 * (x * x + y * y);
+
+    // M = Q diag(exp(s)); world covariance Sg = M M^T
+    const double s0 = exp(l0), s1 = exp(l1), s2 = exp(l2);
+    double M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        M[3 * r + 0] = Q[3 * r + 0] * s0;
+        M[3 * r + 1] = Q[3 * r + 1] * s1;
+        M[3 * r + 2] = Q[3 * r + 2] * s2;
+    }
+    double Sg[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Sg[3 * r + c] = (M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1]) + M[3 * r + 2] * M[3 * c + 2];
+
+    // camera-space covariance V = W Sg W^T (left product first)
+    double L[9], V[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            L[3 * r + c] = (W[3 * r] * Sg[c] + W[3 * r + 1] * Sg[3 + c]) + W[3 * r + 2] * Sg[6 + c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            V[3 * r + c] = (L[3 * r] * W[3 * c] + L[3 * r + 1] * W[3 * c + 1]) + L[3 * r + 2] * W[3 * c + 2];
+
+    // perspective Jacobian with x/z, y/z clamped to 1.3x the half-image tangent
+    const double limx = 1.3 * ((0.5 * (double)a.width) / a.fx);
+    const double limy = 1.3 * ((0.5 * (double)a.height) / a.fy);
+    const double xcl = fmin(limx, fmax(-limx, tx / tz)) * tz;
+    const double ycl = fmin(limy, fmax(-limy, ty / tz)) * tz;
+    double Jm[6];
+    Jm[0] = a.fx / tz;
+    Jm[1] = 0.0;
+    Jm[2] = -(a.fx * xcl) / (tz * tz);
+    Jm[3] = 0.0;
+    Jm[4] = a.fy / tz;
+    Jm[5] = -(a.fy * ycl) / (tz * tz);
+    double Bm[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Bm[3 * r + c] = (Jm[3 * r] * V[c] + Jm[3 * r + 1] * V[3 + c]) + Jm[3 * r + 2] * V[6 + c];
+    const double p00 = (Bm[0] * Jm[0] + Bm[1] * Jm[1]) + Bm[2] * Jm[2];
+    const double p01 = (Bm[0] * Jm[3] + Bm[1] * Jm[4]) + Bm[2] * Jm[5];
+    const double p11 = (Bm[3] * Jm[3] + Bm[4] * Jm[4]) + Bm[5] * Jm[5];
+
+    // EWA low-pass of 0.3 px^2, then the conic (inverse 2D covariance)
+    const double ca = p00 + 0.3, cb = p01, cc = p11 + 0.3;
+    const double det = ca * cc - cb * cb;
+    if (!(det > 0.0) || !isfinite(det)) return false;
+    g.A = cc / det;
+    g.B = -cb / det;
+    g.C = ca / det;
+
+    // 3 sigma of the larger eigenvalue, whole pixels
+    const double mid = 0.5 * (ca + cc);
+    const double lam = mid + sqrt(fmax(0.0, mid * mid - det));
+    const double r = ceil(3.0 * sqrt(lam));
+    if (!(r > 0.0) || !(r < 1e9)) return false;
+    g.radius = (int32_t)r;
+
+    g.u = (a.fx * tx) / tz + a.cx;
+    g.v = (a.fy * ty) / tz + a.cy;
+    if (!isfinite(g.u) || !isfinite(g.v)) return false;
+    g.tz = tz;
+    return true;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t n = a.n;
+    const float mxf = a.means[i], myf = a.means[n + i], mzf = a.means[2 * n + i];
+    const float l0 = load_attr<DT>(a.log_scales, i);
+    const float l1 = load_attr<DT>(a.log_scales, n + i);
+    const float l2 = load_attr<DT>(a.log_scales, 2 * n + i);
+    const float qw = load_attr<DT>(a.quats, i);
+    const float qx = load_attr<DT>(a.quats, n + i);
+    const float qy = load_attr<DT>(a.quats, 2 * n + i);
+    const float qz = load_attr<DT>(a.quats, 3 * n + i);
+
+    Geometry g;
+    bool ok = project_geometry(a, mxf, myf, mzf, l0, l1, l2, qw, qx, qy, qz, g);
+
+    uint32_t tiles = 0;
+    ushort4 rc = make_ushort4(0, 0, 0, 0);
+    if (ok) {
+        const double big = 1073741824.0;
+        const double uc = fmin(big, fmax(-big, g.u)), vc = fmin(big, fmax(-big, g.v));
+        int64_t xlo = (int64_t)ceil(uc) - g.radius, xhi = (int64_t)floor(uc) + g.radius;
+        int64_t ylo = (int64_t)ceil(vc) - g.radius, yhi = (int64_t)floor(vc) + g.radius;
+        if (!(xhi < 0 || xlo > a.width - 1 || yhi < 0 || ylo > a.height - 1)) {
+            xlo = xlo < 0 ? 0 : xlo;
+            ylo = ylo < 0 ? 0 : ylo;
+            xhi = xhi > a.width - 1 ? a.width - 1 : xhi;
+            yhi = yhi > a.height - 1 ? a.height - 1 : yhi;
+            const int x0 = (int)(xlo / kTile), x1 = (int)(xhi / kTile) + 1;
+            const int y0 = (int)(ylo / kTile), y1 = (int)(yhi / kTile) + 1;
+            rc = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1);
+            tiles = (uint32_t)((x1 - x0) * (y1 - y0));
+        }
+    }
+
+    Splat sp;
+    sp.a = sp.b = sp.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tiles > 0) {
+        const float uh = (float)g.u, vh = (float)g.v;
+        sp.a = make_float4(uh, vh, (float)(g.u - (double)uh), (float)(g.v - (double)vh));
+        const float logit = load_attr<DT>(a.logits, i);
+        const float opacity = 1.0f / (1.0f + __expf(-logit));
+        sp.b = make_float4((float)g.A, (float)g.B, (float)g.C, opacity);
+        // view direction from the camera centre
+        float dx = mxf - a.campos[0], dy = myf - a.campos[1], dz = mzf - a.campos[2];
+        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= inv;
+        dy *= inv;
+        dz *= inv;
+        float Y[16];
+        sh_basis(dx, dy, dz, a.sh_degree, Y);
+        const int ncoef = (a.sh_degree + 1) * (a.sh_degree + 1);
+        float col[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.0f;
+            for (int k = 0; k < ncoef; ++k) acc += load_attr<DT>(a.sh, ((int64_t)k * 3 + ch) * n + i) * Y[k];
+            col[ch] = fmaxf(acc + 0.5f, 0.0f);
+        }
+        sp.c = make_float4(col[0], col[1], col[2], (float)g.tz);
+    }
+    float4* dst = reinterpret_cast<float4*>(a.splats + i);
+    dst[0] = sp.a;
+    dst[1] = sp.b;
+    dst[2] = sp.c;
+    a.depth_key[i] = tiles > 0 ? __float_as_uint((float)g.tz) : 0xFFFFFFFFu;
+    a.radius[i] = tiles > 0 ? g.radius : 0;
+    a.tiles_touched[i] = tiles;
+    a.rect[i] = rc;
+
+    // one atomic per wave for the visible count
+    const uint64_t vis = __ballot(tiles > 0);
+    const uint64_t act = __ballot(1);
+    if ((int)(__ffsll((long long)act) - 1) == (int)(threadIdx.x & 63) && vis)
+        atomicAdd(a.n_visible, (uint32_t)__popcll(vis));
+}
+
+}  // namespace
+
+hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((a.n + 255) / 256);
+    switch (a.dtype) {
+    case 0: hipLaunchKernelGGL(project_kernel<0>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(project_kernel<1>, dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(project_kernel<2>, dim3(blocks), dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gsmi

@@ -1,0 +1,129 @@
+"""Helpers shared by the GPU parity tests: run the HIP render through the C
+ABI, run the FP64 oracle on the same seeded inputs, and compare.
+
+Bars (from the arithmetic of each step):
+  * integers -- radius, tile rectangle, tiles touched, depth keys, K, tile
+    offsets, sorted values and keys -- bit-exact;
+  * the projected centre: float32 hi/lo pair bit-exact against the oracle's
+    double (same IEEE double expression on both sides);
+  * image: max-abs <= 1e-4 against the FP64 oracle on pixels whose threshold
+    decisions are not within float32 reach of the edge (ambiguous pixels are
+    counted, bounded, and checked against a looser bound).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+import scenes
+
+IMAGE_TOL = 1e-4
+CONIC_RTOL = 2e-6
+RADIUS_MARGIN = 1e-9
+
+
+def gpu_render(renderer, scene, cam, dtype=0, background=(0.0, 0.0, 0.0), keys=True, pair_capacity=0):
+    import torch
+    import paper_2607_15951_amd as gs
+    dev = gs.scene_to_device(scene, dtype)
+    W, H = cam["width"], cam["height"]
+    out = renderer.render(dev, cam, W, H, background=background, pair_capacity=pair_capacity)
+    torch.cuda.synchronize()
+    lists = renderer.lists(keys=keys)
+    proj = renderer.projection()
+    torch.cuda.synchronize()
+    res = dict(image=out["image"].cpu().numpy().astype(np.float64),
+               final_T=out["final_T"].cpu().numpy().astype(np.float64),
+               n_contrib=out["n_contrib"].cpu().numpy(),
+               values=lists["values"].cpu().numpy().view(np.uint32),
+               tile_offsets=lists["tile_offsets"].cpu().numpy().view(np.uint32),
+               num_pairs=lists["num_pairs"], n_visible=lists["n_visible"],
+               splats=proj["splats"].cpu().numpy(),
+               depth_key=proj["depth_key"].cpu().numpy().view(np.uint32),
+               radius=proj["radius"].cpu().numpy(),
+               tiles_touched=proj["tiles_touched"].cpu().numpy().view(np.uint32),
+               rect=proj["rect"].cpu().numpy().view(np.uint16).astype(np.int32))
+    if keys:
+        res["keys"] = lists["keys"].cpu().numpy().view(np.uint64)
+    return res
+
+
+def dequantised(scene, dtype):
+    """The float32 values the renderer sees for a BF16/FP16-stored scene."""
+    if dtype == 0:
+        return scene
+    out = dict(scene)
+    for k in ("log_scales", "quats", "opacity_logits", "sh"):
+        a = np.ascontiguousarray(scene[k], np.float32)
+        if dtype == 1:
+            out[k] = scenes.bf16_to_f32(scenes.to_bf16_storage(a)).reshape(a.shape)
+        else:
+            out[k] = a.astype(np.float16).astype(np.float32)
+    return out
+
+
+def check_projection(g, p, label=""):
+    """Per-Gaussian parity; returns the indices excluded for a radius margin."""
+    n = p["n"]
+    amb = np.nonzero(p["radius_margin"] < RADIUS_MARGIN)[0]
+    ok = np.ones(n, bool)
+    ok[amb] = False
+    assert len(amb) <= max(2, n // 100000), f"{label}: {len(amb)} radius-ambiguous Gaussians"
+    np.testing.assert_array_equal(g["tiles_touched"][ok], p["tiles_touched"][ok], err_msg=label)
+    np.testing.assert_array_equal(g["radius"][ok], p["radius"][ok], err_msg=label)
+    rect = p["rect"].T
+    np.testing.assert_array_equal(g["rect"][ok], rect[ok], err_msg=label)
+    vis = (p["tiles_touched"] > 0) & ok
+    want_key = np.where(p["tiles_touched"] > 0, p["depth_bits"], np.uint32(0xFFFFFFFF))
+    np.testing.assert_array_equal(g["depth_key"][ok], want_key[ok], err_msg=label)
+    sp = g["splats"]
+    for axis, (hi, lo) in enumerate(((0, 2), (1, 3))):
+        want = p["mean2d"][axis][vis]
+        want_hi = want.astype(np.float32)
+        want_lo = (want - want_hi.astype(np.float64)).astype(np.float32)
+        np.testing.assert_array_equal(sp[vis, hi], want_hi, err_msg=f"{label} mean2d hi")
+        np.testing.assert_array_equal(sp[vis, lo], want_lo, err_msg=f"{label} mean2d lo")
+    np.testing.assert_allclose(sp[vis, 4:7], p["conic"].T[vis], rtol=CONIC_RTOL, atol=0, err_msg=label)
+    np.testing.assert_allclose(sp[vis, 7], p["opacity"][vis], rtol=1e-6, atol=1e-7, err_msg=label)
+    np.testing.assert_allclose(sp[vis, 8:11], p["rgb"].T[vis], rtol=2e-6, atol=2e-6, err_msg=label)
+    np.testing.assert_array_equal(sp[vis, 11], p["depth"][vis].astype(np.float32), err_msg=label)
+    return amb
+
+
+def check_image(g, o, label="", tol=IMAGE_TOL, max_ambiguous_frac=5e-3):
+    """Image, final T and n_contrib against the oracle composite."""
+    amb = oracle.ambiguous_mask(o)
+    P = amb.size
+    n_amb = int(amb.sum())
+    assert n_amb <= max(4, max_ambiguous_frac * P), f"{label}: {n_amb} ambiguous pixels of {P}"
+    good = ~amb
+    d = np.abs(g["image"] - o["image"]).max(axis=0)
+    worst = float(d[good].max()) if good.any() else 0.0
+    assert worst <= tol, f"{label}: max-abs {worst:.3e} > {tol} on unambiguous pixels"
+    dT = np.abs(g["final_T"] - o["final_T"])
+    assert float(dT[good].max()) <= tol, label
+    np.testing.assert_array_equal(g["n_contrib"][good], o["n_contrib"][good], err_msg=label)
+    if n_amb:
+        # one threshold decision may flip there: a term of at most 1/255 * T * rgb
+        # (alpha test) or of alpha * T < 1e-4 / (1 - alpha) (termination)
+        assert float(d[amb].max()) <= 0.01 * max(1.0, float(o["image"].max())), label
+    return dict(max_abs=worst, ambiguous=n_amb,
+                psnr=psnr(g["image"], o["image"]))
+
+
+def psnr(a, b):
+    mse = float(np.mean((a - b) ** 2))
+    return math.inf if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+def check_lists_full(g, o, label=""):
+    """Whole sorted lists against the oracle's qsort of the emitted pairs."""
+    assert g["num_pairs"] == len(o["keys"]), label
+    counts = (o["ranges"][:, 1] - o["ranges"][:, 0]).astype(np.uint64)
+    want_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.uint32)
+    np.testing.assert_array_equal(g["tile_offsets"], want_off, err_msg=label)
+    np.testing.assert_array_equal(g["values"], o["values"], err_msg=label)
+    if "keys" in g:
+        np.testing.assert_array_equal(g["keys"], o["keys"], err_msg=label)

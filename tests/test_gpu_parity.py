@@ -1,0 +1,217 @@
+"""GPU parity of the HIP render path against the FP64 oracle, through the C ABI.
+
+Every test renders on the GPU via ``paper_2607_15951_amd.Renderer`` (which
+calls ``gs_render``) and compares with ``oracle`` on the same seeded inputs:
+bit-exact projection integers, keys, sorted lists and tile offsets; images
+within 1e-4 max-abs on pixels whose threshold decisions are unambiguous.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from parity import (check_image, check_lists_full, check_projection, dequantised, gpu_render)
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+
+@pytest.fixture(scope="module")
+def renderer():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_15951_amd as gs
+    r = gs.Renderer(0)
+    yield r
+    r.close()
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def full_parity(renderer, scene, cam, label, dtype=0, background=(0.0, 0.0, 0.0)):
+    say(f"[parity] {label}: n={scene['means'].shape[1]} {cam['width']}x{cam['height']} dtype={dtype}")
+    g = gpu_render(renderer, scene, cam, dtype=dtype, background=background)
+    ref_scene = dequantised(scene, dtype)
+    o = oracle.render(ref_scene, cam, background=background)
+    amb = check_projection(g, o["proj"], label)
+    if len(amb) == 0:
+        check_lists_full(g, o, label)
+    stats = check_image(g, o, label)
+    say(f"[parity] {label}: K={len(o['keys'])} max_abs={stats['max_abs']:.2e} "
+        f"ambiguous={stats['ambiguous']} psnr={stats['psnr']:.1f}")
+    return g, o, stats
+
+
+# --------------------------------------------------------------------------- workloads
+
+def test_c1_full(renderer):
+    sc = scenes.make_scene("C1")
+    full_parity(renderer, sc, scenes.default_camera(128, 128), "C1 128x128")
+
+
+def test_c1_ragged_tiles(renderer):
+    sc = scenes.make_scene("C1", n=3000, seed=11)
+    full_parity(renderer, sc, scenes.default_camera(200, 120), "C1-dist 200x120 ragged")
+
+
+def test_mixture_sh3_medium(renderer):
+    sc = scenes.make_scene("C2", n=40_000, seed=21)
+    full_parity(renderer, sc, scenes.default_camera(333, 197), "C2-dist 40k 333x197")
+
+
+def test_powerlaw_rotated_camera(renderer):
+    sc = scenes.make_scene("C3", n=60_000, seed=31)
+    cam = scenes.look_at_camera([1.2, -0.8, -2.7], 400, 240)
+    full_parity(renderer, sc, cam, "C3-dist 60k rotated 400x240")
+
+
+def test_c2_full_size(renderer):
+    sc = scenes.make_scene("C2")
+    full_parity(renderer, sc, scenes.default_camera(1280, 720), "C2 500k 1280x720")
+
+
+def test_background_colour(renderer):
+    sc = scenes.make_scene("C1", n=800, seed=5)
+    full_parity(renderer, sc, scenes.default_camera(96, 80), "bg", background=(0.2, 0.5, 0.9))
+
+
+@pytest.mark.parametrize("dtype", [1, 2], ids=["bf16", "fp16"])
+def test_reduced_precision_storage(renderer, dtype):
+    sc = scenes.make_scene("C2", n=30_000, seed=41)
+    full_parity(renderer, sc, scenes.default_camera(256, 176), f"storage dtype {dtype}", dtype=dtype)
+
+
+# --------------------------------------------------------------------------- closed forms on the GPU
+
+def _tiny(means, log_scales, quats, logits, rgb):
+    n = np.asarray(means).reshape(3, -1).shape[1]
+    rgb = np.asarray(rgb, np.float64).reshape(3, n)
+    return dict(means=np.ascontiguousarray(np.asarray(means, np.float32).reshape(3, n)),
+                log_scales=np.ascontiguousarray(np.asarray(log_scales, np.float32).reshape(3, n)),
+                quats=np.ascontiguousarray(np.asarray(quats, np.float32).reshape(4, n)),
+                opacity_logits=np.ascontiguousarray(np.asarray(logits, np.float32).reshape(n)),
+                sh=np.ascontiguousarray(((rgb - 0.5) / (0.5 / math.sqrt(math.pi)))[None].astype(np.float32)),
+                sh_degree=0)
+
+
+def test_single_gaussian_centre_is_colour_times_alpha(renderer):
+    cam = scenes.default_camera(64, 64)
+    sc = _tiny([0, 0, 0], [math.log(0.02)] * 3, [1, 0, 0, 0], [0.4], [[0.8], [0.4], [0.2]])
+    g = gpu_render(renderer, sc, cam)
+    alpha = 1 / (1 + math.exp(-float(np.float32(0.4))))
+    rgb = sc["sh"][0, :, 0].astype(np.float64) * (0.5 / math.sqrt(math.pi)) + 0.5
+    np.testing.assert_allclose(g["image"][:, 32, 32], rgb * alpha, rtol=2e-6)
+    np.testing.assert_allclose(g["final_T"][32, 32], 1 - alpha, rtol=2e-6)
+    assert g["n_contrib"][32, 32] == 1
+
+
+def test_termination_after_13_of_20(renderer):
+    n = 20
+    sc = _tiny([np.zeros(n), np.zeros(n), np.linspace(-0.5, 0.5, n)], np.full((3, n), -2.5),
+               np.tile([[1], [0], [0], [0]], (1, n)), np.zeros(n), np.tile([[0.9], [0.5], [0.1]], (1, n)))
+    g = gpu_render(renderer, sc, scenes.default_camera(32, 32))
+    assert g["n_contrib"][16, 16] == 13
+    assert g["final_T"][16, 16] == 2.0 ** -13
+    T = g["final_T"]
+    assert (T >= 1e-4).all() and (T <= 1).all()
+
+
+# --------------------------------------------------------------------------- edge cases
+
+def test_empty_scene(renderer):
+    import torch
+    import paper_2607_15951_amd as gs
+    dev = {"sh_degree": 0, "attr_dtype": 0}
+    for k, shape in (("means", (3, 0)), ("log_scales", (3, 0)), ("quats", (4, 0)), ("opacity_logits", (0,)),
+                     ("sh", (1, 3, 0))):
+        dev[k] = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    out = renderer.render(dev, scenes.default_camera(40, 24), 40, 24, background=(0.25, 0.5, 0.75))
+    torch.cuda.synchronize()
+    img = out["image"].cpu().numpy()
+    np.testing.assert_array_equal(img, np.broadcast_to(np.array([0.25, 0.5, 0.75], np.float32)[:, None, None],
+                                                       img.shape))
+    assert (out["final_T"].cpu().numpy() == 1).all()
+    info = renderer.list_info()
+    assert info["num_pairs"] == 0 and info["n_visible"] == 0
+
+
+def test_everything_culled(renderer):
+    sc = scenes.make_scene("C1", n=500, seed=3)
+    sc["means"][2] = np.float32(-5.0)   # all behind the camera
+    g = gpu_render(renderer, sc, scenes.default_camera(64, 64))
+    assert g["num_pairs"] == 0 and g["n_visible"] == 0
+    assert (g["image"] == 0).all() and (g["final_T"] == 1).all()
+
+
+def test_one_pixel_image(renderer):
+    sc = scenes.make_scene("C1", n=2000, seed=4)
+    full_parity(renderer, sc, scenes.default_camera(1, 1), "1x1")
+
+
+def test_bad_gaussians_cull_only_themselves(renderer):
+    sc = scenes.make_scene("C1", n=400, seed=9)
+    cam = scenes.default_camera(96, 64)
+    bad = dict(sc)
+    bad = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    bad["means"][0, 10] = np.nan
+    bad["quats"][:, 20] = 0.0
+    g_bad = gpu_render(renderer, bad, cam)
+    keep = np.setdiff1d(np.arange(400), [10, 20])
+    ok = {k: (np.ascontiguousarray(v[..., keep]) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    g_ok = gpu_render(renderer, ok, cam)
+    assert g_bad["tiles_touched"][10] == 0 and g_bad["tiles_touched"][20] == 0
+    np.testing.assert_array_equal(g_bad["image"], g_ok["image"])
+    o = oracle.render(bad, cam)
+    check_projection(g_bad, o["proj"], "bad data")
+    check_lists_full(g_bad, o, "bad data")
+
+
+def test_huge_gaussian_covers_every_tile(renderer):
+    sc = scenes.make_scene("C1", n=200, seed=12)
+    sc["log_scales"][:, 0] = np.float32(0.5)
+    sc["means"][:, 0] = 0.0
+    full_parity(renderer, sc, scenes.default_camera(150, 90), "huge")
+
+
+def test_pair_capacity_mode(renderer):
+    import paper_2607_15951_amd as gs
+    sc = scenes.make_scene("C1", n=1500, seed=13)
+    cam = scenes.default_camera(128, 96)
+    ref = gpu_render(renderer, sc, cam)
+    K = ref["num_pairs"]
+    same = gpu_render(renderer, sc, cam, pair_capacity=K)
+    np.testing.assert_array_equal(same["image"], ref["image"])
+    np.testing.assert_array_equal(same["values"], ref["values"])
+    with pytest.raises(gs.GsError) as e:
+        gpu_render(renderer, sc, cam, pair_capacity=K - 1)
+    assert e.value.status == gs.GS_ERR_CAPACITY
+    again = gpu_render(renderer, sc, cam)   # context still usable
+    np.testing.assert_array_equal(again["image"], ref["image"])
+
+
+def test_context_reuse_across_sizes(renderer):
+    a = scenes.make_scene("C2", n=20_000, seed=51)
+    b = scenes.make_scene("C1", n=300, seed=52)
+    ca, cb = scenes.default_camera(300, 200), scenes.default_camera(64, 48)
+    ga1 = gpu_render(renderer, a, ca)
+    gb = gpu_render(renderer, b, cb)
+    ga2 = gpu_render(renderer, a, ca)
+    np.testing.assert_array_equal(ga1["image"], ga2["image"])
+    np.testing.assert_array_equal(ga1["values"], ga2["values"])
+    o = oracle.render(b, cb)
+    check_lists_full(gb, o, "small after large")
+
+
+def test_permutation_and_repeat_determinism(renderer):
+    sc = scenes.make_scene("C2", n=10_000, seed=61)
+    cam = scenes.default_camera(200, 150)
+    g1 = gpu_render(renderer, sc, cam)
+    g2 = gpu_render(renderer, sc, cam)
+    for k in ("image", "final_T", "n_contrib", "values", "keys"):
+        np.testing.assert_array_equal(g1[k], g2[k])
