@@ -1,0 +1,223 @@
+#!/usr/bin/env python
+"""Frames/s of the forward Gaussian-splatting render on one MI355X.
+
+Workload (default): 3,000,000 Gaussians (256-cluster power-law mixture plus
+10% large background Gaussians, SH degree 3, float32 attributes) rendered at
+1920x1080 with 16x16 tiles from the default camera; synthetic, seeded.  A step
+is one gs_render call -- project, depth sort, tile count/offsets, sorted pair
+list, blend -- with the scene already resident in HBM.
+
+Prints ONE JSON line with the frame rate, the per-stage device times (HIP
+events recorded by the library on the render stream during the timed steps),
+a roofline entry for the dominant kernel and the FP64 oracle's time on a
+bounded sample of the same frame on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--variant fp32|bf16|fp16]
+                    [--workload C3] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/s and achieved HBM GB/s (% peak), 1080p / 3M Gaussians, FP32 vs BF16 vs batched"
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+TILE = 16
+# algorithmic FP32 operations of one (pixel, list entry) evaluation of Eq. 1's
+# term: offset (2), quadratic form (3 products, 3 conic products, 2 adds,
+# 1 scale), exp (1), times opacity (1) = 13; a composited entry adds the
+# transmittance update (2) and the weighted colour accumulation (1 + 3 x 2).
+FLOPS_EVAL = 13
+FLOPS_COMPOSITE = 9
+BAND_TILES = 2048     # tiles per binning band (LDS counters of one wave)
+CHUNK_PAIRS = 32768   # pairs per binning wave
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def attr_bytes(dtype: int) -> int:
+    return 4 if dtype == 0 else 2
+
+
+def algorithmic_bytes(stage: str, n: int, n_vis: int, K: int, deg: int, dtype: int, W: int, H: int,
+                      bands: int, chunks: int, stats: dict) -> float:
+    """HBM bytes one launch of a single-kernel stage must move."""
+    T = ((W + TILE - 1) // TILE) * ((H + TILE - 1) // TILE)
+    band_tiles = min(T, BAND_TILES)
+    if stage == "project":
+        per_in = 12 + attr_bytes(dtype) * (3 + 4 + 1 + 3 * (deg + 1) ** 2)
+        per_out = 48 + 4 + 4 + 4 + 8
+        return n * (per_in + per_out)
+    if stage == "bin_count":      # walk: band prefix + rectangle per sorted position and band
+        return bands * n_vis * (4 + 8) + chunks * band_tiles * 4
+    if stage == "bin_scatter":    # walk + Gaussian index, chunk prefixes, tile offsets, the values
+        return bands * n_vis * (4 + 8 + 4) + chunks * band_tiles * 4 + T * 4 + K * 4
+    if stage == "blend":
+        return stats["staged"] * (4 + 48) + W * H * 20
+    raise KeyError(stage)
+
+
+def cpu_baseline(scene, cam, band_rows: int = 4) -> dict:
+    """The FP64 oracle on a bounded sample of the same frame.
+
+    Sample: the whole projection and pair emission of the frame, then the sort,
+    tile ranges and compositing of ``band_rows`` tile rows in the middle of
+    the image; the frame time is extrapolated as project + emit +
+    (sort + composite of the band) / (band share of all pairs)."""
+    import numpy as np
+    import oracle
+    W, H = cam["width"], cam["height"]
+    tx, ty = (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
+    t0 = time.perf_counter()
+    proj = oracle.project(scene, cam)
+    t1 = time.perf_counter()
+    _, keys, values = oracle.bin_pairs(proj)
+    t2 = time.perf_counter()
+    r0 = ty // 2 - band_rows // 2
+    lo, hi = np.uint64(r0 * tx) << np.uint64(32), np.uint64((r0 + band_rows) * tx) << np.uint64(32)
+    sel = (keys >= lo) & (keys < hi)
+    bk, bv = oracle.sort_pairs(keys[sel], values[sel])
+    ranges = oracle.tile_ranges(bk, tx * ty)
+    pxs, pys = [], []
+    for tile in range(r0 * tx, (r0 + band_rows) * tx):
+        x0, y0 = (tile % tx) * TILE, (tile // tx) * TILE
+        ys, xs = np.mgrid[y0:min(y0 + TILE, H), x0:min(x0 + TILE, W)]
+        s, e = ranges[tile]
+        oracle.composite_pixels(proj, xs.ravel(), ys.ravel(), bv[s:e])
+    t3 = time.perf_counter()
+    share = float(sel.sum()) / max(1, len(keys))
+    frame_s = (t1 - t0) + (t2 - t1) + (t3 - t2) / max(share, 1e-9)
+    del keys, values
+    return {"value": 1.0 / frame_s, "unit": "frames/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle: full projection ({t1 - t0:.2f} s) and pair emission ({t2 - t1:.2f} s) "
+                       f"of the frame, then sort + composite of {band_rows} middle tile rows "
+                       f"({t3 - t2:.2f} s, {share * 100:.1f}% of the pairs); frame time extrapolated "
+                       f"to {frame_s:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--variant", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this single-GPU build "
+              "(the render shards by camera or screen tiles, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2607_15951_amd as gs
+    import scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dtype = {"fp32": gs.GS_F32, "bf16": gs.GS_BF16, "fp16": gs.GS_F16}[args.variant]
+    log(f"[bench] generating {args.workload}")
+    scene = scenes.make_scene(args.workload)
+    cam = scenes.make_cameras(args.workload)[0]
+    W, H = cam["width"], cam["height"]
+    n = scene["means"].shape[1]
+    deg = scene["sh_degree"]
+    dev = gs.scene_to_device(scene, dtype)
+    r = gs.Renderer(0)
+    out = {"image": torch.empty((3, H, W), dtype=torch.float32, device="cuda"),
+           "final_T": torch.empty((H, W), dtype=torch.float32, device="cuda"),
+           "n_contrib": torch.empty((H, W), dtype=torch.int32, device="cuda")}
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        r.render(dev, cam, W, H, out=out)
+    torch.cuda.synchronize()
+
+    r.set_profiling(True)
+    stage_sum = {k: 0.0 for k in gs.STAGES}
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r.render(dev, cam, W, H, out=out)
+        st = r.stage_times()
+        for k, v in st.items():
+            stage_sum[k] += v
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    stats = r.blend_stats()
+    info = r.list_info()
+    r.set_profiling(False)
+    stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
+    log("[bench] stages ms " + json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
+
+    K, n_vis = info["num_pairs"], info["n_visible"]
+    tiles_x = (W + TILE - 1) // TILE
+    band_rows = BAND_TILES // tiles_x
+    bands = ((H + TILE - 1) // TILE + band_rows - 1) // band_rows
+    chunks = K // CHUNK_PAIRS + bands
+    single = ["project", "bin_count", "bin_scatter", "blend"]
+    dom = max(single, key=lambda k: stage_ms[k])
+    if dom == "blend":
+        flops = FLOPS_EVAL * stats["evaluations"] + FLOPS_COMPOSITE * stats["composited"]
+        achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
+        roof = {"kernel": "blend_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None, "work": {"evaluations": stats["evaluations"], "composited": stats["composited"],
+                                          "flops_per_evaluation": FLOPS_EVAL,
+                                          "flops_per_composite": FLOPS_COMPOSITE}}
+    else:
+        by = algorithmic_bytes(dom, n, n_vis, K, deg, dtype, W, H, bands, chunks, stats)
+        achieved = by / (stage_ms[dom] * 1e-3) / 1e9
+        roof = {"kernel": dom + "_kernel", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(by)}
+    stage_gbs = {}
+    for k in ("project", "bin_count", "bin_scatter", "blend"):
+        by = algorithmic_bytes(k, n, n_vis, K, deg, dtype, W, H, bands, chunks, stats)
+        stage_gbs[k] = round(by / (stage_ms[k] * 1e-3) / 1e9, 1) if stage_ms[k] > 0 else None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (FP64 oracle, bounded sample)")
+        cpu = cpu_baseline(scene, cam)
+
+    res = {
+        "metric": METRIC,
+        "value": round(1e3 / ms_per_step, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if dtype == gs.GS_F32 else ("f32 compute, bf16 attributes" if dtype == gs.GS_BF16
+                                                     else "f32 compute, f16 attributes"),
+        "data": "synthetic",
+        "config": {"workload": scenes.WORKLOAD_NAMES[args.workload], "gaussians": n, "width": W, "height": H,
+                   "sh_degree": deg, "tile": TILE, "attributes": args.variant, "num_pairs": K,
+                   "visible": n_vis},
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "stages_algorithmic_GBps": stage_gbs,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    r.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

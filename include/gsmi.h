@@ -89,8 +89,11 @@ typedef struct {
  *   tile_size      must be 16
  *   pair_capacity  0: the library reads the pair count back to the host
  *                  and grows its buffers (one host sync per render);
- *                  > 0: fixed upper bound on (Gaussian, tile) pairs, no
- *                  sync; a larger count returns GS_ERR_CAPACITY
+ *                  > 0: fixed upper bound on (Gaussian, tile) pairs and no
+ *                  host sync; pairs past the bound are dropped without any
+ *                  out-of-bounds write, the image is then unspecified, and
+ *                  gs_get_list_info (hence gs_copy_lists) returns
+ *                  GS_ERR_CAPACITY for that render
  *   flags          reserved, must be 0 */
 typedef struct {
     float background[3];
@@ -161,6 +164,32 @@ gs_status gs_copy_lists(gs_context* ctx, uint32_t* values, uint32_t* tile_offset
  *   rect           uint16 [n][4] tile rectangle x0, y0, x1, y1 (exclusive) */
 gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key, int32_t* radius,
                              uint32_t* tiles_touched, uint16_t* rect, void* stream);
+
+/* Stage timing (tracing).  When enabled, gs_render records HIP events on its
+ * stream between the stages below; gs_get_stage_times synchronises on them
+ * and returns the device time of each stage of the last render, in
+ * milliseconds, in this order:
+ *   0 project      (one kernel: cull, EWA projection, SH colour)
+ *   1 depth_sort   (four LSD radix passes over the N depth keys)
+ *   2 bin_prepare  (per-band pair counts, their prefix, chunk table)
+ *   3 bin_count    (one kernel: per-chunk, per-tile pair counts)
+ *   4 bin_offsets  (column and tile scans of the counts)
+ *   5 bin_scatter  (one kernel: the sorted pair list)
+ *   6 blend        (one kernel: per-tile compositing)
+ * The host read of the pair count (pair_capacity 0) falls between stages 2
+ * and 3 and belongs to neither.  count must be GS_NUM_STAGES. */
+#define GS_NUM_STAGES 7
+
+gs_status gs_set_profiling(gs_context* ctx, int32_t enable);
+
+gs_status gs_get_stage_times(gs_context* ctx, float* ms, int32_t count);
+
+/* Blend work of the last traced render (host array of 3):
+ *   [0] (pixel, list entry) evaluations of Eq. 1's term, up to each pixel's
+ *       termination -- the work the per-pixel walk of Sec. 4.5 requires
+ *   [1] evaluations that passed the 1/255 alpha test and were composited
+ *   [2] list entries staged from HBM into LDS (summed over tiles) */
+gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats3);
 
 #ifdef __cplusplus
 }

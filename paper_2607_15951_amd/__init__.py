@@ -21,7 +21,9 @@ GS_F32, GS_BF16, GS_F16 = 0, 1, 2
 TILE = 16
 
 EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
-            "gs_copy_lists", "gs_copy_projection"]
+            "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
+            "gs_get_blend_stats"]
+STAGES = ["project", "depth_sort", "bin_prepare", "bin_count", "bin_offsets", "bin_scatter", "blend"]
 
 
 class GsError(RuntimeError):
@@ -81,6 +83,12 @@ def load_library(path: str = LIB_PATH):
     L.gs_copy_lists.restype = C.c_int
     L.gs_copy_projection.argtypes = [P, P, P, P, P, P, P]
     L.gs_copy_projection.restype = C.c_int
+    L.gs_set_profiling.argtypes = [P, C.c_int32]
+    L.gs_set_profiling.restype = C.c_int
+    L.gs_get_stage_times.argtypes = [P, C.POINTER(C.c_float), C.c_int32]
+    L.gs_get_stage_times.restype = C.c_int
+    L.gs_get_blend_stats.argtypes = [P, C.POINTER(C.c_uint64)]
+    L.gs_get_blend_stats.restype = C.c_int
     _lib = L
     return L
 
@@ -198,6 +206,22 @@ class Renderer:
         self._check(st)
         self._last = (dev, int(g.n))
         return out
+
+    def set_profiling(self, enable: bool):
+        """Record HIP events between render stages (see stage_times)."""
+        self._check(self._L.gs_set_profiling(self._ctx, 1 if enable else 0))
+
+    def stage_times(self) -> dict:
+        """Device milliseconds per stage of the last (timed) render."""
+        ms = (C.c_float * len(STAGES))()
+        self._check(self._L.gs_get_stage_times(self._ctx, ms, len(STAGES)))
+        return {k: float(ms[i]) for i, k in enumerate(STAGES)}
+
+    def blend_stats(self) -> dict:
+        """Blend work counters of the last traced render."""
+        v = (C.c_uint64 * 3)()
+        self._check(self._L.gs_get_blend_stats(self._ctx, v))
+        return dict(evaluations=int(v[0]), composited=int(v[1]), staged=int(v[2]))
 
     def list_info(self) -> dict:
         info = gs_list_info()

@@ -4,6 +4,7 @@
 #include "gsmi.h"
 #include "gs_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -26,10 +27,17 @@ struct gs_context {
     int device = 0;
     std::string err;
     DevBuf splats, depth_key, radius, tiles_touched, rect;
-    DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist;
-    DevBuf counters;   // [0] n_visible, [1] overflow, [2..3] K as u64
-    DevBuf counts, totals, tile_offsets, values;
-    uint64_t* host_k = nullptr;   // pinned readback slot
+    DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist, scan_scratch;
+    DevBuf rect_s, band_pairs, band_info;
+    DevBuf counters;   // [0] n_visible, [1] overflow, [2..3] K as u64, [4..9] blend stats (3 x u64)
+    DevBuf counts, tile_offsets, values;
+    uint32_t* host_info = nullptr;   // pinned readback: band table, then K as u64
+    bool profiling = false;
+    bool timed = false;   // the last render recorded stage events
+    // stage boundaries: 0 start, 1 project, 2 depth sort, 3 bin prepare,
+    // 4 count start (after the host read of K), 5 count, 6 offsets,
+    // 7 scatter, 8 blend
+    hipEvent_t ev[9] = {};
     // last render
     bool have_render = false;
     int64_t n = 0;
@@ -116,6 +124,12 @@ gs_status validate(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam,
         if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
     } while (0)
 
+// records the boundary event k when stage timing is on
+#define STAGE_MARK(k)                                                               \
+    do {                                                                            \
+        if (ctx->profiling) HIP_TRY(hipEventRecord(ctx->ev[(k)], s), "hipEventRecord"); \
+    } while (0)
+
 }  // namespace
 
 extern "C" {
@@ -131,7 +145,8 @@ gs_status gs_create(int device, gs_context** out)
     gs_context* ctx = new gs_context();
     ctx->device = device;
     e = hipSetDevice(device);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->host_k), sizeof(uint64_t));
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&ctx->host_info), sizeof(uint32_t) * (2 * kMaxBands + 8));
     if (e != hipSuccess) {
         delete ctx;
         return hip_fail(nullptr, e, "context set-up");
@@ -146,10 +161,13 @@ void gs_destroy(gs_context* ctx)
     (void)hipSetDevice(ctx->device);
     DevBuf* bufs[] = {&ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
                       &ctx->sort_ka, &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb, &ctx->hist,
-                      &ctx->counters, &ctx->counts, &ctx->totals, &ctx->tile_offsets, &ctx->values};
+                      &ctx->scan_scratch, &ctx->rect_s, &ctx->band_pairs, &ctx->band_info,
+                      &ctx->counters, &ctx->counts, &ctx->tile_offsets, &ctx->values};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
-    if (ctx->host_k) (void)hipHostFree(ctx->host_k);
+    if (ctx->host_info) (void)hipHostFree(ctx->host_info);
+    for (hipEvent_t e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -182,7 +200,7 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     const int64_t T = (int64_t)tiles_x * tiles_y;
     const int band_rows = kMaxBandTiles / tiles_x;
     const int num_bands = (tiles_y + band_rows - 1) / band_rows;
-    const int num_chunks = (int)((n + kBinChunk - 1) / kBinChunk);
+    if (num_bands > kMaxBands) return fail(ctx, GS_ERR_UNSUPPORTED, "image has more than 131072 tiles");
     const size_t nn = (size_t)(n > 0 ? n : 1);
 
     if ((st = ensure(ctx, ctx->splats, nn * sizeof(Splat))) != GS_OK) return st;
@@ -195,15 +213,19 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     if ((st = ensure(ctx, ctx->sort_kb, nn * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->sort_vb, nn * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->hist, depth_sort_hist_elems(n) * 4)) != GS_OK) return st;
+    const size_t scan_elems = scan_scratch_elems(std::max<int64_t>((int64_t)num_bands * n,
+                                                                   std::max<int64_t>((int64_t)depth_sort_hist_elems(n), T)));
+    if ((st = ensure(ctx, ctx->scan_scratch, scan_elems * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->rect_s, nn * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->band_pairs, nn * (size_t)num_bands * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->band_info, (2 * kMaxBands + 8) * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->counters, 64)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->counts, (size_t)(num_chunks > 0 ? num_chunks : 1) * (size_t)T * 4)) != GS_OK)
-        return st;
-    if ((st = ensure(ctx, ctx->totals, (size_t)T * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
 
     uint32_t* counters = static_cast<uint32_t*>(ctx->counters.p);
     uint64_t* k_total = reinterpret_cast<uint64_t*>(counters + 2);
-    HIP_TRY(launch_fill_u32(counters, 0u, 4, s), "clear counters");
+    HIP_TRY(launch_fill_u32(counters, 0u, 10, s), "clear counters");
+    STAGE_MARK(0);
 
     ProjectArgs pa{};
     pa.n = n;
@@ -234,47 +256,69 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     pa.rect = static_cast<ushort4*>(ctx->rect.p);
     pa.n_visible = counters;
     HIP_TRY(launch_project(pa, s), "project");
+    STAGE_MARK(1);
 
     int in_b = 1;
+    uint64_t* scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
     HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
                               static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
-                              static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p), n,
-                              &in_b, s),
+                              static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p),
+                              scan_scratch, n, &in_b, s),
             "depth sort");
+    STAGE_MARK(2);
 
     BinArgs ba{};
     ba.sorted_idx = static_cast<const uint32_t*>(in_b ? ctx->sort_vb.p : ctx->sort_va.p);
     ba.n_visible = counters;
     ba.rect = pa.rect;
+    ba.rect_s = static_cast<ushort4*>(ctx->rect_s.p);
+    ba.bp = static_cast<uint32_t*>(ctx->band_pairs.p);
+    ba.band_info = static_cast<uint32_t*>(ctx->band_info.p);
     ba.n = n;
     ba.tiles_x = tiles_x;
     ba.tiles_y = tiles_y;
     ba.band_rows = band_rows;
     ba.num_bands = num_bands;
-    ba.num_chunks = num_chunks;
-    ba.counts = static_cast<uint32_t*>(ctx->counts.p);
-    ba.totals = static_cast<uint32_t*>(ctx->totals.p);
     ba.tile_offsets = static_cast<uint32_t*>(ctx->tile_offsets.p);
     ba.overflow = counters + 1;
-    ba.capacity = o.pair_capacity ? o.pair_capacity : ~0ull;
-    HIP_TRY(launch_bin_count(ba, s), "bin count");
-    HIP_TRY(launch_bin_offsets(ba, s, k_total), "bin offsets");
-
     uint64_t capacity = o.pair_capacity;
+    // capacity mode: the grids are sized for the worst case the capacity allows
+    ba.max_chunks = capacity ? (int)std::min<uint64_t>(capacity / kChunkPairs + num_bands + 1, 1u << 30)
+                             : (1 << 30);
+    HIP_TRY(launch_bin_prepare(ba, scan_scratch, k_total, s), "bin prepare");
+    STAGE_MARK(3);
+
+    int grid = ba.max_chunks;
     if (capacity == 0) {
-        HIP_TRY(hipMemcpyAsync(ctx->host_k, k_total, sizeof(uint64_t), hipMemcpyDeviceToHost, s), "read K");
+        // eager: one host read of the band table and K sizes the rest
+        HIP_TRY(hipMemcpyAsync(ctx->host_info, ba.band_info, sizeof(uint32_t) * (2 * num_bands + 2),
+                               hipMemcpyDeviceToHost, s),
+                "read band table");
+        HIP_TRY(hipMemcpyAsync(ctx->host_info + 2 * kMaxBands + 4, k_total, sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, s),
+                "read K");
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-        const uint64_t K = *ctx->host_k;
-        if (K > 0xFFFFFFFFull) {
+        uint64_t K64;
+        std::memcpy(&K64, ctx->host_info + 2 * kMaxBands + 4, sizeof K64);
+        if (K64 > 0xFFFFFFFFull) {
             ctx->have_render = false;
             return fail(ctx, GS_ERR_CAPACITY, "more than 2^32-1 (Gaussian, tile) pairs");
         }
-        capacity = K;
+        capacity = K64;
+        grid = (int)ctx->host_info[2 * num_bands + 1];
     }
+    if ((st = ensure(ctx, ctx->counts, (size_t)(grid > 0 ? grid : 1) * kMaxBandTiles * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->values, (size_t)(capacity > 0 ? capacity : 1) * 4)) != GS_OK) return st;
+    ba.counts = static_cast<uint32_t*>(ctx->counts.p);
     ba.values = static_cast<uint32_t*>(ctx->values.p);
     ba.capacity = capacity;
-    HIP_TRY(launch_bin_scatter(ba, s), "bin scatter");
+    STAGE_MARK(4);
+    HIP_TRY(launch_bin_count(ba, grid, s), "bin count");
+    STAGE_MARK(5);
+    HIP_TRY(launch_bin_offsets(ba, scan_scratch, s), "bin offsets");
+    STAGE_MARK(6);
+    HIP_TRY(launch_bin_scatter(ba, grid, s), "bin scatter");
+    STAGE_MARK(7);
 
     BlendArgs bl{};
     bl.splats = pa.splats;
@@ -290,9 +334,12 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     bl.out_rgb = out_rgb;
     bl.out_T = out_final_T;
     bl.out_nc = out_n_contrib;
+    bl.stats = ctx->profiling ? reinterpret_cast<unsigned long long*>(counters + 4) : nullptr;
     HIP_TRY(launch_blend(bl, capacity, s), "blend");
+    STAGE_MARK(8);
 
     ctx->have_render = true;
+    ctx->timed = ctx->profiling;
     ctx->n = n;
     ctx->tiles_x = tiles_x;
     ctx->tiles_y = tiles_y;
@@ -356,6 +403,44 @@ gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key
     if (tiles_touched)
         HIP_TRY(hipMemcpyAsync(tiles_touched, ctx->tiles_touched.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
     if (rect) HIP_TRY(hipMemcpyAsync(rect, ctx->rect.p, n * 8, hipMemcpyDeviceToDevice, s), "copy");
+    return GS_OK;
+}
+
+gs_status gs_set_profiling(gs_context* ctx, int32_t enable)
+{
+    if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (enable && !ctx->ev[0]) {
+        HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+        for (hipEvent_t& e : ctx->ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    }
+    ctx->profiling = enable != 0;
+    return GS_OK;
+}
+
+gs_status gs_get_stage_times(gs_context* ctx, float* ms, int32_t count)
+{
+    if (!ctx || !ms) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (count != GS_NUM_STAGES) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "count must be GS_NUM_STAGES");
+    if (!ctx->have_render || !ctx->timed)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render was not timed (gs_set_profiling)");
+    HIP_TRY(hipEventSynchronize(ctx->ev[8]), "hipEventSynchronize");
+    const int from[GS_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7};
+    const int to[GS_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 8};
+    for (int k = 0; k < GS_NUM_STAGES; ++k)
+        HIP_TRY(hipEventElapsedTime(&ms[k], ctx->ev[from[k]], ctx->ev[to[k]]), "hipEventElapsedTime");
+    return GS_OK;
+}
+
+gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats3)
+{
+    if (!ctx || !stats3) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (!ctx->have_render || !ctx->timed)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render was not traced (gs_set_profiling)");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(hipMemcpyAsync(stats3, static_cast<uint32_t*>(ctx->counters.p) + 4, 3 * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, ctx->stream),
+            "read stats");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     return GS_OK;
 }
 

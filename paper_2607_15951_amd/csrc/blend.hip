@@ -47,10 +47,11 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     const float fx = (float)lx, fy = (float)ly;
 
     float Tr = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-    uint32_t last = 0;
+    uint32_t last = 0, examined = 0, composited = 0, staged = 0;
     bool done = !inside;
     for (uint64_t b0 = start; b0 < end; b0 += 256) {
         if (__syncthreads_count(!done) == 0) break;
+        staged += (end - b0 < 256) ? (uint32_t)(end - b0) : 256u;
         const uint64_t e = b0 + tid;
         if (e < end) {
             const uint32_t g = a.values[e];
@@ -68,7 +69,8 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
         __syncthreads();
         if (!done) {
             const int cnt = (end - b0 < 256) ? (int)(end - b0) : 256;
-            for (int j = 0; j < cnt; ++j) {
+            int j = 0;
+            for (; j < cnt; ++j) {
                 const float4 e0 = s0[j];
                 const float4 e1 = s1[j];
                 const float dx = (e0.x - fx) + e0.z;
@@ -81,6 +83,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
                     done = true;
                     break;
                 }
+                ++composited;
                 const float4 e2 = s2[j];
                 const float wgt = al * Tr;
                 c0 = fmaf(wgt, e2.x, c0);
@@ -89,7 +92,20 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
                 Tr = tn;
                 last = (uint32_t)(b0 - start) + (uint32_t)j + 1u;
             }
+            examined += (uint32_t)(j < cnt ? j + 1 : cnt);
         }
+    }
+    if (a.stats) {   // tracing only: one atomic per wave
+        unsigned long long ev = examined, co = composited;
+        for (int o = 32; o > 0; o >>= 1) {
+            ev += __shfl_xor(ev, o, 64);
+            co += __shfl_xor(co, o, 64);
+        }
+        if ((tid & 63) == 0) {
+            atomicAdd(&a.stats[0], ev);
+            atomicAdd(&a.stats[1], co);
+        }
+        if (tid == 0) atomicAdd(&a.stats[2], (unsigned long long)staged);
     }
     if (!inside) return;
     const int64_t P = (int64_t)a.width * a.height;

@@ -79,31 +79,6 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     }
 }
 
-// Exclusive scan of `count` u32 values by one 1024-thread block, in place.
-__global__ __launch_bounds__(1024) void scan_inplace_kernel(uint32_t* __restrict__ data, int64_t count)
-{
-    __shared__ uint32_t part[1024];
-    const int tid = threadIdx.x;
-    const int64_t per = (count + 1023) / 1024;
-    const int64_t s = tid * per, e = (s + per < count) ? s + per : count;
-    uint32_t sum = 0;
-    for (int64_t j = s; j < e; ++j) sum += data[j];
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[tid] - sum;
-    for (int64_t j = s; j < e; ++j) {
-        const uint32_t v = data[j];
-        data[j] = run;
-        run += v;
-    }
-}
-
 }  // namespace
 
 size_t depth_sort_hist_elems(int64_t n)
@@ -115,7 +90,8 @@ size_t depth_sort_hist_elems(int64_t n)
 // Sorts keys_in[0..n) (not modified) with values 0..n-1.  Four passes:
 // in -> a -> b -> a -> b, so the sorted keys/values end in (keys_b, vals_b).
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
-                             uint32_t* vals_b, uint32_t* hist, int64_t n, int* result_in_b, hipStream_t s)
+                             uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch, int64_t n, int* result_in_b,
+                             hipStream_t s)
 {
     *result_in_b = 1;
     if (n == 0) return hipSuccess;
@@ -127,7 +103,8 @@ hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, hist, nblocks);
-        hipLaunchKernelGGL(scan_inplace_kernel, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * nblocks);
+        hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblocks, scan_scratch, nullptr, nullptr, nullptr, s);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n,
                            shift, hist, nblocks);
         kin = kout;

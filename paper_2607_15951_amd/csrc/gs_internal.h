@@ -13,7 +13,8 @@ constexpr int kMaxBandTiles = 2048;       // LDS cursors per binning wave
 constexpr int kSortBlock = 256;           // threads of a depth-sort block
 constexpr int kSortItems = 8;             // keys per thread per depth-sort block
 constexpr int kSortTile = kSortBlock * kSortItems;
-constexpr int kBinChunk = 8192;           // depth-sorted Gaussians per binning wave
+constexpr int kChunkPairs = 32768;        // (Gaussian, tile) pairs per binning wave
+constexpr int kMaxBands = 64;             // bands of tile rows per image
 
 // One projected Gaussian as the blend reads it: 3 x float4 = 48 bytes.
 //   a = (u_hi, v_hi, u_lo, v_lo)   2D centre as a float pair of the double
@@ -50,26 +51,37 @@ hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
 // passes; *result_in_b tells which ping-pong buffer pair holds the result.
 size_t depth_sort_hist_elems(int64_t n);
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a,
-                             uint32_t* keys_b, uint32_t* vals_b, uint32_t* hist, int64_t n,
-                             int* result_in_b, hipStream_t s);
+                             uint32_t* keys_b, uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch,
+                             int64_t n, int* result_in_b, hipStream_t s);
 
 struct BinArgs {
-    const uint32_t* sorted_idx;   // depth-sorted Gaussian indices
-    const uint32_t* n_visible;    // device counter
-    const ushort4* rect;
-    int64_t n;                    // upper bound of n_visible
-    int tiles_x, tiles_y, band_rows, num_bands, num_chunks;
-    uint32_t* counts;             // [num_chunks][tiles] -> column prefix in place
-    uint32_t* totals;             // [tiles]
+    const uint32_t* sorted_idx;   // [n] Gaussian indices in (depth, index) order
+    const uint32_t* n_visible;    // device counter; visible Gaussians sort first
+    const ushort4* rect;          // [n] tile rectangle by Gaussian index
+    ushort4* rect_s;              // [n] tile rectangle by sorted position
+    uint32_t* bp;                 // [bands][n] pair counts -> exclusive prefix
+    uint32_t* band_info;          // [2 * bands + 3] band and chunk tables
+    int64_t n;
+    int tiles_x, tiles_y, band_rows, num_bands;
+    int max_chunks;               // chunks the count/scatter grids can hold
+    uint32_t* counts;             // [max_chunks][kMaxBandTiles] -> prefix in place
     uint32_t* tile_offsets;       // [tiles + 1]
     uint32_t* values;             // [capacity] sorted pair values
     uint64_t capacity;
-    uint32_t* overflow;           // set to 1 when K > capacity
+    uint32_t* overflow;           // set to 1 when K > capacity or K >= 2^32
 };
 
-hipError_t launch_bin_count(const BinArgs& a, hipStream_t s);
-hipError_t launch_bin_offsets(const BinArgs& a, hipStream_t s, uint64_t* k_total);
-hipError_t launch_bin_scatter(const BinArgs& a, hipStream_t s);
+hipError_t launch_bin_prepare(const BinArgs& a, uint64_t* scan_scratch, uint64_t* k_total, hipStream_t s);
+hipError_t launch_bin_count(const BinArgs& a, int grid, hipStream_t s);
+hipError_t launch_bin_offsets(const BinArgs& a, uint64_t* scan_scratch, hipStream_t s);
+hipError_t launch_bin_scatter(const BinArgs& a, int grid, hipStream_t s);
+
+// Device-wide exclusive scan of n uint32 values in place; 64-bit total to
+// *total64 and/or *total32 (either may be null), overflow flag when the total
+// does not fit 32 bits.  block_scratch holds scan_scratch_elems(n) u64.
+size_t scan_scratch_elems(int64_t n);
+hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scratch, uint64_t* total64,
+                                 uint32_t* total32, uint32_t* overflow, hipStream_t s);
 
 struct BlendArgs {
     const Splat* splats;
@@ -80,6 +92,10 @@ struct BlendArgs {
     float* out_rgb;
     float* out_T;        // may be null
     uint32_t* out_nc;    // may be null
+    // work counters when tracing (else null): [0] (pixel, entry) evaluations,
+    // [1] entries that passed the alpha test and were composited, [2] list
+    // entries staged into LDS
+    unsigned long long* stats;
 };
 
 hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s);

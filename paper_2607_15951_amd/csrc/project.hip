@@ -168,7 +168,7 @@ __device__ __forceinline__ bool project_geometry(const ProjectArgs& a, double mx
     return true;
 }
 
-template <int DT>
+template <int DT, int DEG>
 __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -220,12 +220,13 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
         dy *= inv;
         dz *= inv;
         float Y[16];
-        sh_basis(dx, dy, dz, a.sh_degree, Y);
-        const int ncoef = (a.sh_degree + 1) * (a.sh_degree + 1);
+        sh_basis(dx, dy, dz, DEG, Y);
+        constexpr int ncoef = (DEG + 1) * (DEG + 1);
         float col[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float acc = 0.0f;
+#pragma unroll
             for (int k = 0; k < ncoef; ++k) acc += load_attr<DT>(a.sh, ((int64_t)k * 3 + ch) * n + i) * Y[k];
             col[ch] = fmaxf(acc + 0.5f, 0.0f);
         }
@@ -249,14 +250,25 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 
 }  // namespace
 
+template <int DT>
+void launch_project_dt(const ProjectArgs& a, unsigned blocks, hipStream_t s)
+{
+    switch (a.sh_degree) {
+    case 0: hipLaunchKernelGGL((project_kernel<DT, 0>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((project_kernel<DT, 1>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((project_kernel<DT, 2>), dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((project_kernel<DT, 3>), dim3(blocks), dim3(256), 0, s, a); break;
+    }
+}
+
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((a.n + 255) / 256);
     switch (a.dtype) {
-    case 0: hipLaunchKernelGGL(project_kernel<0>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(project_kernel<1>, dim3(blocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(project_kernel<2>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 0: launch_project_dt<0>(a, blocks, s); break;
+    case 1: launch_project_dt<1>(a, blocks, s); break;
+    default: launch_project_dt<2>(a, blocks, s); break;
     }
     return hipGetLastError();
 }

@@ -1,0 +1,122 @@
+// scan.hip -- device-wide exclusive prefix sum of uint32 values (reduce, scan
+// of block sums, down-sweep), used by the depth sort's digit offsets and by
+// the per-band pair prefix of the binning.  Block sums and the total are
+// accumulated in 64 bits; the total is written to *total (and an overflow
+// flag raised when it does not fit 32 bits).
+#include "gs_internal.h"
+
+namespace gsmi {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t v, uint64_t* sh, uint64_t* total)
+{
+    // Hillis-Steele over 256 lanes in LDS (once per block, not per item)
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+        const uint64_t t = tid >= o ? sh[tid - o] : 0ull;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    const uint64_t incl = sh[tid];
+    *total = sh[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                                    uint64_t* __restrict__ block_sums)
+{
+    __shared__ uint64_t sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k * kScanThreads + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint64_t tot;
+    (void)block_exclusive_u64(s, sh, &tot);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// exclusive scan of nb block sums by one block; writes the 64-bit total
+__global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(uint64_t* __restrict__ sums, int64_t nb,
+                                                                   uint64_t* total_out, uint32_t* total32,
+                                                                   uint32_t* overflow)
+{
+    __shared__ uint64_t sh[kScanThreads];
+    const int64_t per = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t s = threadIdx.x * per, e = (s + per < nb) ? s + per : nb;
+    uint64_t acc = 0;
+    for (int64_t j = s; j < e; ++j) acc += sums[j];
+    uint64_t tot;
+    uint64_t run = block_exclusive_u64(acc, sh, &tot);
+    for (int64_t j = s; j < e; ++j) {
+        const uint64_t v = sums[j];
+        sums[j] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) {
+        if (total_out) *total_out = tot;
+        if (total32) *total32 = (uint32_t)tot;
+        if (overflow && tot > 0xFFFFFFFFull) *overflow = 1u;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __restrict__ data, int64_t n,
+                                                                 const uint64_t* __restrict__ block_prefix)
+{
+    __shared__ uint64_t sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // thread t owns the kScanItems consecutive items [t*16, t*16+16) of the tile
+    uint32_t v[kScanItems];
+    const int64_t mine = base + (int64_t)threadIdx.x * kScanItems;
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (mine + k < n) ? data[mine + k] : 0u;
+        s += v[k];
+    }
+    uint64_t tot;
+    uint64_t run = block_exclusive_u64(s, sh, &tot) + block_prefix[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (mine + k < n) data[mine + k] = (uint32_t)run;
+        run += v[k];
+    }
+}
+
+}  // namespace
+
+size_t scan_scratch_elems(int64_t n)
+{
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return (size_t)(nb > 0 ? nb : 1);
+}
+
+hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scratch, uint64_t* total64,
+                                 uint32_t* total32, uint32_t* overflow, hipStream_t s)
+{
+    if (n <= 0) {
+        if (total64 || total32) {
+            hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, block_scratch, (int64_t)0,
+                               total64, total32, overflow);
+        }
+        return hipGetLastError();
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, block_scratch);
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, block_scratch, nb, total64, total32,
+                       overflow);
+    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, block_scratch);
+    return hipGetLastError();
+}
+
+}  // namespace gsmi

@@ -7,191 +7,253 @@
 // (depth_sort.hip), so a stable counting sort on the tile digit leaves every
 // tile's list in front-to-back order: the output IS the sorted pair list.
 //
-// Work decomposition: one wavefront per (chunk of kBinChunk consecutive
-// depth-sorted Gaussians, band of tile rows with <= kMaxBandTiles tiles).  A
-// wave expands its Gaussians' rectangles, clipped to its band, into a flat
-// sequence of pairs (Gaussian-major, then tile row, then column) and walks it
-// 64 pairs at a time, so large and small Gaussians share lanes evenly.
-//   count:   LDS histogram per (chunk, band) -> counts[chunk][tile]
-//   offsets: exclusive scan over chunks per tile, then over tiles
-//   scatter: per (chunk, band) LDS cursors start at tile offset + chunk
-//            prefix; equal tiles within a 64-pair group are ranked by lane
-//            (ballot match on the tile bits), which keeps Gaussian order.
+// Work decomposition.  Tile rows are grouped into bands of at most
+// kMaxBandTiles tiles (one LDS counter per tile of a band).  Per band, the
+// pairs form one flat sequence in (depth order, tile row, tile column) order;
+// its prefix over the depth-sorted Gaussians is one device-wide scan.  A
+// wavefront owns a chunk of kChunkPairs consecutive pairs of one band, so
+// every wave does the same amount of work however the pairs are spread over
+// Gaussians (the big background Gaussians all sort to the back).
+//   prep:    per sorted position, the pair count in each band
+//   scan:    exclusive prefix of those counts (all bands in one sequence)
+//   info:    band bases and chunk bases
+//   count:   per chunk, an LDS histogram over the band's tiles
+//   colscan: per tile, exclusive prefix over the band's chunks
+//   offsets: exclusive scan of the tile totals -> tile_offsets
+//   scatter: per chunk, LDS cursors at tile offset + chunk prefix; equal tiles
+//            inside a 64-pair group are ranked by lane (ballot match), which
+//            keeps depth order within every tile
 #include "gs_internal.h"
 
 namespace gsmi {
 namespace {
 
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane)
+__global__ __launch_bounds__(256) void band_prep_kernel(BinArgs a)
 {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= a.n) return;
+    const int64_t nv = (int64_t)*a.n_visible;
+    ushort4 r = make_ushort4(0, 0, 0, 0);
+    if (k < nv) r = a.rect[a.sorted_idx[k]];
+    a.rect_s[k] = r;
+    const int w = (int)r.z - (int)r.x;
+    for (int b = 0; b < a.num_bands; ++b) {
+        const int b0 = b * a.band_rows, b1 = b0 + a.band_rows;
+        const int y0 = (int)r.y > b0 ? (int)r.y : b0;
+        const int y1 = (int)r.w < b1 ? (int)r.w : b1;
+        a.bp[(int64_t)b * a.n + k] = (k < nv && y1 > y0) ? (uint32_t)(w * (y1 - y0)) : 0u;
     }
-    return v;
 }
 
-// Shared walk over the pairs of one (chunk, band); calls emit(local_tile,
-// gaussian, active) once per 64-pair group with every lane of the wave.
-template <class Emit>
-__device__ __forceinline__ void walk_pairs(const BinArgs& a, int chunk, int ty0, int ty1, Emit&& emit)
+// band_info[0..B]: pair prefix at each band start (band_info[B] = K);
+// band_info[B+1 .. 2B+1]: chunk prefix (band_info[2B+1] = number of chunks).
+// With K >= 2^32 the 32-bit prefixes wrap: no chunk is handed out then (the
+// overflow flag is already set by the scan).
+__global__ void band_info_kernel(BinArgs a, const uint32_t* total32, const uint64_t* total64)
 {
-    __shared__ uint32_t s_incl[64];
-    __shared__ int s_x0[64], s_w[64], s_row0[64];
-    __shared__ uint32_t s_g[64];
-    const int lane = threadIdx.x;
+    if (threadIdx.x != 0) return;
+    const int B = a.num_bands;
+    const bool wrapped = *total64 > 0xFFFFFFFFull;
+    uint32_t chunks = 0;
+    for (int b = 0; b <= B; ++b) a.band_info[b] = (b < B) ? a.bp[(int64_t)b * a.n] : *total32;
+    for (int b = 0; b < B; ++b) {
+        a.band_info[B + 1 + b] = chunks;
+        const uint32_t kb = a.band_info[b + 1] - a.band_info[b];
+        if (!wrapped) chunks += (kb + kChunkPairs - 1) / kChunkPairs;
+    }
+    a.band_info[2 * B + 1] = chunks;
+    if ((int64_t)chunks > (int64_t)a.max_chunks) {
+        *a.overflow = 1u;
+        a.band_info[2 * B + 1] = 0u;   // nothing is binned past the grid's room
+    }
+}
+
+struct ChunkView {
+    int band;
+    uint32_t lo, hi;   // band-local pair range of the chunk
+    uint32_t base;     // global prefix at the band start
+    uint32_t kb;       // pairs in the band
+    int64_t k0;        // last sorted position whose band prefix is <= lo
+};
+
+// Locates wave w's band and pair range, then k0 by a 64-ary search (each
+// step probes 64 positions with one ballot).
+__device__ __forceinline__ bool locate_chunk(const BinArgs& a, int w, int lane, ChunkView& v)
+{
+    const int B = a.num_bands;
+    const uint32_t* info = a.band_info;
+    if ((uint32_t)w >= info[2 * B + 1]) return false;
+    int b = 0;
+    while (b + 1 < B && info[B + 1 + b + 1] <= (uint32_t)w) ++b;
+    const uint32_t c = (uint32_t)w - info[B + 1 + b];
+    v.band = b;
+    v.base = info[b];
+    v.kb = info[b + 1] - info[b];
+    v.lo = c * (uint32_t)kChunkPairs;
+    v.hi = (v.lo + kChunkPairs < v.kb) ? v.lo + kChunkPairs : v.kb;
     const int64_t nv = (int64_t)*a.n_visible;
-    const int64_t start = (int64_t)chunk * kBinChunk;
-    const int64_t end = (start + kBinChunk < nv) ? start + kBinChunk : nv;
-    for (int64_t base = start; base < end; base += 64) {
-        const int64_t pos = base + lane;
-        uint32_t mine = 0, g = 0;
-        int x0 = 0, w = 1, row0 = 0;
-        if (pos < end) {
-            g = a.sorted_idx[pos];
-            const ushort4 r = a.rect[g];
-            const int y0 = (int)r.y > ty0 ? (int)r.y : ty0;
-            const int y1 = (int)r.w < ty1 ? (int)r.w : ty1;
-            if (y1 > y0) {
-                x0 = r.x;
-                w = (int)r.z - (int)r.x;
-                row0 = y0 - ty0;
-                mine = (uint32_t)(w * (y1 - y0));
-            }
+    const uint32_t* pre = a.bp + (int64_t)b * a.n;
+    int64_t L = 0, R = nv;   // invariant: pre[L] - base <= lo
+    while (R - L > 1) {
+        const int64_t step = (R - L + 63) / 64;
+        const int64_t q = L + (int64_t)lane * step;
+        const bool ok = q < R && (pre[q] - v.base) <= v.lo;
+        const uint64_t m = __ballot(ok);
+        const int top = 63 - (int)__clzll((long long)m);
+        const int64_t nl = L + (int64_t)top * step;
+        R = (nl + step < R) ? nl + step : R;
+        L = nl;
+    }
+    v.k0 = L;
+    return true;
+}
+
+// Walks the pairs of one chunk 64 at a time; emit(local_tile, gaussian,
+// active) is called by every lane of the wave for each group of 64 pairs.
+template <class Emit>
+__device__ __forceinline__ void walk_chunk(const BinArgs& a, const ChunkView& v, int lane, Emit&& emit)
+{
+    __shared__ uint32_t s_pre[64];
+    __shared__ uint32_t s_x0w[64];   // x0 | w << 16
+    __shared__ int s_row0[64];
+    __shared__ uint32_t s_g[64];
+    const int64_t nv = (int64_t)*a.n_visible;
+    const uint32_t* pre_arr = a.bp + (int64_t)v.band * a.n;
+    const int by0 = v.band * a.band_rows;
+    for (int64_t kpos = v.k0; kpos < nv; kpos += 64) {
+        const int64_t k = kpos + lane;
+        uint32_t pre = v.kb, x0w = 1u << 16, g = 0;
+        int row0 = 0;
+        if (k < nv) {
+            pre = pre_arr[k] - v.base;
+            const ushort4 r = a.rect_s[k];
+            const int y0 = (int)r.y > by0 ? (int)r.y : by0;
+            x0w = (uint32_t)r.x | ((uint32_t)(r.z - r.x) << 16);
+            row0 = y0 - by0;
+            g = a.sorted_idx[k];
         }
-        const uint32_t incl = wave_inclusive_scan(mine, lane);
-        const uint32_t total = __shfl(incl, 63, 64);
-        s_incl[lane] = incl;
-        s_x0[lane] = x0;
-        s_w[lane] = w;
+        s_pre[lane] = pre;
+        s_x0w[lane] = x0w;
         s_row0[lane] = row0;
         s_g[lane] = g;
         __syncthreads();
-        for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+        // this batch holds the band pairs [pre of lane 0, pre of the next batch)
+        const int64_t knext = kpos + 64;
+        const uint32_t batch_end = (knext < nv) ? pre_arr[knext] - v.base : v.kb;
+        const uint32_t p_start = (s_pre[0] > v.lo) ? s_pre[0] : v.lo;
+        const uint32_t p_end = (batch_end < v.hi) ? batch_end : v.hi;
+        for (uint32_t p0 = p_start; p0 < p_end; p0 += 64) {
             const uint32_t p = p0 + lane;
-            const bool active = p < total;
+            const bool active = p < p_end;
             int local = 0;
             uint32_t gi = 0;
             if (active) {
-                int lo = 0, hi = 63;   // first lane whose inclusive count exceeds p
+                int lo = 0, hi = 63;   // last lane whose interval starts at or before p
                 while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_incl[mid] > p) hi = mid; else lo = mid + 1;
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pre[mid] <= p) lo = mid; else hi = mid - 1;
                 }
-                const uint32_t j = p - (lo ? s_incl[lo - 1] : 0u);
-                const uint32_t ws = (uint32_t)s_w[lo];
-                const uint32_t row = j / ws;
-                const uint32_t col = j - row * ws;
-                local = (s_row0[lo] + (int)row) * a.tiles_x + s_x0[lo] + (int)col;
+                const uint32_t j = p - s_pre[lo];
+                const uint32_t xw = s_x0w[lo];
+                const int w = (int)(xw >> 16);
+                // j / w for j, w <= 2^11: float estimate, then exact correction
+                int row = (int)((float)j * __builtin_amdgcn_rcpf((float)w));
+                int col = (int)j - row * w;
+                if (col < 0) {
+                    --row;
+                    col += w;
+                }
+                if (col >= w) {
+                    ++row;
+                    col -= w;
+                }
+                local = (s_row0[lo] + row) * a.tiles_x + (int)(xw & 0xFFFFu) + col;
                 gi = s_g[lo];
             }
             emit(local, gi, active);
         }
         __syncthreads();
+        if (batch_end >= v.hi) break;
     }
 }
 
 __global__ __launch_bounds__(64) void bin_count_kernel(BinArgs a)
 {
     __shared__ uint32_t cnt[kMaxBandTiles];
-    const int chunk = blockIdx.x, band = blockIdx.y, lane = threadIdx.x;
-    const int ty0 = band * a.band_rows;
-    const int ty1 = (ty0 + a.band_rows < a.tiles_y) ? ty0 + a.band_rows : a.tiles_y;
-    const int band_tiles = (ty1 - ty0) * a.tiles_x;
+    const int lane = threadIdx.x;
+    ChunkView v;
+    if (!locate_chunk(a, blockIdx.x, lane, v)) return;
+    const int by0 = v.band * a.band_rows;
+    const int by1 = (by0 + a.band_rows < a.tiles_y) ? by0 + a.band_rows : a.tiles_y;
+    const int band_tiles = (by1 - by0) * a.tiles_x;
     for (int k = lane; k < band_tiles; k += 64) cnt[k] = 0;
     __syncthreads();
-    walk_pairs(a, chunk, ty0, ty1, [&](int local, uint32_t, bool active) {
+    walk_chunk(a, v, lane, [&](int local, uint32_t, bool active) {
         if (active) atomicAdd(&cnt[local], 1u);
     });
     __syncthreads();
-    const int64_t T = (int64_t)a.tiles_x * a.tiles_y;
-    uint32_t* dst = a.counts + (int64_t)chunk * T + (int64_t)ty0 * a.tiles_x;
+    uint32_t* dst = a.counts + (int64_t)blockIdx.x * kMaxBandTiles;
     for (int k = lane; k < band_tiles; k += 64) dst[k] = cnt[k];
 }
 
-// counts[c][t] -> exclusive prefix over c (in place); totals[t] = column sum.
-// Block: 64 tiles x 16 chunk segments.
-__global__ __launch_bounds__(1024) void bin_colscan_kernel(uint32_t* __restrict__ counts, int C, int T,
-                                                           uint32_t* __restrict__ totals)
+// counts[chunk][t] -> exclusive prefix over the band's chunks (in place);
+// tile totals -> tile_offsets[tile].  Block = (band, 64 tiles) x 16 segments.
+__global__ __launch_bounds__(1024) void bin_colscan_kernel(BinArgs a)
 {
     __shared__ uint32_t part[16][64];
+    const int B = a.num_bands;
+    const int groups = kMaxBandTiles / 64;
+    const int band = blockIdx.x / groups, tg = blockIdx.x % groups;
     const int tl = threadIdx.x & 63, seg = threadIdx.x >> 6;
-    const int t = blockIdx.x * 64 + tl;
-    const int per = (C + 15) / 16;
-    const int c0 = seg * per, c1 = (c0 + per < C) ? c0 + per : C;
+    const int by0 = band * a.band_rows;
+    const int by1 = (by0 + a.band_rows < a.tiles_y) ? by0 + a.band_rows : a.tiles_y;
+    const int band_tiles = (by1 - by0) * a.tiles_x;
+    const int t = tg * 64 + tl;
+    const int c_begin = (int)a.band_info[B + 1 + band];
+    const int c_end = (int)a.band_info[B + 1 + band + 1];
+    const int per = (c_end - c_begin + 15) / 16;
+    const int c0 = c_begin + seg * per;
+    const int c1 = (c0 + per < c_end) ? c0 + per : c_end;
+    const bool valid = t < band_tiles;
     uint32_t s = 0;
-    if (t < T)
-        for (int c = c0; c < c1; ++c) s += counts[(int64_t)c * T + t];
+    if (valid)
+        for (int c = c0; c < c1; ++c) s += a.counts[(int64_t)c * kMaxBandTiles + t];
     part[seg][tl] = s;
     __syncthreads();
     uint32_t run = 0, tot = 0;
     for (int k = 0; k < 16; ++k) {
-        const uint32_t v = part[k][tl];
-        if (k < seg) run += v;
-        tot += v;
+        const uint32_t x = part[k][tl];
+        if (k < seg) run += x;
+        tot += x;
     }
-    if (t < T) {
+    if (valid) {
         for (int c = c0; c < c1; ++c) {
-            const int64_t o = (int64_t)c * T + t;
-            const uint32_t v = counts[o];
-            counts[o] = run;
-            run += v;
+            const int64_t o = (int64_t)c * kMaxBandTiles + t;
+            const uint32_t x = a.counts[o];
+            a.counts[o] = run;
+            run += x;
         }
-        if (seg == 0) totals[t] = tot;
-    }
-}
-
-// tile_offsets[t] = sum of totals[<t]; tile_offsets[T] = K (u32), and K in
-// 64 bits at *k_total.  Flags overflow when K does not fit the capacity or
-// 32 bits.  One 1024-thread block.
-__global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t* __restrict__ totals, int T,
-                                                         uint32_t* __restrict__ offsets, uint64_t* k_total,
-                                                         uint64_t capacity, uint32_t* overflow)
-{
-    __shared__ uint64_t part[1024];
-    const int tid = threadIdx.x;
-    const int per = (T + 1023) / 1024;
-    const int s = tid * per, e = (s + per < T) ? s + per : T;
-    uint64_t sum = 0;
-    for (int j = s; j < e; ++j) sum += totals[j];
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint64_t v = tid >= off ? part[tid - off] : 0ull;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    uint64_t run = part[tid] - sum;
-    for (int j = s; j < e; ++j) {
-        offsets[j] = (uint32_t)run;
-        run += totals[j];
-    }
-    if (tid == 1023) {
-        const uint64_t K = part[1023];
-        offsets[T] = (uint32_t)K;
-        *k_total = K;
-        if (K > capacity || K > 0xFFFFFFFFull) *overflow = 1u;
+        if (seg == 0) a.tile_offsets[(int64_t)by0 * a.tiles_x + t] = tot;
     }
 }
 
 __global__ __launch_bounds__(64) void bin_scatter_kernel(BinArgs a)
 {
     __shared__ uint32_t cursor[kMaxBandTiles];
-    const int chunk = blockIdx.x, band = blockIdx.y, lane = threadIdx.x;
-    const int ty0 = band * a.band_rows;
-    const int ty1 = (ty0 + a.band_rows < a.tiles_y) ? ty0 + a.band_rows : a.tiles_y;
-    const int band_tiles = (ty1 - ty0) * a.tiles_x;
-    const int64_t T = (int64_t)a.tiles_x * a.tiles_y;
-    const uint32_t* prefix = a.counts + (int64_t)chunk * T + (int64_t)ty0 * a.tiles_x;
-    const uint32_t* toff = a.tile_offsets + (int64_t)ty0 * a.tiles_x;
+    const int lane = threadIdx.x;
+    ChunkView v;
+    if (!locate_chunk(a, blockIdx.x, lane, v)) return;
+    const int by0 = v.band * a.band_rows;
+    const int by1 = (by0 + a.band_rows < a.tiles_y) ? by0 + a.band_rows : a.tiles_y;
+    const int band_tiles = (by1 - by0) * a.tiles_x;
+    const uint32_t* prefix = a.counts + (int64_t)blockIdx.x * kMaxBandTiles;
+    const uint32_t* toff = a.tile_offsets + (int64_t)by0 * a.tiles_x;
     for (int k = lane; k < band_tiles; k += 64) cursor[k] = toff[k] + prefix[k];
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t cap = a.capacity;
     uint32_t* values = a.values;
-    walk_pairs(a, chunk, ty0, ty1, [&](int local, uint32_t g, bool active) {
+    walk_chunk(a, v, lane, [&](int local, uint32_t g, bool active) {
         const uint64_t act = __ballot(active);
         if (!active) return;
         uint64_t m = act;
@@ -211,30 +273,39 @@ __global__ __launch_bounds__(64) void bin_scatter_kernel(BinArgs a)
 
 }  // namespace
 
-hipError_t launch_bin_count(const BinArgs& a, hipStream_t s)
+hipError_t launch_bin_prepare(const BinArgs& a, uint64_t* scan_scratch, uint64_t* k_total, hipStream_t s)
 {
-    if (a.num_chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(bin_count_kernel, dim3(a.num_chunks, a.num_bands), dim3(64), 0, s, a);
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(band_prep_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    // one exclusive scan over all bands' counts; its total is K
+    uint32_t* total32 = a.band_info + 2 * a.num_bands + 2;   // slot after the table
+    hipError_t e = launch_scan_exclusive(a.bp, (int64_t)a.num_bands * a.n, scan_scratch, k_total, total32,
+                                         a.overflow, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(band_info_kernel, dim3(1), dim3(64), 0, s, a, (const uint32_t*)total32,
+                       (const uint64_t*)k_total);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_offsets(const BinArgs& a, hipStream_t s, uint64_t* k_total)
+hipError_t launch_bin_count(const BinArgs& a, int grid, hipStream_t s)
 {
-    const int T = a.tiles_x * a.tiles_y;
-    if (a.num_chunks > 0)
-        hipLaunchKernelGGL(bin_colscan_kernel, dim3((T + 63) / 64), dim3(1024), 0, s, a.counts, a.num_chunks, T,
-                           a.totals);
-    else
-        (void)launch_fill_u32(a.totals, 0u, T, s);
-    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, a.totals, T, a.tile_offsets, k_total,
-                       a.capacity, a.overflow);
+    if (a.n == 0 || grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bin_count_kernel, dim3(grid), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(const BinArgs& a, hipStream_t s)
+hipError_t launch_bin_offsets(const BinArgs& a, uint64_t* scan_scratch, hipStream_t s)
 {
-    if (a.num_chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(a.num_chunks, a.num_bands), dim3(64), 0, s, a);
+    const int64_t T = (int64_t)a.tiles_x * a.tiles_y;
+    if (a.n == 0) return launch_fill_u32(a.tile_offsets, 0u, T + 1, s);
+    hipLaunchKernelGGL(bin_colscan_kernel, dim3(a.num_bands * (kMaxBandTiles / 64)), dim3(1024), 0, s, a);
+    return launch_scan_exclusive(a.tile_offsets, T, scan_scratch, nullptr, a.tile_offsets + T, nullptr, s);
+}
+
+hipError_t launch_bin_scatter(const BinArgs& a, int grid, hipStream_t s)
+{
+    if (a.n == 0 || grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(grid), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
