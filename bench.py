@@ -105,6 +105,19 @@ def cpu_baseline(scene, cam, band_rows: int = 4) -> dict:
                        f"to {frame_s:.1f} s")}
 
 
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
+    """A plain device-to-device copy of known size: reads and writes nbytes
+    per launch.  Profiled with the same FETCH_SIZE / WRITE_SIZE counters, it
+    gives the factor between counter readings and bytes moved."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,7 +126,12 @@ def main():
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--variant", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this single-GPU build "
               "(the render shards by camera or screen tiles, see DESIGN.md)", file=sys.stderr)
@@ -212,6 +230,8 @@ def main():
                    "visible": n_vis},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stages_algorithmic_GBps": stage_gbs,
+        "blend_work": {**stats, "tflops": round((FLOPS_EVAL * stats["evaluations"] + FLOPS_COMPOSITE *
+                                                 stats["composited"]) / (stage_ms["blend"] * 1e-3) / 1e12, 3)},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

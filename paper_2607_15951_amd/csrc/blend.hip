@@ -11,9 +11,14 @@
 // 48-byte record, re-expresses the centre relative to the tile origin as a
 // float hi/lo pair computed in double precision (so a pixel's dx, dy keep
 // full float accuracy wherever the centre lies) and folds -0.5*log2(e) into
-// the conic so the per-pixel work is one exp2 and a few FMAs.  The workgroup
-// leaves as soon as every pixel has terminated (a barrier count of the lanes
-// still running).  No MFMA: there is no dense contraction in this loop.
+// the conic so the per-pixel work is one exp2 and a few FMAs.  Entries whose
+// largest alpha over the whole tile is provably below 1/255 are dropped at
+// staging (a conservative lower bound of the quadratic form over the tile's
+// pixel box): every pixel would skip them, so the image is unchanged, and the
+// 3-sigma square of the lists leaves many such (Gaussian, tile) pairs.  The
+// per-pixel loop is predicated rather than branched; a wave leaves once all
+// 64 of its pixels have terminated and the workgroup once all 256 have.  No
+// MFMA: there is no dense contraction in this loop.
 //
 // Workgroup -> tile mapping is XCD-aware: the dispatcher deals consecutive
 // workgroups round-robin to the 8 XCDs, so block b takes tile
@@ -25,18 +30,51 @@ namespace gsmi {
 namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr int kUnroll = 8;
+
+// Smallest value of the quadratic form A x^2 + 2 B x y + C y^2 (positive
+// definite) over the box [x0, x0 + 15] x [y0, y0 + 15] of pixel offsets, made
+// a lower bound by subtracting 1e-5 of the size of its terms.  The form is
+// convex, so its minimum is 0 when the origin lies in the box and on an edge
+// otherwise; on an edge it is a 1D quadratic minimised in closed form.
+__device__ __forceinline__ float quad_min_over_tile(float x0, float y0, float A, float B, float C)
+{
+    const float x1 = x0 + 15.0f, y1 = y0 + 15.0f;
+    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return 0.0f;
+    float q = INFINITY, S = 0.0f;
+    const float xs[2] = {x0, x1}, ys[2] = {y0, y1};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float xe = xs[e];
+        const float y = fminf(y1, fmaxf(y0, -B * xe / C));
+        const float qe = A * xe * xe + 2.0f * B * xe * y + C * y * y;
+        if (qe < q) {
+            q = qe;
+            S = A * xe * xe + 2.0f * fabsf(B * xe * y) + C * y * y;
+        }
+        const float ye = ys[e];
+        const float x = fminf(x1, fmaxf(x0, -B * ye / A));
+        const float qf = A * x * x + 2.0f * B * x * ye + C * ye * ye;
+        if (qf < q) {
+            q = qf;
+            S = A * x * x + 2.0f * fabsf(B * x * ye) + C * ye * ye;
+        }
+    }
+    return q - 1e-5f * (S + 1.0f);
+}
 
 __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capacity)
 {
-    __shared__ float4 s0[256];   // du_hi, dv_hi, du_lo, dv_lo  (centre - tile origin)
-    __shared__ float4 s1[256];   // A', B', C', opacity         (A' = -0.5 log2(e) A, ...)
-    __shared__ float4 s2[256];   // r, g, b, -
+    __shared__ float4 s0[256 + kUnroll];   // du_hi, dv_hi, du_lo, dv_lo  (centre - tile origin)
+    __shared__ float4 s1[256 + kUnroll];   // A', B', C', opacity  (A' = -0.5 log2(e) A, ...)
+    __shared__ float4 s2[256 + kUnroll];   // r, g, b, list position (int bits)
+    __shared__ uint32_t s_wave_keep[4];
     const int T = a.tiles_x * a.tiles_y;
     const int per_xcd = (T + 7) / 8;
     const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
     if (tile >= T) return;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lx = tid & 15, ly = tid >> 4;
     const int px = tx * kTile + lx, py = ty * kTile + ly;
     const bool inside = px < a.width && py < a.height;
@@ -45,63 +83,88 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     if (start > end) start = end;
     const double ox = (double)(tx * kTile), oy = (double)(ty * kTile);
     const float fx = (float)lx, fy = (float)ly;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     float Tr = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-    uint32_t last = 0, examined = 0, composited = 0, staged = 0;
+    uint32_t last = 0, term = 0, composited = 0, staged = 0;
     bool done = !inside;
     for (uint64_t b0 = start; b0 < end; b0 += 256) {
         if (__syncthreads_count(!done) == 0) break;
-        staged += (end - b0 < 256) ? (uint32_t)(end - b0) : 256u;
+        // stage: gather one entry per lane, drop it when no pixel of the tile
+        // can reach alpha 1/255 (the per-pixel test would skip it everywhere)
         const uint64_t e = b0 + tid;
+        bool keep = false;
+        float4 v0, v1, v2;
         if (e < end) {
             const uint32_t g = a.values[e];
             const float4* rec = reinterpret_cast<const float4*>(a.splats + g);
             const float4 ra = rec[0], rb = rec[1], rc = rec[2];
-            // centre relative to the tile origin as a float pair: the per-pixel
-            // offset (hi - lx) + lo then carries ~2 ulp of its own size
             const double du = ((double)ra.x + (double)ra.z) - ox;
             const double dv = ((double)ra.y + (double)ra.w) - oy;
             const float du_hi = (float)du, dv_hi = (float)dv;
-            s0[tid] = make_float4(du_hi, dv_hi, (float)(du - (double)du_hi), (float)(dv - (double)dv_hi));
-            s1[tid] = make_float4(-0.5f * kLog2e * rb.x, -kLog2e * rb.y, -0.5f * kLog2e * rb.z, rb.w);
-            s2[tid] = rc;
+            const float qmin = quad_min_over_tile(du_hi - 15.0f, dv_hi - 15.0f, rb.x, rb.y, rb.z);
+            keep = rb.w * __expf(-0.5f * qmin) >= (1.0f / 255.0f) * (1.0f - 1e-5f);
+            v0 = make_float4(du_hi, dv_hi, (float)(du - (double)du_hi), (float)(dv - (double)dv_hi));
+            v1 = make_float4(-0.5f * kLog2e * rb.x, -kLog2e * rb.y, -0.5f * kLog2e * rb.z, rb.w);
+            v2 = make_float4(rc.x, rc.y, rc.z, __int_as_float((int)(e - start)));
+        }
+        // order-preserving compaction of the kept entries
+        const uint64_t km = __ballot(keep);
+        if (lane == 0) s_wave_keep[wave] = (uint32_t)__popcll(km);
+        staged += (end - b0 < 256) ? (uint32_t)(end - b0) : 256u;
+        __syncthreads();
+        uint32_t slot = (uint32_t)__popcll(km & lt);
+        for (int w = 0; w < wave; ++w) slot += s_wave_keep[w];
+        const int nk = (int)(s_wave_keep[0] + s_wave_keep[1] + s_wave_keep[2] + s_wave_keep[3]);
+        if (keep) {
+            s0[slot] = v0;
+            s1[slot] = v1;
+            s2[slot] = v2;
+        }
+        if (tid < kUnroll) {   // padding entries with zero opacity never pass
+            s0[nk + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s1[nk + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s2[nk + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
-        if (!done) {
-            const int cnt = (end - b0 < 256) ? (int)(end - b0) : 256;
-            int j = 0;
-            for (; j < cnt; ++j) {
+        for (int j0 = 0; j0 < nk; j0 += kUnroll) {
+            if (__ballot(!done) == 0) break;   // whole wave finished
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int j = j0 + u;
                 const float4 e0 = s0[j];
                 const float4 e1 = s1[j];
+                const float4 e2 = s2[j];
                 const float dx = (e0.x - fx) + e0.z;
                 const float dy = (e0.y - fy) + e0.w;
                 const float pw = fmaf(e1.x * dx, dx, fmaf(e1.z * dy, dy, (e1.y * dx) * dy));
                 const float al = fminf(0.99f, e1.w * __builtin_amdgcn_exp2f(pw));
-                if (al < 1.0f / 255.0f) continue;
                 const float tn = Tr * (1.0f - al);
-                if (tn < 1e-4f) {
-                    done = true;
-                    break;
-                }
-                ++composited;
-                const float4 e2 = s2[j];
-                const float wgt = al * Tr;
+                const bool pass = al >= 1.0f / 255.0f;
+                const bool stop = pass && tn < 1e-4f && !done;
+                const bool take = pass && !stop && !done;
+                const uint32_t pos = (uint32_t)__float_as_int(e2.w);
+                term = stop ? pos + 1u : term;
+                done = done || stop;
+                const float wgt = take ? al * Tr : 0.0f;
                 c0 = fmaf(wgt, e2.x, c0);
                 c1 = fmaf(wgt, e2.y, c1);
                 c2 = fmaf(wgt, e2.z, c2);
-                Tr = tn;
-                last = (uint32_t)(b0 - start) + (uint32_t)j + 1u;
+                Tr = take ? tn : Tr;
+                last = take ? pos + 1u : last;
+                composited += take ? 1u : 0u;
             }
-            examined += (uint32_t)(j < cnt ? j + 1 : cnt);
         }
     }
     if (a.stats) {   // tracing only: one atomic per wave
-        unsigned long long ev = examined, co = composited;
+        // a pixel examines its tile's list up to its terminating entry
+        const uint32_t list_len = (uint32_t)(end - start);
+        unsigned long long ev = inside ? (term ? term : list_len) : 0u, co = composited;
         for (int o = 32; o > 0; o >>= 1) {
             ev += __shfl_xor(ev, o, 64);
             co += __shfl_xor(co, o, 64);
         }
-        if ((tid & 63) == 0) {
+        if (lane == 0) {
             atomicAdd(&a.stats[0], ev);
             atomicAdd(&a.stats[1], co);
         }

@@ -171,9 +171,12 @@ __device__ __forceinline__ bool project_geometry(const ProjectArgs& a, double mx
 template <int DT, int DEG>
 __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 {
+    constexpr int ncoef = (DEG + 1) * (DEG + 1);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     const int64_t n = a.n;
+    // every attribute load is issued before any arithmetic, so a wave has all
+    // of its 11 + 3 (DEG+1)^2 coalesced streams in flight at once
     const float mxf = a.means[i], myf = a.means[n + i], mzf = a.means[2 * n + i];
     const float l0 = load_attr<DT>(a.log_scales, i);
     const float l1 = load_attr<DT>(a.log_scales, n + i);
@@ -182,6 +185,10 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
     const float qx = load_attr<DT>(a.quats, n + i);
     const float qy = load_attr<DT>(a.quats, 2 * n + i);
     const float qz = load_attr<DT>(a.quats, 3 * n + i);
+    const float logit = load_attr<DT>(a.logits, i);
+    float coef[3 * ncoef];
+#pragma unroll
+    for (int k = 0; k < 3 * ncoef; ++k) coef[k] = load_attr<DT>(a.sh, (int64_t)k * n + i);
 
     Geometry g;
     bool ok = project_geometry(a, mxf, myf, mzf, l0, l1, l2, qw, qx, qy, qz, g);
@@ -210,7 +217,6 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
     if (tiles > 0) {
         const float uh = (float)g.u, vh = (float)g.v;
         sp.a = make_float4(uh, vh, (float)(g.u - (double)uh), (float)(g.v - (double)vh));
-        const float logit = load_attr<DT>(a.logits, i);
         const float opacity = 1.0f / (1.0f + __expf(-logit));
         sp.b = make_float4((float)g.A, (float)g.B, (float)g.C, opacity);
         // view direction from the camera centre
@@ -221,13 +227,12 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
         dz *= inv;
         float Y[16];
         sh_basis(dx, dy, dz, DEG, Y);
-        constexpr int ncoef = (DEG + 1) * (DEG + 1);
         float col[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float acc = 0.0f;
 #pragma unroll
-            for (int k = 0; k < ncoef; ++k) acc += load_attr<DT>(a.sh, ((int64_t)k * 3 + ch) * n + i) * Y[k];
+            for (int k = 0; k < ncoef; ++k) acc += coef[k * 3 + ch] * Y[k];
             col[ch] = fmaxf(acc + 0.5f, 0.0f);
         }
         sp.c = make_float4(col[0], col[1], col[2], (float)g.tz);

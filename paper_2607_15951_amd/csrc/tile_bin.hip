@@ -76,6 +76,16 @@ struct ChunkView {
     int64_t k0;        // last sorted position whose band prefix is <= lo
 };
 
+// Chunk of the workgroup: the dispatcher deals workgroups round-robin to the
+// 8 XCDs, so block b takes chunk (b % 8) * ceil(grid / 8) + b / 8 and every
+// XCD works through a contiguous run of chunks.  Consecutive chunks write
+// adjacent pieces of each tile's list, which then meet in the same L2.
+__device__ __forceinline__ int chunk_of_block()
+{
+    const int per_xcd = (int)((gridDim.x + 7) / 8);
+    return (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+}
+
 // Locates wave w's band and pair range, then k0 by a 64-ary search (each
 // step probes 64 positions with one ballot).
 __device__ __forceinline__ bool locate_chunk(const BinArgs& a, int w, int lane, ChunkView& v)
@@ -181,8 +191,9 @@ __global__ __launch_bounds__(64) void bin_count_kernel(BinArgs a)
 {
     __shared__ uint32_t cnt[kMaxBandTiles];
     const int lane = threadIdx.x;
+    const int chunk = chunk_of_block();
     ChunkView v;
-    if (!locate_chunk(a, blockIdx.x, lane, v)) return;
+    if (!locate_chunk(a, chunk, lane, v)) return;
     const int by0 = v.band * a.band_rows;
     const int by1 = (by0 + a.band_rows < a.tiles_y) ? by0 + a.band_rows : a.tiles_y;
     const int band_tiles = (by1 - by0) * a.tiles_x;
@@ -192,7 +203,7 @@ __global__ __launch_bounds__(64) void bin_count_kernel(BinArgs a)
         if (active) atomicAdd(&cnt[local], 1u);
     });
     __syncthreads();
-    uint32_t* dst = a.counts + (int64_t)blockIdx.x * kMaxBandTiles;
+    uint32_t* dst = a.counts + (int64_t)chunk * kMaxBandTiles;
     for (int k = lane; k < band_tiles; k += 64) dst[k] = cnt[k];
 }
 
@@ -241,12 +252,13 @@ __global__ __launch_bounds__(64) void bin_scatter_kernel(BinArgs a)
 {
     __shared__ uint32_t cursor[kMaxBandTiles];
     const int lane = threadIdx.x;
+    const int chunk = chunk_of_block();
     ChunkView v;
-    if (!locate_chunk(a, blockIdx.x, lane, v)) return;
+    if (!locate_chunk(a, chunk, lane, v)) return;
     const int by0 = v.band * a.band_rows;
     const int by1 = (by0 + a.band_rows < a.tiles_y) ? by0 + a.band_rows : a.tiles_y;
     const int band_tiles = (by1 - by0) * a.tiles_x;
-    const uint32_t* prefix = a.counts + (int64_t)blockIdx.x * kMaxBandTiles;
+    const uint32_t* prefix = a.counts + (int64_t)chunk * kMaxBandTiles;
     const uint32_t* toff = a.tile_offsets + (int64_t)by0 * a.tiles_x;
     for (int k = lane; k < band_tiles; k += 64) cursor[k] = toff[k] + prefix[k];
     __syncthreads();
@@ -290,7 +302,7 @@ hipError_t launch_bin_prepare(const BinArgs& a, uint64_t* scan_scratch, uint64_t
 hipError_t launch_bin_count(const BinArgs& a, int grid, hipStream_t s)
 {
     if (a.n == 0 || grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(bin_count_kernel, dim3(grid), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)(8 * ((grid + 7) / 8))), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -305,7 +317,7 @@ hipError_t launch_bin_offsets(const BinArgs& a, uint64_t* scan_scratch, hipStrea
 hipError_t launch_bin_scatter(const BinArgs& a, int grid, hipStream_t s)
 {
     if (a.n == 0 || grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(grid), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)(8 * ((grid + 7) / 8))), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
