@@ -37,8 +37,7 @@ TILE = 16
 # transmittance update (2) and the weighted colour accumulation (1 + 3 x 2).
 FLOPS_EVAL = 13
 FLOPS_COMPOSITE = 9
-BAND_TILES = 2048     # tiles per binning band (LDS counters of one wave)
-CHUNK_PAIRS = 32768   # pairs per binning wave
+CHUNK_ENTRIES = 1024  # row entries per second-level binning wave
 
 
 def log(msg):
@@ -49,20 +48,20 @@ def attr_bytes(dtype: int) -> int:
     return 4 if dtype == 0 else 2
 
 
-def algorithmic_bytes(stage: str, n: int, n_vis: int, K: int, deg: int, dtype: int, W: int, H: int,
-                      bands: int, chunks: int, stats: dict) -> float:
+def algorithmic_bytes(stage: str, n: int, n_vis: int, K: int, R: int, deg: int, dtype: int, W: int, H: int,
+                      stats: dict) -> float:
     """HBM bytes one launch of a single-kernel stage must move."""
-    T = ((W + TILE - 1) // TILE) * ((H + TILE - 1) // TILE)
-    band_tiles = min(T, BAND_TILES)
+    tx, ty = (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
     if stage == "project":
         per_in = 12 + attr_bytes(dtype) * (3 + 4 + 1 + 3 * (deg + 1) ** 2)
         per_out = 48 + 4 + 4 + 4 + 8
         return n * (per_in + per_out)
-    if stage == "bin_count":      # walk: band prefix + rectangle per sorted position and band
-        return bands * n_vis * (4 + 8) + chunks * band_tiles * 4
-    if stage == "bin_scatter":    # walk + Gaussian index, chunk prefixes, tile offsets, the values
-        return bands * n_vis * (4 + 8 + 4) + chunks * band_tiles * 4 + T * 4 + K * 4
-    if stage == "blend":
+    if stage == "bin_row_scatter":   # sorted index + rectangle per Gaussian, 8-byte row entries out
+        return n_vis * (4 + 8) + R * 8 + ((n + 511) // 512) * ty * 4
+    if stage == "bin_tile_scatter":  # row entries in, chunk prefixes, the values out
+        chunks2 = R // CHUNK_ENTRIES + ty
+        return R * 8 + chunks2 * tx * 4 * 2 + K * 4
+    if stage == "blend":             # list entry + 48-byte record per staged entry; rgb, T, n_contrib per pixel
         return stats["staged"] * (4 + 48) + W * H * 20
     raise KeyError(stage)
 
@@ -180,12 +179,8 @@ def main():
     stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
     log("[bench] stages ms " + json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
 
-    K, n_vis = info["num_pairs"], info["n_visible"]
-    tiles_x = (W + TILE - 1) // TILE
-    band_rows = BAND_TILES // tiles_x
-    bands = ((H + TILE - 1) // TILE + band_rows - 1) // band_rows
-    chunks = K // CHUNK_PAIRS + bands
-    single = ["project", "bin_count", "bin_scatter", "blend"]
+    K, n_vis, R = info["num_pairs"], info["n_visible"], info["num_row_entries"]
+    single = ["project", "bin_row_scatter", "bin_tile_scatter", "blend"]
     dom = max(single, key=lambda k: stage_ms[k])
     if dom == "blend":
         flops = FLOPS_EVAL * stats["evaluations"] + FLOPS_COMPOSITE * stats["composited"]
@@ -196,14 +191,14 @@ def main():
                                           "flops_per_evaluation": FLOPS_EVAL,
                                           "flops_per_composite": FLOPS_COMPOSITE}}
     else:
-        by = algorithmic_bytes(dom, n, n_vis, K, deg, dtype, W, H, bands, chunks, stats)
+        by = algorithmic_bytes(dom, n, n_vis, K, R, deg, dtype, W, H, stats)
         achieved = by / (stage_ms[dom] * 1e-3) / 1e9
         roof = {"kernel": dom + "_kernel", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "bytes_per_launch": int(by)}
     stage_gbs = {}
-    for k in ("project", "bin_count", "bin_scatter", "blend"):
-        by = algorithmic_bytes(k, n, n_vis, K, deg, dtype, W, H, bands, chunks, stats)
+    for k in single:
+        by = algorithmic_bytes(k, n, n_vis, K, R, deg, dtype, W, H, stats)
         stage_gbs[k] = round(by / (stage_ms[k] * 1e-3) / 1e9, 1) if stage_ms[k] > 0 else None
 
     cpu = None
@@ -227,7 +222,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": scenes.WORKLOAD_NAMES[args.workload], "gaussians": n, "width": W, "height": H,
                    "sh_degree": deg, "tile": TILE, "attributes": args.variant, "num_pairs": K,
-                   "visible": n_vis},
+                   "row_entries": R, "visible": n_vis},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stages_algorithmic_GBps": stage_gbs,
         "blend_work": {**stats, "tflops": round((FLOPS_EVAL * stats["evaluations"] + FLOPS_COMPOSITE *

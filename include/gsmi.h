@@ -134,9 +134,10 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
 /* Sizes of the last render's per-tile lists (host values; synchronises the
  * context's last stream). */
 typedef struct {
-    uint64_t num_pairs;   /* K, total (Gaussian, tile) pairs */
+    uint64_t num_pairs;        /* K, total (Gaussian, tile) pairs */
     int32_t tiles_x, tiles_y;
-    int64_t n_visible;    /* Gaussians overlapping at least one tile */
+    int64_t n_visible;         /* Gaussians overlapping at least one tile */
+    uint64_t num_row_entries;  /* (Gaussian, tile row) pairs of the binning */
 } gs_list_info;
 
 gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out);
@@ -171,11 +172,12 @@ gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key
  * milliseconds, in this order:
  *   0 project      (one kernel: cull, EWA projection, SH colour)
  *   1 depth_sort   (four LSD radix passes over the N depth keys)
- *   2 bin_prepare  (per-band pair counts, their prefix, chunk table)
- *   3 bin_count    (one kernel: per-chunk, per-tile pair counts)
- *   4 bin_offsets  (column and tile scans of the counts)
- *   5 bin_scatter  (one kernel: the sorted pair list)
- *   6 blend        (one kernel: per-tile compositing)
+ *   2 bin_row_count     (per-row counts of the depth-sorted Gaussians, row
+ *                        offsets, chunk table of the second level)
+ *   3 bin_row_scatter   (one kernel: per-row lists in depth order)
+ *   4 bin_tile_count    (per-tile counts within each row, tile offsets)
+ *   5 bin_tile_scatter  (one kernel: the sorted pair list)
+ *   6 blend             (one kernel: per-tile compositing)
  * The host read of the pair count (pair_capacity 0) falls between stages 2
  * and 3 and belongs to neither.  count must be GS_NUM_STAGES. */
 #define GS_NUM_STAGES 7

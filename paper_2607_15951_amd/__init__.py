@@ -23,7 +23,8 @@ TILE = 16
 EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
             "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
             "gs_get_blend_stats"]
-STAGES = ["project", "depth_sort", "bin_prepare", "bin_count", "bin_offsets", "bin_scatter", "blend"]
+STAGES = ["project", "depth_sort", "bin_row_count", "bin_row_scatter", "bin_tile_count", "bin_tile_scatter",
+          "blend"]
 
 
 class GsError(RuntimeError):
@@ -50,7 +51,7 @@ class gs_render_opts(C.Structure):
 
 class gs_list_info(C.Structure):
     _fields_ = [("num_pairs", C.c_uint64), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
-                ("n_visible", C.c_int64)]
+                ("n_visible", C.c_int64), ("num_row_entries", C.c_uint64)]
 
 
 _lib = None
@@ -227,7 +228,7 @@ class Renderer:
         info = gs_list_info()
         self._check(self._L.gs_get_list_info(self._ctx, C.byref(info)))
         return dict(num_pairs=int(info.num_pairs), tiles_x=info.tiles_x, tiles_y=info.tiles_y,
-                    n_visible=int(info.n_visible))
+                    n_visible=int(info.n_visible), num_row_entries=int(info.num_row_entries))
 
     def lists(self, keys: bool = False) -> dict:
         """Sorted per-tile lists of the last render as device tensors."""

@@ -28,9 +28,11 @@ struct gs_context {
     std::string err;
     DevBuf splats, depth_key, radius, tiles_touched, rect;
     DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist, scan_scratch;
-    DevBuf rect_s, band_pairs, band_info;
-    DevBuf counters;   // [0] n_visible, [1] overflow, [2..3] K as u64, [4..9] blend stats (3 x u64)
-    DevBuf counts, tile_offsets, values;
+    DevBuf bin_info, counts1, rows_off, row_ent, counts2, partials;
+    // [0] n_visible, [1] overflow, [4..9] blend stats (3 x u64),
+    // [10..11] K from the projection (u64)
+    DevBuf counters;
+    DevBuf tile_offsets, values;
     uint32_t* host_info = nullptr;   // pinned readback: band table, then K as u64
     bool profiling = false;
     bool timed = false;   // the last render recorded stage events
@@ -146,7 +148,7 @@ gs_status gs_create(int device, gs_context** out)
     ctx->device = device;
     e = hipSetDevice(device);
     if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&ctx->host_info), sizeof(uint32_t) * (2 * kMaxBands + 8));
+        e = hipHostMalloc(reinterpret_cast<void**>(&ctx->host_info), sizeof(uint32_t) * 32);
     if (e != hipSuccess) {
         delete ctx;
         return hip_fail(nullptr, e, "context set-up");
@@ -161,8 +163,9 @@ void gs_destroy(gs_context* ctx)
     (void)hipSetDevice(ctx->device);
     DevBuf* bufs[] = {&ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
                       &ctx->sort_ka, &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb, &ctx->hist,
-                      &ctx->scan_scratch, &ctx->rect_s, &ctx->band_pairs, &ctx->band_info,
-                      &ctx->counters, &ctx->counts, &ctx->tile_offsets, &ctx->values};
+                      &ctx->scan_scratch, &ctx->bin_info, &ctx->counts1, &ctx->rows_off, &ctx->row_ent,
+                      &ctx->counts2, &ctx->partials,
+                      &ctx->counters, &ctx->tile_offsets, &ctx->values};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->host_info) (void)hipHostFree(ctx->host_info);
@@ -198,9 +201,6 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     const int64_t n = g->n;
     const int tiles_x = (width + kTile - 1) / kTile, tiles_y = (height + kTile - 1) / kTile;
     const int64_t T = (int64_t)tiles_x * tiles_y;
-    const int band_rows = kMaxBandTiles / tiles_x;
-    const int num_bands = (tiles_y + band_rows - 1) / band_rows;
-    if (num_bands > kMaxBands) return fail(ctx, GS_ERR_UNSUPPORTED, "image has more than 131072 tiles");
     const size_t nn = (size_t)(n > 0 ? n : 1);
 
     if ((st = ensure(ctx, ctx->splats, nn * sizeof(Splat))) != GS_OK) return st;
@@ -213,18 +213,16 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     if ((st = ensure(ctx, ctx->sort_kb, nn * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->sort_vb, nn * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->hist, depth_sort_hist_elems(n) * 4)) != GS_OK) return st;
-    const size_t scan_elems = scan_scratch_elems(std::max<int64_t>((int64_t)num_bands * n,
-                                                                   std::max<int64_t>((int64_t)depth_sort_hist_elems(n), T)));
-    if ((st = ensure(ctx, ctx->scan_scratch, scan_elems * 8)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->rect_s, nn * 8)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->band_pairs, nn * (size_t)num_bands * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->band_info, (2 * kMaxBands + 8) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->partials, project_partials_elems(n) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->bin_info, bin_info_elems(tiles_y) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->rows_off, (size_t)(tiles_y + 1) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->counts1, (size_t)std::max(bin_level1_chunks(n), 1) * tiles_y * 4)) != GS_OK)
+        return st;
     if ((st = ensure(ctx, ctx->counters, 64)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
 
     uint32_t* counters = static_cast<uint32_t*>(ctx->counters.p);
-    uint64_t* k_total = reinterpret_cast<uint64_t*>(counters + 2);
-    HIP_TRY(launch_fill_u32(counters, 0u, 10, s), "clear counters");
+    HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
     STAGE_MARK(0);
 
     ProjectArgs pa{};
@@ -255,69 +253,78 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     pa.tiles_touched = static_cast<uint32_t*>(ctx->tiles_touched.p);
     pa.rect = static_cast<ushort4*>(ctx->rect.p);
     pa.n_visible = counters;
+    pa.k_total = reinterpret_cast<unsigned long long*>(counters + 10);
+    pa.partials = static_cast<uint32_t*>(ctx->partials.p);
     HIP_TRY(launch_project(pa, s), "project");
     STAGE_MARK(1);
 
-    int in_b = 1;
+    BinArgs ba{};
+    ba.n_visible = counters;
+    ba.rect = pa.rect;
+    ba.n = n;
+    ba.tiles_x = tiles_x;
+    ba.tiles_y = tiles_y;
+    ba.info = static_cast<uint32_t*>(ctx->bin_info.p);
+    ba.counts1 = static_cast<uint32_t*>(ctx->counts1.p);
+    ba.rows_off = static_cast<uint32_t*>(ctx->rows_off.p);
+    ba.tile_offsets = static_cast<uint32_t*>(ctx->tile_offsets.p);
+    ba.overflow = counters + 1;
+    uint64_t capacity = o.pair_capacity;
+    // pair_capacity > 0: every size below is the bound the capacity implies
+    // (row entries <= pairs); else the host reads K, R and the chunk count once
+    ba.row_capacity = capacity ? capacity : ~0ull;
+    ba.max_chunks2 = capacity ? bin_level2_chunk_bound(capacity, tiles_y) : (1 << 30);
+    const size_t scan0 = scan_scratch_elems(std::max<int64_t>(std::max<int64_t>(n, T),
+                                                              (int64_t)depth_sort_hist_elems(n)));
+    if ((st = ensure(ctx, ctx->scan_scratch, scan0 * 8)) != GS_OK) return st;
     uint64_t* scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
+    int in_b = 1;
     HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
                               static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
                               static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p),
                               scan_scratch, n, &in_b, s),
             "depth sort");
-    STAGE_MARK(2);
-
-    BinArgs ba{};
     ba.sorted_idx = static_cast<const uint32_t*>(in_b ? ctx->sort_vb.p : ctx->sort_va.p);
-    ba.n_visible = counters;
-    ba.rect = pa.rect;
-    ba.rect_s = static_cast<ushort4*>(ctx->rect_s.p);
-    ba.bp = static_cast<uint32_t*>(ctx->band_pairs.p);
-    ba.band_info = static_cast<uint32_t*>(ctx->band_info.p);
-    ba.n = n;
-    ba.tiles_x = tiles_x;
-    ba.tiles_y = tiles_y;
-    ba.band_rows = band_rows;
-    ba.num_bands = num_bands;
-    ba.tile_offsets = static_cast<uint32_t*>(ctx->tile_offsets.p);
-    ba.overflow = counters + 1;
-    uint64_t capacity = o.pair_capacity;
-    // capacity mode: the grids are sized for the worst case the capacity allows
-    ba.max_chunks = capacity ? (int)std::min<uint64_t>(capacity / kChunkPairs + num_bands + 1, 1u << 30)
-                             : (1 << 30);
-    HIP_TRY(launch_bin_prepare(ba, scan_scratch, k_total, s), "bin prepare");
+    STAGE_MARK(2);
+    HIP_TRY(launch_bin_rows(ba, scan_scratch, s), "bin rows");
     STAGE_MARK(3);
 
-    int grid = ba.max_chunks;
+    int grid2 = ba.max_chunks2;
     if (capacity == 0) {
-        // eager: one host read of the band table and K sizes the rest
-        HIP_TRY(hipMemcpyAsync(ctx->host_info, ba.band_info, sizeof(uint32_t) * (2 * num_bands + 2),
-                               hipMemcpyDeviceToHost, s),
-                "read band table");
-        HIP_TRY(hipMemcpyAsync(ctx->host_info + 2 * kMaxBands + 4, k_total, sizeof(uint64_t),
-                               hipMemcpyDeviceToHost, s),
-                "read K");
+        // eager: one host read of K, R and the level-2 chunk count
+        HIP_TRY(hipMemcpyAsync(ctx->host_info, counters, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                "read counters");
+        HIP_TRY(hipMemcpyAsync(ctx->host_info + 16, ba.rows_off + tiles_y, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               s),
+                "read R");
+        HIP_TRY(hipMemcpyAsync(ctx->host_info + 17, ba.info, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                "read chunk count");
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         uint64_t K64;
-        std::memcpy(&K64, ctx->host_info + 2 * kMaxBands + 4, sizeof K64);
-        if (K64 > 0xFFFFFFFFull) {
+        std::memcpy(&K64, ctx->host_info + 10, sizeof K64);
+        if (K64 > 0xFFFFFFFFull || ctx->host_info[1] != 0u) {
             ctx->have_render = false;
             return fail(ctx, GS_ERR_CAPACITY, "more than 2^32-1 (Gaussian, tile) pairs");
         }
         capacity = K64;
-        grid = (int)ctx->host_info[2 * num_bands + 1];
+        ba.row_capacity = ctx->host_info[16];
+        grid2 = (int)ctx->host_info[17];
+        ba.max_chunks2 = grid2;
     }
-    if ((st = ensure(ctx, ctx->counts, (size_t)(grid > 0 ? grid : 1) * kMaxBandTiles * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->values, (size_t)(capacity > 0 ? capacity : 1) * 4)) != GS_OK) return st;
-    ba.counts = static_cast<uint32_t*>(ctx->counts.p);
-    ba.values = static_cast<uint32_t*>(ctx->values.p);
     ba.capacity = capacity;
+    const size_t rows_cap = (size_t)std::max<uint64_t>(ba.row_capacity, 1);
+    if ((st = ensure(ctx, ctx->row_ent, rows_cap * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->counts2, (size_t)std::max(grid2, 1) * tiles_x * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->values, (size_t)std::max<uint64_t>(capacity, 1) * 4)) != GS_OK) return st;
+    ba.row_ent = static_cast<uint2*>(ctx->row_ent.p);
+    ba.counts2 = static_cast<uint32_t*>(ctx->counts2.p);
+    ba.values = static_cast<uint32_t*>(ctx->values.p);
     STAGE_MARK(4);
-    HIP_TRY(launch_bin_count(ba, grid, s), "bin count");
+    HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
     STAGE_MARK(5);
-    HIP_TRY(launch_bin_offsets(ba, scan_scratch, s), "bin offsets");
+    HIP_TRY(launch_bin_tiles(ba, grid2, scan_scratch, s), "bin tile counts");
     STAGE_MARK(6);
-    HIP_TRY(launch_bin_scatter(ba, grid, s), "bin scatter");
+    HIP_TRY(launch_bin_tile_scatter(ba, grid2, s), "bin tile scatter");
     STAGE_MARK(7);
 
     BlendArgs bl{};
@@ -354,16 +361,20 @@ gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out)
     if (!ctx || !out) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
     if (!ctx->have_render) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "no render on this context yet");
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-    uint32_t c[4];
+    uint32_t c[16], r32 = 0;
     HIP_TRY(hipMemcpyAsync(c, ctx->counters.p, sizeof c, hipMemcpyDeviceToHost, ctx->stream), "read counters");
+    HIP_TRY(hipMemcpyAsync(&r32, static_cast<uint32_t*>(ctx->rows_off.p) + ctx->tiles_y, sizeof r32,
+                           hipMemcpyDeviceToHost, ctx->stream),
+            "read R");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    uint64_t K;
-    std::memcpy(&K, c + 2, 8);
+    uint64_t K, R = r32;
+    std::memcpy(&K, c + 10, 8);
     out->num_pairs = K;
+    out->num_row_entries = R;
     out->tiles_x = ctx->tiles_x;
     out->tiles_y = ctx->tiles_y;
     out->n_visible = c[0];
-    if (c[1] != 0 || K > ctx->capacity)
+    if (c[1] != 0 || K > ctx->capacity || R > K)
         return fail(ctx, GS_ERR_CAPACITY, "the last render produced more pairs than pair_capacity");
     return GS_OK;
 }
@@ -436,6 +447,7 @@ gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats3)
     if (!ctx || !stats3) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
     if (!ctx->have_render || !ctx->timed)
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render was not traced (gs_set_profiling)");
+    // stats live at counters[4..9]
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_TRY(hipMemcpyAsync(stats3, static_cast<uint32_t*>(ctx->counters.p) + 4, 3 * sizeof(uint64_t),
                            hipMemcpyDeviceToHost, ctx->stream),

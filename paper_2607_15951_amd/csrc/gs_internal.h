@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace gsmi {
 
 constexpr int kTile = 16;                 // screen tile edge in pixels
@@ -13,8 +15,8 @@ constexpr int kMaxBandTiles = 2048;       // LDS cursors per binning wave
 constexpr int kSortBlock = 256;           // threads of a depth-sort block
 constexpr int kSortItems = 8;             // keys per thread per depth-sort block
 constexpr int kSortTile = kSortBlock * kSortItems;
-constexpr int kChunkPairs = 32768;        // (Gaussian, tile) pairs per binning wave
-constexpr int kMaxBands = 64;             // bands of tile rows per image
+constexpr int kItemsL1 = 8;               // depth-sorted Gaussians per lane of a level-1 binning wave
+constexpr int kItemsL2 = 16;              // row entries per lane of a level-2 binning wave
 
 // One projected Gaussian as the blend reads it: 3 x float4 = 48 bytes.
 //   a = (u_hi, v_hi, u_lo, v_lo)   2D centre as a float pair of the double
@@ -43,8 +45,11 @@ struct ProjectArgs {
     uint32_t* tiles_touched;
     ushort4* rect;
     uint32_t* n_visible;
+    unsigned long long* k_total;  // sum of tiles_touched (pairs K)
+    uint32_t* partials;           // [2 * blocks] per-block visible count and pairs
 };
 
+size_t project_partials_elems(int64_t n);
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
 
 // Stable LSD radix sort of n 32-bit keys with values 0..n-1, four 8-bit
@@ -58,30 +63,36 @@ struct BinArgs {
     const uint32_t* sorted_idx;   // [n] Gaussian indices in (depth, index) order
     const uint32_t* n_visible;    // device counter; visible Gaussians sort first
     const ushort4* rect;          // [n] tile rectangle by Gaussian index
-    ushort4* rect_s;              // [n] tile rectangle by sorted position
-    uint32_t* bp;                 // [bands][n] pair counts -> exclusive prefix
-    uint32_t* band_info;          // [2 * bands + 3] band and chunk tables
     int64_t n;
-    int tiles_x, tiles_y, band_rows, num_bands;
-    int max_chunks;               // chunks the count/scatter grids can hold
-    uint32_t* counts;             // [max_chunks][kMaxBandTiles] -> prefix in place
-    uint32_t* tile_offsets;       // [tiles + 1]
+    int tiles_x, tiles_y;
+    uint32_t* info;               // level-2 chunk table (bin_info_elems(tiles_y))
+    uint32_t* counts1;            // [level-1 chunks][tiles_y] -> prefix over chunks
+    uint32_t* rows_off;           // [tiles_y + 1] row-list offsets; [tiles_y] = R
+    uint2* row_ent;               // [row_capacity] (Gaussian, x0 | x1 << 16)
+    uint64_t row_capacity;
+    uint32_t* counts2;            // [max_chunks2][tiles_x] -> prefix over chunks
+    uint32_t* tile_offsets;       // [tiles + 1]; [tiles] = K
     uint32_t* values;             // [capacity] sorted pair values
     uint64_t capacity;
-    uint32_t* overflow;           // set to 1 when K > capacity or K >= 2^32
+    int max_chunks2;
+    uint32_t* overflow;           // set to 1 when a capacity is exceeded
 };
 
-hipError_t launch_bin_prepare(const BinArgs& a, uint64_t* scan_scratch, uint64_t* k_total, hipStream_t s);
-hipError_t launch_bin_count(const BinArgs& a, int grid, hipStream_t s);
-hipError_t launch_bin_offsets(const BinArgs& a, uint64_t* scan_scratch, hipStream_t s);
-hipError_t launch_bin_scatter(const BinArgs& a, int grid, hipStream_t s);
+size_t bin_info_elems(int tiles_y);
+int bin_level1_chunks(int64_t n);
+int bin_level2_chunk_bound(uint64_t row_entries, int tiles_y);
+hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t s);
+hipError_t launch_bin_row_scatter(const BinArgs& a, hipStream_t s);
+hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch, hipStream_t s);
+hipError_t launch_bin_tile_scatter(const BinArgs& a, int grid2, hipStream_t s);
 
 // Device-wide exclusive scan of n uint32 values in place; 64-bit total to
 // *total64 and/or *total32 (either may be null), overflow flag when the total
 // does not fit 32 bits.  block_scratch holds scan_scratch_elems(n) u64.
 size_t scan_scratch_elems(int64_t n);
 hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scratch, uint64_t* total64,
-                                 uint32_t* total32, uint32_t* overflow, hipStream_t s);
+                                 uint32_t* total32, uint32_t* overflow, hipStream_t s,
+                                 const uint32_t* n_dev = nullptr);
 
 struct BlendArgs {
     const Splat* splats;

@@ -66,6 +66,12 @@ struct Geometry {
     int32_t radius;
 };
 
+}  // namespace
+
+size_t project_partials_elems(int64_t n) { return (size_t)(2 * ((n + 255) / 256 + 1)); }
+
+namespace {
+
 // Culling and projection in double precision.  Returns false for a culled
 // Gaussian.  The expression shapes below fix the rounding order.
 __device__ __forceinline__ bool project_geometry(const ProjectArgs& a, double mx, double my, double mz,
@@ -172,8 +178,10 @@ template <int DT, int DEG>
 __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 {
     constexpr int ncoef = (DEG + 1) * (DEG + 1);
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.n) return;
+    // lanes past n stay active (reading Gaussian 0) until the wave reduction
+    const int64_t i_raw = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = i_raw < a.n;
+    const int64_t i = valid ? i_raw : 0;
     const int64_t n = a.n;
     // every attribute load is issued before any arithmetic, so a wave has all
     // of its 11 + 3 (DEG+1)^2 coalesced streams in flight at once
@@ -195,7 +203,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 
     uint32_t tiles = 0;
     ushort4 rc = make_ushort4(0, 0, 0, 0);
-    if (ok) {
+    if (ok && valid) {
         const double big = 1073741824.0;
         const double uc = fmin(big, fmax(-big, g.u)), vc = fmin(big, fmax(-big, g.v));
         int64_t xlo = (int64_t)ceil(uc) - g.radius, xhi = (int64_t)floor(uc) + g.radius;
@@ -237,23 +245,61 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
         }
         sp.c = make_float4(col[0], col[1], col[2], (float)g.tz);
     }
-    float4* dst = reinterpret_cast<float4*>(a.splats + i);
-    dst[0] = sp.a;
-    dst[1] = sp.b;
-    dst[2] = sp.c;
-    a.depth_key[i] = tiles > 0 ? __float_as_uint((float)g.tz) : 0xFFFFFFFFu;
-    a.radius[i] = tiles > 0 ? g.radius : 0;
-    a.tiles_touched[i] = tiles;
-    a.rect[i] = rc;
+    if (valid) {
+        float4* dst = reinterpret_cast<float4*>(a.splats + i);
+        dst[0] = sp.a;
+        dst[1] = sp.b;
+        dst[2] = sp.c;
+        a.depth_key[i] = tiles > 0 ? __float_as_uint((float)g.tz) : 0xFFFFFFFFu;
+        a.radius[i] = tiles > 0 ? g.radius : 0;
+        a.tiles_touched[i] = tiles;
+        a.rect[i] = rc;
+    }
 
-    // one atomic per wave for the visible count
+    // per-block visible count and pair total (no atomics: a single counter
+    // hit by every wave serialises); reduce_partials_kernel sums them
+    __shared__ uint32_t s_vis[4], s_pairs[4];
     const uint64_t vis = __ballot(tiles > 0);
-    const uint64_t act = __ballot(1);
-    if ((int)(__ffsll((long long)act) - 1) == (int)(threadIdx.x & 63) && vis)
-        atomicAdd(a.n_visible, (uint32_t)__popcll(vis));
+    uint32_t wave_pairs = tiles;
+    for (int o = 32; o > 0; o >>= 1) wave_pairs += __shfl_xor(wave_pairs, o, 64);
+    if ((threadIdx.x & 63) == 0) {
+        s_vis[threadIdx.x >> 6] = (uint32_t)__popcll(vis);
+        s_pairs[threadIdx.x >> 6] = wave_pairs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.partials[2 * blockIdx.x] = s_vis[0] + s_vis[1] + s_vis[2] + s_vis[3];
+        a.partials[2 * blockIdx.x + 1] = s_pairs[0] + s_pairs[1] + s_pairs[2] + s_pairs[3];
+    }
 }
 
 }  // namespace
+
+// n_visible = sum of the blocks' visible counts, k_total = sum of their pairs
+__global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* __restrict__ partials, int blocks,
+                                                               uint32_t* n_visible, unsigned long long* k_total)
+{
+    __shared__ unsigned long long sv[1024], sp[1024];
+    unsigned long long v = 0, p = 0;
+    for (int b = threadIdx.x; b < blocks; b += 1024) {
+        v += partials[2 * b];
+        p += partials[2 * b + 1];
+    }
+    sv[threadIdx.x] = v;
+    sp[threadIdx.x] = p;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sv[threadIdx.x] += sv[threadIdx.x + o];
+            sp[threadIdx.x] += sp[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *n_visible = (uint32_t)sv[0];
+        *k_total = sp[0];
+    }
+}
 
 template <int DT>
 void launch_project_dt(const ProjectArgs& a, unsigned blocks, hipStream_t s)
@@ -275,6 +321,8 @@ hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
     case 1: launch_project_dt<1>(a, blocks, s); break;
     default: launch_project_dt<2>(a, blocks, s); break;
     }
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(1024), 0, s, (const uint32_t*)a.partials, (int)blocks,
+                       a.n_visible, a.k_total);
     return hipGetLastError();
 }
 

@@ -2,7 +2,8 @@
 // of block sums, down-sweep), used by the depth sort's digit offsets and by
 // the per-band pair prefix of the binning.  Block sums and the total are
 // accumulated in 64 bits; the total is written to *total (and an overflow
-// flag raised when it does not fit 32 bits).
+// flag raised when it does not fit 32 bits).  With n_dev set, the length is
+// min(n, *n_dev), read on the device (no host sync).
 #include "gs_internal.h"
 
 namespace gsmi {
@@ -30,9 +31,18 @@ __device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t v, uint64_t* sh
     return incl - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
+__device__ __forceinline__ int64_t scan_length(int64_t n, const uint32_t* n_dev)
+{
+    if (!n_dev) return n;
+    const int64_t d = (int64_t)*n_dev;
+    return d < n ? d : n;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n_max,
+                                                                    const uint32_t* n_dev,
                                                                     uint64_t* __restrict__ block_sums)
 {
+    const int64_t n = scan_length(n_max, n_dev);
     __shared__ uint64_t sh[kScanThreads];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     uint64_t s = 0;
@@ -70,9 +80,11 @@ __global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(uint64_t* __r
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __restrict__ data, int64_t n,
+__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __restrict__ data, int64_t n_max,
+                                                                 const uint32_t* n_dev,
                                                                  const uint64_t* __restrict__ block_prefix)
 {
+    const int64_t n = scan_length(n_max, n_dev);
     __shared__ uint64_t sh[kScanThreads];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     // thread t owns the kScanItems consecutive items [t*16, t*16+16) of the tile
@@ -102,7 +114,7 @@ size_t scan_scratch_elems(int64_t n)
 }
 
 hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scratch, uint64_t* total64,
-                                 uint32_t* total32, uint32_t* overflow, hipStream_t s)
+                                 uint32_t* total32, uint32_t* overflow, hipStream_t s, const uint32_t* n_dev)
 {
     if (n <= 0) {
         if (total64 || total32) {
@@ -112,10 +124,12 @@ hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scra
         return hipGetLastError();
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, block_scratch);
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, n_dev,
+                       block_scratch);
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, block_scratch, nb, total64, total32,
                        overflow);
-    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, block_scratch);
+    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, n_dev,
+                       block_scratch);
     return hipGetLastError();
 }
 

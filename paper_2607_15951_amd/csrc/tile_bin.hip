@@ -3,321 +3,369 @@
 //
 // Every Gaussian overlapping a screen tile (the 3-sigma square of Sec. 4.4)
 // yields one pair; a pair's key is (tile << 32 | depth bits), its value the
-// Gaussian index.  Gaussians arrive here already in (depth, index) order
-// (depth_sort.hip), so a stable counting sort on the tile digit leaves every
+// Gaussian index.  Gaussians arrive here in (depth, index) order
+// (depth_sort.hip), so a stable distribution on the tile digit leaves every
 // tile's list in front-to-back order: the output IS the sorted pair list.
 //
-// Work decomposition.  Tile rows are grouped into bands of at most
-// kMaxBandTiles tiles (one LDS counter per tile of a band).  Per band, the
-// pairs form one flat sequence in (depth order, tile row, tile column) order;
-// its prefix over the depth-sorted Gaussians is one device-wide scan.  A
-// wavefront owns a chunk of kChunkPairs consecutive pairs of one band, so
-// every wave does the same amount of work however the pairs are spread over
-// Gaussians (the big background Gaussians all sort to the back).
-//   prep:    per sorted position, the pair count in each band
-//   scan:    exclusive prefix of those counts (all bands in one sequence)
-//   info:    band bases and chunk bases
-//   count:   per chunk, an LDS histogram over the band's tiles
-//   colscan: per tile, exclusive prefix over the band's chunks
-//   offsets: exclusive scan of the tile totals -> tile_offsets
-//   scatter: per chunk, LDS cursors at tile offset + chunk prefix; equal tiles
-//            inside a 64-pair group are ranked by lane (ballot match), which
-//            keeps depth order within every tile
+// The tile digit is distributed in two stable levels:
+//   level 1  every depth-sorted Gaussian is copied to the list of each tile
+//            row its rectangle spans: row entries (index, x0 | x1 << 16);
+//   level 2  every row entry is copied to the list of each tile of that row
+//            its column span covers: the pair values.
+// A wavefront owns a chunk of consecutive items (Gaussians, or one row's
+// entries), kept in registers, kItemsL* per lane.  It walks the buckets
+// (rows, or the row's tile columns) in order; for bucket x every item of a
+// batch of 64 tests whether its span covers x, M = ballot(covers), and the
+// covering lanes write at cursor[x] + (number of covering lanes below them),
+// after which cursor[x] advances by popcount(M).  Items keep their order
+// inside every bucket, each bucket's run is written front to back, and the
+// work is one compare per (item, bucket) -- no per-pair search or ranking.
+//   count    the same walk, summing popcount(M) per bucket;
+//   colscan  per bucket, exclusive prefix over the chunks; bucket totals;
+//   offsets  exclusive scan of the totals (row lists, then tiles);
+//   scatter  the walk with cursors at bucket offset + chunk prefix.
 #include "gs_internal.h"
 
 namespace gsmi {
 namespace {
 
-__global__ __launch_bounds__(256) void band_prep_kernel(BinArgs a)
-{
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= a.n) return;
-    const int64_t nv = (int64_t)*a.n_visible;
-    ushort4 r = make_ushort4(0, 0, 0, 0);
-    if (k < nv) r = a.rect[a.sorted_idx[k]];
-    a.rect_s[k] = r;
-    const int w = (int)r.z - (int)r.x;
-    for (int b = 0; b < a.num_bands; ++b) {
-        const int b0 = b * a.band_rows, b1 = b0 + a.band_rows;
-        const int y0 = (int)r.y > b0 ? (int)r.y : b0;
-        const int y1 = (int)r.w < b1 ? (int)r.w : b1;
-        a.bp[(int64_t)b * a.n + k] = (k < nv && y1 > y0) ? (uint32_t)(w * (y1 - y0)) : 0u;
-    }
-}
+constexpr int kChunk1 = kItemsL1 * 64;   // Gaussians per level-1 wave
+constexpr int kChunk2 = kItemsL2 * 64;   // row entries per level-2 wave
 
-// band_info[0..B]: pair prefix at each band start (band_info[B] = K);
-// band_info[B+1 .. 2B+1]: chunk prefix (band_info[2B+1] = number of chunks).
-// With K >= 2^32 the 32-bit prefixes wrap: no chunk is handed out then (the
-// overflow flag is already set by the scan).
-__global__ void band_info_kernel(BinArgs a, const uint32_t* total32, const uint64_t* total64)
-{
-    if (threadIdx.x != 0) return;
-    const int B = a.num_bands;
-    const bool wrapped = *total64 > 0xFFFFFFFFull;
-    uint32_t chunks = 0;
-    for (int b = 0; b <= B; ++b) a.band_info[b] = (b < B) ? a.bp[(int64_t)b * a.n] : *total32;
-    for (int b = 0; b < B; ++b) {
-        a.band_info[B + 1 + b] = chunks;
-        const uint32_t kb = a.band_info[b + 1] - a.band_info[b];
-        if (!wrapped) chunks += (kb + kChunkPairs - 1) / kChunkPairs;
-    }
-    a.band_info[2 * B + 1] = chunks;
-    if ((int64_t)chunks > (int64_t)a.max_chunks) {
-        *a.overflow = 1u;
-        a.band_info[2 * B + 1] = 0u;   // nothing is binned past the grid's room
-    }
-}
+// info[] layout (uint32): [0] level-2 chunks, [1..tiles_y+1] level-2 chunk
+// prefix at each row start.
+constexpr int kInfoC2 = 0;
+constexpr int kInfoRowChunks = 1;
 
-struct ChunkView {
-    int band;
-    uint32_t lo, hi;   // band-local pair range of the chunk
-    uint32_t base;     // global prefix at the band start
-    uint32_t kb;       // pairs in the band
-    int64_t k0;        // last sorted position whose band prefix is <= lo
-};
-
-// Chunk of the workgroup: the dispatcher deals workgroups round-robin to the
-// 8 XCDs, so block b takes chunk (b % 8) * ceil(grid / 8) + b / 8 and every
-// XCD works through a contiguous run of chunks.  Consecutive chunks write
-// adjacent pieces of each tile's list, which then meet in the same L2.
+// Workgroup b -> chunk: the dispatcher deals workgroups round-robin to the 8
+// XCDs; block b takes chunk (b % 8) * ceil(grid / 8) + b / 8 so each XCD works
+// through a contiguous run of chunks, whose output pieces are adjacent.
 __device__ __forceinline__ int chunk_of_block()
 {
     const int per_xcd = (int)((gridDim.x + 7) / 8);
     return (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
 }
 
-// Locates wave w's band and pair range, then k0 by a 64-ary search (each
-// step probes 64 positions with one ballot).
-__device__ __forceinline__ bool locate_chunk(const BinArgs& a, int w, int lane, ChunkView& v)
+// Number of covering lanes below this one in mask m (lanes 0..lane-1).
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
-    const int B = a.num_bands;
-    const uint32_t* info = a.band_info;
-    if ((uint32_t)w >= info[2 * B + 1]) return false;
-    int b = 0;
-    while (b + 1 < B && info[B + 1 + b + 1] <= (uint32_t)w) ++b;
-    const uint32_t c = (uint32_t)w - info[B + 1 + b];
-    v.band = b;
-    v.base = info[b];
-    v.kb = info[b + 1] - info[b];
-    v.lo = c * (uint32_t)kChunkPairs;
-    v.hi = (v.lo + kChunkPairs < v.kb) ? v.lo + kChunkPairs : v.kb;
-    const int64_t nv = (int64_t)*a.n_visible;
-    const uint32_t* pre = a.bp + (int64_t)b * a.n;
-    int64_t L = 0, R = nv;   // invariant: pre[L] - base <= lo
-    while (R - L > 1) {
-        const int64_t step = (R - L + 63) / 64;
-        const int64_t q = L + (int64_t)lane * step;
-        const bool ok = q < R && (pre[q] - v.base) <= v.lo;
-        const uint64_t m = __ballot(ok);
-        const int top = 63 - (int)__clzll((long long)m);
-        const int64_t nl = L + (int64_t)top * step;
-        R = (nl + step < R) ? nl + step : R;
-        L = nl;
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const int t = __shfl_xor(v, o, 64);
+        v = t < v ? t : v;
     }
-    v.k0 = L;
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const int t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ level 1
+// items: depth-sorted Gaussians; buckets: tile rows; payload (index, x-span)
+
+struct Items1 {
+    uint32_t y0[kItemsL1], y1[kItemsL1], xs[kItemsL1], g[kItemsL1];
+    int lo, hi;   // rows spanned by the chunk
+};
+
+__device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, Items1& it)
+{
+    const int64_t nv = (int64_t)*a.n_visible;
+    const int64_t start = (int64_t)c * kChunk1;
+    if (start >= nv) return false;
+    int lo = 1 << 30, hi = 0;
+#pragma unroll
+    for (int b = 0; b < kItemsL1; ++b) {
+        const int64_t k = start + b * 64 + lane;
+        ushort4 r = make_ushort4(0, 0, 0, 0);
+        uint32_t g = 0;
+        if (k < nv) {
+            g = a.sorted_idx[k];
+            r = a.rect[g];
+            lo = (int)r.y < lo ? (int)r.y : lo;
+            hi = (int)r.w > hi ? (int)r.w : hi;
+        }
+        it.y0[b] = r.y;
+        it.y1[b] = r.w;
+        it.xs[b] = (uint32_t)r.x | ((uint32_t)r.z << 16);
+        it.g[b] = g;
+    }
+    it.lo = wave_min(lo);
+    it.hi = wave_max(hi);
     return true;
 }
 
-// Walks the pairs of one chunk 64 at a time; emit(local_tile, gaussian,
-// active) is called by every lane of the wave for each group of 64 pairs.
-template <class Emit>
-__device__ __forceinline__ void walk_chunk(const BinArgs& a, const ChunkView& v, int lane, Emit&& emit)
+__global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
 {
-    __shared__ uint32_t s_pre[64];
-    __shared__ uint32_t s_x0w[64];   // x0 | w << 16
-    __shared__ int s_row0[64];
-    __shared__ uint32_t s_g[64];
-    const int64_t nv = (int64_t)*a.n_visible;
-    const uint32_t* pre_arr = a.bp + (int64_t)v.band * a.n;
-    const int by0 = v.band * a.band_rows;
-    for (int64_t kpos = v.k0; kpos < nv; kpos += 64) {
-        const int64_t k = kpos + lane;
-        uint32_t pre = v.kb, x0w = 1u << 16, g = 0;
-        int row0 = 0;
-        if (k < nv) {
-            pre = pre_arr[k] - v.base;
-            const ushort4 r = a.rect_s[k];
-            const int y0 = (int)r.y > by0 ? (int)r.y : by0;
-            x0w = (uint32_t)r.x | ((uint32_t)(r.z - r.x) << 16);
-            row0 = y0 - by0;
-            g = a.sorted_idx[k];
-        }
-        s_pre[lane] = pre;
-        s_x0w[lane] = x0w;
-        s_row0[lane] = row0;
-        s_g[lane] = g;
-        __syncthreads();
-        // this batch holds the band pairs [pre of lane 0, pre of the next batch)
-        const int64_t knext = kpos + 64;
-        const uint32_t batch_end = (knext < nv) ? pre_arr[knext] - v.base : v.kb;
-        const uint32_t p_start = (s_pre[0] > v.lo) ? s_pre[0] : v.lo;
-        const uint32_t p_end = (batch_end < v.hi) ? batch_end : v.hi;
-        for (uint32_t p0 = p_start; p0 < p_end; p0 += 64) {
-            const uint32_t p = p0 + lane;
-            const bool active = p < p_end;
-            int local = 0;
-            uint32_t gi = 0;
-            if (active) {
-                int lo = 0, hi = 63;   // last lane whose interval starts at or before p
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_pre[mid] <= p) lo = mid; else hi = mid - 1;
-                }
-                const uint32_t j = p - s_pre[lo];
-                const uint32_t xw = s_x0w[lo];
-                const int w = (int)(xw >> 16);
-                // j / w for j, w <= 2^11: float estimate, then exact correction
-                int row = (int)((float)j * __builtin_amdgcn_rcpf((float)w));
-                int col = (int)j - row * w;
-                if (col < 0) {
-                    --row;
-                    col += w;
-                }
-                if (col >= w) {
-                    ++row;
-                    col -= w;
-                }
-                local = (s_row0[lo] + row) * a.tiles_x + (int)(xw & 0xFFFFu) + col;
-                gi = s_g[lo];
-            }
-            emit(local, gi, active);
-        }
-        __syncthreads();
-        if (batch_end >= v.hi) break;
+    const int lane = threadIdx.x, c = chunk_of_block();
+    uint32_t* dst = a.counts1 + (int64_t)c * a.tiles_y;
+    Items1 it;
+    if (!load_items1(a, c, lane, it)) {
+        for (int r = lane; r < a.tiles_y; r += 64) dst[r] = 0u;
+        return;
+    }
+    for (int r = lane; r < a.tiles_y; r += 64)
+        if (r < it.lo || r >= it.hi) dst[r] = 0u;
+    for (int r = it.lo; r < it.hi; ++r) {
+        uint32_t n = 0;
+#pragma unroll
+        for (int b = 0; b < kItemsL1; ++b) n += (uint32_t)__popcll(__ballot(it.y0[b] <= (uint32_t)r && (uint32_t)r < it.y1[b]));
+        if (lane == 0) dst[r] = n;
     }
 }
 
-__global__ __launch_bounds__(64) void bin_count_kernel(BinArgs a)
+__global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
 {
-    __shared__ uint32_t cnt[kMaxBandTiles];
-    const int lane = threadIdx.x;
-    const int chunk = chunk_of_block();
-    ChunkView v;
-    if (!locate_chunk(a, chunk, lane, v)) return;
-    const int by0 = v.band * a.band_rows;
-    const int by1 = (by0 + a.band_rows < a.tiles_y) ? by0 + a.band_rows : a.tiles_y;
-    const int band_tiles = (by1 - by0) * a.tiles_x;
-    for (int k = lane; k < band_tiles; k += 64) cnt[k] = 0;
-    __syncthreads();
-    walk_chunk(a, v, lane, [&](int local, uint32_t, bool active) {
-        if (active) atomicAdd(&cnt[local], 1u);
-    });
-    __syncthreads();
-    uint32_t* dst = a.counts + (int64_t)chunk * kMaxBandTiles;
-    for (int k = lane; k < band_tiles; k += 64) dst[k] = cnt[k];
+    const int lane = threadIdx.x, c = chunk_of_block();
+    Items1 it;
+    if (!load_items1(a, c, lane, it)) return;
+    const uint32_t* prefix = a.counts1 + (int64_t)c * a.tiles_y;
+    for (int r = it.lo; r < it.hi; ++r) {
+        uint32_t cur = a.rows_off[r] + prefix[r];
+#pragma unroll
+        for (int b = 0; b < kItemsL1; ++b) {
+            const bool cover = it.y0[b] <= (uint32_t)r && (uint32_t)r < it.y1[b];
+            const uint64_t m = __ballot(cover);
+            if (cover) {
+                const uint64_t pos = (uint64_t)cur + lanes_below(m);
+                if (pos < a.row_capacity) a.row_ent[pos] = make_uint2(it.g[b], it.xs[b]);
+            }
+            cur += (uint32_t)__popcll(m);
+        }
+    }
 }
 
-// counts[chunk][t] -> exclusive prefix over the band's chunks (in place);
-// tile totals -> tile_offsets[tile].  Block = (band, 64 tiles) x 16 segments.
-__global__ __launch_bounds__(1024) void bin_colscan_kernel(BinArgs a)
+// Level-2 chunk table: row r owns ceil(len_r / kChunk2) chunks; info holds
+// their prefix (one 1024-thread block, two rows per thread).
+__global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
+{
+    __shared__ uint32_t part[1024];
+    const int tid = threadIdx.x, ty_n = a.tiles_y;
+    uint32_t c[2] = {0u, 0u};
+    for (int k = 0; k < 2; ++k) {
+        const int r = 2 * tid + k;
+        if (r < ty_n) {
+            const uint32_t len = a.rows_off[r + 1] - a.rows_off[r];
+            c[k] = (len + kChunk2 - 1) / kChunk2;
+        }
+    }
+    part[tid] = c[0] + c[1];
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t t = tid >= o ? part[tid - o] : 0u;
+        __syncthreads();
+        part[tid] += t;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - (c[0] + c[1]);
+    uint32_t* base = a.info + kInfoRowChunks;
+    for (int k = 0; k < 2; ++k) {
+        const int r = 2 * tid + k;
+        if (r < ty_n) base[r] = run;
+        run += c[k];
+    }
+    if (tid == 1023) {
+        uint32_t total = part[1023];
+        // rows_off[ty_n] is the number of row entries R
+        if ((int64_t)total > (int64_t)a.max_chunks2 || (uint64_t)a.rows_off[ty_n] > a.row_capacity) {
+            *a.overflow = 1u;
+            total = 0;
+        }
+        base[ty_n] = total;
+        a.info[kInfoC2] = total;
+    }
+}
+
+// ------------------------------------------------------------------ level 2
+// items: one row's entries; buckets: that row's tile columns; payload: index
+
+struct Items2 {
+    uint32_t x0[kItemsL2], x1[kItemsL2], g[kItemsL2];
+    int row, lo, hi;   // row, columns spanned by the chunk
+};
+
+__device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, Items2& it)
+{
+    if ((uint32_t)c >= a.info[kInfoC2]) return false;
+    const int ty_n = a.tiles_y;
+    const uint32_t* base = a.info + kInfoRowChunks;
+    // owning row: the last r with base[r] <= c (64-ary search over rows; rows
+    // without chunks share base with the next row, so the last one owns c)
+    int L = 0, R = ty_n;
+    while (R - L > 1) {
+        const int step = (R - L + 63) / 64;
+        const int q = L + lane * step;
+        const bool ok = q < R && base[q] <= (uint32_t)c;
+        const uint64_t m = __ballot(ok);
+        const int top = 63 - (int)__clzll((long long)m);
+        const int nl = L + top * step;
+        R = (nl + step < R) ? nl + step : R;
+        L = nl;
+    }
+    it.row = L;
+    const int64_t eb = (int64_t)a.rows_off[L] + (int64_t)((uint32_t)c - base[L]) * kChunk2;
+    const int64_t ee = a.rows_off[L + 1];
+    int lo = 1 << 30, hi = 0;
+#pragma unroll
+    for (int b = 0; b < kItemsL2; ++b) {
+        const int64_t e = eb + b * 64 + lane;
+        uint2 ent = make_uint2(0u, 0u);
+        if (e < ee) {
+            ent = a.row_ent[e];
+            const int x0 = (int)(ent.y & 0xFFFFu), x1 = (int)(ent.y >> 16);
+            lo = x0 < lo ? x0 : lo;
+            hi = x1 > hi ? x1 : hi;
+        }
+        it.x0[b] = ent.y & 0xFFFFu;
+        it.x1[b] = ent.y >> 16;
+        it.g[b] = ent.x;
+    }
+    it.lo = wave_min(lo);
+    it.hi = wave_max(hi);
+    return true;
+}
+
+__global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
+{
+    const int lane = threadIdx.x, c = chunk_of_block();
+    Items2 it;
+    if (!load_items2(a, c, lane, it)) return;
+    uint32_t* dst = a.counts2 + (int64_t)c * a.tiles_x;
+    for (int x = lane; x < a.tiles_x; x += 64)
+        if (x < it.lo || x >= it.hi) dst[x] = 0u;
+    for (int x = it.lo; x < it.hi; ++x) {
+        uint32_t n = 0;
+#pragma unroll
+        for (int b = 0; b < kItemsL2; ++b) n += (uint32_t)__popcll(__ballot(it.x0[b] <= (uint32_t)x && (uint32_t)x < it.x1[b]));
+        if (lane == 0) dst[x] = n;
+    }
+}
+
+__global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
+{
+    const int lane = threadIdx.x, c = chunk_of_block();
+    Items2 it;
+    if (!load_items2(a, c, lane, it)) return;
+    const uint32_t* prefix = a.counts2 + (int64_t)c * a.tiles_x;
+    const uint32_t* toff = a.tile_offsets + (int64_t)it.row * a.tiles_x;
+    for (int x = it.lo; x < it.hi; ++x) {
+        uint32_t cur = toff[x] + prefix[x];
+#pragma unroll
+        for (int b = 0; b < kItemsL2; ++b) {
+            const bool cover = it.x0[b] <= (uint32_t)x && (uint32_t)x < it.x1[b];
+            const uint64_t m = __ballot(cover);
+            if (cover) {
+                const uint64_t pos = (uint64_t)cur + lanes_below(m);
+                if (pos < a.capacity) a.values[pos] = it.g[b];
+            }
+            cur += (uint32_t)__popcll(m);
+        }
+    }
+}
+
+// counts[chunk][col] -> exclusive prefix over each segment's chunks (in
+// place); segment totals -> totals[seg * ncols + col].  Segment s owns chunks
+// [seg_chunks[s], seg_chunks[s+1]), or [0, nchunks) when seg_chunks is null.
+// Block = (segment, 64 columns) x 16 chunk ranges.
+__global__ __launch_bounds__(1024) void colscan_kernel(uint32_t* __restrict__ counts, int ncols,
+                                                       const uint32_t* __restrict__ seg_chunks, int nchunks,
+                                                       int col_groups, uint32_t* __restrict__ totals)
 {
     __shared__ uint32_t part[16][64];
-    const int B = a.num_bands;
-    const int groups = kMaxBandTiles / 64;
-    const int band = blockIdx.x / groups, tg = blockIdx.x % groups;
-    const int tl = threadIdx.x & 63, seg = threadIdx.x >> 6;
-    const int by0 = band * a.band_rows;
-    const int by1 = (by0 + a.band_rows < a.tiles_y) ? by0 + a.band_rows : a.tiles_y;
-    const int band_tiles = (by1 - by0) * a.tiles_x;
-    const int t = tg * 64 + tl;
-    const int c_begin = (int)a.band_info[B + 1 + band];
-    const int c_end = (int)a.band_info[B + 1 + band + 1];
+    const int seg = blockIdx.x / col_groups, cg = blockIdx.x % col_groups;
+    const int tl = threadIdx.x & 63, part_id = threadIdx.x >> 6;
+    const int col = cg * 64 + tl;
+    const int c_begin = seg_chunks ? (int)seg_chunks[seg] : 0;
+    const int c_end = seg_chunks ? (int)seg_chunks[seg + 1] : nchunks;
     const int per = (c_end - c_begin + 15) / 16;
-    const int c0 = c_begin + seg * per;
+    const int c0 = c_begin + part_id * per;
     const int c1 = (c0 + per < c_end) ? c0 + per : c_end;
-    const bool valid = t < band_tiles;
+    const bool valid = col < ncols;
     uint32_t s = 0;
     if (valid)
-        for (int c = c0; c < c1; ++c) s += a.counts[(int64_t)c * kMaxBandTiles + t];
-    part[seg][tl] = s;
+        for (int c = c0; c < c1; ++c) s += counts[(int64_t)c * ncols + col];
+    part[part_id][tl] = s;
     __syncthreads();
     uint32_t run = 0, tot = 0;
     for (int k = 0; k < 16; ++k) {
         const uint32_t x = part[k][tl];
-        if (k < seg) run += x;
+        if (k < part_id) run += x;
         tot += x;
     }
     if (valid) {
         for (int c = c0; c < c1; ++c) {
-            const int64_t o = (int64_t)c * kMaxBandTiles + t;
-            const uint32_t x = a.counts[o];
-            a.counts[o] = run;
+            const int64_t o = (int64_t)c * ncols + col;
+            const uint32_t x = counts[o];
+            counts[o] = run;
             run += x;
         }
-        if (seg == 0) a.tile_offsets[(int64_t)by0 * a.tiles_x + t] = tot;
+        if (part_id == 0) totals[(int64_t)seg * ncols + col] = tot;
     }
 }
 
-__global__ __launch_bounds__(64) void bin_scatter_kernel(BinArgs a)
-{
-    __shared__ uint32_t cursor[kMaxBandTiles];
-    const int lane = threadIdx.x;
-    const int chunk = chunk_of_block();
-    ChunkView v;
-    if (!locate_chunk(a, chunk, lane, v)) return;
-    const int by0 = v.band * a.band_rows;
-    const int by1 = (by0 + a.band_rows < a.tiles_y) ? by0 + a.band_rows : a.tiles_y;
-    const int band_tiles = (by1 - by0) * a.tiles_x;
-    const uint32_t* prefix = a.counts + (int64_t)chunk * kMaxBandTiles;
-    const uint32_t* toff = a.tile_offsets + (int64_t)by0 * a.tiles_x;
-    for (int k = lane; k < band_tiles; k += 64) cursor[k] = toff[k] + prefix[k];
-    __syncthreads();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t cap = a.capacity;
-    uint32_t* values = a.values;
-    walk_chunk(a, v, lane, [&](int local, uint32_t g, bool active) {
-        const uint64_t act = __ballot(active);
-        if (!active) return;
-        uint64_t m = act;
-#pragma unroll
-        for (int b = 0; b < 11; ++b) {   // kMaxBandTiles = 2^11
-            const bool bit = (local >> b) & 1;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
-        }
-        const uint32_t rank = (uint32_t)__popcll(m & lt);
-        const uint32_t first = cursor[local];
-        const uint32_t pos = first + rank;
-        if (rank == 0) cursor[local] = first + (uint32_t)__popcll(m);
-        if ((uint64_t)pos < cap) values[pos] = g;
-    });
-}
+unsigned grid8(int g) { return (unsigned)(8 * ((g + 7) / 8)); }
 
 }  // namespace
 
-hipError_t launch_bin_prepare(const BinArgs& a, uint64_t* scan_scratch, uint64_t* k_total, hipStream_t s)
+size_t bin_info_elems(int tiles_y) { return (size_t)(kInfoRowChunks + tiles_y + 2); }
+int bin_level1_chunks(int64_t n) { return (int)((n + kChunk1 - 1) / kChunk1); }
+int bin_level2_chunk_bound(uint64_t row_entries, int tiles_y)
 {
-    if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(band_prep_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
-    // one exclusive scan over all bands' counts; its total is K
-    uint32_t* total32 = a.band_info + 2 * a.num_bands + 2;   // slot after the table
-    hipError_t e = launch_scan_exclusive(a.bp, (int64_t)a.num_bands * a.n, scan_scratch, k_total, total32,
+    return (int)std::min<uint64_t>(row_entries / kChunk2 + (uint64_t)tiles_y + 1, 1u << 30);
+}
+
+// Level 1 up to the row offsets (R = rows_off[tiles_y]) and the level-2
+// chunk table; no host dependence.
+hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t s)
+{
+    if (a.n == 0) {
+        hipError_t e = launch_fill_u32(a.rows_off, 0u, a.tiles_y + 1, s);
+        if (e != hipSuccess) return e;
+        return launch_fill_u32(a.info, 0u, (int64_t)bin_info_elems(a.tiles_y), s);
+    }
+    const int c1 = bin_level1_chunks(a.n);
+    hipLaunchKernelGGL(level1_count_kernel, dim3(grid8(c1)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(colscan_kernel, dim3((unsigned)((a.tiles_y + 63) / 64)), dim3(1024), 0, s, a.counts1,
+                       a.tiles_y, (const uint32_t*)nullptr, c1, (a.tiles_y + 63) / 64, a.rows_off);
+    hipError_t e = launch_scan_exclusive(a.rows_off, a.tiles_y, scan_scratch, nullptr, a.rows_off + a.tiles_y,
                                          a.overflow, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(band_info_kernel, dim3(1), dim3(64), 0, s, a, (const uint32_t*)total32,
-                       (const uint64_t*)k_total);
+    hipLaunchKernelGGL(level2_table_kernel, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_count(const BinArgs& a, int grid, hipStream_t s)
+hipError_t launch_bin_row_scatter(const BinArgs& a, hipStream_t s)
 {
-    if (a.n == 0 || grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)(8 * ((grid + 7) / 8))), dim3(64), 0, s, a);
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(level1_scatter_kernel, dim3(grid8(bin_level1_chunks(a.n))), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_offsets(const BinArgs& a, uint64_t* scan_scratch, hipStream_t s)
+hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch, hipStream_t s)
 {
     const int64_t T = (int64_t)a.tiles_x * a.tiles_y;
     if (a.n == 0) return launch_fill_u32(a.tile_offsets, 0u, T + 1, s);
-    hipLaunchKernelGGL(bin_colscan_kernel, dim3(a.num_bands * (kMaxBandTiles / 64)), dim3(1024), 0, s, a);
-    return launch_scan_exclusive(a.tile_offsets, T, scan_scratch, nullptr, a.tile_offsets + T, nullptr, s);
+    if (grid2 > 0) hipLaunchKernelGGL(level2_count_kernel, dim3(grid8(grid2)), dim3(64), 0, s, a);
+    const int groups = (a.tiles_x + 63) / 64;
+    hipLaunchKernelGGL(colscan_kernel, dim3((unsigned)(a.tiles_y * groups)), dim3(1024), 0, s, a.counts2, a.tiles_x,
+                       (const uint32_t*)(a.info + kInfoRowChunks), 0, groups, a.tile_offsets);
+    return launch_scan_exclusive(a.tile_offsets, T, scan_scratch, nullptr, a.tile_offsets + T, a.overflow, s);
 }
 
-hipError_t launch_bin_scatter(const BinArgs& a, int grid, hipStream_t s)
+hipError_t launch_bin_tile_scatter(const BinArgs& a, int grid2, hipStream_t s)
 {
-    if (a.n == 0 || grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)(8 * ((grid + 7) / 8))), dim3(64), 0, s, a);
+    if (a.n == 0 || grid2 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(level2_scatter_kernel, dim3(grid8(grid2)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
