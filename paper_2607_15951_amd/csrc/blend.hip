@@ -16,6 +16,8 @@
 // staging (a conservative lower bound of the quadratic form over the tile's
 // pixel box): every pixel would skip them, so the image is unchanged, and the
 // 3-sigma square of the lists leaves many such (Gaussian, tile) pairs.  The
+// same bound per 8x8 quad gives each entry a 4-bit mask: a wave owns one quad
+// and steps over entries outside its reach with one scalar branch.  The
 // per-pixel loop is predicated rather than branched; a wave leaves once all
 // 64 of its pixels have terminated and the workgroup once all 256 have.  No
 // MFMA: there is no dense contraction in this loop.
@@ -33,13 +35,13 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kUnroll = 8;
 
 // Smallest value of the quadratic form A x^2 + 2 B x y + C y^2 (positive
-// definite) over the box [x0, x0 + 15] x [y0, y0 + 15] of pixel offsets, made
-// a lower bound by subtracting 1e-5 of the size of its terms.  The form is
+// definite) over the box [x0, x0 + 7] x [y0, y0 + 7] of pixel offsets, made a
+// lower bound by subtracting 1e-5 of the size of its terms.  The form is
 // convex, so its minimum is 0 when the origin lies in the box and on an edge
 // otherwise; on an edge it is a 1D quadratic minimised in closed form.
-__device__ __forceinline__ float quad_min_over_tile(float x0, float y0, float A, float B, float C)
+__device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, float B, float C)
 {
-    const float x1 = x0 + 15.0f, y1 = y0 + 15.0f;
+    const float x1 = x0 + 7.0f, y1 = y0 + 7.0f;
     if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return 0.0f;
     float q = INFINITY, S = 0.0f;
     const float xs[2] = {x0, x1}, ys[2] = {y0, y1};
@@ -68,6 +70,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     __shared__ float4 s0[256 + kUnroll];   // du_hi, dv_hi, du_lo, dv_lo  (centre - tile origin)
     __shared__ float4 s1[256 + kUnroll];   // A', B', C', opacity  (A' = -0.5 log2(e) A, ...)
     __shared__ float4 s2[256 + kUnroll];   // r, g, b, list position (int bits)
+    __shared__ uint32_t s_mask[256 + kUnroll];   // quads (waves) the entry can reach
     __shared__ uint32_t s_wave_keep[4];
     const int T = a.tiles_x * a.tiles_y;
     const int per_xcd = (T + 7) / 8;
@@ -75,7 +78,8 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     if (tile >= T) return;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lx = tid & 15, ly = tid >> 4;
+    // each wave owns one 8x8 quad of the tile
+    const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
     const int px = tx * kTile + lx, py = ty * kTile + ly;
     const bool inside = px < a.width && py < a.height;
     uint64_t start = a.tile_offsets[tile], end = a.tile_offsets[tile + 1];
@@ -88,22 +92,46 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     float Tr = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     uint32_t last = 0, term = 0, composited = 0, staged = 0;
     bool done = !inside;
+    // software pipeline of the gathers: list values two batches ahead, the
+    // 48-byte records one batch ahead, both overlapping the compositing
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t g_next = (start + tid < end) ? a.values[start + tid] : 0u;
+    uint32_t g_after = (start + 256 + tid < end) ? a.values[start + 256 + tid] : 0u;
+    float4 na = zero4, nb = zero4, nc = zero4;
+    if (start + tid < end) {
+        const float4* rec = reinterpret_cast<const float4*>(a.splats + g_next);
+        na = rec[0];
+        nb = rec[1];
+        nc = rec[2];
+    }
     for (uint64_t b0 = start; b0 < end; b0 += 256) {
         if (__syncthreads_count(!done) == 0) break;
-        // stage: gather one entry per lane, drop it when no pixel of the tile
-        // can reach alpha 1/255 (the per-pixel test would skip it everywhere)
+        const float4 ra = na, rb = nb, rc = nc;
+        if (b0 + 256 + tid < end) {
+            const float4* rec = reinterpret_cast<const float4*>(a.splats + g_after);
+            na = rec[0];
+            nb = rec[1];
+            nc = rec[2];
+        }
+        g_after = (b0 + 512 + tid < end) ? a.values[b0 + 512 + tid] : 0u;
+        // stage: one entry per lane, dropped when no pixel of the tile can
+        // reach alpha 1/255 (the per-pixel test would skip it everywhere)
         const uint64_t e = b0 + tid;
         bool keep = false;
+        uint32_t qmask = 0u;
         float4 v0, v1, v2;
         if (e < end) {
-            const uint32_t g = a.values[e];
-            const float4* rec = reinterpret_cast<const float4*>(a.splats + g);
-            const float4 ra = rec[0], rb = rec[1], rc = rec[2];
             const double du = ((double)ra.x + (double)ra.z) - ox;
             const double dv = ((double)ra.y + (double)ra.w) - oy;
             const float du_hi = (float)du, dv_hi = (float)dv;
-            const float qmin = quad_min_over_tile(du_hi - 15.0f, dv_hi - 15.0f, rb.x, rb.y, rb.z);
-            keep = rb.w * __expf(-0.5f * qmin) >= (1.0f / 255.0f) * (1.0f - 1e-5f);
+            // reachable quads: alpha 1/255 is within reach somewhere in the quad
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float qmin =
+                    quad_min_over_box(du_hi - (float)((q & 1) * 8 + 7), dv_hi - (float)((q >> 1) * 8 + 7), rb.x, rb.y, rb.z);
+                if (rb.w * __expf(-0.5f * qmin) >= (1.0f / 255.0f) * (1.0f - 1e-5f)) qmask |= 1u << q;
+            }
+            keep = qmask != 0u;
             v0 = make_float4(du_hi, dv_hi, (float)(du - (double)du_hi), (float)(dv - (double)dv_hi));
             v1 = make_float4(-0.5f * kLog2e * rb.x, -kLog2e * rb.y, -0.5f * kLog2e * rb.z, rb.w);
             v2 = make_float4(rc.x, rc.y, rc.z, __int_as_float((int)(e - start)));
@@ -120,11 +148,13 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
             s0[slot] = v0;
             s1[slot] = v1;
             s2[slot] = v2;
+            s_mask[slot] = qmask;
         }
-        if (tid < kUnroll) {   // padding entries with zero opacity never pass
+        if (tid < kUnroll) {   // padding entries reach no quad
             s0[nk + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
             s1[nk + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
             s2[nk + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s_mask[nk + tid] = 0u;
         }
         __syncthreads();
         for (int j0 = 0; j0 < nk; j0 += kUnroll) {
@@ -132,6 +162,9 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const int j = j0 + u;
+                // an entry out of this quad's reach is skipped by the whole wave
+                const uint32_t qm = __builtin_amdgcn_readfirstlane(s_mask[j]);
+                if (!((qm >> wave) & 1u)) continue;
                 const float4 e0 = s0[j];
                 const float4 e1 = s1[j];
                 const float4 e2 = s2[j];

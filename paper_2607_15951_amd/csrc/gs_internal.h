@@ -17,6 +17,7 @@ constexpr int kSortItems = 8;             // keys per thread per depth-sort bloc
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kItemsL1 = 8;               // depth-sorted Gaussians per lane of a level-1 binning wave
 constexpr int kItemsL2 = 16;              // row entries per lane of a level-2 binning wave
+constexpr int kMaxRows = 2048;            // tile rows per image (height <= 32768)
 
 // One projected Gaussian as the blend reads it: 3 x float4 = 48 bytes.
 //   a = (u_hi, v_hi, u_lo, v_lo)   2D centre as a float pair of the double

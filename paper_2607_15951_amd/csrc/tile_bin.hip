@@ -20,7 +20,8 @@
 // after which cursor[x] advances by popcount(M).  Items keep their order
 // inside every bucket, each bucket's run is written front to back, and the
 // work is one compare per (item, bucket) -- no per-pair search or ranking.
-//   count    the same walk, summing popcount(M) per bucket;
+//   count    per chunk, an LDS difference array (+1 at a span's first bucket,
+//            -1 past its last), summed into per-bucket counts;
 //   colscan  per bucket, exclusive prefix over the chunks; bucket totals;
 //   offsets  exclusive scan of the totals (row lists, then tiles);
 //   scatter  the walk with cursors at bucket offset + chunk prefix.
@@ -105,23 +106,49 @@ __device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, I
     return true;
 }
 
+// Exclusive-then-inclusive sum of a difference array diff[0..m) (LDS) by one
+// wave: dst[x] = diff[0] + ... + diff[x], the count of spans covering x.
+__device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, uint32_t* dst, int lane)
+{
+    const int per = (m + 63) / 64;
+    const int b = lane * per, e = (b + per < m) ? b + per : m;
+    uint32_t s = 0;
+    for (int k = b; k < e; ++k) s += diff[k];
+    uint32_t run = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(run, o, 64);
+        if (lane >= o) run += t;
+    }
+    run -= s;
+    for (int k = b; k < e; ++k) {
+        run += diff[k];
+        dst[k] = run;
+    }
+}
+
+// Counting needs no order: each span adds +1 at its first bucket and -1 past
+// its last in an LDS difference array (two atomics per item), summed at the end.
 __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
 {
+    __shared__ uint32_t diff[kMaxRows + 1];
     const int lane = threadIdx.x, c = chunk_of_block();
     uint32_t* dst = a.counts1 + (int64_t)c * a.tiles_y;
-    Items1 it;
-    if (!load_items1(a, c, lane, it)) {
-        for (int r = lane; r < a.tiles_y; r += 64) dst[r] = 0u;
-        return;
-    }
-    for (int r = lane; r < a.tiles_y; r += 64)
-        if (r < it.lo || r >= it.hi) dst[r] = 0u;
-    for (int r = it.lo; r < it.hi; ++r) {
-        uint32_t n = 0;
+    for (int r = lane; r <= a.tiles_y; r += 64) diff[r] = 0u;
+    __syncthreads();
+    const int64_t nv = (int64_t)*a.n_visible;
+    const int64_t start = (int64_t)c * kChunk1;
 #pragma unroll
-        for (int b = 0; b < kItemsL1; ++b) n += (uint32_t)__popcll(__ballot(it.y0[b] <= (uint32_t)r && (uint32_t)r < it.y1[b]));
-        if (lane == 0) dst[r] = n;
+    for (int b = 0; b < kItemsL1; ++b) {
+        const int64_t k = start + b * 64 + lane;
+        if (k < nv) {
+            const ushort4 r = a.rect[a.sorted_idx[k]];
+            atomicAdd(&diff[r.y], 1u);
+            atomicSub(&diff[r.w], 1u);
+        }
     }
+    __syncthreads();
+    counts_from_diff(diff, a.tiles_y, dst, lane);
 }
 
 __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
@@ -194,9 +221,9 @@ struct Items2 {
     int row, lo, hi;   // row, columns spanned by the chunk
 };
 
-__device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, Items2& it)
+// Row and entry range [eb, ee) of level-2 chunk c.
+__device__ __forceinline__ void chunk2_range(const BinArgs& a, int c, int lane, int* row, int64_t* eb, int64_t* ee)
 {
-    if ((uint32_t)c >= a.info[kInfoC2]) return false;
     const int ty_n = a.tiles_y;
     const uint32_t* base = a.info + kInfoRowChunks;
     // owning row: the last r with base[r] <= c (64-ary search over rows; rows
@@ -212,9 +239,17 @@ __device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, I
         R = (nl + step < R) ? nl + step : R;
         L = nl;
     }
-    it.row = L;
-    const int64_t eb = (int64_t)a.rows_off[L] + (int64_t)((uint32_t)c - base[L]) * kChunk2;
-    const int64_t ee = a.rows_off[L + 1];
+    *row = L;
+    *eb = (int64_t)a.rows_off[L] + (int64_t)((uint32_t)c - base[L]) * kChunk2;
+    const int64_t end_row = a.rows_off[L + 1];
+    *ee = (*eb + kChunk2 < end_row) ? *eb + kChunk2 : end_row;
+}
+
+__device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, Items2& it)
+{
+    if ((uint32_t)c >= a.info[kInfoC2]) return false;
+    int64_t eb, ee;
+    chunk2_range(a, c, lane, &it.row, &eb, &ee);
     int lo = 1 << 30, hi = 0;
 #pragma unroll
     for (int b = 0; b < kItemsL2; ++b) {
@@ -237,18 +272,25 @@ __device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, I
 
 __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
 {
+    __shared__ uint32_t diff[kMaxBandTiles + 1];
     const int lane = threadIdx.x, c = chunk_of_block();
-    Items2 it;
-    if (!load_items2(a, c, lane, it)) return;
-    uint32_t* dst = a.counts2 + (int64_t)c * a.tiles_x;
-    for (int x = lane; x < a.tiles_x; x += 64)
-        if (x < it.lo || x >= it.hi) dst[x] = 0u;
-    for (int x = it.lo; x < it.hi; ++x) {
-        uint32_t n = 0;
+    if ((uint32_t)c >= a.info[kInfoC2]) return;
+    int row;
+    int64_t eb, ee;
+    chunk2_range(a, c, lane, &row, &eb, &ee);
+    for (int x = lane; x <= a.tiles_x; x += 64) diff[x] = 0u;
+    __syncthreads();
 #pragma unroll
-        for (int b = 0; b < kItemsL2; ++b) n += (uint32_t)__popcll(__ballot(it.x0[b] <= (uint32_t)x && (uint32_t)x < it.x1[b]));
-        if (lane == 0) dst[x] = n;
+    for (int b = 0; b < kItemsL2; ++b) {
+        const int64_t e = eb + b * 64 + lane;
+        if (e < ee) {
+            const uint32_t xs = a.row_ent[e].y;
+            atomicAdd(&diff[xs & 0xFFFFu], 1u);
+            atomicSub(&diff[xs >> 16], 1u);
+        }
     }
+    __syncthreads();
+    counts_from_diff(diff, a.tiles_x, a.counts2 + (int64_t)c * a.tiles_x, lane);
 }
 
 __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
