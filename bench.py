@@ -160,7 +160,7 @@ def main():
         r.render(dev, cam, W, H, out=out)
     torch.cuda.synchronize()
 
-    r.set_profiling(True)
+    r.set_profiling(stages=True)
     stage_sum = {k: 0.0 for k in gs.STAGES}
     log(f"[bench] timing {args.steps} steps")
     torch.cuda.synchronize()
@@ -173,9 +173,12 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    stats = r.blend_stats()
     info = r.list_info()
-    r.set_profiling(False)
+    # one more render with the work-counting blend (not timed)
+    r.set_profiling(stages=False, blend_work=True)
+    r.render(dev, cam, W, H, out=out)
+    stats = r.blend_stats()
+    r.set_profiling(stages=False)
     stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
     log("[bench] stages ms " + json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
 

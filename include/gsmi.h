@@ -166,10 +166,14 @@ gs_status gs_copy_lists(gs_context* ctx, uint32_t* values, uint32_t* tile_offset
 gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key, int32_t* radius,
                              uint32_t* tiles_touched, uint16_t* rect, void* stream);
 
-/* Stage timing (tracing).  When enabled, gs_render records HIP events on its
- * stream between the stages below; gs_get_stage_times synchronises on them
- * and returns the device time of each stage of the last render, in
- * milliseconds, in this order:
+/* Tracing.  gs_set_profiling takes a set of GS_PROFILE_* flags (0 turns
+ * tracing off) that apply to the following gs_render calls on ctx; an
+ * unknown flag gives GS_ERR_INVALID_ARGUMENT.
+ *
+ * GS_PROFILE_STAGES: gs_render records HIP events on its stream between the
+ * stages below; gs_get_stage_times synchronises on them and returns the
+ * device time of each stage of the last render, in milliseconds, in this
+ * order:
  *   0 project      (one kernel: cull, EWA projection, SH colour)
  *   1 depth_sort   (four LSD radix passes over the N depth keys)
  *   2 bin_row_count     (per-row counts of the depth-sorted Gaussians, row
@@ -179,19 +183,39 @@ gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key
  *   5 bin_tile_scatter  (one kernel: the sorted pair list)
  *   6 blend             (one kernel: per-tile compositing)
  * The host read of the pair count (pair_capacity 0) falls between stages 2
- * and 3 and belongs to neither.  count must be GS_NUM_STAGES. */
-#define GS_NUM_STAGES 7
-
-gs_status gs_set_profiling(gs_context* ctx, int32_t enable);
-
-gs_status gs_get_stage_times(gs_context* ctx, float* ms, int32_t count);
-
-/* Blend work of the last traced render (host array of 3):
+ * and 3 and belongs to neither.  count must be GS_NUM_STAGES; a last render
+ * without this flag gives GS_ERR_INVALID_ARGUMENT.
+ *
+ * GS_PROFILE_BLEND_WORK: the blend runs a variant that counts its work
+ * (a few extra instructions per evaluation and one atomic per wave, so it is
+ * not the variant to time); gs_get_blend_stats returns, for the last render
+ * (host array of 4, GS_ERR_INVALID_ARGUMENT if it was not counted):
  *   [0] (pixel, list entry) evaluations of Eq. 1's term, up to each pixel's
  *       termination -- the work the per-pixel walk of Sec. 4.5 requires
  *   [1] evaluations that passed the 1/255 alpha test and were composited
- *   [2] list entries staged from HBM into LDS (summed over tiles) */
-gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats3);
+ *   [2] list entries staged from HBM into LDS (summed over tiles)
+ *   [3] lane evaluations the kernel executed: 64 per (wave, staged entry)
+ *       that the wave did not skip, whether or not its pixels needed it */
+#define GS_NUM_STAGES 7
+#define GS_PROFILE_STAGES 1
+#define GS_PROFILE_BLEND_WORK 2
+
+gs_status gs_set_profiling(gs_context* ctx, int32_t flags);
+
+gs_status gs_get_stage_times(gs_context* ctx, float* ms, int32_t count);
+
+gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats4);
+
+/* Per-tile blend trace of the last render counted with
+ * GS_PROFILE_BLEND_WORK (host array [tiles][6], tiles = tiles_x * tiles_y of
+ * that render, tile index ty * tiles_x + tx): [0] start and [1] end of the
+ * tile's workgroup on the device's constant 100 MHz clock, [2] list entries
+ * staged, [3] (wave, entry) bodies executed, [4] (pixel, entry) evaluations
+ * up to each pixel's termination, [5] evaluations composited.  Per-tile work
+ * and time are the GPU counterpart of the per-tile min/mean/max timings of
+ * Table 2.  gs_get_blend_stats holds the sums over tiles.
+ * GS_ERR_INVALID_ARGUMENT if the render was not counted or tiles differs. */
+gs_status gs_get_blend_tile_work(gs_context* ctx, uint64_t* work, int64_t tiles);
 
 #ifdef __cplusplus
 }

@@ -18,11 +18,12 @@ LIB_PATH = os.path.join(_PKG, "libgsmi.so")
 
 GS_OK, GS_ERR_INVALID_ARGUMENT, GS_ERR_OUT_OF_MEMORY, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = range(6)
 GS_F32, GS_BF16, GS_F16 = 0, 1, 2
+PROFILE_STAGES, PROFILE_BLEND_WORK = 1, 2
 TILE = 16
 
 EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
             "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
-            "gs_get_blend_stats"]
+            "gs_get_blend_stats", "gs_get_blend_tile_work"]
 STAGES = ["project", "depth_sort", "bin_row_count", "bin_row_scatter", "bin_tile_count", "bin_tile_scatter",
           "blend"]
 
@@ -90,6 +91,8 @@ def load_library(path: str = LIB_PATH):
     L.gs_get_stage_times.restype = C.c_int
     L.gs_get_blend_stats.argtypes = [P, C.POINTER(C.c_uint64)]
     L.gs_get_blend_stats.restype = C.c_int
+    L.gs_get_blend_tile_work.argtypes = [P, C.POINTER(C.c_uint64), C.c_int64]
+    L.gs_get_blend_tile_work.restype = C.c_int
     _lib = L
     return L
 
@@ -208,9 +211,11 @@ class Renderer:
         self._last = (dev, int(g.n))
         return out
 
-    def set_profiling(self, enable: bool):
-        """Record HIP events between render stages (see stage_times)."""
-        self._check(self._L.gs_set_profiling(self._ctx, 1 if enable else 0))
+    def set_profiling(self, stages: bool = True, blend_work: bool = False):
+        """Tracing of the following renders: HIP events between the stages
+        (stage_times) and/or the counting variant of the blend (blend_stats)."""
+        flags = (PROFILE_STAGES if stages else 0) | (PROFILE_BLEND_WORK if blend_work else 0)
+        self._check(self._L.gs_set_profiling(self._ctx, flags))
 
     def stage_times(self) -> dict:
         """Device milliseconds per stage of the last (timed) render."""
@@ -220,9 +225,20 @@ class Renderer:
 
     def blend_stats(self) -> dict:
         """Blend work counters of the last traced render."""
-        v = (C.c_uint64 * 3)()
+        v = (C.c_uint64 * 4)()
         self._check(self._L.gs_get_blend_stats(self._ctx, v))
-        return dict(evaluations=int(v[0]), composited=int(v[1]), staged=int(v[2]))
+        return dict(evaluations=int(v[0]), composited=int(v[1]), staged=int(v[2]), lane_evaluations=int(v[3]))
+
+    def blend_tile_work(self):
+        """Per-tile trace of the last counted render: numpy uint64 [tiles, 6]
+        (start, end on the 100 MHz device clock, entries staged, wave bodies,
+        evaluations, composited)."""
+        import numpy as np
+        info = self.list_info()
+        T = info["tiles_x"] * info["tiles_y"]
+        buf = (C.c_uint64 * (6 * T))()
+        self._check(self._L.gs_get_blend_tile_work(self._ctx, buf, T))
+        return np.frombuffer(buf, dtype=np.uint64).reshape(T, 6).copy()
 
     def list_info(self) -> dict:
         info = gs_list_info()

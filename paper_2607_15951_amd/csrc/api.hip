@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 #include <string>
 
 using namespace gsmi;
@@ -29,13 +30,14 @@ struct gs_context {
     DevBuf splats, depth_key, radius, tiles_touched, rect;
     DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist, scan_scratch;
     DevBuf bin_info, counts1, rows_off, row_ent, counts2, partials;
-    // [0] n_visible, [1] overflow, [4..9] blend stats (3 x u64),
-    // [10..11] K from the projection (u64)
+    // [0] n_visible, [1] overflow, [12..13] K from the projection (u64)
     DevBuf counters;
     DevBuf tile_offsets, values;
+    DevBuf tile_work;   // per-tile blend trace [T][kTileWorkFields] u64 (GS_PROFILE_BLEND_WORK)
     uint32_t* host_info = nullptr;   // pinned readback: band table, then K as u64
-    bool profiling = false;
-    bool timed = false;   // the last render recorded stage events
+    uint32_t profiling = 0;   // GS_PROFILE_* flags
+    bool timed = false;       // the last render recorded stage events
+    bool traced = false;      // the last render counted blend work
     // stage boundaries: 0 start, 1 project, 2 depth sort, 3 bin prepare,
     // 4 count start (after the host read of K), 5 count, 6 offsets,
     // 7 scatter, 8 blend
@@ -129,7 +131,7 @@ gs_status validate(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam,
 // records the boundary event k when stage timing is on
 #define STAGE_MARK(k)                                                               \
     do {                                                                            \
-        if (ctx->profiling) HIP_TRY(hipEventRecord(ctx->ev[(k)], s), "hipEventRecord"); \
+        if (ctx->profiling & GS_PROFILE_STAGES) HIP_TRY(hipEventRecord(ctx->ev[(k)], s), "hipEventRecord"); \
     } while (0)
 
 }  // namespace
@@ -218,11 +220,11 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     if ((st = ensure(ctx, ctx->rows_off, (size_t)(tiles_y + 1) * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->counts1, (size_t)std::max(bin_level1_chunks(n), 1) * tiles_y * 4)) != GS_OK)
         return st;
-    if ((st = ensure(ctx, ctx->counters, 64)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->counters, 128)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
 
     uint32_t* counters = static_cast<uint32_t*>(ctx->counters.p);
-    HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
+    HIP_TRY(launch_fill_u32(counters, 0u, 32, s), "clear counters");
     STAGE_MARK(0);
 
     ProjectArgs pa{};
@@ -253,7 +255,7 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     pa.tiles_touched = static_cast<uint32_t*>(ctx->tiles_touched.p);
     pa.rect = static_cast<ushort4*>(ctx->rect.p);
     pa.n_visible = counters;
-    pa.k_total = reinterpret_cast<unsigned long long*>(counters + 10);
+    pa.k_total = reinterpret_cast<unsigned long long*>(counters + 12);
     pa.partials = static_cast<uint32_t*>(ctx->partials.p);
     HIP_TRY(launch_project(pa, s), "project");
     STAGE_MARK(1);
@@ -301,7 +303,7 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
                 "read chunk count");
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         uint64_t K64;
-        std::memcpy(&K64, ctx->host_info + 10, sizeof K64);
+        std::memcpy(&K64, ctx->host_info + 12, sizeof K64);
         if (K64 > 0xFFFFFFFFull || ctx->host_info[1] != 0u) {
             ctx->have_render = false;
             return fail(ctx, GS_ERR_CAPACITY, "more than 2^32-1 (Gaussian, tile) pairs");
@@ -341,12 +343,18 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     bl.out_rgb = out_rgb;
     bl.out_T = out_final_T;
     bl.out_nc = out_n_contrib;
-    bl.stats = ctx->profiling ? reinterpret_cast<unsigned long long*>(counters + 4) : nullptr;
+    bl.tile_work = nullptr;
+    if (ctx->profiling & GS_PROFILE_BLEND_WORK) {
+        if ((st = ensure(ctx, ctx->tile_work, (size_t)std::max<int64_t>(T, 1) * kTileWorkFields * 8)) != GS_OK)
+            return st;
+        bl.tile_work = static_cast<unsigned long long*>(ctx->tile_work.p);
+    }
     HIP_TRY(launch_blend(bl, capacity, s), "blend");
     STAGE_MARK(8);
 
     ctx->have_render = true;
-    ctx->timed = ctx->profiling;
+    ctx->timed = (ctx->profiling & GS_PROFILE_STAGES) != 0;
+    ctx->traced = bl.tile_work != nullptr;
     ctx->n = n;
     ctx->tiles_x = tiles_x;
     ctx->tiles_y = tiles_y;
@@ -368,7 +376,7 @@ gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out)
             "read R");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     uint64_t K, R = r32;
-    std::memcpy(&K, c + 10, 8);
+    std::memcpy(&K, c + 12, 8);
     out->num_pairs = K;
     out->num_row_entries = R;
     out->tiles_x = ctx->tiles_x;
@@ -417,14 +425,16 @@ gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key
     return GS_OK;
 }
 
-gs_status gs_set_profiling(gs_context* ctx, int32_t enable)
+gs_status gs_set_profiling(gs_context* ctx, int32_t flags)
 {
     if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
-    if (enable && !ctx->ev[0]) {
+    if (flags & ~(GS_PROFILE_STAGES | GS_PROFILE_BLEND_WORK))
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "unknown profiling flag");
+    if ((flags & GS_PROFILE_STAGES) && !ctx->ev[0]) {
         HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
         for (hipEvent_t& e : ctx->ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
     }
-    ctx->profiling = enable != 0;
+    ctx->profiling = (uint32_t)flags;
     return GS_OK;
 }
 
@@ -442,17 +452,52 @@ gs_status gs_get_stage_times(gs_context* ctx, float* ms, int32_t count)
     return GS_OK;
 }
 
-gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats3)
+namespace {
+gs_status read_tile_work(gs_context* ctx, std::vector<uint64_t>& w)
 {
-    if (!ctx || !stats3) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
-    if (!ctx->have_render || !ctx->timed)
-        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render was not traced (gs_set_profiling)");
-    // stats live at counters[4..9]
+    if (!ctx->have_render || !ctx->traced)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render did not count blend work (GS_PROFILE_BLEND_WORK)");
+    const size_t T = (size_t)ctx->tiles_x * ctx->tiles_y;
+    w.assign(T * kTileWorkFields, 0);
+    if (T == 0) return GS_OK;
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-    HIP_TRY(hipMemcpyAsync(stats3, static_cast<uint32_t*>(ctx->counters.p) + 4, 3 * sizeof(uint64_t),
-                           hipMemcpyDeviceToHost, ctx->stream),
-            "read stats");
+    HIP_TRY(hipMemcpyAsync(w.data(), ctx->tile_work.p, T * kTileWorkFields * 8, hipMemcpyDeviceToHost, ctx->stream),
+            "read tile work");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return GS_OK;
+}
+}  // namespace
+
+gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats4)
+{
+    if (!ctx || !stats4) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    std::vector<uint64_t> w;
+    gs_status st = read_tile_work(ctx, w);
+    if (st != GS_OK) return st;
+    uint64_t ev = 0, co = 0, staged = 0, bodies = 0;
+    for (size_t t = 0; t * kTileWorkFields < w.size(); ++t) {
+        const uint64_t* r = w.data() + t * kTileWorkFields;
+        staged += r[2];
+        bodies += r[3];
+        ev += r[4];
+        co += r[5];
+    }
+    stats4[0] = ev;
+    stats4[1] = co;
+    stats4[2] = staged;
+    stats4[3] = 64 * bodies;
+    return GS_OK;
+}
+
+gs_status gs_get_blend_tile_work(gs_context* ctx, uint64_t* work, int64_t tiles)
+{
+    if (!ctx || !work) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (!ctx->have_render || tiles != (int64_t)ctx->tiles_x * ctx->tiles_y)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "tiles must be tiles_x * tiles_y of the last render");
+    std::vector<uint64_t> w;
+    gs_status st = read_tile_work(ctx, w);
+    if (st != GS_OK) return st;
+    std::memcpy(work, w.data(), w.size() * sizeof(uint64_t));
     return GS_OK;
 }
 

@@ -65,6 +65,9 @@ __device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, 
     return q - 1e-5f * (S + 1.0f);
 }
 
+// kStats: the tracing variant, which also records its work per tile
+// (a.tile_work)
+template <bool kStats>
 __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capacity)
 {
     __shared__ float4 s0[256 + kUnroll];   // du_hi, dv_hi, du_lo, dv_lo  (centre - tile origin)
@@ -78,6 +81,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     if (tile >= T) return;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t t_start = kStats ? wall_clock64() : 0ull;
     // each wave owns one 8x8 quad of the tile
     const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
     const int px = tx * kTile + lx, py = ty * kTile + ly;
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     float Tr = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-    uint32_t last = 0, term = 0, composited = 0, staged = 0;
+    uint32_t last = 0, term = 0, composited = 0, staged = 0, bodies = 0;
     bool done = !inside;
     // software pipeline of the gathers: list values two batches ahead, the
     // 48-byte records one batch ahead, both overlapping the compositing
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
         // order-preserving compaction of the kept entries
         const uint64_t km = __ballot(keep);
         if (lane == 0) s_wave_keep[wave] = (uint32_t)__popcll(km);
-        staged += (end - b0 < 256) ? (uint32_t)(end - b0) : 256u;
+        if (kStats) staged += (end - b0 < 256) ? (uint32_t)(end - b0) : 256u;
         __syncthreads();
         uint32_t slot = (uint32_t)__popcll(km & lt);
         for (int w = 0; w < wave; ++w) slot += s_wave_keep[w];
@@ -165,6 +169,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
                 // an entry out of this quad's reach is skipped by the whole wave
                 const uint32_t qm = __builtin_amdgcn_readfirstlane(s_mask[j]);
                 if (!((qm >> wave) & 1u)) continue;
+                if (kStats) ++bodies;
                 const float4 e0 = s0[j];
                 const float4 e1 = s1[j];
                 const float4 e2 = s2[j];
@@ -177,7 +182,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
                 const bool stop = pass && tn < 1e-4f && !done;
                 const bool take = pass && !stop && !done;
                 const uint32_t pos = (uint32_t)__float_as_int(e2.w);
-                term = stop ? pos + 1u : term;
+                if (kStats) term = stop ? pos + 1u : term;
                 done = done || stop;
                 const float wgt = take ? al * Tr : 0.0f;
                 c0 = fmaf(wgt, e2.x, c0);
@@ -185,11 +190,11 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
                 c2 = fmaf(wgt, e2.z, c2);
                 Tr = take ? tn : Tr;
                 last = take ? pos + 1u : last;
-                composited += take ? 1u : 0u;
+                if (kStats) composited += take ? 1u : 0u;
             }
         }
     }
-    if (a.stats) {   // tracing only: one atomic per wave
+    if (kStats) {   // tracing only: one record per tile, no shared counters
         // a pixel examines its tile's list up to its terminating entry
         const uint32_t list_len = (uint32_t)(end - start);
         unsigned long long ev = inside ? (term ? term : list_len) : 0u, co = composited;
@@ -197,11 +202,23 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
             ev += __shfl_xor(ev, o, 64);
             co += __shfl_xor(co, o, 64);
         }
+        __shared__ unsigned long long s_ev[4], s_co[4];
+        __shared__ uint32_t s_bodies[4];
         if (lane == 0) {
-            atomicAdd(&a.stats[0], ev);
-            atomicAdd(&a.stats[1], co);
+            s_ev[wave] = ev;
+            s_co[wave] = co;
+            s_bodies[wave] = bodies;
         }
-        if (tid == 0) atomicAdd(&a.stats[2], (unsigned long long)staged);
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long* w = a.tile_work + kTileWorkFields * (int64_t)tile;
+            w[0] = t_start;
+            w[1] = wall_clock64();
+            w[2] = staged;
+            w[3] = (unsigned long long)s_bodies[0] + s_bodies[1] + s_bodies[2] + s_bodies[3];
+            w[4] = s_ev[0] + s_ev[1] + s_ev[2] + s_ev[3];
+            w[5] = s_co[0] + s_co[1] + s_co[2] + s_co[3];
+        }
     }
     if (!inside) return;
     const int64_t P = (int64_t)a.width * a.height;
@@ -236,7 +253,8 @@ hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s)
 {
     const int T = a.tiles_x * a.tiles_y;
     const int blocks = 8 * ((T + 7) / 8);
-    hipLaunchKernelGGL(blend_kernel, dim3(blocks), dim3(256), 0, s, a, capacity);
+    if (a.tile_work) hipLaunchKernelGGL(blend_kernel<true>, dim3(blocks), dim3(256), 0, s, a, capacity);
+    else hipLaunchKernelGGL(blend_kernel<false>, dim3(blocks), dim3(256), 0, s, a, capacity);
     return hipGetLastError();
 }
 

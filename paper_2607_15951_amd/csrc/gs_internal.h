@@ -17,6 +17,7 @@ constexpr int kSortItems = 8;             // keys per thread per depth-sort bloc
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kItemsL1 = 8;               // depth-sorted Gaussians per lane of a level-1 binning wave
 constexpr int kItemsL2 = 16;              // row entries per lane of a level-2 binning wave
+constexpr int kTileWorkFields = 6;        // u64 fields of a per-tile blend trace record
 constexpr int kMaxRows = 2048;            // tile rows per image (height <= 32768)
 
 // One projected Gaussian as the blend reads it: 3 x float4 = 48 bytes.
@@ -104,10 +105,11 @@ struct BlendArgs {
     float* out_rgb;
     float* out_T;        // may be null
     uint32_t* out_nc;    // may be null
-    // work counters when tracing (else null): [0] (pixel, entry) evaluations,
-    // [1] entries that passed the alpha test and were composited, [2] list
-    // entries staged into LDS
-    unsigned long long* stats;
+    // per-tile trace when tracing (else null), [T][kTileWorkFields]: start
+    // and end of the tile's workgroup (s_memrealtime, 100 MHz), entries
+    // staged, wave bodies, (pixel, entry) evaluations up to each pixel's
+    // termination, evaluations composited
+    unsigned long long* tile_work;
 };
 
 hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s);

@@ -215,3 +215,39 @@ def test_permutation_and_repeat_determinism(renderer):
     g2 = gpu_render(renderer, sc, cam)
     for k in ("image", "final_T", "n_contrib", "values", "keys"):
         np.testing.assert_array_equal(g1[k], g2[k])
+
+
+def test_traced_render_is_identical_and_consistent(renderer):
+    """The work-counting blend variant renders the same image as the timed one,
+    and its per-tile records are consistent with the lists and each other."""
+    import torch
+    import paper_2607_15951_amd as gs
+    sc = scenes.make_scene("C2", n=20_000, seed=71)
+    cam = scenes.default_camera(300, 200)
+    g0 = gpu_render(renderer, sc, cam)
+    renderer.set_profiling(stages=True, blend_work=True)
+    try:
+        g1 = gpu_render(renderer, sc, cam)
+        stats = renderer.blend_stats()
+        tw = renderer.blend_tile_work().astype(np.int64)
+        st = renderer.stage_times()
+    finally:
+        renderer.set_profiling(stages=False)
+    for k in ("image", "final_T", "n_contrib", "values"):
+        np.testing.assert_array_equal(g0[k], g1[k])
+    T = ((300 + 15) // 16) * ((200 + 15) // 16)
+    assert tw.shape == (T, 6)
+    lens = np.diff(g1["tile_offsets"].astype(np.int64))
+    assert (tw[:, 1] >= tw[:, 0]).all()
+    assert (tw[:, 2] <= lens).all() and (tw[:, 5] <= tw[:, 4]).all()
+    assert stats["staged"] == tw[:, 2].sum() and stats["lane_evaluations"] == 64 * tw[:, 3].sum()
+    assert stats["evaluations"] == tw[:, 4].sum() and stats["composited"] == tw[:, 5].sum()
+    # every composited evaluation is one a wave executed
+    assert stats["composited"] <= stats["lane_evaluations"]
+    # a pixel's last contributor was composited: n_contrib > 0 implies one composite
+    assert stats["composited"] >= int((g1["n_contrib"] > 0).sum())
+    assert all(v >= 0 for v in st.values())
+    # a render without the flag is not counted
+    gpu_render(renderer, sc, cam)
+    with pytest.raises(gs.GsError):
+        renderer.blend_stats()
