@@ -23,9 +23,14 @@
 // MFMA: there is no dense contraction in this loop.
 //
 // Workgroup -> tile mapping is XCD-aware: the dispatcher deals consecutive
-// workgroups round-robin to the 8 XCDs, so block b takes tile
-// (b % 8) * ceil(T/8) + b / 8 and each XCD's L2 serves a contiguous band of
-// tiles whose lists share Gaussians.
+// workgroups round-robin to the 8 XCDs, so block b runs on XCD b % 8.  Tiles
+// are cut into groups of kGroup consecutive tiles (row-major), dealt to the XCDs
+// in turn: XCD x takes groups x, x + 8, x + 16, ... in screen order.  Each
+// group's tiles share Gaussians in one L2, and every XCD gets an even share of
+// every part of the screen: blend work per tile varies by an order of
+// magnitude between the dense centre and sparse edges (tiles that never
+// saturate walk their whole list), and contiguous bands per XCD would leave
+// the XCDs with the heavy bands running long after the others finish.
 #include "gs_internal.h"
 
 namespace gsmi {
@@ -33,6 +38,7 @@ namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kUnroll = 8;
+constexpr int kGroup = 16;   // consecutive tiles one XCD takes in turn
 
 // Smallest value of the quadratic form A x^2 + 2 B x y + C y^2 (positive
 // definite) over the box [x0, x0 + 7] x [y0, y0 + 7] of pixel offsets, made a
@@ -76,11 +82,12 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     __shared__ uint32_t s_mask[256 + kUnroll];   // quads (waves) the entry can reach
     __shared__ uint32_t s_wave_keep[4];
     const int T = a.tiles_x * a.tiles_y;
-    const int per_xcd = (T + 7) / 8;
-    const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    const int i = (int)(blockIdx.x >> 3);
+    const int tile = ((i / kGroup) * 8 + (int)(blockIdx.x & 7)) * kGroup + i % kGroup;
     if (tile >= T) return;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wave index is uniform: readfirstlane lets the compiler keep it scalar
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t t_start = kStats ? wall_clock64() : 0ull;
     // each wave owns one 8x8 quad of the tile
     const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
@@ -252,7 +259,7 @@ __global__ __launch_bounds__(256) void write_keys_kernel(const uint32_t* __restr
 hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s)
 {
     const int T = a.tiles_x * a.tiles_y;
-    const int blocks = 8 * ((T + 7) / 8);
+    const int blocks = 8 * kGroup * ((T + 8 * kGroup - 1) / (8 * kGroup));
     if (a.tile_work) hipLaunchKernelGGL(blend_kernel<true>, dim3(blocks), dim3(256), 0, s, a, capacity);
     else hipLaunchKernelGGL(blend_kernel<false>, dim3(blocks), dim3(256), 0, s, a, capacity);
     return hipGetLastError();
