@@ -75,7 +75,8 @@ __device__ __forceinline__ int wave_max(int v)
 // items: depth-sorted Gaussians; buckets: tile rows; payload (index, x-span)
 
 struct Items1 {
-    uint32_t y0[kItemsL1], y1[kItemsL1], xs[kItemsL1], g[kItemsL1];
+    // rows [y0, y0 + h) covered; h = 0 for padding lanes
+    uint32_t y0[kItemsL1], h[kItemsL1], xs[kItemsL1], g[kItemsL1];
     int lo, hi;   // rows spanned by the chunk
 };
 
@@ -97,7 +98,7 @@ __device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, I
             hi = (int)r.w > hi ? (int)r.w : hi;
         }
         it.y0[b] = r.y;
-        it.y1[b] = r.w;
+        it.h[b] = (uint32_t)r.w - (uint32_t)r.y;
         it.xs[b] = (uint32_t)r.x | ((uint32_t)r.z << 16);
         it.g[b] = g;
     }
@@ -151,24 +152,67 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
     counts_from_diff(diff, a.tiles_y, dst, lane);
 }
 
+// Cursor windows: bucket cursors are loaded 128 at a time into two VGPRs
+// (lane l holds buckets w0 + l and w0 + 64 + l) and read back as scalars, so
+// a bucket's walk starts without a dependent memory load.
+constexpr int kWindow = 128;
+
+// The walk of one bucket: for each batch of 64 items, covering lanes write
+// their payload at cur + (covering lanes below them).  The base pointer and
+// cursor are wave-uniform (scalar registers).  A bucket whose run cannot pass
+// the capacity (cur + every item of the chunk) takes the walk without the
+// per-lane bound test.
+template <bool kChecked, int kItems, typename P>
+__device__ __forceinline__ void walk_run(uint32_t bucket, uint32_t cur, const uint32_t (&first)[kItems],
+                                         const uint32_t (&span)[kItems], const P (&payload)[kItems],
+                                         P* __restrict__ out, uint64_t capacity)
+{
+    P* base = out + cur;
+#pragma unroll
+    for (int b = 0; b < kItems; ++b) {
+        const bool cover = bucket - first[b] < span[b];
+        const uint64_t m = __ballot(cover);
+        if (cover) {
+            const uint32_t below = lanes_below(m);
+            if (!kChecked || (uint64_t)cur + below < capacity) base[below] = payload[b];
+        }
+        const uint32_t n = (uint32_t)__popcll(m);
+        cur += n;
+        base += n;
+    }
+}
+
+template <int kItems, typename P>
+__device__ __forceinline__ void walk_bucket(uint32_t bucket, uint32_t cur, const uint32_t (&first)[kItems],
+                                            const uint32_t (&span)[kItems], const P (&payload)[kItems],
+                                            P* __restrict__ out, uint64_t capacity)
+{
+    if ((uint64_t)cur + kItems * 64 <= capacity)
+        walk_run<false>(bucket, cur, first, span, payload, out, capacity);
+    else
+        walk_run<true>(bucket, cur, first, span, payload, out, capacity);
+}
+
 __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
 {
     const int lane = threadIdx.x, c = chunk_of_block();
     Items1 it;
     if (!load_items1(a, c, lane, it)) return;
     const uint32_t* prefix = a.counts1 + (int64_t)c * a.tiles_y;
-    for (int r = it.lo; r < it.hi; ++r) {
-        uint32_t cur = a.rows_off[r] + prefix[r];
+    uint2 payload[kItemsL1];
 #pragma unroll
-        for (int b = 0; b < kItemsL1; ++b) {
-            const bool cover = it.y0[b] <= (uint32_t)r && (uint32_t)r < it.y1[b];
-            const uint64_t m = __ballot(cover);
-            if (cover) {
-                const uint64_t pos = (uint64_t)cur + lanes_below(m);
-                if (pos < a.row_capacity) a.row_ent[pos] = make_uint2(it.g[b], it.xs[b]);
-            }
-            cur += (uint32_t)__popcll(m);
-        }
+    for (int b = 0; b < kItemsL1; ++b) payload[b] = make_uint2(it.g[b], it.xs[b]);
+    for (int w0 = it.lo; w0 < it.hi; w0 += kWindow) {
+        const int ra = w0 + lane, rb = w0 + 64 + lane;
+        const uint32_t cur_a = ra < it.hi ? a.rows_off[ra] + prefix[ra] : 0u;
+        const uint32_t cur_b = rb < it.hi ? a.rows_off[rb] + prefix[rb] : 0u;
+        const int e0 = min(it.hi, w0 + 64), e1 = min(it.hi, w0 + kWindow);
+        for (int r = w0; r < e0; ++r)
+            walk_bucket<kItemsL1>((uint32_t)r, __builtin_amdgcn_readlane(cur_a, r - w0), it.y0, it.h, payload,
+                                  a.row_ent, a.row_capacity);
+        for (int r = w0 + 64; r < e1; ++r)
+            walk_bucket<kItemsL1>((uint32_t)r, __builtin_amdgcn_readlane(cur_b, r - w0 - 64), it.y0, it.h, payload,
+                                  a.row_ent, a.row_capacity);
     }
 }
 
@@ -217,7 +261,8 @@ __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
 // items: one row's entries; buckets: that row's tile columns; payload: index
 
 struct Items2 {
-    uint32_t x0[kItemsL2], x1[kItemsL2], g[kItemsL2];
+    // columns [x0, x0 + w) covered; w = 0 for padding lanes
+    uint32_t x0[kItemsL2], w[kItemsL2], g[kItemsL2];
     int row, lo, hi;   // row, columns spanned by the chunk
 };
 
@@ -262,7 +307,7 @@ __device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, I
             hi = x1 > hi ? x1 : hi;
         }
         it.x0[b] = ent.y & 0xFFFFu;
-        it.x1[b] = ent.y >> 16;
+        it.w[b] = (ent.y >> 16) - (ent.y & 0xFFFFu);
         it.g[b] = ent.x;
     }
     it.lo = wave_min(lo);
@@ -300,18 +345,17 @@ __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
     if (!load_items2(a, c, lane, it)) return;
     const uint32_t* prefix = a.counts2 + (int64_t)c * a.tiles_x;
     const uint32_t* toff = a.tile_offsets + (int64_t)it.row * a.tiles_x;
-    for (int x = it.lo; x < it.hi; ++x) {
-        uint32_t cur = toff[x] + prefix[x];
-#pragma unroll
-        for (int b = 0; b < kItemsL2; ++b) {
-            const bool cover = it.x0[b] <= (uint32_t)x && (uint32_t)x < it.x1[b];
-            const uint64_t m = __ballot(cover);
-            if (cover) {
-                const uint64_t pos = (uint64_t)cur + lanes_below(m);
-                if (pos < a.capacity) a.values[pos] = it.g[b];
-            }
-            cur += (uint32_t)__popcll(m);
-        }
+    for (int w0 = it.lo; w0 < it.hi; w0 += kWindow) {
+        const int xa = w0 + lane, xb = w0 + 64 + lane;
+        const uint32_t cur_a = xa < it.hi ? toff[xa] + prefix[xa] : 0u;
+        const uint32_t cur_b = xb < it.hi ? toff[xb] + prefix[xb] : 0u;
+        const int e0 = min(it.hi, w0 + 64), e1 = min(it.hi, w0 + kWindow);
+        for (int x = w0; x < e0; ++x)
+            walk_bucket<kItemsL2>((uint32_t)x, __builtin_amdgcn_readlane(cur_a, x - w0), it.x0, it.w, it.g, a.values,
+                                  a.capacity);
+        for (int x = w0 + 64; x < e1; ++x)
+            walk_bucket<kItemsL2>((uint32_t)x, __builtin_amdgcn_readlane(cur_b, x - w0 - 64), it.x0, it.w, it.g,
+                                  a.values, a.capacity);
     }
 }
 
