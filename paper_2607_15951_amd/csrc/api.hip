@@ -266,6 +266,7 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     ba.n = n;
     ba.tiles_x = tiles_x;
     ba.tiles_y = tiles_y;
+    ba.chunks1 = bin_level1_chunks(n);
     ba.info = static_cast<uint32_t*>(ctx->bin_info.p);
     ba.counts1 = static_cast<uint32_t*>(ctx->counts1.p);
     ba.rows_off = static_cast<uint32_t*>(ctx->rows_off.p);
@@ -276,10 +277,15 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     // (row entries <= pairs); else the host reads K, R and the chunk count once
     ba.row_capacity = capacity ? capacity : ~0ull;
     ba.max_chunks2 = capacity ? bin_level2_chunk_bound(capacity, tiles_y) : (1 << 30);
-    const size_t scan0 = scan_scratch_elems(std::max<int64_t>(std::max<int64_t>(n, T),
-                                                              (int64_t)depth_sort_hist_elems(n)));
+    // scan lengths: depth-sort digit counts, level-1 counts, tile offsets, and
+    // (pair_capacity > 0) the bound on the level-2 counts; the eager path
+    // grows the scratch for the level-2 counts after its host read
+    int64_t scan_max = std::max<int64_t>({T + 1, (int64_t)depth_sort_hist_elems(n),
+                                          (int64_t)tiles_y * std::max(ba.chunks1, 1)});
+    if (capacity) scan_max = std::max<int64_t>(scan_max, (int64_t)ba.max_chunks2 * tiles_x);
+    const size_t scan0 = scan_scratch_elems(scan_max);
     if ((st = ensure(ctx, ctx->scan_scratch, scan0 * 8)) != GS_OK) return st;
-    uint64_t* scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
+    uint64_t* scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);   // re-read after growth below
     int in_b = 1;
     HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
                               static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
@@ -314,6 +320,11 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
         ba.max_chunks2 = grid2;
     }
     ba.capacity = capacity;
+    // the device is idle here in eager mode (host read above), so growing the
+    // scan scratch cannot pull memory from under a queued kernel
+    if ((st = ensure(ctx, ctx->scan_scratch, scan_scratch_elems((int64_t)std::max(grid2, 1) * tiles_x) * 8)) != GS_OK)
+        return st;
+    scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
     const size_t rows_cap = (size_t)std::max<uint64_t>(ba.row_capacity, 1);
     if ((st = ensure(ctx, ctx->row_ent, rows_cap * 8)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->counts2, (size_t)std::max(grid2, 1) * tiles_x * 4)) != GS_OK) return st;

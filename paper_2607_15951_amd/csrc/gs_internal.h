@@ -67,12 +67,13 @@ struct BinArgs {
     const ushort4* rect;          // [n] tile rectangle by Gaussian index
     int64_t n;
     int tiles_x, tiles_y;
+    int chunks1;                  // level-1 chunks, bin_level1_chunks(n)
     uint32_t* info;               // level-2 chunk table (bin_info_elems(tiles_y))
-    uint32_t* counts1;            // [level-1 chunks][tiles_y] -> prefix over chunks
+    uint32_t* counts1;            // [tiles_y][chunks1] counts -> exclusive scan = cursors
     uint32_t* rows_off;           // [tiles_y + 1] row-list offsets; [tiles_y] = R
     uint2* row_ent;               // [row_capacity] (Gaussian, x0 | x1 << 16)
     uint64_t row_capacity;
-    uint32_t* counts2;            // [max_chunks2][tiles_x] -> prefix over chunks
+    uint32_t* counts2;            // per row: [tiles_x][row's chunks] counts -> scan = cursors
     uint32_t* tile_offsets;       // [tiles + 1]; [tiles] = K
     uint32_t* values;             // [capacity] sorted pair values
     uint64_t capacity;

@@ -21,10 +21,12 @@
 // inside every bucket, each bucket's run is written front to back, and the
 // work is one compare per (item, bucket) -- no per-pair search or ranking.
 //   count    per chunk, an LDS difference array (+1 at a span's first bucket,
-//            -1 past its last), summed into per-bucket counts;
-//   colscan  per bucket, exclusive prefix over the chunks; bucket totals;
-//   offsets  exclusive scan of the totals (row lists, then tiles);
-//   scatter  the walk with cursors at bucket offset + chunk prefix.
+//            -1 past its last), summed into per-bucket counts, stored
+//            bucket-major: count[bucket][chunk];
+//   scan     one device-wide exclusive scan of that array: entry
+//            [bucket][chunk] becomes the chunk's cursor in the bucket, i.e.
+//            the bucket's list offset plus the items of earlier chunks;
+//   scatter  the walk from those cursors.
 #include "gs_internal.h"
 
 namespace gsmi {
@@ -33,10 +35,13 @@ namespace {
 constexpr int kChunk1 = kItemsL1 * 64;   // Gaussians per level-1 wave
 constexpr int kChunk2 = kItemsL2 * 64;   // row entries per level-2 wave
 
-// info[] layout (uint32): [0] level-2 chunks, [1..tiles_y+1] level-2 chunk
-// prefix at each row start.
+// info[] layout (uint32): [0] level-2 chunks C2, [1] C2 * tiles_x (length of
+// the level-2 count array), [2 .. tiles_y + 2] level-2 chunk prefix at each
+// row start.  Row r's level-2 counts occupy [prefix[r] * tiles_x,
+// prefix[r + 1] * tiles_x), column-major: count[x * chunks(r) + j].
 constexpr int kInfoC2 = 0;
-constexpr int kInfoRowChunks = 1;
+constexpr int kInfoC2Elems = 1;
+constexpr int kInfoRowChunks = 2;
 
 // Workgroup b -> chunk: the dispatcher deals workgroups round-robin to the 8
 // XCDs; block b takes chunk (b % 8) * ceil(grid / 8) + b / 8 so each XCD works
@@ -108,8 +113,9 @@ __device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, I
 }
 
 // Exclusive-then-inclusive sum of a difference array diff[0..m) (LDS) by one
-// wave: dst[x] = diff[0] + ... + diff[x], the count of spans covering x.
-__device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, uint32_t* dst, int lane)
+// wave: dst[x * stride] = diff[0] + ... + diff[x], the count of spans covering x.
+__device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, uint32_t* dst, int64_t stride,
+                                                 int lane)
 {
     const int per = (m + 63) / 64;
     const int b = lane * per, e = (b + per < m) ? b + per : m;
@@ -124,7 +130,7 @@ __device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, ui
     run -= s;
     for (int k = b; k < e; ++k) {
         run += diff[k];
-        dst[k] = run;
+        dst[k * stride] = run;
     }
 }
 
@@ -134,7 +140,7 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
 {
     __shared__ uint32_t diff[kMaxRows + 1];
     const int lane = threadIdx.x, c = chunk_of_block();
-    uint32_t* dst = a.counts1 + (int64_t)c * a.tiles_y;
+    if (c >= a.chunks1) return;
     for (int r = lane; r <= a.tiles_y; r += 64) diff[r] = 0u;
     __syncthreads();
     const int64_t nv = (int64_t)*a.n_visible;
@@ -149,7 +155,7 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
         }
     }
     __syncthreads();
-    counts_from_diff(diff, a.tiles_y, dst, lane);
+    counts_from_diff(diff, a.tiles_y, a.counts1 + c, a.chunks1, lane);
 }
 
 // Cursor windows: bucket cursors are loaded 128 at a time into two VGPRs
@@ -198,14 +204,14 @@ __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
     const int lane = threadIdx.x, c = chunk_of_block();
     Items1 it;
     if (!load_items1(a, c, lane, it)) return;
-    const uint32_t* prefix = a.counts1 + (int64_t)c * a.tiles_y;
+    const uint32_t* cursor = a.counts1 + c;   // row r: cursor[r * chunks1]
     uint2 payload[kItemsL1];
 #pragma unroll
     for (int b = 0; b < kItemsL1; ++b) payload[b] = make_uint2(it.g[b], it.xs[b]);
     for (int w0 = it.lo; w0 < it.hi; w0 += kWindow) {
         const int ra = w0 + lane, rb = w0 + 64 + lane;
-        const uint32_t cur_a = ra < it.hi ? a.rows_off[ra] + prefix[ra] : 0u;
-        const uint32_t cur_b = rb < it.hi ? a.rows_off[rb] + prefix[rb] : 0u;
+        const uint32_t cur_a = ra < it.hi ? cursor[(int64_t)ra * a.chunks1] : 0u;
+        const uint32_t cur_b = rb < it.hi ? cursor[(int64_t)rb * a.chunks1] : 0u;
         const int e0 = min(it.hi, w0 + 64), e1 = min(it.hi, w0 + kWindow);
         for (int r = w0; r < e0; ++r)
             walk_bucket<kItemsL1>((uint32_t)r, __builtin_amdgcn_readlane(cur_a, r - w0), it.y0, it.h, payload,
@@ -216,12 +222,20 @@ __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
     }
 }
 
-// Level-2 chunk table: row r owns ceil(len_r / kChunk2) chunks; info holds
-// their prefix (one 1024-thread block, two rows per thread).
+// Row offsets and the level-2 chunk table (one 1024-thread block, two rows
+// per thread).  The scanned level-1 counts give rows_off[r] (chunk 0's cursor
+// in row r); row r owns ceil(len_r / kChunk2) level-2 chunks, and info holds
+// their prefix.  On overflow every row gets zero chunks.
 __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
 {
     __shared__ uint32_t part[1024];
+    __shared__ uint32_t s_total;
     const int tid = threadIdx.x, ty_n = a.tiles_y;
+    for (int k = 0; k < 2; ++k) {
+        const int r = 2 * tid + k;
+        if (r < ty_n) a.rows_off[r] = a.counts1[(int64_t)r * a.chunks1];
+    }
+    __syncthreads();   // rows_off[ty_n] (= R) was written by the scan
     uint32_t c[2] = {0u, 0u};
     for (int k = 0; k < 2; ++k) {
         const int r = 2 * tid + k;
@@ -238,22 +252,27 @@ __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
         part[tid] += t;
         __syncthreads();
     }
-    uint32_t run = part[tid] - (c[0] + c[1]);
-    uint32_t* base = a.info + kInfoRowChunks;
-    for (int k = 0; k < 2; ++k) {
-        const int r = 2 * tid + k;
-        if (r < ty_n) base[r] = run;
-        run += c[k];
-    }
     if (tid == 1023) {
         uint32_t total = part[1023];
-        // rows_off[ty_n] is the number of row entries R
         if ((int64_t)total > (int64_t)a.max_chunks2 || (uint64_t)a.rows_off[ty_n] > a.row_capacity) {
             *a.overflow = 1u;
             total = 0;
         }
+        s_total = total;
+    }
+    __syncthreads();
+    const uint32_t total = s_total;
+    uint32_t run = total ? part[tid] - (c[0] + c[1]) : 0u;
+    uint32_t* base = a.info + kInfoRowChunks;
+    for (int k = 0; k < 2; ++k) {
+        const int r = 2 * tid + k;
+        if (r < ty_n) base[r] = run;
+        if (total) run += c[k];
+    }
+    if (tid == 0) {
         base[ty_n] = total;
         a.info[kInfoC2] = total;
+        a.info[kInfoC2Elems] = total * (uint32_t)a.tiles_x;
     }
 }
 
@@ -264,7 +283,19 @@ struct Items2 {
     // columns [x0, x0 + w) covered; w = 0 for padding lanes
     uint32_t x0[kItemsL2], w[kItemsL2], g[kItemsL2];
     int row, lo, hi;   // row, columns spanned by the chunk
+    const uint32_t* cursor;   // column x's cursor at cursor[x * stride]
+    int64_t stride;           // the row's level-2 chunks
 };
+
+// Start of chunk c's cursors in the scanned level-2 counts: row r's block
+// starts at prefix[r] * tiles_x, column x at x * chunks(r), chunk c at
+// c - prefix[r].
+__device__ __forceinline__ const uint32_t* level2_slot(const BinArgs& a, int row, int c, int64_t* stride)
+{
+    const uint32_t* base = a.info + kInfoRowChunks;
+    *stride = (int64_t)(base[row + 1] - base[row]);
+    return a.counts2 + (int64_t)base[row] * a.tiles_x + (c - (int64_t)base[row]);
+}
 
 // Row and entry range [eb, ee) of level-2 chunk c.
 __device__ __forceinline__ void chunk2_range(const BinArgs& a, int c, int lane, int* row, int64_t* eb, int64_t* ee)
@@ -312,6 +343,7 @@ __device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, I
     }
     it.lo = wave_min(lo);
     it.hi = wave_max(hi);
+    it.cursor = level2_slot(a, it.row, c, &it.stride);
     return true;
 }
 
@@ -335,7 +367,9 @@ __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
         }
     }
     __syncthreads();
-    counts_from_diff(diff, a.tiles_x, a.counts2 + (int64_t)c * a.tiles_x, lane);
+    int64_t stride;
+    uint32_t* dst = const_cast<uint32_t*>(level2_slot(a, row, c, &stride));
+    counts_from_diff(diff, a.tiles_x, dst, stride, lane);
 }
 
 __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
@@ -343,12 +377,10 @@ __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
     const int lane = threadIdx.x, c = chunk_of_block();
     Items2 it;
     if (!load_items2(a, c, lane, it)) return;
-    const uint32_t* prefix = a.counts2 + (int64_t)c * a.tiles_x;
-    const uint32_t* toff = a.tile_offsets + (int64_t)it.row * a.tiles_x;
     for (int w0 = it.lo; w0 < it.hi; w0 += kWindow) {
         const int xa = w0 + lane, xb = w0 + 64 + lane;
-        const uint32_t cur_a = xa < it.hi ? toff[xa] + prefix[xa] : 0u;
-        const uint32_t cur_b = xb < it.hi ? toff[xb] + prefix[xb] : 0u;
+        const uint32_t cur_a = xa < it.hi ? it.cursor[xa * it.stride] : 0u;
+        const uint32_t cur_b = xb < it.hi ? it.cursor[xb * it.stride] : 0u;
         const int e0 = min(it.hi, w0 + 64), e1 = min(it.hi, w0 + kWindow);
         for (int x = w0; x < e0; ++x)
             walk_bucket<kItemsL2>((uint32_t)x, __builtin_amdgcn_readlane(cur_a, x - w0), it.x0, it.w, it.g, a.values,
@@ -359,44 +391,24 @@ __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
     }
 }
 
-// counts[chunk][col] -> exclusive prefix over each segment's chunks (in
-// place); segment totals -> totals[seg * ncols + col].  Segment s owns chunks
-// [seg_chunks[s], seg_chunks[s+1]), or [0, nchunks) when seg_chunks is null.
-// Block = (segment, 64 columns) x 16 chunk ranges.
-__global__ __launch_bounds__(1024) void colscan_kernel(uint32_t* __restrict__ counts, int ncols,
-                                                       const uint32_t* __restrict__ seg_chunks, int nchunks,
-                                                       int col_groups, uint32_t* __restrict__ totals)
+// Tile offsets from the scanned level-2 counts: tile (r, x) starts at chunk
+// 0's cursor in column x of row r.  A row without chunks starts where the
+// next row's block starts (the scan's running total there), or at the total
+// K when it is the last.
+__global__ __launch_bounds__(256) void tile_offsets_kernel(BinArgs a)
 {
-    __shared__ uint32_t part[16][64];
-    const int seg = blockIdx.x / col_groups, cg = blockIdx.x % col_groups;
-    const int tl = threadIdx.x & 63, part_id = threadIdx.x >> 6;
-    const int col = cg * 64 + tl;
-    const int c_begin = seg_chunks ? (int)seg_chunks[seg] : 0;
-    const int c_end = seg_chunks ? (int)seg_chunks[seg + 1] : nchunks;
-    const int per = (c_end - c_begin + 15) / 16;
-    const int c0 = c_begin + part_id * per;
-    const int c1 = (c0 + per < c_end) ? c0 + per : c_end;
-    const bool valid = col < ncols;
-    uint32_t s = 0;
-    if (valid)
-        for (int c = c0; c < c1; ++c) s += counts[(int64_t)c * ncols + col];
-    part[part_id][tl] = s;
-    __syncthreads();
-    uint32_t run = 0, tot = 0;
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t x = part[k][tl];
-        if (k < part_id) run += x;
-        tot += x;
-    }
-    if (valid) {
-        for (int c = c0; c < c1; ++c) {
-            const int64_t o = (int64_t)c * ncols + col;
-            const uint32_t x = counts[o];
-            counts[o] = run;
-            run += x;
-        }
-        if (part_id == 0) totals[(int64_t)seg * ncols + col] = tot;
-    }
+    const int64_t T = (int64_t)a.tiles_x * a.tiles_y;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= T) return;
+    const int r = (int)(t / a.tiles_x), x = (int)(t % a.tiles_x);
+    const uint32_t* base = a.info + kInfoRowChunks;
+    const uint32_t nch = base[r + 1] - base[r];
+    const int64_t start = (int64_t)base[r] * a.tiles_x;
+    uint32_t off;
+    if (nch > 0) off = a.counts2[start + (int64_t)x * nch];
+    else if (start < (int64_t)a.info[kInfoC2Elems]) off = a.counts2[start];
+    else off = a.tile_offsets[T];
+    a.tile_offsets[t] = off;
 }
 
 unsigned grid8(int g) { return (unsigned)(8 * ((g + 7) / 8)); }
@@ -419,12 +431,9 @@ hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t
         if (e != hipSuccess) return e;
         return launch_fill_u32(a.info, 0u, (int64_t)bin_info_elems(a.tiles_y), s);
     }
-    const int c1 = bin_level1_chunks(a.n);
-    hipLaunchKernelGGL(level1_count_kernel, dim3(grid8(c1)), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(colscan_kernel, dim3((unsigned)((a.tiles_y + 63) / 64)), dim3(1024), 0, s, a.counts1,
-                       a.tiles_y, (const uint32_t*)nullptr, c1, (a.tiles_y + 63) / 64, a.rows_off);
-    hipError_t e = launch_scan_exclusive(a.rows_off, a.tiles_y, scan_scratch, nullptr, a.rows_off + a.tiles_y,
-                                         a.overflow, s);
+    hipLaunchKernelGGL(level1_count_kernel, dim3(grid8(a.chunks1)), dim3(64), 0, s, a);
+    hipError_t e = launch_scan_exclusive(a.counts1, (int64_t)a.tiles_y * a.chunks1, scan_scratch, nullptr,
+                                         a.rows_off + a.tiles_y, a.overflow, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(level2_table_kernel, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
@@ -442,10 +451,12 @@ hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch,
     const int64_t T = (int64_t)a.tiles_x * a.tiles_y;
     if (a.n == 0) return launch_fill_u32(a.tile_offsets, 0u, T + 1, s);
     if (grid2 > 0) hipLaunchKernelGGL(level2_count_kernel, dim3(grid8(grid2)), dim3(64), 0, s, a);
-    const int groups = (a.tiles_x + 63) / 64;
-    hipLaunchKernelGGL(colscan_kernel, dim3((unsigned)(a.tiles_y * groups)), dim3(1024), 0, s, a.counts2, a.tiles_x,
-                       (const uint32_t*)(a.info + kInfoRowChunks), 0, groups, a.tile_offsets);
-    return launch_scan_exclusive(a.tile_offsets, T, scan_scratch, nullptr, a.tile_offsets + T, a.overflow, s);
+    // the scan's length is C2 * tiles_x, read on the device (info[1])
+    hipError_t e = launch_scan_exclusive(a.counts2, (int64_t)grid2 * a.tiles_x, scan_scratch, nullptr,
+                                         a.tile_offsets + T, a.overflow, s, a.info + kInfoC2Elems);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tile_offsets_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_bin_tile_scatter(const BinArgs& a, int grid2, hipStream_t s)
