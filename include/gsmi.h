@@ -47,7 +47,7 @@ typedef enum { GS_F32 = 0, GS_BF16 = 1, GS_F16 = 2 } gs_dtype;
 typedef struct gs_context gs_context;
 
 /* Gaussians of the scene (Sec. 3.1: mean, rotation and scale of the
- * covariance Sigma = R S S^T R^T, opacity, SH colour; the record of Sec. 4.6
+ * covariance Sigma = R S S^T R^T, opacity, SH colour; the record of Sec. 4.5
  * stores scale in log space and rotation as a quaternion).
  *   n               number of Gaussians, 0 <= n < 2^31
  *   sh_degree       0..3; (sh_degree+1)^2 coefficients per colour channel

@@ -16,7 +16,7 @@ Layout (structure of arrays, channel-major, float32):
 
 The scene parameterisation (mean, rotation + scale covariance, opacity, SH
 colour) follows the background section on 3D Gaussian Splatting (Sec. 3.1);
-the Gaussian record of Sec. 4.6 stores the same fields with log-space scale.
+the Gaussian record of Sec. 4.5 (Gaussian representation) stores the same fields with log-space scale.
 
 The paper measures on SLAM-exported scenes that are not available here; the
 five workloads below stand in for them (see ``CONFIGS``).
