@@ -104,6 +104,110 @@ def cpu_baseline(scene, cam, band_rows: int = 4) -> dict:
                        f"to {frame_s:.1f} s")}
 
 
+# kernel -> the sources its code comes from (a counter reading stays valid
+# while these files are unchanged)
+KERNEL_SOURCES = {
+    "project_kernel": ["project.hip", "gs_internal.h"],
+    "level1_scatter_kernel": ["tile_bin.hip", "gs_internal.h"],
+    "level2_scatter_kernel": ["tile_bin.hip", "gs_internal.h"],
+    "blend_kernel": ["blend.hip", "gs_internal.h"],
+}
+STAGE_KERNEL = {"project": "project_kernel", "bin_row_scatter": "level1_scatter_kernel",
+                "bin_tile_scatter": "level2_scatter_kernel", "blend": "blend_kernel"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt")
+
+
+def source_digest(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2607_15951_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str, variant: str):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary,
+    or None when there is none or the kernel's sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) >= 6 and parts[0] == "kernel":
+                # kernel <name> <workload> <variant> <digest> <fetch_bytes> <write_bytes>
+                rec[(parts[1], parts[2], parts[3])] = (parts[4], float(parts[5]), float(parts[6]))
+    r = rec.get((kernel, workload, variant))
+    if r is None or r[0] != source_digest(kernel):
+        return None
+    return r[1] + r[2]
+
+
+def kernel_short_name(name: str, templates: bool = True) -> str:
+    """'void gsmi::(anonymous namespace)::blend_kernel<false>(gsmi::BlendArgs, ...)'
+    -> 'blend_kernel<false>' (or 'blend_kernel' without template arguments)."""
+    name = name.replace("(anonymous namespace)::", "")
+    name = name.split("(")[0].strip()
+    if name.startswith("void "):
+        name = name[5:]
+    name = name.split("::")[-1] if "<" not in name else name[name.rfind("::", 0, name.index("<")) + 2:]
+    return name if templates else name.split("<")[0]
+
+
+def _csv_rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_stats(path: str) -> str:
+    """Markdown table of a rocprofv3 --stats kernel summary (run_kernel_stats.csv)."""
+    rows = sorted(_csv_rows(path), key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | avg (us) | min (us) | max (us) | total (ms) | share |", "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| {kernel_short_name(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |")
+    return "\n".join(out)
+
+
+def _pmc_avg(path: str, counter: str) -> dict:
+    """Average per dispatch of one counter, by kernel name."""
+    acc = {}
+    for r in _csv_rows(path):
+        # the work-counting blend variant (one launch per bench run) is not the timed kernel
+        if r["Counter_Name"] != counter or "blend_kernel<true>" in kernel_short_name(r["Kernel_Name"]):
+            continue
+        k = kernel_short_name(r["Kernel_Name"], templates=False)
+        acc.setdefault(k, []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str, workload: str,
+                  variant: str) -> str:
+    """HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    each scaled by the reading of a plain copy of known size."""
+    copy_bytes = 1 << 30
+    cf = max(_pmc_avg(copy_fetch_csv, "FETCH_SIZE").items(), key=lambda kv: kv[1])
+    cw = max(_pmc_avg(copy_write_csv, "WRITE_SIZE").items(), key=lambda kv: kv[1])
+    f_fac = copy_bytes / (cf[1] * 1024.0)
+    w_fac = copy_bytes / (cw[1] * 1024.0)
+    fetch = _pmc_avg(fetch_csv, "FETCH_SIZE")
+    write = _pmc_avg(write_csv, "WRITE_SIZE")
+    lines = [f"# copy calibration: {cf[0]} FETCH_SIZE {cf[1]:.0f} KiB, WRITE_SIZE {cw[1]:.0f} KiB for "
+             f"{copy_bytes} B read and written -> factors fetch {f_fac:.3f}, write {w_fac:.3f}",
+             "# kernel <name> <workload> <variant> <source digest> <fetch bytes/launch> <write bytes/launch>"]
+    for k in sorted(KERNEL_SOURCES):
+        if k in fetch and k in write:
+            lines.append(f"kernel {k} {workload} {variant} {source_digest(k)} {fetch[k] * 1024 * f_fac:.0f} "
+                         f"{write[k] * 1024 * w_fac:.0f}")
+    for k in sorted(set(fetch) | set(write)):
+        lines.append(f"# raw {k}: FETCH_SIZE {fetch.get(k, float('nan')):.0f} KiB, "
+                     f"WRITE_SIZE {write.get(k, float('nan')):.0f} KiB per dispatch")
+    return "\n".join(lines)
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     """A plain device-to-device copy of known size: reads and writes nbytes
     per launch.  Profiled with the same FETCH_SIZE / WRITE_SIZE counters, it
@@ -127,9 +231,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV",
+                    help="print a rocprofv3 --stats kernel summary as a markdown table, then exit")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="print HBM bytes per launch from rocprofv3 --pmc counter files, then exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.summarize_stats:
+        print(summarize_stats(args.summarize_stats))
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(*args.summarize_pmc, workload=args.workload, variant=args.variant))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this single-GPU build "
@@ -190,14 +304,15 @@ def main():
         achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
         roof = {"kernel": "blend_kernel", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "work": {"evaluations": stats["evaluations"], "composited": stats["composited"],
+                "traffic": read_traffic("blend_kernel", args.workload, args.variant), "work": {"evaluations": stats["evaluations"], "composited": stats["composited"],
                                           "flops_per_evaluation": FLOPS_EVAL,
                                           "flops_per_composite": FLOPS_COMPOSITE}}
     else:
         by = algorithmic_bytes(dom, n, n_vis, K, R, deg, dtype, W, H, stats)
         achieved = by / (stage_ms[dom] * 1e-3) / 1e9
-        roof = {"kernel": dom + "_kernel", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        roof = {"kernel": STAGE_KERNEL[dom], "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": read_traffic(STAGE_KERNEL[dom], args.workload, args.variant),
                 "bytes_per_launch": int(by)}
     stage_gbs = {}
     for k in single:
@@ -207,7 +322,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (FP64 oracle, bounded sample)")
-        cpu = cpu_baseline(scene, cam)
+        cpu = cpu_baseline(scene, cam, band_rows=16)
 
     res = {
         "metric": METRIC,
