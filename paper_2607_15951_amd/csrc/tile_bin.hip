@@ -34,6 +34,7 @@ namespace {
 
 constexpr int kChunk1 = kItemsL1 * 64;   // Gaussians per level-1 wave
 constexpr int kChunk2 = kItemsL2 * 64;   // row entries per level-2 wave
+constexpr int kBand = 16;                // tile columns per band of the level-2 walk
 
 // info[] layout (uint32): [0] level-2 chunks C2, [1] C2 * tiles_x (length of
 // the level-2 count array), [2 .. tiles_y + 2] level-2 chunk prefix at each
@@ -372,22 +373,90 @@ __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
     counts_from_diff(diff, a.tiles_x, dst, stride, lane);
 }
 
+// The walk of one column over the first nbat batches of packed items.
+template <bool kChecked>
+__device__ __forceinline__ void walk_packed(uint32_t x, uint32_t cur, int nbat, const uint32_t (&x0)[kItemsL2],
+                                            const uint32_t (&w)[kItemsL2], const uint32_t (&g)[kItemsL2],
+                                            uint32_t* __restrict__ out, uint64_t capacity)
+{
+    uint32_t* base = out + cur;
+#pragma unroll
+    for (int b = 0; b < kItemsL2; ++b) {
+        if (b < nbat) {   // uniform
+            const bool cover = x - x0[b] < w[b];
+            const uint64_t m = __ballot(cover);
+            if (cover) {
+                const uint32_t below = lanes_below(m);
+                if (!kChecked || (uint64_t)cur + below < capacity) base[below] = g[b];
+            }
+            const uint32_t n = (uint32_t)__popcll(m);
+            cur += n;
+            base += n;
+        }
+    }
+}
+
+// A plain walk would test every batch of the chunk against every column the
+// chunk spans (about the row width), while an entry covers a few columns.
+// The chunk is walked band by band instead (kBand columns): the entries that
+// reach band b are packed, in chunk order, into dense batches through LDS,
+// and only those batches walk the band's columns.  Inside a column the
+// entries keep their chunk order, so the output is that of the plain walk.
 __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
 {
+    __shared__ uint32_t s_g[kChunk2], s_x[kChunk2];
     const int lane = threadIdx.x, c = chunk_of_block();
     Items2 it;
     if (!load_items2(a, c, lane, it)) return;
-    for (int w0 = it.lo; w0 < it.hi; w0 += kWindow) {
-        const int xa = w0 + lane, xb = w0 + 64 + lane;
-        const uint32_t cur_a = xa < it.hi ? it.cursor[xa * it.stride] : 0u;
-        const uint32_t cur_b = xb < it.hi ? it.cursor[xb * it.stride] : 0u;
-        const int e0 = min(it.hi, w0 + 64), e1 = min(it.hi, w0 + kWindow);
-        for (int x = w0; x < e0; ++x)
-            walk_bucket<kItemsL2>((uint32_t)x, __builtin_amdgcn_readlane(cur_a, x - w0), it.x0, it.w, it.g, a.values,
-                                  a.capacity);
-        for (int x = w0 + 64; x < e1; ++x)
-            walk_bucket<kItemsL2>((uint32_t)x, __builtin_amdgcn_readlane(cur_b, x - w0 - 64), it.x0, it.w, it.g,
-                                  a.values, a.capacity);
+    const int blo = it.lo / kBand, bhi = (it.hi + kBand - 1) / kBand;
+    // cursors of band b's columns: lane l < kBand holds column b * kBand + l
+    auto band_cursors = [&](int b) -> uint32_t {
+        const int col = b * kBand + lane;
+        return (lane < kBand && col < a.tiles_x) ? it.cursor[col * it.stride] : 0u;
+    };
+    uint32_t cur_b = band_cursors(blo);
+    for (int b = blo; b < bhi; ++b) {
+        const uint32_t bx0 = (uint32_t)(b * kBand), bx1 = min(bx0 + kBand, (uint32_t)a.tiles_x);
+        const uint32_t cur_next = (b + 1 < bhi) ? band_cursors(b + 1) : 0u;   // prefetch
+        // pack the entries reaching the band, clipped to it, in chunk order
+        uint32_t n = 0;
+#pragma unroll
+        for (int j = 0; j < kItemsL2; ++j) {
+            const uint32_t e0 = max(it.x0[j], bx0), e1 = min(it.x0[j] + it.w[j], bx1);
+            const bool reach = e1 > e0;
+            const uint64_t m = __ballot(reach);
+            if (reach) {
+                const uint32_t slot = n + lanes_below(m);
+                s_g[slot] = it.g[j];
+                s_x[slot] = e0 | (e1 << 16);
+            }
+            n += (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        const int nbat = (int)((n + 63) / 64);
+        uint32_t px0[kItemsL2], pw[kItemsL2], pg[kItemsL2];
+#pragma unroll
+        for (int j = 0; j < kItemsL2; ++j) {
+            const uint32_t k = (uint32_t)(j * 64 + lane);
+            uint32_t xs = 0u, gg = 0u;
+            if (j < nbat && k < n) {
+                xs = s_x[k];
+                gg = s_g[k];
+            }
+            px0[j] = xs & 0xFFFFu;
+            pw[j] = (xs >> 16) - (xs & 0xFFFFu);
+            pg[j] = gg;
+        }
+        __syncthreads();   // the LDS is free for the next band
+        const int xlo = max((int)bx0, it.lo), xhi = min((int)bx1, it.hi);
+        for (int x = xlo; x < xhi; ++x) {
+            const uint32_t cur = __builtin_amdgcn_readlane(cur_b, x - (int)bx0);
+            if ((uint64_t)cur + n <= a.capacity)
+                walk_packed<false>((uint32_t)x, cur, nbat, px0, pw, pg, a.values, a.capacity);
+            else
+                walk_packed<true>((uint32_t)x, cur, nbat, px0, pw, pg, a.values, a.capacity);
+        }
+        cur_b = cur_next;
     }
 }
 
