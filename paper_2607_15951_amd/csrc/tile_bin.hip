@@ -108,8 +108,8 @@ __device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, I
         it.xs[b] = (uint32_t)r.x | ((uint32_t)r.z << 16);
         it.g[b] = g;
     }
-    it.lo = wave_min(lo);
-    it.hi = wave_max(hi);
+    it.lo = __builtin_amdgcn_readfirstlane(wave_min(lo));   // uniform: keep it scalar
+    it.hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     return true;
 }
 
@@ -342,8 +342,8 @@ __device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, I
         it.w[b] = (ent.y >> 16) - (ent.y & 0xFFFFu);
         it.g[b] = ent.x;
     }
-    it.lo = wave_min(lo);
-    it.hi = wave_max(hi);
+    it.lo = __builtin_amdgcn_readfirstlane(wave_min(lo));   // uniform: keep it scalar
+    it.hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     it.cursor = level2_slot(a, it.row, c, &it.stride);
     return true;
 }
@@ -373,25 +373,36 @@ __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
     counts_from_diff(diff, a.tiles_x, dst, stride, lane);
 }
 
-// The walk of one column over the first nbat batches of packed items.
+// The walk of one band over the n packed entries in LDS (s_g, s_x): batch
+// by batch, each batch against the band's kBand columns, unrolled so that
+// every column's cursor stays in a scalar register.  cur_b holds the cursors
+// (lane q: column bx0 + q).
 template <bool kChecked>
-__device__ __forceinline__ void walk_packed(uint32_t x, uint32_t cur, int nbat, const uint32_t (&x0)[kItemsL2],
-                                            const uint32_t (&w)[kItemsL2], const uint32_t (&g)[kItemsL2],
-                                            uint32_t* __restrict__ out, uint64_t capacity)
+__device__ __forceinline__ void walk_band(const uint32_t* s_g, const uint32_t* s_x, uint32_t n, uint32_t bx0,
+                                          uint32_t cur_b, uint32_t* __restrict__ out, uint64_t capacity, int lane)
 {
-    uint32_t* base = out + cur;
+    uint32_t cur[kBand];
 #pragma unroll
-    for (int b = 0; b < kItemsL2; ++b) {
-        if (b < nbat) {   // uniform
-            const bool cover = x - x0[b] < w[b];
+    for (int q = 0; q < kBand; ++q) cur[q] = __builtin_amdgcn_readlane(cur_b, q);
+    for (uint32_t k0 = 0; k0 < n; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        uint32_t xs = 0u, g = 0u;
+        if (k < n) {
+            xs = s_x[k];
+            g = s_g[k];
+        }
+        const uint32_t x0 = xs & 0xFFFFu, w = (xs >> 16) - x0;
+        // all kBand columns: packed entries are clipped to the band and to
+        // the image, so a column outside them is never covered
+#pragma unroll
+        for (int q = 0; q < kBand; ++q) {
+            const bool cover = bx0 + q - x0 < w;
             const uint64_t m = __ballot(cover);
             if (cover) {
-                const uint32_t below = lanes_below(m);
-                if (!kChecked || (uint64_t)cur + below < capacity) base[below] = g[b];
+                const uint32_t pos = cur[q] + lanes_below(m);
+                if (!kChecked || pos < capacity) out[pos] = g;
             }
-            const uint32_t n = (uint32_t)__popcll(m);
-            cur += n;
-            base += n;
+            cur[q] += (uint32_t)__popcll(m);
         }
     }
 }
@@ -433,29 +444,13 @@ __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
             n += (uint32_t)__popcll(m);
         }
         __syncthreads();
-        const int nbat = (int)((n + 63) / 64);
-        uint32_t px0[kItemsL2], pw[kItemsL2], pg[kItemsL2];
-#pragma unroll
-        for (int j = 0; j < kItemsL2; ++j) {
-            const uint32_t k = (uint32_t)(j * 64 + lane);
-            uint32_t xs = 0u, gg = 0u;
-            if (j < nbat && k < n) {
-                xs = s_x[k];
-                gg = s_g[k];
-            }
-            px0[j] = xs & 0xFFFFu;
-            pw[j] = (xs >> 16) - (xs & 0xFFFFu);
-            pg[j] = gg;
-        }
+        // column cursors increase along the row: the last one bounds them all
+        const uint32_t cur_last = __builtin_amdgcn_readlane(cur_b, (int)(bx1 - bx0) - 1);
+        if ((uint64_t)cur_last + n <= a.capacity)
+            walk_band<false>(s_g, s_x, n, bx0, cur_b, a.values, a.capacity, lane);
+        else
+            walk_band<true>(s_g, s_x, n, bx0, cur_b, a.values, a.capacity, lane);
         __syncthreads();   // the LDS is free for the next band
-        const int xlo = max((int)bx0, it.lo), xhi = min((int)bx1, it.hi);
-        for (int x = xlo; x < xhi; ++x) {
-            const uint32_t cur = __builtin_amdgcn_readlane(cur_b, x - (int)bx0);
-            if ((uint64_t)cur + n <= a.capacity)
-                walk_packed<false>((uint32_t)x, cur, nbat, px0, pw, pg, a.values, a.capacity);
-            else
-                walk_packed<true>((uint32_t)x, cur, nbat, px0, pw, pg, a.values, a.capacity);
-        }
         cur_b = cur_next;
     }
 }
