@@ -7,13 +7,15 @@ Workload (default): 3,000,000 Gaussians (256-cluster power-law mixture plus
 is one gs_render call -- project, depth sort, tile count/offsets, sorted pair
 list, blend -- with the scene already resident in HBM.
 
-Prints ONE JSON line with the frame rate, the per-stage device times (HIP
-events recorded by the library on the render stream during the timed steps),
-a roofline entry for the dominant kernel and the FP64 oracle's time on a
-bounded sample of the same frame on the host cores.
+Prints ONE JSON line with the frame rate of back-to-back renders, the
+per-stage device times (HIP events recorded by the library on the render
+stream, from a separate profiled pass), a roofline entry for the dominant
+kernel, the frame rate of the BF16 / FP16 attribute-storage variants of the
+same frame, and the FP64 oracle's time on a bounded sample of the frame on the
+host cores.
 
     python bench.py [--steps K] [--warmup W] [--variant fp32|bf16|fp16]
-                    [--workload C3] [--no-cpu-baseline]
+                    [--workload C3] [--no-cpu-baseline] [--no-variants]
 """
 from __future__ import annotations
 
@@ -229,6 +231,7 @@ def main():
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--variant", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the BF16/FP16 storage variants")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV",
@@ -274,27 +277,61 @@ def main():
         r.render(dev, cam, W, H, out=out)
     torch.cuda.synchronize()
 
-    r.set_profiling(stages=True)
-    stage_sum = {k: 0.0 for k in gs.STAGES}
+    # frame rate: plain renders back to back (the library's own host read of
+    # the pair count is the only synchronisation inside a frame)
     log(f"[bench] timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r.render(dev, cam, W, H, out=out)
-        st = r.stage_times()
-        for k, v in st.items():
-            stage_sum[k] += v
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # per-stage device times: HIP events the library records on its stream
+    prof_steps = min(args.steps, 20)
+    r.set_profiling(stages=True)
+    stage_sum = {k: 0.0 for k in gs.STAGES}
+    for _ in range(prof_steps):
+        r.render(dev, cam, W, H, out=out)
+        for k, v in r.stage_times().items():
+            stage_sum[k] += v
     info = r.list_info()
     # one more render with the work-counting blend (not timed)
     r.set_profiling(stages=False, blend_work=True)
     r.render(dev, cam, W, H, out=out)
     stats = r.blend_stats()
     r.set_profiling(stages=False)
-    stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
+    stage_ms = {k: v / prof_steps for k, v in stage_sum.items()}
     log("[bench] stages ms " + json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
+
+    # storage variants of the same frame: attributes other than means in
+    # BF16 / FP16 (the error of each against the FP64 render is reported by
+    # the full-size parity tests)
+    variants = {}
+    if not args.no_variants:
+        for name, vd in (("bf16", gs.GS_BF16), ("fp16", gs.GS_F16)):
+            if vd == dtype:
+                continue
+            vdev = gs.scene_to_device(scene, vd)
+            for _ in range(3):
+                r.render(vdev, cam, W, H, out=out)
+            vsteps = min(args.steps, 20)
+            torch.cuda.synchronize()
+            v0 = time.perf_counter()
+            for _ in range(vsteps):
+                r.render(vdev, cam, W, H, out=out)
+            torch.cuda.synchronize()
+            vms = (time.perf_counter() - v0) * 1e3 / vsteps
+            r.set_profiling(stages=True)
+            r.render(vdev, cam, W, H, out=out)
+            vst = r.stage_times()
+            r.set_profiling(stages=False)
+            pb = algorithmic_bytes("project", n, 0, 0, 0, deg, vd, W, H, {})
+            variants[name] = {"frames_per_s": round(1e3 / vms, 2), "ms_per_step": round(vms, 4), "steps": vsteps,
+                              "project_ms": round(vst["project"], 4),
+                              "project_algorithmic_GBps": round(pb / (vst["project"] * 1e-3) / 1e9, 1)}
+            del vdev
+            log(f"[bench] variant {name}: " + json.dumps(variants[name]))
 
     K, n_vis, R = info["num_pairs"], info["n_visible"], info["num_row_entries"]
     single = ["project", "bin_row_scatter", "bin_tile_scatter", "blend"]
@@ -346,6 +383,7 @@ def main():
         "blend_work": {**stats, "tflops": round((FLOPS_EVAL * stats["evaluations"] + FLOPS_COMPOSITE *
                                                  stats["composited"]) / (stage_ms["blend"] * 1e-3) / 1e12, 3)},
         "roofline": roof,
+        "variants": variants,
         "cpu_baseline": cpu,
     }
     r.close()
