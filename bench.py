@@ -223,6 +223,35 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
 
 
+def time_batched(r, dev, cams, steps: int) -> dict:
+    """Views/s of one gs_render_batched call over ``cams`` per step, and of
+    the same views rendered by one gs_render call each."""
+    import torch
+    outs = r.render_batched(dev, cams)
+    torch.cuda.synchronize()
+    bsteps = max(3, min(steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(bsteps):
+        r.render_batched(dev, cams, outs=outs)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / bsteps
+    info = r.list_info()
+    for c, o in zip(cams, outs):   # warm the single-view sizes
+        r.render(dev, c, c["width"], c["height"], out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(bsteps):
+        for c, o in zip(cams, outs):
+            r.render(dev, c, c["width"], c["height"], out=o)
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t0) * 1e3 / bsteps
+    pixels = sum(c["width"] * c["height"] for c in cams)
+    return {"views": len(cams), "megapixels": round(pixels / 1e6, 2), "pairs": info["num_pairs"],
+            "ms_per_batch": round(ms_batch, 3), "views_per_s": round(len(cams) * 1e3 / ms_batch, 1),
+            "ms_one_call_per_view": round(ms_single, 3),
+            "views_per_s_one_call_per_view": round(len(cams) * 1e3 / ms_single, 1), "steps": bsteps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +361,20 @@ def main():
                               "project_algorithmic_GBps": round(pb / (vst["project"] * 1e-3) / 1e9, 1)}
             del vdev
             log(f"[bench] variant {name}: " + json.dumps(variants[name]))
+        # batched: the same frame's scene from 8 cameras on a ring (1080p each),
+        # and the 64-camera mixed-resolution workload, each one
+        # gs_render_batched call per step, against the same views rendered one
+        # gs_render call at a time
+        if dtype == gs.GS_F32:
+            variants["batched_ring8_1080p"] = time_batched(r, dev, scenes.ring_cameras(8, W, H), args.steps)
+            log("[bench] variant batched_ring8_1080p: " + json.dumps(variants["batched_ring8_1080p"]))
+            del dev
+            sc4 = scenes.make_scene("C4")
+            dev4 = gs.scene_to_device(sc4)
+            variants["batched_C4_64views"] = time_batched(r, dev4, scenes.make_cameras("C4"), args.steps)
+            variants["batched_C4_64views"]["workload"] = scenes.WORKLOAD_NAMES["C4"]
+            log("[bench] variant batched_C4_64views: " + json.dumps(variants["batched_C4_64views"]))
+            del dev4
 
     K, n_vis, R = info["num_pairs"], info["n_visible"], info["num_row_entries"]
     single = ["project", "bin_row_scatter", "bin_tile_scatter", "blend"]

@@ -131,6 +131,33 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
                     int32_t width, int32_t height, const gs_render_opts* opts,
                     float* out_rgb, float* out_final_T, uint32_t* out_n_contrib, void* stream);
 
+/* One view of a batched render: a camera, its image size and its outputs
+ * (device memory owned by the caller, laid out as for gs_render). */
+typedef struct {
+    gs_camera camera;
+    int32_t width, height;        /* 1..32768 each */
+    float* out_rgb;               /* float [3][height][width] */
+    float* out_final_T;           /* float [height][width], or NULL */
+    uint32_t* out_n_contrib;      /* uint32 [height][width], or NULL */
+} gs_view;
+
+/* Renders n_views views of one scene in one call: the batched form of
+ * gs_render (the same computation per view, Sec. 3.1 stages 1-4 and Eq. 1).
+ * Every stage runs once over all views: each Gaussian's attributes are read
+ * once and projected into every view; the depth sort sorts each view's
+ * Gaussians (as one segmented sort); binning and blending run over the
+ * concatenated tile grids of the views, so small and large images share the
+ * launches.  Each view's image equals what gs_render returns for it alone.
+ *   views     host array [n_views], 1 <= n_views <= 1024
+ *   lists     the per-tile lists cover all views: global tile t indexes the
+ *             views' row-major tile grids concatenated in view order, and a
+ *             list holds items v * n + i (view v, Gaussian i); requires
+ *             n_views * n < 2^32 and at most 16384 tile rows over all views
+ *             (GS_ERR_UNSUPPORTED otherwise)
+ * Errors as for gs_render, checked for every view before any launch. */
+gs_status gs_render_batched(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
+                            const gs_render_opts* opts, void* stream);
+
 /* Sizes of the last render's per-tile lists (host values; synchronises the
  * context's last stream). */
 typedef struct {
@@ -138,6 +165,8 @@ typedef struct {
     int32_t tiles_x, tiles_y;
     int64_t n_visible;         /* Gaussians overlapping at least one tile */
     uint64_t num_row_entries;  /* (Gaussian, tile row) pairs of the binning */
+    int64_t num_tiles;         /* tiles over all views (tiles_x * tiles_y for one view) */
+    int32_t num_views;         /* views of the last render */
 } gs_list_info;
 
 gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out);
@@ -153,7 +182,9 @@ gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out);
 gs_status gs_copy_lists(gs_context* ctx, uint32_t* values, uint32_t* tile_offsets, uint64_t* keys,
                         void* stream);
 
-/* Projected Gaussians of the last render (any pointer may be NULL).
+/* Projected Gaussians of the last render (any pointer may be NULL); after a
+ * batched render every array holds n_views * n items, item v * n + i being
+ * Gaussian i in view v.
  *   splats         float [n][12]: u_hi, v_hi, u_lo, v_lo, conic A, B, C,
  *                  opacity, r, g, b, depth, where the 2D centre is
  *                  u = u_hi + u_lo (float32 pair of the double value) and

@@ -23,7 +23,7 @@ TILE = 16
 
 EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
             "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
-            "gs_get_blend_stats", "gs_get_blend_tile_work"]
+            "gs_get_blend_stats", "gs_get_blend_tile_work", "gs_render_batched"]
 STAGES = ["project", "depth_sort", "bin_row_count", "bin_row_scatter", "bin_tile_count", "bin_tile_scatter",
           "blend"]
 
@@ -52,7 +52,13 @@ class gs_render_opts(C.Structure):
 
 class gs_list_info(C.Structure):
     _fields_ = [("num_pairs", C.c_uint64), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
-                ("n_visible", C.c_int64), ("num_row_entries", C.c_uint64)]
+                ("n_visible", C.c_int64), ("num_row_entries", C.c_uint64), ("num_tiles", C.c_int64),
+                ("num_views", C.c_int32)]
+
+
+class gs_view(C.Structure):
+    _fields_ = [("camera", gs_camera), ("width", C.c_int32), ("height", C.c_int32), ("out_rgb", C.c_void_p),
+                ("out_final_T", C.c_void_p), ("out_n_contrib", C.c_void_p)]
 
 
 _lib = None
@@ -79,6 +85,9 @@ def load_library(path: str = LIB_PATH):
     L.gs_render.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(gs_camera), C.c_int32, C.c_int32,
                             C.POINTER(gs_render_opts), P, P, P, P]
     L.gs_render.restype = C.c_int
+    L.gs_render_batched.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(gs_view), C.c_int32,
+                                    C.POINTER(gs_render_opts), P]
+    L.gs_render_batched.restype = C.c_int
     L.gs_get_list_info.argtypes = [P, C.POINTER(gs_list_info)]
     L.gs_get_list_info.restype = C.c_int
     L.gs_copy_lists.argtypes = [P, P, P, P, P]
@@ -211,6 +220,36 @@ class Renderer:
         self._last = (dev, int(g.n))
         return out
 
+    def render_batched(self, dev_scene: dict, cameras: list, background=(0.0, 0.0, 0.0), pair_capacity: int = 0,
+                       outs=None, want_T: bool = True, want_n_contrib: bool = True, stream=None):
+        """Renders every camera dict of ``cameras`` (each with its own
+        width/height) in one gs_render_batched call; returns one output dict
+        per view, as render() does."""
+        torch = _torch()
+        dev = dev_scene["means"].device
+        if outs is None:
+            outs = []
+            for c in cameras:
+                W, H = int(c["width"]), int(c["height"])
+                outs.append({"image": torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                             "final_T": torch.empty((H, W), dtype=torch.float32, device=dev) if want_T else None,
+                             "n_contrib": torch.empty((H, W), dtype=torch.int32, device=dev)
+                             if want_n_contrib else None})
+        views = (gs_view * len(cameras))()
+        for k, (c, o) in enumerate(zip(cameras, outs)):
+            views[k].camera = make_camera(c)
+            views[k].width, views[k].height = int(c["width"]), int(c["height"])
+            views[k].out_rgb = _ptr(o["image"])
+            views[k].out_final_T = _ptr(o.get("final_T"))
+            views[k].out_n_contrib = _ptr(o.get("n_contrib"))
+        g = make_gaussians(dev_scene)
+        opts = make_opts(background, pair_capacity)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        self._check(self._L.gs_render_batched(self._ctx, C.byref(g), views, len(cameras), C.byref(opts),
+                                              C.c_void_p(s)))
+        self._last = (dev, int(g.n) * len(cameras))
+        return outs
+
     def set_profiling(self, stages: bool = True, blend_work: bool = False):
         """Tracing of the following renders: HIP events between the stages
         (stage_times) and/or the counting variant of the blend (blend_stats)."""
@@ -235,7 +274,7 @@ class Renderer:
         evaluations, composited)."""
         import numpy as np
         info = self.list_info()
-        T = info["tiles_x"] * info["tiles_y"]
+        T = info["num_tiles"]
         buf = (C.c_uint64 * (6 * T))()
         self._check(self._L.gs_get_blend_tile_work(self._ctx, buf, T))
         return np.frombuffer(buf, dtype=np.uint64).reshape(T, 6).copy()
@@ -244,7 +283,8 @@ class Renderer:
         info = gs_list_info()
         self._check(self._L.gs_get_list_info(self._ctx, C.byref(info)))
         return dict(num_pairs=int(info.num_pairs), tiles_x=info.tiles_x, tiles_y=info.tiles_y,
-                    n_visible=int(info.n_visible), num_row_entries=int(info.num_row_entries))
+                    n_visible=int(info.n_visible), num_row_entries=int(info.num_row_entries),
+                    num_tiles=int(info.num_tiles), num_views=int(info.num_views))
 
     def lists(self, keys: bool = False) -> dict:
         """Sorted per-tile lists of the last render as device tensors."""
@@ -252,7 +292,7 @@ class Renderer:
         info = self.list_info()
         dev = self._last[0]
         K = info["num_pairs"]
-        T = info["tiles_x"] * info["tiles_y"]
+        T = info["num_tiles"]
         values = torch.empty(max(K, 1), dtype=torch.int32, device=dev)
         offsets = torch.empty(T + 1, dtype=torch.int32, device=dev)
         kt = torch.empty(max(K, 1), dtype=torch.int64, device=dev) if keys else None

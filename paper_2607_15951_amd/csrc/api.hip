@@ -1,6 +1,7 @@
 // api.hip -- host side of the C ABI declared in include/gsmi.h: argument
 // validation, the context's device workspace and the launch sequence of one
-// render (project -> depth sort -> tile count/offsets -> scatter -> blend).
+// render of one or several views (project -> depth sort -> tile counts and
+// offsets -> scatter -> blend).  A single-image render is the one-view case.
 #include "gsmi.h"
 #include "gs_internal.h"
 
@@ -8,8 +9,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <vector>
 #include <string>
+#include <vector>
 
 using namespace gsmi;
 
@@ -22,6 +23,8 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+constexpr int kMaxViews = 1024;
+
 }  // namespace
 
 struct gs_context {
@@ -30,22 +33,26 @@ struct gs_context {
     DevBuf splats, depth_key, radius, tiles_touched, rect;
     DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist, scan_scratch;
     DevBuf bin_info, counts1, rows_off, row_ent, counts2, partials;
-    // [0] n_visible, [1] overflow, [12..13] K from the projection (u64)
-    DevBuf counters;
+    DevBuf views, row_tiles_x;   // device view table and tiles_x of every global tile row
+    DevBuf view_counts;          // [n_views][kViewCounters] visible Gaussians and pairs per view
+    DevBuf counters;             // [1] capacity overflow flag
     DevBuf tile_offsets, values;
     DevBuf tile_work;   // per-tile blend trace [T][kTileWorkFields] u64 (GS_PROFILE_BLEND_WORK)
-    uint32_t* host_info = nullptr;   // pinned readback: band table, then K as u64
+    uint32_t* host_info = nullptr;   // pinned readback of the per-frame sizes
     uint32_t profiling = 0;   // GS_PROFILE_* flags
     bool timed = false;       // the last render recorded stage events
     bool traced = false;      // the last render counted blend work
-    // stage boundaries: 0 start, 1 project, 2 depth sort, 3 bin prepare,
-    // 4 count start (after the host read of K), 5 count, 6 offsets,
-    // 7 scatter, 8 blend
+    // stage boundaries: 0 start, 1 project, 2 depth sort, 3 row counts,
+    // 4 after the host read of K, 5 row scatter, 6 tile counts, 7 tile
+    // scatter, 8 blend
     hipEvent_t ev[9] = {};
     // last render
     bool have_render = false;
     int64_t n = 0;
-    int tiles_x = 0, tiles_y = 0;
+    int n_views = 0;
+    int tiles_x = 0, tiles_y = 0;   // of the first view
+    int64_t tiles = 0;              // global tiles over all views
+    int rows = 0;                   // global tile rows
     uint64_t capacity = 0;
     int sorted_in_b = 1;
     hipStream_t stream = nullptr;
@@ -91,12 +98,9 @@ bool finite_all(const float* v, int k)
     return true;
 }
 
-gs_status validate(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam, int32_t width, int32_t height,
-                   const gs_render_opts* opts, const float* out_rgb)
+gs_status validate_gaussians(gs_context* ctx, const gs_gaussians* g)
 {
     if (!g) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "gaussians is NULL");
-    if (!cam) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "camera is NULL");
-    if (!out_rgb) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "out_rgb is NULL");
     if (g->n < 0 || g->n >= (int64_t(1) << 31))
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "n must lie in [0, 2^31)");
     if (g->sh_degree < 0 || g->sh_degree > 3) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "sh_degree must be 0..3");
@@ -104,6 +108,24 @@ gs_status validate(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam,
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "attr_dtype must be GS_F32, GS_BF16 or GS_F16");
     if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "a Gaussian attribute pointer is NULL");
+    return GS_OK;
+}
+
+gs_status validate_opts(gs_context* ctx, const gs_render_opts* opts)
+{
+    if (opts) {
+        if (opts->tile_size != kTile) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "tile_size must be 16");
+        if (opts->flags != 0) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "flags must be 0");
+        if (!finite_all(opts->background, 3))
+            return fail(ctx, GS_ERR_INVALID_ARGUMENT, "background holds a non-finite value");
+    }
+    return GS_OK;
+}
+
+gs_status validate_view(gs_context* ctx, const gs_camera* cam, int32_t width, int32_t height, const float* out_rgb)
+{
+    if (!cam) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    if (!out_rgb) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "out_rgb is NULL");
     if (width < 1 || height < 1 || width > 32768 || height > 32768)
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "width and height must lie in [1, 32768]");
     const int tiles_x = (width + kTile - 1) / kTile;
@@ -113,13 +135,16 @@ gs_status validate(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam,
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "camera holds a non-finite value");
     if (!(cam->fx > 0.f) || !(cam->fy > 0.f) || !(cam->near_plane > 0.f))
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "camera fx, fy and near_plane must be positive");
-    if (opts) {
-        if (opts->tile_size != kTile) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "tile_size must be 16");
-        if (opts->flags != 0) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "flags must be 0");
-        if (!finite_all(opts->background, 3))
-            return fail(ctx, GS_ERR_INVALID_ARGUMENT, "background holds a non-finite value");
-    }
     return GS_OK;
+}
+
+gs_status validate(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam, int32_t width, int32_t height,
+                   const gs_render_opts* opts, const float* out_rgb)
+{
+    gs_status st = validate_gaussians(ctx, g);
+    if (st == GS_OK) st = validate_view(ctx, cam, width, height, out_rgb);
+    if (st == GS_OK) st = validate_opts(ctx, opts);
+    return st;
 }
 
 #define HIP_TRY(expr, what)                                   \
@@ -133,6 +158,263 @@ gs_status validate(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam,
     do {                                                                            \
         if (ctx->profiling & GS_PROFILE_STAGES) HIP_TRY(hipEventRecord(ctx->ev[(k)], s), "hipEventRecord"); \
     } while (0)
+
+
+// The view table is written by a kernel whose arguments carry up to
+// kViewsPerLaunch views (kernel arguments are copied at launch, so the host
+// array can be reused at once and the upload stays on the compute queue).
+constexpr int kViewsPerLaunch = 16;
+struct ViewBatch {
+    ViewParams v[kViewsPerLaunch];
+};
+static_assert(sizeof(ViewBatch) <= 4000, "kernel argument size");
+
+__global__ void write_views_kernel(ViewBatch b, int count, ViewParams* dst)
+{
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&b.v[0]);
+    uint32_t* out = reinterpret_cast<uint32_t*>(dst);
+    const int words = count * (int)(sizeof(ViewParams) / 4);
+    for (int k = threadIdx.x; k < words; k += blockDim.x) out[k] = src[k];
+}
+
+// tiles_x of every global tile row (rows of view v are [row_base, row_base + tiles_y))
+__global__ void row_table_kernel(const ViewParams* views, int n_views, uint32_t* row_tiles_x, int rows)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    int lo = 0, hi = n_views;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)views[mid].row_base <= r) lo = mid;
+        else hi = mid;
+    }
+    row_tiles_x[r] = (uint32_t)views[lo].tiles_x;
+}
+
+
+// One render of n_views views of the scene g (validated by the caller).
+gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector<ViewParams>& hv,
+                       const gs_render_opts* opts, hipStream_t s)
+{
+    gs_status st;
+    gs_render_opts o{};
+    o.tile_size = kTile;
+    if (opts) o = *opts;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    ctx->have_render = false;
+
+    const int V = (int)hv.size();
+    const int64_t n = g->n;
+    const int64_t items = n * V;
+    const int rows = (int)(hv.back().row_base + hv.back().tiles_y);
+    const int64_t T = (int64_t)hv.back().tile_base + (int64_t)hv.back().tiles_x * hv.back().tiles_y;
+    int max_tx = 0;
+    for (const ViewParams& v : hv) max_tx = std::max(max_tx, v.tiles_x);
+    const size_t ni = (size_t)(items > 0 ? items : 1);
+    const int chunks1 = std::max(bin_level1_chunks(n), 1);
+
+    if ((st = ensure(ctx, ctx->splats, ni * sizeof(Splat))) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->depth_key, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->radius, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->tiles_touched, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->rect, ni * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->sort_ka, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->sort_va, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->sort_kb, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->sort_vb, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->hist, depth_sort_hist_elems(n, V) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->partials, project_partials_elems(n, V) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->views, (size_t)V * sizeof(ViewParams))) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->view_counts, (size_t)V * kViewCounters * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->row_tiles_x, (size_t)rows * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->bin_info, bin_info_elems(rows) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->rows_off, (size_t)(rows + 1) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->counts1, (size_t)chunks1 * rows * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->counters, 64)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
+
+    ViewParams* views = static_cast<ViewParams*>(ctx->views.p);
+    uint32_t* counters = static_cast<uint32_t*>(ctx->counters.p);
+    uint32_t* view_counts = static_cast<uint32_t*>(ctx->view_counts.p);
+    HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
+    for (int v0 = 0; v0 < V; v0 += kViewsPerLaunch) {
+        ViewBatch b;
+        const int cnt = std::min(kViewsPerLaunch, V - v0);
+        std::memcpy(b.v, hv.data() + v0, (size_t)cnt * sizeof(ViewParams));
+        hipLaunchKernelGGL(write_views_kernel, dim3(1), dim3(256), 0, s, b, cnt, views + v0);
+    }
+    hipLaunchKernelGGL(row_table_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, (const ViewParams*)views,
+                       V, static_cast<uint32_t*>(ctx->row_tiles_x.p), rows);
+    HIP_TRY(hipGetLastError(), "view table");
+    STAGE_MARK(0);
+
+    ProjectArgs pa{};
+    pa.n = n;
+    pa.sh_degree = g->sh_degree;
+    pa.dtype = g->attr_dtype;
+    pa.means = g->means;
+    pa.log_scales = g->log_scales;
+    pa.quats = g->quats;
+    pa.logits = g->opacity_logits;
+    pa.sh = g->sh;
+    pa.views = views;
+    pa.n_views = V;
+    pa.splats = static_cast<Splat*>(ctx->splats.p);
+    pa.depth_key = static_cast<uint32_t*>(ctx->depth_key.p);
+    pa.radius = static_cast<int32_t*>(ctx->radius.p);
+    pa.tiles_touched = static_cast<uint32_t*>(ctx->tiles_touched.p);
+    pa.rect = static_cast<ushort4*>(ctx->rect.p);
+    pa.view_counts = view_counts;
+    pa.partials = static_cast<uint32_t*>(ctx->partials.p);
+    HIP_TRY(launch_project(pa, s), "project");
+    STAGE_MARK(1);
+
+    BinArgs ba{};
+    ba.view_counts = view_counts;
+    ba.rect = pa.rect;
+    ba.n = n;
+    ba.n_views = V;
+    ba.views = views;
+    ba.row_tiles_x = static_cast<const uint32_t*>(ctx->row_tiles_x.p);
+    ba.rows = rows;
+    ba.tiles = T;
+    ba.chunks1 = chunks1;
+    ba.info = static_cast<uint32_t*>(ctx->bin_info.p);
+    ba.counts1 = static_cast<uint32_t*>(ctx->counts1.p);
+    ba.rows_off = static_cast<uint32_t*>(ctx->rows_off.p);
+    ba.tile_offsets = static_cast<uint32_t*>(ctx->tile_offsets.p);
+    ba.overflow = counters + 1;
+    uint64_t capacity = o.pair_capacity;
+    // pair_capacity > 0: every size below is the bound the capacity implies
+    // (row entries <= pairs); else the host reads K, R and the level-2 sizes
+    // once
+    ba.row_capacity = capacity ? capacity : ~0ull;
+    ba.max_chunks2 = capacity ? bin_level2_chunk_bound(capacity, rows) : (1 << 30);
+    ba.counts2_capacity = capacity ? (uint64_t)ba.max_chunks2 * max_tx : ~0ull;
+    // scan lengths: depth-sort digit counts, level-1 counts, tile offsets and
+    // (pair_capacity > 0) the level-2 counts; the eager path grows the scratch
+    // for the level-2 counts after its host read
+    int64_t scan_max = std::max<int64_t>({T + 1, (int64_t)depth_sort_hist_elems(n, V), (int64_t)rows * chunks1});
+    if (capacity) scan_max = std::max<int64_t>(scan_max, (int64_t)ba.counts2_capacity);
+    if ((st = ensure(ctx, ctx->scan_scratch, scan_scratch_elems(scan_max) * 8)) != GS_OK) return st;
+    uint64_t* scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
+    int in_b = 1;
+    HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
+                              static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
+                              static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p),
+                              scan_scratch, n, V, &in_b, s),
+            "depth sort");
+    ba.sorted_idx = static_cast<const uint32_t*>(in_b ? ctx->sort_vb.p : ctx->sort_va.p);
+    STAGE_MARK(2);
+    HIP_TRY(launch_bin_rows(ba, scan_scratch, s), "bin rows");
+    STAGE_MARK(3);
+
+    int grid2 = ba.max_chunks2;
+    if (capacity == 0) {
+        // eager: one host read of the per-view pairs, R and the level-2 sizes
+        uint32_t* hi = ctx->host_info;
+        HIP_TRY(hipMemcpyAsync(hi, view_counts, (size_t)V * kViewCounters * 4, hipMemcpyDeviceToHost, s),
+                "read view counts");
+        uint32_t* tail = hi + (size_t)kMaxViews * kViewCounters;
+        HIP_TRY(hipMemcpyAsync(tail, counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read counters");
+        HIP_TRY(hipMemcpyAsync(tail + 4, ba.rows_off + rows, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read R");
+        HIP_TRY(hipMemcpyAsync(tail + 5, ba.info, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read sizes");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        uint64_t K64 = 0;
+        for (int v = 0; v < V; ++v) {
+            const uint32_t* c = hi + (size_t)v * kViewCounters;
+            K64 += (uint64_t)c[2] | ((uint64_t)c[3] << 32);
+        }
+        if (K64 > 0xFFFFFFFFull || tail[1] != 0u)
+            return fail(ctx, GS_ERR_CAPACITY, "more than 2^32-1 (Gaussian, tile) pairs");
+        capacity = K64;
+        ba.row_capacity = tail[4];
+        grid2 = (int)tail[5];
+        ba.max_chunks2 = grid2;
+        ba.counts2_capacity = tail[6];
+    }
+    ba.capacity = capacity;
+    // the device is idle here in eager mode (host read above), so growing the
+    // scan scratch cannot pull memory from under a queued kernel
+    if ((st = ensure(ctx, ctx->scan_scratch, scan_scratch_elems((int64_t)std::max<uint64_t>(ba.counts2_capacity, 1)) *
+                                                 8)) != GS_OK)
+        return st;
+    scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
+    const size_t rows_cap = (size_t)std::max<uint64_t>(ba.row_capacity, 1);
+    if ((st = ensure(ctx, ctx->row_ent, rows_cap * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->counts2, (size_t)std::max<uint64_t>(ba.counts2_capacity, 1) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->values, (size_t)std::max<uint64_t>(capacity, 1) * 4)) != GS_OK) return st;
+    ba.row_ent = static_cast<uint2*>(ctx->row_ent.p);
+    ba.counts2 = static_cast<uint32_t*>(ctx->counts2.p);
+    ba.values = static_cast<uint32_t*>(ctx->values.p);
+    STAGE_MARK(4);
+    HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
+    STAGE_MARK(5);
+    HIP_TRY(launch_bin_tiles(ba, grid2, scan_scratch, s), "bin tile counts");
+    STAGE_MARK(6);
+    HIP_TRY(launch_bin_tile_scatter(ba, grid2, s), "bin tile scatter");
+    STAGE_MARK(7);
+
+    BlendArgs bl{};
+    bl.splats = pa.splats;
+    bl.values = ba.values;
+    bl.tile_offsets = ba.tile_offsets;
+    bl.views = views;
+    bl.n_views = V;
+    bl.tiles = T;
+    const float zero_bg[3] = {0.f, 0.f, 0.f};
+    const float* bg = opts ? o.background : zero_bg;
+    for (int k = 0; k < 3; ++k) bl.bg[k] = bg[k];
+    bl.tile_work = nullptr;
+    if (ctx->profiling & GS_PROFILE_BLEND_WORK) {
+        if ((st = ensure(ctx, ctx->tile_work, (size_t)std::max<int64_t>(T, 1) * kTileWorkFields * 8)) != GS_OK)
+            return st;
+        bl.tile_work = static_cast<unsigned long long*>(ctx->tile_work.p);
+    }
+    HIP_TRY(launch_blend(bl, capacity, s), "blend");
+    STAGE_MARK(8);
+
+    ctx->have_render = true;
+    ctx->timed = (ctx->profiling & GS_PROFILE_STAGES) != 0;
+    ctx->traced = bl.tile_work != nullptr;
+    ctx->n = n;
+    ctx->n_views = V;
+    ctx->tiles_x = hv[0].tiles_x;
+    ctx->tiles_y = hv[0].tiles_y;
+    ctx->tiles = T;
+    ctx->rows = rows;
+    ctx->capacity = capacity;
+    ctx->sorted_in_b = in_b;
+    ctx->stream = s;
+    return GS_OK;
+}
+
+// The device-table entry of one view; tile_base / row_base follow the views
+// before it.
+ViewParams make_view(const gs_camera* cam, int32_t width, int32_t height, float* out_rgb, float* out_T,
+                     uint32_t* out_nc, uint32_t tile_base, uint32_t row_base)
+{
+    ViewParams v{};
+    for (int k = 0; k < 9; ++k) v.R[k] = cam->R[k];
+    for (int k = 0; k < 3; ++k) v.t[k] = cam->t[k];
+    v.fx = cam->fx;
+    v.fy = cam->fy;
+    v.cx = cam->cx;
+    v.cy = cam->cy;
+    v.near_plane = cam->near_plane;
+    for (int k = 0; k < 3; ++k)   // camera centre -R^T t
+        v.campos[k] = (float)-(v.R[k] * v.t[0] + v.R[3 + k] * v.t[1] + v.R[6 + k] * v.t[2]);
+    v.width = width;
+    v.height = height;
+    v.tiles_x = (width + kTile - 1) / kTile;
+    v.tiles_y = (height + kTile - 1) / kTile;
+    v.tile_base = tile_base;
+    v.row_base = row_base;
+    v.out_rgb = out_rgb;
+    v.out_T = out_T;
+    v.out_nc = out_nc;
+    return v;
+}
 
 }  // namespace
 
@@ -150,7 +432,8 @@ gs_status gs_create(int device, gs_context** out)
     ctx->device = device;
     e = hipSetDevice(device);
     if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&ctx->host_info), sizeof(uint32_t) * 32);
+        e = hipHostMalloc(reinterpret_cast<void**>(&ctx->host_info),
+                          sizeof(uint32_t) * ((size_t)kMaxViews * kViewCounters + 16));
     if (e != hipSuccess) {
         delete ctx;
         return hip_fail(nullptr, e, "context set-up");
@@ -166,8 +449,8 @@ void gs_destroy(gs_context* ctx)
     DevBuf* bufs[] = {&ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
                       &ctx->sort_ka, &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb, &ctx->hist,
                       &ctx->scan_scratch, &ctx->bin_info, &ctx->counts1, &ctx->rows_off, &ctx->row_ent,
-                      &ctx->counts2, &ctx->partials,
-                      &ctx->counters, &ctx->tile_offsets, &ctx->values};
+                      &ctx->counts2, &ctx->partials, &ctx->views, &ctx->row_tiles_x, &ctx->view_counts,
+                      &ctx->counters, &ctx->tile_offsets, &ctx->values, &ctx->tile_work};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->host_info) (void)hipHostFree(ctx->host_info);
@@ -194,185 +477,35 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
     gs_status st = validate(ctx, g, cam, width, height, opts, out_rgb);
     if (st != GS_OK) return st;
-    gs_render_opts o{};
-    o.tile_size = kTile;
-    if (opts) o = *opts;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    std::vector<ViewParams> hv(1, make_view(cam, width, height, out_rgb, out_final_T, out_n_contrib, 0u, 0u));
+    return render_views(ctx, g, hv, opts, static_cast<hipStream_t>(stream));
+}
 
-    const int64_t n = g->n;
-    const int tiles_x = (width + kTile - 1) / kTile, tiles_y = (height + kTile - 1) / kTile;
-    const int64_t T = (int64_t)tiles_x * tiles_y;
-    const size_t nn = (size_t)(n > 0 ? n : 1);
-
-    if ((st = ensure(ctx, ctx->splats, nn * sizeof(Splat))) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->depth_key, nn * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->radius, nn * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->tiles_touched, nn * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->rect, nn * 8)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->sort_ka, nn * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->sort_va, nn * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->sort_kb, nn * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->sort_vb, nn * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->hist, depth_sort_hist_elems(n) * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->partials, project_partials_elems(n) * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->bin_info, bin_info_elems(tiles_y) * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->rows_off, (size_t)(tiles_y + 1) * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->counts1, (size_t)std::max(bin_level1_chunks(n), 1) * tiles_y * 4)) != GS_OK)
-        return st;
-    if ((st = ensure(ctx, ctx->counters, 128)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
-
-    uint32_t* counters = static_cast<uint32_t*>(ctx->counters.p);
-    HIP_TRY(launch_fill_u32(counters, 0u, 32, s), "clear counters");
-    STAGE_MARK(0);
-
-    ProjectArgs pa{};
-    pa.n = n;
-    pa.sh_degree = g->sh_degree;
-    pa.dtype = g->attr_dtype;
-    pa.means = g->means;
-    pa.log_scales = g->log_scales;
-    pa.quats = g->quats;
-    pa.logits = g->opacity_logits;
-    pa.sh = g->sh;
-    for (int k = 0; k < 9; ++k) pa.R[k] = cam->R[k];
-    for (int k = 0; k < 3; ++k) pa.t[k] = cam->t[k];
-    pa.fx = cam->fx;
-    pa.fy = cam->fy;
-    pa.cx = cam->cx;
-    pa.cy = cam->cy;
-    pa.near_plane = cam->near_plane;
-    for (int k = 0; k < 3; ++k)   // camera centre -R^T t
-        pa.campos[k] = (float)-(pa.R[k] * pa.t[0] + pa.R[3 + k] * pa.t[1] + pa.R[6 + k] * pa.t[2]);
-    pa.width = width;
-    pa.height = height;
-    pa.tiles_x = tiles_x;
-    pa.tiles_y = tiles_y;
-    pa.splats = static_cast<Splat*>(ctx->splats.p);
-    pa.depth_key = static_cast<uint32_t*>(ctx->depth_key.p);
-    pa.radius = static_cast<int32_t*>(ctx->radius.p);
-    pa.tiles_touched = static_cast<uint32_t*>(ctx->tiles_touched.p);
-    pa.rect = static_cast<ushort4*>(ctx->rect.p);
-    pa.n_visible = counters;
-    pa.k_total = reinterpret_cast<unsigned long long*>(counters + 12);
-    pa.partials = static_cast<uint32_t*>(ctx->partials.p);
-    HIP_TRY(launch_project(pa, s), "project");
-    STAGE_MARK(1);
-
-    BinArgs ba{};
-    ba.n_visible = counters;
-    ba.rect = pa.rect;
-    ba.n = n;
-    ba.tiles_x = tiles_x;
-    ba.tiles_y = tiles_y;
-    ba.chunks1 = bin_level1_chunks(n);
-    ba.info = static_cast<uint32_t*>(ctx->bin_info.p);
-    ba.counts1 = static_cast<uint32_t*>(ctx->counts1.p);
-    ba.rows_off = static_cast<uint32_t*>(ctx->rows_off.p);
-    ba.tile_offsets = static_cast<uint32_t*>(ctx->tile_offsets.p);
-    ba.overflow = counters + 1;
-    uint64_t capacity = o.pair_capacity;
-    // pair_capacity > 0: every size below is the bound the capacity implies
-    // (row entries <= pairs); else the host reads K, R and the chunk count once
-    ba.row_capacity = capacity ? capacity : ~0ull;
-    ba.max_chunks2 = capacity ? bin_level2_chunk_bound(capacity, tiles_y) : (1 << 30);
-    // scan lengths: depth-sort digit counts, level-1 counts, tile offsets, and
-    // (pair_capacity > 0) the bound on the level-2 counts; the eager path
-    // grows the scratch for the level-2 counts after its host read
-    int64_t scan_max = std::max<int64_t>({T + 1, (int64_t)depth_sort_hist_elems(n),
-                                          (int64_t)tiles_y * std::max(ba.chunks1, 1)});
-    if (capacity) scan_max = std::max<int64_t>(scan_max, (int64_t)ba.max_chunks2 * tiles_x);
-    const size_t scan0 = scan_scratch_elems(scan_max);
-    if ((st = ensure(ctx, ctx->scan_scratch, scan0 * 8)) != GS_OK) return st;
-    uint64_t* scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);   // re-read after growth below
-    int in_b = 1;
-    HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
-                              static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
-                              static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p),
-                              scan_scratch, n, &in_b, s),
-            "depth sort");
-    ba.sorted_idx = static_cast<const uint32_t*>(in_b ? ctx->sort_vb.p : ctx->sort_va.p);
-    STAGE_MARK(2);
-    HIP_TRY(launch_bin_rows(ba, scan_scratch, s), "bin rows");
-    STAGE_MARK(3);
-
-    int grid2 = ba.max_chunks2;
-    if (capacity == 0) {
-        // eager: one host read of K, R and the level-2 chunk count
-        HIP_TRY(hipMemcpyAsync(ctx->host_info, counters, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s),
-                "read counters");
-        HIP_TRY(hipMemcpyAsync(ctx->host_info + 16, ba.rows_off + tiles_y, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                               s),
-                "read R");
-        HIP_TRY(hipMemcpyAsync(ctx->host_info + 17, ba.info, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
-                "read chunk count");
-        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-        uint64_t K64;
-        std::memcpy(&K64, ctx->host_info + 12, sizeof K64);
-        if (K64 > 0xFFFFFFFFull || ctx->host_info[1] != 0u) {
-            ctx->have_render = false;
-            return fail(ctx, GS_ERR_CAPACITY, "more than 2^32-1 (Gaussian, tile) pairs");
-        }
-        capacity = K64;
-        ba.row_capacity = ctx->host_info[16];
-        grid2 = (int)ctx->host_info[17];
-        ba.max_chunks2 = grid2;
+gs_status gs_render_batched(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
+                            const gs_render_opts* opts, void* stream)
+{
+    if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
+    gs_status st = validate_gaussians(ctx, g);
+    if (st == GS_OK) st = validate_opts(ctx, opts);
+    if (st != GS_OK) return st;
+    if (!views) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "views is NULL");
+    if (n_views < 1 || n_views > kMaxViews) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "n_views must lie in [1, 1024]");
+    if ((int64_t)n_views * g->n > 0xFFFFFFFFll)
+        return fail(ctx, GS_ERR_UNSUPPORTED, "n_views * n must stay below 2^32");
+    std::vector<ViewParams> hv;
+    hv.reserve((size_t)n_views);
+    int64_t tile_base = 0, row_base = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const gs_view& w = views[v];
+        if ((st = validate_view(ctx, &w.camera, w.width, w.height, w.out_rgb)) != GS_OK) return st;
+        hv.push_back(make_view(&w.camera, w.width, w.height, w.out_rgb, w.out_final_T, w.out_n_contrib,
+                               (uint32_t)tile_base, (uint32_t)row_base));
+        tile_base += (int64_t)hv.back().tiles_x * hv.back().tiles_y;
+        row_base += hv.back().tiles_y;
+        if (row_base > kMaxTotalRows) return fail(ctx, GS_ERR_UNSUPPORTED, "more than 16384 tile rows over all views");
+        if (tile_base >= (int64_t(1) << 31)) return fail(ctx, GS_ERR_UNSUPPORTED, "too many tiles over all views");
     }
-    ba.capacity = capacity;
-    // the device is idle here in eager mode (host read above), so growing the
-    // scan scratch cannot pull memory from under a queued kernel
-    if ((st = ensure(ctx, ctx->scan_scratch, scan_scratch_elems((int64_t)std::max(grid2, 1) * tiles_x) * 8)) != GS_OK)
-        return st;
-    scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
-    const size_t rows_cap = (size_t)std::max<uint64_t>(ba.row_capacity, 1);
-    if ((st = ensure(ctx, ctx->row_ent, rows_cap * 8)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->counts2, (size_t)std::max(grid2, 1) * tiles_x * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->values, (size_t)std::max<uint64_t>(capacity, 1) * 4)) != GS_OK) return st;
-    ba.row_ent = static_cast<uint2*>(ctx->row_ent.p);
-    ba.counts2 = static_cast<uint32_t*>(ctx->counts2.p);
-    ba.values = static_cast<uint32_t*>(ctx->values.p);
-    STAGE_MARK(4);
-    HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
-    STAGE_MARK(5);
-    HIP_TRY(launch_bin_tiles(ba, grid2, scan_scratch, s), "bin tile counts");
-    STAGE_MARK(6);
-    HIP_TRY(launch_bin_tile_scatter(ba, grid2, s), "bin tile scatter");
-    STAGE_MARK(7);
-
-    BlendArgs bl{};
-    bl.splats = pa.splats;
-    bl.values = ba.values;
-    bl.tile_offsets = ba.tile_offsets;
-    bl.width = width;
-    bl.height = height;
-    bl.tiles_x = tiles_x;
-    bl.tiles_y = tiles_y;
-    const float zero_bg[3] = {0.f, 0.f, 0.f};
-    const float* bg = opts ? o.background : zero_bg;
-    for (int k = 0; k < 3; ++k) bl.bg[k] = bg[k];
-    bl.out_rgb = out_rgb;
-    bl.out_T = out_final_T;
-    bl.out_nc = out_n_contrib;
-    bl.tile_work = nullptr;
-    if (ctx->profiling & GS_PROFILE_BLEND_WORK) {
-        if ((st = ensure(ctx, ctx->tile_work, (size_t)std::max<int64_t>(T, 1) * kTileWorkFields * 8)) != GS_OK)
-            return st;
-        bl.tile_work = static_cast<unsigned long long*>(ctx->tile_work.p);
-    }
-    HIP_TRY(launch_blend(bl, capacity, s), "blend");
-    STAGE_MARK(8);
-
-    ctx->have_render = true;
-    ctx->timed = (ctx->profiling & GS_PROFILE_STAGES) != 0;
-    ctx->traced = bl.tile_work != nullptr;
-    ctx->n = n;
-    ctx->tiles_x = tiles_x;
-    ctx->tiles_y = tiles_y;
-    ctx->capacity = capacity;
-    ctx->sorted_in_b = in_b;
-    ctx->stream = s;
-    return GS_OK;
+    return render_views(ctx, g, hv, opts, static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out)
@@ -380,19 +513,28 @@ gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out)
     if (!ctx || !out) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
     if (!ctx->have_render) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "no render on this context yet");
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-    uint32_t c[16], r32 = 0;
+    std::vector<uint32_t> vc((size_t)ctx->n_views * kViewCounters);
+    uint32_t c[4], r32 = 0;
+    HIP_TRY(hipMemcpyAsync(vc.data(), ctx->view_counts.p, vc.size() * 4, hipMemcpyDeviceToHost, ctx->stream),
+            "read view counts");
     HIP_TRY(hipMemcpyAsync(c, ctx->counters.p, sizeof c, hipMemcpyDeviceToHost, ctx->stream), "read counters");
-    HIP_TRY(hipMemcpyAsync(&r32, static_cast<uint32_t*>(ctx->rows_off.p) + ctx->tiles_y, sizeof r32,
+    HIP_TRY(hipMemcpyAsync(&r32, static_cast<uint32_t*>(ctx->rows_off.p) + ctx->rows, sizeof r32,
                            hipMemcpyDeviceToHost, ctx->stream),
             "read R");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    uint64_t K, R = r32;
-    std::memcpy(&K, c + 12, 8);
+    uint64_t K = 0, vis = 0;
+    for (int v = 0; v < ctx->n_views; ++v) {
+        vis += vc[(size_t)v * kViewCounters];
+        K += (uint64_t)vc[(size_t)v * kViewCounters + 2] | ((uint64_t)vc[(size_t)v * kViewCounters + 3] << 32);
+    }
+    const uint64_t R = r32;
     out->num_pairs = K;
     out->num_row_entries = R;
     out->tiles_x = ctx->tiles_x;
     out->tiles_y = ctx->tiles_y;
-    out->n_visible = c[0];
+    out->n_visible = (int64_t)vis;
+    out->num_tiles = ctx->tiles;
+    out->num_views = ctx->n_views;
     if (c[1] != 0 || K > ctx->capacity || R > K)
         return fail(ctx, GS_ERR_CAPACITY, "the last render produced more pairs than pair_capacity");
     return GS_OK;
@@ -404,7 +546,7 @@ gs_status gs_copy_lists(gs_context* ctx, uint32_t* values, uint32_t* tile_offset
     gs_status st = gs_get_list_info(ctx, &info);
     if (st != GS_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t T = (int64_t)ctx->tiles_x * ctx->tiles_y;
+    const int64_t T = ctx->tiles;
     if (values && info.num_pairs)
         HIP_TRY(hipMemcpyAsync(values, ctx->values.p, info.num_pairs * 4, hipMemcpyDeviceToDevice, s), "copy values");
     if (tile_offsets)
@@ -425,7 +567,7 @@ gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key
     if (!ctx->have_render) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "no render on this context yet");
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t n = (size_t)ctx->n;
+    const size_t n = (size_t)ctx->n * (size_t)ctx->n_views;
     if (n == 0) return GS_OK;
     if (splats) HIP_TRY(hipMemcpyAsync(splats, ctx->splats.p, n * sizeof(Splat), hipMemcpyDeviceToDevice, s), "copy");
     if (depth_key) HIP_TRY(hipMemcpyAsync(depth_key, ctx->depth_key.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
@@ -468,7 +610,7 @@ gs_status read_tile_work(gs_context* ctx, std::vector<uint64_t>& w)
 {
     if (!ctx->have_render || !ctx->traced)
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render did not count blend work (GS_PROFILE_BLEND_WORK)");
-    const size_t T = (size_t)ctx->tiles_x * ctx->tiles_y;
+    const size_t T = (size_t)ctx->tiles;
     w.assign(T * kTileWorkFields, 0);
     if (T == 0) return GS_OK;
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
@@ -503,8 +645,8 @@ gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats4)
 gs_status gs_get_blend_tile_work(gs_context* ctx, uint64_t* work, int64_t tiles)
 {
     if (!ctx || !work) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
-    if (!ctx->have_render || tiles != (int64_t)ctx->tiles_x * ctx->tiles_y)
-        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "tiles must be tiles_x * tiles_y of the last render");
+    if (!ctx->have_render || tiles != ctx->tiles)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "tiles must be the tile count of the last render");
     std::vector<uint64_t> w;
     gs_status st = read_tile_work(ctx, w);
     if (st != GS_OK) return st;

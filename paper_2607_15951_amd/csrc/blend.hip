@@ -81,18 +81,21 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     __shared__ float4 s2[256 + kUnroll];   // r, g, b, list position (int bits)
     __shared__ uint32_t s_mask[256 + kUnroll];   // quads (waves) the entry can reach
     __shared__ uint32_t s_wave_keep[4];
-    const int T = a.tiles_x * a.tiles_y;
     const int i = (int)(blockIdx.x >> 3);
     const int tile = ((i / kGroup) * 8 + (int)(blockIdx.x & 7)) * kGroup + i % kGroup;
-    if (tile >= T) return;
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    if (tile >= a.tiles) return;
+    // the view owning this global tile: its size, tile grid and outputs
+    const ViewParams& vp = a.views[view_of_tile(a.views, a.n_views, (uint32_t)tile)];
+    const int width = vp.width, height = vp.height;
+    const int local = tile - (int)vp.tile_base;
+    const int tx = local % vp.tiles_x, ty = local / vp.tiles_x;
     // the wave index is uniform: readfirstlane lets the compiler keep it scalar
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t t_start = kStats ? wall_clock64() : 0ull;
     // each wave owns one 8x8 quad of the tile
     const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
     const int px = tx * kTile + lx, py = ty * kTile + ly;
-    const bool inside = px < a.width && py < a.height;
+    const bool inside = px < width && py < height;
     uint64_t start = a.tile_offsets[tile], end = a.tile_offsets[tile + 1];
     if (end > capacity) end = capacity;
     if (start > end) start = end;
@@ -228,13 +231,14 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
         }
     }
     if (!inside) return;
-    const int64_t P = (int64_t)a.width * a.height;
-    const int64_t p = (int64_t)py * a.width + px;
-    a.out_rgb[p] = fmaf(Tr, a.bg[0], c0);
-    a.out_rgb[P + p] = fmaf(Tr, a.bg[1], c1);
-    a.out_rgb[2 * P + p] = fmaf(Tr, a.bg[2], c2);
-    if (a.out_T) a.out_T[p] = Tr;
-    if (a.out_nc) a.out_nc[p] = last;
+    const int64_t P = (int64_t)width * height;
+    const int64_t p = (int64_t)py * width + px;
+    float* out_rgb = vp.out_rgb;
+    out_rgb[p] = fmaf(Tr, a.bg[0], c0);
+    out_rgb[P + p] = fmaf(Tr, a.bg[1], c1);
+    out_rgb[2 * P + p] = fmaf(Tr, a.bg[2], c2);
+    if (vp.out_T) vp.out_T[p] = Tr;
+    if (vp.out_nc) vp.out_nc[p] = last;
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n)
@@ -258,8 +262,9 @@ __global__ __launch_bounds__(256) void write_keys_kernel(const uint32_t* __restr
 
 hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s)
 {
-    const int T = a.tiles_x * a.tiles_y;
-    const int blocks = 8 * kGroup * ((T + 8 * kGroup - 1) / (8 * kGroup));
+    const int64_t T = a.tiles;
+    if (T <= 0) return hipSuccess;
+    const int blocks = (int)(8 * kGroup * ((T + 8 * kGroup - 1) / (8 * kGroup)));
     if (a.tile_work) hipLaunchKernelGGL(blend_kernel<true>, dim3(blocks), dim3(256), 0, s, a, capacity);
     else hipLaunchKernelGGL(blend_kernel<false>, dim3(blocks), dim3(256), 0, s, a, capacity);
     return hipGetLastError();

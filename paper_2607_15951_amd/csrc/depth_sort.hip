@@ -7,8 +7,11 @@
 // K ~ 80 N pairs.  The tile digit is then one stable counting pass
 // (tile_bin.hip) that writes each pair straight to its sorted position.
 //
+// Several views are sorted at once as segments of one array (one segment per
+// view, items v * n + i); no block straddles two segments.
+//
 // Each 8-bit pass is reduce-then-scan: an LDS histogram per block, one
-// exclusive scan of the digit-major [digit][block] table, and a stable
+// exclusive scan of the digit-major [segment][digit][block] table, and a stable
 // scatter that ranks equal digits with wavefront ballots (lower lanes and
 // earlier waves first).  Keys of Gaussians that overlap no tile are
 // 0xFFFFFFFF and sink to the end; values start as the Gaussian index, so ties
@@ -18,38 +21,52 @@
 namespace gsmi {
 namespace {
 
+// Block b sorts part lb = b % bpv of segment v = b / bpv: items
+// [v * n + lb * kSortTile, min(.. + kSortTile, (v + 1) * n)).  The digit table
+// is [segment][digit][part], so its exclusive scan keeps the segments apart
+// and stable within each.
+__device__ __forceinline__ void sort_block_range(int64_t n, int bpv, int64_t* begin, int64_t* end, int64_t* row)
+{
+    const int v = (int)(blockIdx.x / (unsigned)bpv), lb = (int)(blockIdx.x % (unsigned)bpv);
+    *begin = (int64_t)v * n + (int64_t)lb * kSortTile;
+    const int64_t seg_end = (int64_t)(v + 1) * n;
+    *end = (*begin + kSortTile < seg_end) ? *begin + kSortTile : seg_end;
+    *row = (int64_t)v * 256 * bpv + lb;   // table index of digit 0; digit d adds d * bpv
+}
+
 __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
-                                                                 int shift, uint32_t* __restrict__ hist,
-                                                                 int nblocks)
+                                                                 int shift, uint32_t* __restrict__ hist, int bpv)
 {
     __shared__ uint32_t h[4][256];   // one private histogram per wave
     const int tid = threadIdx.x, wave = tid >> 6;
 #pragma unroll
     for (int w = 0; w < 4; ++w) h[w][tid] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    int64_t begin, end, row;
+    sort_block_range(n, bpv, &begin, &end, &row);
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
-        const int64_t idx = base + k * kSortBlock + tid;
-        if (idx < n) atomicAdd(&h[wave][(keys[idx] >> shift) & 255u], 1u);
+        const int64_t idx = begin + k * kSortBlock + tid;
+        if (idx < end) atomicAdd(&h[wave][(keys[idx] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)tid * nblocks + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+    hist[row + (int64_t)tid * bpv] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
 }
 
 __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, int64_t n, int shift, const uint32_t* __restrict__ offsets, int nblocks)
+    uint32_t* __restrict__ vals_out, int64_t n, int shift, const uint32_t* __restrict__ offsets, int bpv)
 {
     __shared__ uint32_t base[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    base[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+    int64_t begin, end, row;
+    sort_block_range(n, bpv, &begin, &end, &row);
+    base[tid] = offsets[row + (int64_t)tid * bpv];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t blk = (int64_t)blockIdx.x * kSortTile;
     __syncthreads();
     for (int k = 0; k < kSortItems; ++k) {
-        const int64_t idx = blk + k * kSortBlock + tid;
-        const bool valid = idx < n;
+        const int64_t idx = begin + k * kSortBlock + tid;
+        const bool valid = idx < end;
         const uint32_t key = valid ? keys_in[idx] : 0u;
         const uint32_t val = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
         const uint32_t d = (key >> shift) & 255u;
@@ -81,32 +98,35 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
 
 }  // namespace
 
-size_t depth_sort_hist_elems(int64_t n)
+size_t depth_sort_hist_elems(int64_t n, int n_views)
 {
-    const int64_t nb = (n + kSortTile - 1) / kSortTile;
+    const int64_t bpv = (n + kSortTile - 1) / kSortTile;
+    const int64_t nb = bpv * (n_views > 0 ? n_views : 1);
     return (size_t)(256 * (nb > 0 ? nb : 1));
 }
 
-// Sorts keys_in[0..n) (not modified) with values 0..n-1.  Four passes:
-// in -> a -> b -> a -> b, so the sorted keys/values end in (keys_b, vals_b).
+// Sorts each of the n_views segments keys_in[v * n .. (v + 1) * n) (not
+// modified) with values v * n + i.  Four passes: in -> a -> b -> a -> b, so
+// the sorted keys/values end in (keys_b, vals_b).
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
-                             uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch, int64_t n, int* result_in_b,
-                             hipStream_t s)
+                             uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch, int64_t n, int n_views,
+                             int* result_in_b, hipStream_t s)
 {
     *result_in_b = 1;
-    if (n == 0) return hipSuccess;
-    const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+    if (n == 0 || n_views <= 0) return hipSuccess;
+    const int bpv = (int)((n + kSortTile - 1) / kSortTile);
+    const unsigned nblocks = (unsigned)bpv * (unsigned)n_views;
     const uint32_t* kin = keys_in;
     const uint32_t* vin = nullptr;
     uint32_t* kout = keys_a;
     uint32_t* vout = vals_a;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, hist, nblocks);
+        hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, hist, bpv);
         hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblocks, scan_scratch, nullptr, nullptr, nullptr, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n,
-                           shift, hist, nblocks);
+                           shift, hist, bpv);
         kin = kout;
         vin = vout;
         if (pass % 2 == 0) {

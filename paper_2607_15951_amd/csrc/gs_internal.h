@@ -19,6 +19,7 @@ constexpr int kItemsL1 = 8;               // depth-sorted Gaussians per lane of 
 constexpr int kItemsL2 = 16;              // row entries per lane of a level-2 binning wave
 constexpr int kTileWorkFields = 6;        // u64 fields of a per-tile blend trace record
 constexpr int kMaxRows = 2048;            // tile rows per image (height <= 32768)
+constexpr int kMaxTotalRows = 16384;      // tile rows over all views of one render
 
 // One projected Gaussian as the blend reads it: 3 x float4 = 48 bytes.
 //   a = (u_hi, v_hi, u_lo, v_lo)   2D centre as a float pair of the double
@@ -28,8 +29,38 @@ struct Splat {
     float4 a, b, c;
 };
 
+// One view of a render (a camera and its image), as the kernels read it from
+// the device view table.  A single-image render is a table of one view.
+struct ViewParams {
+    double R[9], t[3];              // world -> camera, row-major
+    double fx, fy, cx, cy, near_plane;
+    float campos[3];                // camera centre -R^T t
+    int width, height, tiles_x, tiles_y;
+    uint32_t tile_base;             // global index of the view's first tile
+    uint32_t row_base;              // global index of the view's first tile row
+    float* out_rgb;                 // [3][H][W]
+    float* out_T;                   // [H][W] or null
+    uint32_t* out_nc;               // [H][W] or null
+};
+
+// Per-view counters written on the device: [0] visible Gaussians, [2..3]
+// pairs K of the view (u64).
+constexpr int kViewCounters = 4;
+
+// Finds the view owning global tile t (views hold ascending tile bases).
+__device__ __forceinline__ int view_of_tile(const ViewParams* views, int n_views, uint32_t t)
+{
+    int lo = 0, hi = n_views;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (views[mid].tile_base <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 struct ProjectArgs {
-    int64_t n;
+    int64_t n;                // Gaussians (per view)
     int sh_degree;
     int dtype;                // 0 f32, 1 bf16, 2 f16 (all but means)
     const float* means;
@@ -37,57 +68,66 @@ struct ProjectArgs {
     const void* quats;
     const void* logits;
     const void* sh;
-    double R[9], t[3];
-    double fx, fy, cx, cy, near_plane;
-    float campos[3];
-    int width, height, tiles_x, tiles_y;
+    const ViewParams* views;  // device table
+    int n_views;
+    // outputs per item v * n + i (view v, Gaussian i)
     Splat* splats;
     uint32_t* depth_key;
     int32_t* radius;
     uint32_t* tiles_touched;
     ushort4* rect;
-    uint32_t* n_visible;
-    unsigned long long* k_total;  // sum of tiles_touched (pairs K)
-    uint32_t* partials;           // [2 * blocks] per-block visible count and pairs
+    uint32_t* view_counts;        // [n_views][kViewCounters]
+    uint32_t* partials;           // [blocks][n_views][2] per-block visible count and pairs
 };
 
-size_t project_partials_elems(int64_t n);
+size_t project_partials_elems(int64_t n, int n_views);
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
 
-// Stable LSD radix sort of n 32-bit keys with values 0..n-1, four 8-bit
-// passes; *result_in_b tells which ping-pong buffer pair holds the result.
-size_t depth_sort_hist_elems(int64_t n);
+// Stable LSD radix sort of the 32-bit keys of n_views segments of n items
+// each, four 8-bit passes, every segment sorted on its own (values start as
+// the item index v * n + i); *result_in_b tells which ping-pong buffer pair
+// holds the result.
+size_t depth_sort_hist_elems(int64_t n, int n_views);
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a,
                              uint32_t* keys_b, uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch,
-                             int64_t n, int* result_in_b, hipStream_t s);
+                             int64_t n, int n_views, int* result_in_b, hipStream_t s);
 
 struct BinArgs {
-    const uint32_t* sorted_idx;   // [n] Gaussian indices in (depth, index) order
-    const uint32_t* n_visible;    // device counter; visible Gaussians sort first
-    const ushort4* rect;          // [n] tile rectangle by Gaussian index
-    int64_t n;
-    int tiles_x, tiles_y;
-    int chunks1;                  // level-1 chunks, bin_level1_chunks(n)
-    uint32_t* info;               // level-2 chunk table (bin_info_elems(tiles_y))
-    uint32_t* counts1;            // [tiles_y][chunks1] counts -> exclusive scan = cursors
-    uint32_t* rows_off;           // [tiles_y + 1] row-list offsets; [tiles_y] = R
-    uint2* row_ent;               // [row_capacity] (Gaussian, x0 | x1 << 16)
+    const uint32_t* sorted_idx;   // [n_views * n] items (v * n + i), each view's segment in (depth, index) order
+    const uint32_t* view_counts;  // device [n_views][kViewCounters]; visible items sort first in a segment
+    const ushort4* rect;          // [n_views * n] tile rectangle of each item in its view
+    int64_t n;                    // Gaussians per view
+    int n_views;
+    const ViewParams* views;      // device table
+    const uint32_t* row_tiles_x;  // [rows] tiles_x of each global tile row
+    int rows;                     // global tile rows (sum of the views' tiles_y)
+    int64_t tiles;                // global tiles (sum of the views' tiles)
+    int chunks1;                  // level-1 chunks per view, bin_level1_chunks(n)
+    uint32_t* info;               // level-2 chunk table (bin_info_elems(rows))
+    uint32_t* counts1;            // [rows][chunks1] counts -> exclusive scan = cursors
+    uint32_t* rows_off;           // [rows + 1] row-list offsets; [rows] = R
+    uint2* row_ent;               // [row_capacity] (item, x0 | x1 << 16)
     uint64_t row_capacity;
     uint32_t* counts2;            // per row: [tiles_x][row's chunks] counts -> scan = cursors
+    uint64_t counts2_capacity;    // elements of counts2
     uint32_t* tile_offsets;       // [tiles + 1]; [tiles] = K
-    uint32_t* values;             // [capacity] sorted pair values
+    uint32_t* values;             // [capacity] sorted pair values (items)
     uint64_t capacity;
     int max_chunks2;
     uint32_t* overflow;           // set to 1 when a capacity is exceeded
 };
 
-size_t bin_info_elems(int tiles_y);
+size_t bin_info_elems(int rows);
 int bin_level1_chunks(int64_t n);
-int bin_level2_chunk_bound(uint64_t row_entries, int tiles_y);
+int bin_level2_chunk_bound(uint64_t row_entries, int rows);
 hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t s);
 hipError_t launch_bin_row_scatter(const BinArgs& a, hipStream_t s);
 hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch, hipStream_t s);
 hipError_t launch_bin_tile_scatter(const BinArgs& a, int grid2, hipStream_t s);
+// info[] words the host reads after launch_bin_rows: level-2 chunks, level-2
+// count elements
+constexpr int kInfoC2 = 0;
+constexpr int kInfoC2Elems = 1;
 
 // Device-wide exclusive scan of n uint32 values in place; 64-bit total to
 // *total64 and/or *total32 (either may be null), overflow flag when the total
@@ -101,11 +141,10 @@ struct BlendArgs {
     const Splat* splats;
     const uint32_t* values;
     const uint32_t* tile_offsets;
-    int width, height, tiles_x, tiles_y;
+    const ViewParams* views;   // device table: sizes, tile bases, outputs
+    int n_views;
+    int64_t tiles;             // global tiles
     float bg[3];
-    float* out_rgb;
-    float* out_T;        // may be null
-    uint32_t* out_nc;    // may be null
     // per-tile trace when tracing (else null), [T][kTileWorkFields]: start
     // and end of the tile's workgroup (s_memrealtime, 100 MHz), entries
     // staged, wave bodies, (pixel, entry) evaluations up to each pixel's

@@ -68,23 +68,21 @@ struct Geometry {
 
 }  // namespace
 
-size_t project_partials_elems(int64_t n) { return (size_t)(2 * ((n + 255) / 256 + 1)); }
+size_t project_partials_elems(int64_t n, int n_views)
+{
+    return (size_t)(2 * ((n + 255) / 256 + 1) * (size_t)(n_views > 0 ? n_views : 1));
+}
 
 namespace {
 
-// Culling and projection in double precision.  Returns false for a culled
-// Gaussian.  The expression shapes below fix the rounding order.
-__device__ __forceinline__ bool project_geometry(const ProjectArgs& a, double mx, double my, double mz,
-                                                 double l0, double l1, double l2, double qw, double qx,
-                                                 double qy, double qz, Geometry& g)
+// World-space covariance Sg = (Q S)(Q S)^T of a Gaussian (rotation Q of the
+// normalised quaternion, S = diag(exp(log_scale))), in double precision with
+// the operation order written here.  False for a zero or non-finite
+// quaternion (the Gaussian is culled in every view).
+__device__ __forceinline__ bool world_covariance(double l0, double l1, double l2, double qw, double qx, double qy,
+                                                 double qz, double Sg[9])
 {
 #pragma clang fp contract(off)
-    const double* W = a.R;
-    const double tx = ((W[0] * mx + W[1] * my) + W[2] * mz) + a.t[0];
-    const double ty = ((W[3] * mx + W[4] * my) + W[5] * mz) + a.t[1];
-    const double tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + a.t[2];
-    if (!(tz > a.near_plane) || !isfinite(tx) || !isfinite(ty) || !isfinite(tz)) return false;
-
     const double n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
     if (!(n2 > 0.0) || !isfinite(n2)) return false;
     const double qn = sqrt(n2);
@@ -110,12 +108,26 @@ __device__ __forceinline__ bool project_geometry(const ProjectArgs& a, double mx
         M[3 * r + 1] = Q[3 * r + 1] * s1;
         M[3 * r + 2] = Q[3 * r + 2] * s2;
     }
-    double Sg[9];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             Sg[3 * r + c] = (M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1]) + M[3 * r + 2] * M[3 * c + 2];
+    return true;
+}
+
+// Culling and projection of one Gaussian (centre m, world covariance Sg) in
+// one view, in double precision.  Returns false for a culled Gaussian.  The
+// expression shapes below fix the rounding order.
+__device__ __forceinline__ bool project_view(const ViewParams& vp, double mx, double my, double mz,
+                                             const double Sg[9], Geometry& g)
+{
+#pragma clang fp contract(off)
+    const double* W = vp.R;
+    const double tx = ((W[0] * mx + W[1] * my) + W[2] * mz) + vp.t[0];
+    const double ty = ((W[3] * mx + W[4] * my) + W[5] * mz) + vp.t[1];
+    const double tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + vp.t[2];
+    if (!(tz > vp.near_plane) || !isfinite(tx) || !isfinite(ty) || !isfinite(tz)) return false;
 
     // camera-space covariance V = W Sg W^T (left product first)
     double L[9], V[9];
@@ -131,17 +143,17 @@ __device__ __forceinline__ bool project_geometry(const ProjectArgs& a, double mx
             V[3 * r + c] = (L[3 * r] * W[3 * c] + L[3 * r + 1] * W[3 * c + 1]) + L[3 * r + 2] * W[3 * c + 2];
 
     // perspective Jacobian with x/z, y/z clamped to 1.3x the half-image tangent
-    const double limx = 1.3 * ((0.5 * (double)a.width) / a.fx);
-    const double limy = 1.3 * ((0.5 * (double)a.height) / a.fy);
+    const double limx = 1.3 * ((0.5 * (double)vp.width) / vp.fx);
+    const double limy = 1.3 * ((0.5 * (double)vp.height) / vp.fy);
     const double xcl = fmin(limx, fmax(-limx, tx / tz)) * tz;
     const double ycl = fmin(limy, fmax(-limy, ty / tz)) * tz;
     double Jm[6];
-    Jm[0] = a.fx / tz;
+    Jm[0] = vp.fx / tz;
     Jm[1] = 0.0;
-    Jm[2] = -(a.fx * xcl) / (tz * tz);
+    Jm[2] = -(vp.fx * xcl) / (tz * tz);
     Jm[3] = 0.0;
-    Jm[4] = a.fy / tz;
-    Jm[5] = -(a.fy * ycl) / (tz * tz);
+    Jm[4] = vp.fy / tz;
+    Jm[5] = -(vp.fy * ycl) / (tz * tz);
     double Bm[6];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
@@ -167,8 +179,8 @@ __device__ __forceinline__ bool project_geometry(const ProjectArgs& a, double mx
     if (!(r > 0.0) || !(r < 1e9)) return false;
     g.radius = (int32_t)r;
 
-    g.u = (a.fx * tx) / tz + a.cx;
-    g.v = (a.fy * ty) / tz + a.cy;
+    g.u = (vp.fx * tx) / tz + vp.cx;
+    g.v = (vp.fy * ty) / tz + vp.cy;
     if (!isfinite(g.u) || !isfinite(g.v)) return false;
     g.tz = tz;
     return true;
@@ -198,95 +210,107 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 #pragma unroll
     for (int k = 0; k < 3 * ncoef; ++k) coef[k] = load_attr<DT>(a.sh, (int64_t)k * n + i);
 
-    Geometry g;
-    bool ok = project_geometry(a, mxf, myf, mzf, l0, l1, l2, qw, qx, qy, qz, g);
-
-    uint32_t tiles = 0;
-    ushort4 rc = make_ushort4(0, 0, 0, 0);
-    if (ok && valid) {
-        const double big = 1073741824.0;
-        const double uc = fmin(big, fmax(-big, g.u)), vc = fmin(big, fmax(-big, g.v));
-        int64_t xlo = (int64_t)ceil(uc) - g.radius, xhi = (int64_t)floor(uc) + g.radius;
-        int64_t ylo = (int64_t)ceil(vc) - g.radius, yhi = (int64_t)floor(vc) + g.radius;
-        if (!(xhi < 0 || xlo > a.width - 1 || yhi < 0 || ylo > a.height - 1)) {
-            xlo = xlo < 0 ? 0 : xlo;
-            ylo = ylo < 0 ? 0 : ylo;
-            xhi = xhi > a.width - 1 ? a.width - 1 : xhi;
-            yhi = yhi > a.height - 1 ? a.height - 1 : yhi;
-            const int x0 = (int)(xlo / kTile), x1 = (int)(xhi / kTile) + 1;
-            const int y0 = (int)(ylo / kTile), y1 = (int)(yhi / kTile) + 1;
-            rc = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1);
-            tiles = (uint32_t)((x1 - x0) * (y1 - y0));
-        }
-    }
-
-    Splat sp;
-    sp.a = sp.b = sp.c = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (tiles > 0) {
-        const float uh = (float)g.u, vh = (float)g.v;
-        sp.a = make_float4(uh, vh, (float)(g.u - (double)uh), (float)(g.v - (double)vh));
-        const float opacity = 1.0f / (1.0f + __expf(-logit));
-        sp.b = make_float4((float)g.A, (float)g.B, (float)g.C, opacity);
-        // view direction from the camera centre
-        float dx = mxf - a.campos[0], dy = myf - a.campos[1], dz = mzf - a.campos[2];
-        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-        dx *= inv;
-        dy *= inv;
-        dz *= inv;
-        float Y[16];
-        sh_basis(dx, dy, dz, DEG, Y);
-        float col[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int k = 0; k < ncoef; ++k) acc += coef[k * 3 + ch] * Y[k];
-            col[ch] = fmaxf(acc + 0.5f, 0.0f);
-        }
-        sp.c = make_float4(col[0], col[1], col[2], (float)g.tz);
-    }
-    if (valid) {
-        float4* dst = reinterpret_cast<float4*>(a.splats + i);
-        dst[0] = sp.a;
-        dst[1] = sp.b;
-        dst[2] = sp.c;
-        a.depth_key[i] = tiles > 0 ? __float_as_uint((float)g.tz) : 0xFFFFFFFFu;
-        a.radius[i] = tiles > 0 ? g.radius : 0;
-        a.tiles_touched[i] = tiles;
-        a.rect[i] = rc;
-    }
-
-    // per-block visible count and pair total (no atomics: a single counter
-    // hit by every wave serialises); reduce_partials_kernel sums them
+    double Sg[9];
+    const bool cov_ok = world_covariance(l0, l1, l2, qw, qx, qy, qz, Sg);
+    const float opacity = 1.0f / (1.0f + __expf(-logit));
     __shared__ uint32_t s_vis[4], s_pairs[4];
-    const uint64_t vis = __ballot(tiles > 0);
-    uint32_t wave_pairs = tiles;
-    for (int o = 32; o > 0; o >>= 1) wave_pairs += __shfl_xor(wave_pairs, o, 64);
-    if ((threadIdx.x & 63) == 0) {
-        s_vis[threadIdx.x >> 6] = (uint32_t)__popcll(vis);
-        s_pairs[threadIdx.x >> 6] = wave_pairs;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        a.partials[2 * blockIdx.x] = s_vis[0] + s_vis[1] + s_vis[2] + s_vis[3];
-        a.partials[2 * blockIdx.x + 1] = s_pairs[0] + s_pairs[1] + s_pairs[2] + s_pairs[3];
+
+    for (int v = 0; v < a.n_views; ++v) {
+        const ViewParams& vp = a.views[v];
+        Geometry g;
+        const bool ok = cov_ok && project_view(vp, mxf, myf, mzf, Sg, g);
+
+        uint32_t tiles = 0;
+        ushort4 rc = make_ushort4(0, 0, 0, 0);
+        if (ok && valid) {
+            const double big = 1073741824.0;
+            const double uc = fmin(big, fmax(-big, g.u)), vc = fmin(big, fmax(-big, g.v));
+            int64_t xlo = (int64_t)ceil(uc) - g.radius, xhi = (int64_t)floor(uc) + g.radius;
+            int64_t ylo = (int64_t)ceil(vc) - g.radius, yhi = (int64_t)floor(vc) + g.radius;
+            if (!(xhi < 0 || xlo > vp.width - 1 || yhi < 0 || ylo > vp.height - 1)) {
+                xlo = xlo < 0 ? 0 : xlo;
+                ylo = ylo < 0 ? 0 : ylo;
+                xhi = xhi > vp.width - 1 ? vp.width - 1 : xhi;
+                yhi = yhi > vp.height - 1 ? vp.height - 1 : yhi;
+                const int x0 = (int)(xlo / kTile), x1 = (int)(xhi / kTile) + 1;
+                const int y0 = (int)(ylo / kTile), y1 = (int)(yhi / kTile) + 1;
+                rc = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1);
+                tiles = (uint32_t)((x1 - x0) * (y1 - y0));
+            }
+        }
+
+        Splat sp;
+        sp.a = sp.b = sp.c = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (tiles > 0) {
+            const float uh = (float)g.u, vh = (float)g.v;
+            sp.a = make_float4(uh, vh, (float)(g.u - (double)uh), (float)(g.v - (double)vh));
+            sp.b = make_float4((float)g.A, (float)g.B, (float)g.C, opacity);
+            // view direction from the camera centre
+            float dx = mxf - vp.campos[0], dy = myf - vp.campos[1], dz = mzf - vp.campos[2];
+            const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            dx *= inv;
+            dy *= inv;
+            dz *= inv;
+            float Y[16];
+            sh_basis(dx, dy, dz, DEG, Y);
+            float col[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < ncoef; ++k) acc += coef[k * 3 + ch] * Y[k];
+                col[ch] = fmaxf(acc + 0.5f, 0.0f);
+            }
+            sp.c = make_float4(col[0], col[1], col[2], (float)g.tz);
+        }
+        if (valid) {
+            const int64_t o = (int64_t)v * n + i;
+            float4* dst = reinterpret_cast<float4*>(a.splats + o);
+            dst[0] = sp.a;
+            dst[1] = sp.b;
+            dst[2] = sp.c;
+            a.depth_key[o] = tiles > 0 ? __float_as_uint((float)g.tz) : 0xFFFFFFFFu;
+            a.radius[o] = tiles > 0 ? g.radius : 0;
+            a.tiles_touched[o] = tiles;
+            a.rect[o] = rc;
+        }
+
+        // per-block visible count and pair total of the view (no atomics: a
+        // single counter hit by every wave serialises); reduce_partials_kernel
+        // sums them
+        const uint64_t vis = __ballot(tiles > 0);
+        uint32_t wave_pairs = tiles;
+        for (int o = 32; o > 0; o >>= 1) wave_pairs += __shfl_xor(wave_pairs, o, 64);
+        if ((threadIdx.x & 63) == 0) {
+            s_vis[threadIdx.x >> 6] = (uint32_t)__popcll(vis);
+            s_pairs[threadIdx.x >> 6] = wave_pairs;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t* pp = a.partials + 2 * ((int64_t)blockIdx.x * a.n_views + v);
+            pp[0] = s_vis[0] + s_vis[1] + s_vis[2] + s_vis[3];
+            pp[1] = s_pairs[0] + s_pairs[1] + s_pairs[2] + s_pairs[3];
+        }
+        __syncthreads();   // s_vis / s_pairs are reused by the next view
     }
 }
 
 }  // namespace
 
-// n_visible = sum of the blocks' visible counts, k_total = sum of their pairs
+// Per view (one block each): visible Gaussians and pairs, summed over the
+// projection blocks' partials.
 __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* __restrict__ partials, int blocks,
-                                                               uint32_t* n_visible, unsigned long long* k_total)
+                                                               int n_views, uint32_t* view_counts)
 {
     __shared__ unsigned long long sv[1024], sp[1024];
-    unsigned long long v = 0, p = 0;
+    const int v = blockIdx.x;
+    unsigned long long vis = 0, pairs = 0;
     for (int b = threadIdx.x; b < blocks; b += 1024) {
-        v += partials[2 * b];
-        p += partials[2 * b + 1];
+        vis += partials[2 * ((int64_t)b * n_views + v)];
+        pairs += partials[2 * ((int64_t)b * n_views + v) + 1];
     }
-    sv[threadIdx.x] = v;
-    sp[threadIdx.x] = p;
+    sv[threadIdx.x] = vis;
+    sp[threadIdx.x] = pairs;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) {
@@ -296,8 +320,11 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* _
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        *n_visible = (uint32_t)sv[0];
-        *k_total = sp[0];
+        uint32_t* c = view_counts + (int64_t)kViewCounters * v;
+        c[0] = (uint32_t)sv[0];
+        c[1] = 0u;
+        c[2] = (uint32_t)sp[0];
+        c[3] = (uint32_t)(sp[0] >> 32);
     }
 }
 
@@ -314,15 +341,16 @@ void launch_project_dt(const ProjectArgs& a, unsigned blocks, hipStream_t s)
 
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
 {
-    if (a.n == 0) return hipSuccess;
+    if (a.n_views <= 0) return hipSuccess;
+    if (a.n == 0) return launch_fill_u32(a.view_counts, 0u, (int64_t)kViewCounters * a.n_views, s);
     const unsigned blocks = (unsigned)((a.n + 255) / 256);
     switch (a.dtype) {
     case 0: launch_project_dt<0>(a, blocks, s); break;
     case 1: launch_project_dt<1>(a, blocks, s); break;
     default: launch_project_dt<2>(a, blocks, s); break;
     }
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(1024), 0, s, (const uint32_t*)a.partials, (int)blocks,
-                       a.n_visible, a.k_total);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)a.n_views), dim3(1024), 0, s,
+                       (const uint32_t*)a.partials, (int)blocks, a.n_views, a.view_counts);
     return hipGetLastError();
 }
 

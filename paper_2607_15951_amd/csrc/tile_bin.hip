@@ -36,13 +36,19 @@ constexpr int kChunk1 = kItemsL1 * 64;   // Gaussians per level-1 wave
 constexpr int kChunk2 = kItemsL2 * 64;   // row entries per level-2 wave
 constexpr int kBand = 16;                // tile columns per band of the level-2 walk
 
-// info[] layout (uint32): [0] level-2 chunks C2, [1] C2 * tiles_x (length of
-// the level-2 count array), [2 .. tiles_y + 2] level-2 chunk prefix at each
-// row start.  Row r's level-2 counts occupy [prefix[r] * tiles_x,
-// prefix[r + 1] * tiles_x), column-major: count[x * chunks(r) + j].
-constexpr int kInfoC2 = 0;
-constexpr int kInfoC2Elems = 1;
+// info[] layout (uint32): [0] level-2 chunks C2, [1] level-2 count elements
+// E2, then for the global tile rows r = 0..rows: [kInfoRowChunks + r] level-2
+// chunk prefix, [kInfoRowChunks + rows + 1 + r] count-element prefix.  Row r
+// owns chunks(r) = prefix[r + 1] - prefix[r] chunks and the count elements
+// [eprefix[r], eprefix[r] + tiles_x(r) * chunks(r)), bucket-major:
+// count[x * chunks(r) + j].
 constexpr int kInfoRowChunks = 2;
+
+__device__ __forceinline__ const uint32_t* row_chunk_prefix(const BinArgs& a) { return a.info + kInfoRowChunks; }
+__device__ __forceinline__ const uint32_t* row_elem_prefix(const BinArgs& a)
+{
+    return a.info + kInfoRowChunks + a.rows + 1;
+}
 
 // Workgroup b -> chunk: the dispatcher deals workgroups round-robin to the 8
 // XCDs; block b takes chunk (b % 8) * ceil(grid / 8) + b / 8 so each XCD works
@@ -78,26 +84,42 @@ __device__ __forceinline__ int wave_max(int v)
 }
 
 // ------------------------------------------------------------------ level 1
-// items: depth-sorted Gaussians; buckets: tile rows; payload (index, x-span)
+// items: depth-sorted Gaussians of one view; buckets: that view's tile rows;
+// payload (item, x-span).  Level-1 chunk c belongs to view c / chunks1 and is
+// part c % chunks1 of that view's visible items (which open its segment).
 
 struct Items1 {
-    // rows [y0, y0 + h) covered; h = 0 for padding lanes
+    // rows [y0, y0 + h) covered (rows of the view); h = 0 for padding lanes
     uint32_t y0[kItemsL1], h[kItemsL1], xs[kItemsL1], g[kItemsL1];
-    int lo, hi;   // rows spanned by the chunk
+    int lo, hi;        // rows spanned by the chunk
+    int view, part;    // view, chunk index within the view
 };
+
+// Visible-item range [start, end) of level-1 chunk c; false when empty.
+__device__ __forceinline__ bool chunk1_range(const BinArgs& a, int c, int* view, int* part, int64_t* start,
+                                             int64_t* end)
+{
+    *view = c / a.chunks1;
+    *part = c % a.chunks1;
+    if (*view >= a.n_views) return false;
+    const int64_t seg = (int64_t)(*view) * a.n;
+    const int64_t nv = (int64_t)a.view_counts[(int64_t)kViewCounters * (*view)];
+    *start = seg + (int64_t)(*part) * kChunk1;
+    *end = seg + nv;
+    return *start < *end;
+}
 
 __device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, Items1& it)
 {
-    const int64_t nv = (int64_t)*a.n_visible;
-    const int64_t start = (int64_t)c * kChunk1;
-    if (start >= nv) return false;
+    int64_t start, end;
+    if (!chunk1_range(a, c, &it.view, &it.part, &start, &end)) return false;
     int lo = 1 << 30, hi = 0;
 #pragma unroll
     for (int b = 0; b < kItemsL1; ++b) {
         const int64_t k = start + b * 64 + lane;
         ushort4 r = make_ushort4(0, 0, 0, 0);
         uint32_t g = 0;
-        if (k < nv) {
+        if (k < end) {
             g = a.sorted_idx[k];
             r = a.rect[g];
             lo = (int)r.y < lo ? (int)r.y : lo;
@@ -141,22 +163,25 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
 {
     __shared__ uint32_t diff[kMaxRows + 1];
     const int lane = threadIdx.x, c = chunk_of_block();
-    if (c >= a.chunks1) return;
-    for (int r = lane; r <= a.tiles_y; r += 64) diff[r] = 0u;
+    const int view = c / a.chunks1, part = c % a.chunks1;
+    if (view >= a.n_views) return;
+    const ViewParams& vp = a.views[view];
+    for (int r = lane; r <= vp.tiles_y; r += 64) diff[r] = 0u;
     __syncthreads();
-    const int64_t nv = (int64_t)*a.n_visible;
-    const int64_t start = (int64_t)c * kChunk1;
+    int v2, p2;
+    int64_t start = 0, end = 0;
+    (void)chunk1_range(a, c, &v2, &p2, &start, &end);
 #pragma unroll
     for (int b = 0; b < kItemsL1; ++b) {
         const int64_t k = start + b * 64 + lane;
-        if (k < nv) {
+        if (k < end) {
             const ushort4 r = a.rect[a.sorted_idx[k]];
             atomicAdd(&diff[r.y], 1u);
             atomicSub(&diff[r.w], 1u);
         }
     }
     __syncthreads();
-    counts_from_diff(diff, a.tiles_y, a.counts1 + c, a.chunks1, lane);
+    counts_from_diff(diff, vp.tiles_y, a.counts1 + (int64_t)vp.row_base * a.chunks1 + part, a.chunks1, lane);
 }
 
 // Cursor windows: bucket cursors are loaded 128 at a time into two VGPRs
@@ -205,7 +230,8 @@ __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
     const int lane = threadIdx.x, c = chunk_of_block();
     Items1 it;
     if (!load_items1(a, c, lane, it)) return;
-    const uint32_t* cursor = a.counts1 + c;   // row r: cursor[r * chunks1]
+    // row r of the view: cursor[r * chunks1]
+    const uint32_t* cursor = a.counts1 + (int64_t)a.views[it.view].row_base * a.chunks1 + it.part;
     uint2 payload[kItemsL1];
 #pragma unroll
     for (int b = 0; b < kItemsL1; ++b) payload[b] = make_uint2(it.g[b], it.xs[b]);
@@ -223,57 +249,77 @@ __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
     }
 }
 
-// Row offsets and the level-2 chunk table (one 1024-thread block, two rows
-// per thread).  The scanned level-1 counts give rows_off[r] (chunk 0's cursor
-// in row r); row r owns ceil(len_r / kChunk2) level-2 chunks, and info holds
-// their prefix.  On overflow every row gets zero chunks.
+// Row offsets and the level-2 chunk table (one 1024-thread block, a run of
+// rows per thread).  The scanned level-1 counts give rows_off[r] (chunk 0's
+// cursor in row r); row r owns ceil(len_r / kChunk2) level-2 chunks and
+// tiles_x(r) count elements per chunk; info holds both prefixes.  On
+// overflow every row gets zero chunks.
+constexpr int kTableRowsPerThread = kMaxTotalRows / 1024;
+
 __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
 {
-    __shared__ uint32_t part[1024];
-    __shared__ uint32_t s_total;
-    const int tid = threadIdx.x, ty_n = a.tiles_y;
-    for (int k = 0; k < 2; ++k) {
-        const int r = 2 * tid + k;
-        if (r < ty_n) a.rows_off[r] = a.counts1[(int64_t)r * a.chunks1];
+    __shared__ uint32_t part_c[1024], part_e[1024];
+    __shared__ uint32_t s_total_c, s_total_e;
+    const int tid = threadIdx.x, rows = a.rows;
+    const int r0 = tid * kTableRowsPerThread;
+    for (int k = 0; k < kTableRowsPerThread; ++k) {
+        const int r = r0 + k;
+        if (r < rows) a.rows_off[r] = a.counts1[(int64_t)r * a.chunks1];
     }
-    __syncthreads();   // rows_off[ty_n] (= R) was written by the scan
-    uint32_t c[2] = {0u, 0u};
-    for (int k = 0; k < 2; ++k) {
-        const int r = 2 * tid + k;
-        if (r < ty_n) {
+    __syncthreads();   // rows_off[rows] (= R) was written by the scan
+    uint32_t sc = 0, se = 0;
+    for (int k = 0; k < kTableRowsPerThread; ++k) {
+        const int r = r0 + k;
+        if (r < rows) {
             const uint32_t len = a.rows_off[r + 1] - a.rows_off[r];
-            c[k] = (len + kChunk2 - 1) / kChunk2;
+            const uint32_t ch = (len + kChunk2 - 1) / kChunk2;
+            sc += ch;
+            se += ch * a.row_tiles_x[r];
         }
     }
-    part[tid] = c[0] + c[1];
+    part_c[tid] = sc;
+    part_e[tid] = se;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t t = tid >= o ? part[tid - o] : 0u;
+        const uint32_t tc = tid >= o ? part_c[tid - o] : 0u;
+        const uint32_t te = tid >= o ? part_e[tid - o] : 0u;
         __syncthreads();
-        part[tid] += t;
+        part_c[tid] += tc;
+        part_e[tid] += te;
         __syncthreads();
     }
     if (tid == 1023) {
-        uint32_t total = part[1023];
-        if ((int64_t)total > (int64_t)a.max_chunks2 || (uint64_t)a.rows_off[ty_n] > a.row_capacity) {
+        uint32_t tc = part_c[1023], te = part_e[1023];
+        if ((int64_t)tc > (int64_t)a.max_chunks2 || (uint64_t)te > a.counts2_capacity ||
+            (uint64_t)a.rows_off[rows] > a.row_capacity) {
             *a.overflow = 1u;
-            total = 0;
+            tc = te = 0;
         }
-        s_total = total;
+        s_total_c = tc;
+        s_total_e = te;
     }
     __syncthreads();
-    const uint32_t total = s_total;
-    uint32_t run = total ? part[tid] - (c[0] + c[1]) : 0u;
-    uint32_t* base = a.info + kInfoRowChunks;
-    for (int k = 0; k < 2; ++k) {
-        const int r = 2 * tid + k;
-        if (r < ty_n) base[r] = run;
-        if (total) run += c[k];
+    const bool ok = s_total_c != 0u;
+    uint32_t run_c = ok ? part_c[tid] - sc : 0u, run_e = ok ? part_e[tid] - se : 0u;
+    uint32_t* cpre = a.info + kInfoRowChunks;
+    uint32_t* epre = a.info + kInfoRowChunks + rows + 1;
+    for (int k = 0; k < kTableRowsPerThread; ++k) {
+        const int r = r0 + k;
+        if (r < rows) {
+            cpre[r] = run_c;
+            epre[r] = run_e;
+            if (ok) {
+                const uint32_t ch = (a.rows_off[r + 1] - a.rows_off[r] + kChunk2 - 1) / kChunk2;
+                run_c += ch;
+                run_e += ch * a.row_tiles_x[r];
+            }
+        }
     }
     if (tid == 0) {
-        base[ty_n] = total;
-        a.info[kInfoC2] = total;
-        a.info[kInfoC2Elems] = total * (uint32_t)a.tiles_x;
+        cpre[rows] = s_total_c;
+        epre[rows] = s_total_e;
+        a.info[kInfoC2] = s_total_c;
+        a.info[kInfoC2Elems] = s_total_e;
     }
 }
 
@@ -289,23 +335,22 @@ struct Items2 {
 };
 
 // Start of chunk c's cursors in the scanned level-2 counts: row r's block
-// starts at prefix[r] * tiles_x, column x at x * chunks(r), chunk c at
-// c - prefix[r].
+// starts at eprefix[r], column x at x * chunks(r), chunk c at c - prefix[r].
 __device__ __forceinline__ const uint32_t* level2_slot(const BinArgs& a, int row, int c, int64_t* stride)
 {
-    const uint32_t* base = a.info + kInfoRowChunks;
+    const uint32_t* base = row_chunk_prefix(a);
     *stride = (int64_t)(base[row + 1] - base[row]);
-    return a.counts2 + (int64_t)base[row] * a.tiles_x + (c - (int64_t)base[row]);
+    return a.counts2 + (int64_t)row_elem_prefix(a)[row] + (c - (int64_t)base[row]);
 }
 
 // Row and entry range [eb, ee) of level-2 chunk c.
 __device__ __forceinline__ void chunk2_range(const BinArgs& a, int c, int lane, int* row, int64_t* eb, int64_t* ee)
 {
-    const int ty_n = a.tiles_y;
-    const uint32_t* base = a.info + kInfoRowChunks;
+    const int rows = a.rows;
+    const uint32_t* base = row_chunk_prefix(a);
     // owning row: the last r with base[r] <= c (64-ary search over rows; rows
     // without chunks share base with the next row, so the last one owns c)
-    int L = 0, R = ty_n;
+    int L = 0, R = rows;
     while (R - L > 1) {
         const int step = (R - L + 63) / 64;
         const int q = L + lane * step;
@@ -316,9 +361,9 @@ __device__ __forceinline__ void chunk2_range(const BinArgs& a, int c, int lane, 
         R = (nl + step < R) ? nl + step : R;
         L = nl;
     }
-    *row = L;
-    *eb = (int64_t)a.rows_off[L] + (int64_t)((uint32_t)c - base[L]) * kChunk2;
-    const int64_t end_row = a.rows_off[L + 1];
+    *row = __builtin_amdgcn_readfirstlane(L);
+    *eb = (int64_t)a.rows_off[*row] + (int64_t)((uint32_t)c - base[*row]) * kChunk2;
+    const int64_t end_row = a.rows_off[*row + 1];
     *ee = (*eb + kChunk2 < end_row) ? *eb + kChunk2 : end_row;
 }
 
@@ -356,7 +401,8 @@ __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
     int row;
     int64_t eb, ee;
     chunk2_range(a, c, lane, &row, &eb, &ee);
-    for (int x = lane; x <= a.tiles_x; x += 64) diff[x] = 0u;
+    const int row_tx = (int)a.row_tiles_x[row];
+    for (int x = lane; x <= row_tx; x += 64) diff[x] = 0u;
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < kItemsL2; ++b) {
@@ -370,7 +416,7 @@ __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
     __syncthreads();
     int64_t stride;
     uint32_t* dst = const_cast<uint32_t*>(level2_slot(a, row, c, &stride));
-    counts_from_diff(diff, a.tiles_x, dst, stride, lane);
+    counts_from_diff(diff, row_tx, dst, stride, lane);
 }
 
 // The walk of one band over the n packed entries in LDS (s_g, s_x): batch
@@ -420,14 +466,15 @@ __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
     Items2 it;
     if (!load_items2(a, c, lane, it)) return;
     const int blo = it.lo / kBand, bhi = (it.hi + kBand - 1) / kBand;
+    const int row_tx = (int)a.row_tiles_x[it.row];
     // cursors of band b's columns: lane l < kBand holds column b * kBand + l
     auto band_cursors = [&](int b) -> uint32_t {
         const int col = b * kBand + lane;
-        return (lane < kBand && col < a.tiles_x) ? it.cursor[col * it.stride] : 0u;
+        return (lane < kBand && col < row_tx) ? it.cursor[col * it.stride] : 0u;
     };
     uint32_t cur_b = band_cursors(blo);
     for (int b = blo; b < bhi; ++b) {
-        const uint32_t bx0 = (uint32_t)(b * kBand), bx1 = min(bx0 + kBand, (uint32_t)a.tiles_x);
+        const uint32_t bx0 = (uint32_t)(b * kBand), bx1 = min(bx0 + kBand, (uint32_t)row_tx);
         const uint32_t cur_next = (b + 1 < bhi) ? band_cursors(b + 1) : 0u;   // prefetch
         // pack the entries reaching the band, clipped to it, in chunk order
         uint32_t n = 0;
@@ -461,17 +508,18 @@ __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
 // K when it is the last.
 __global__ __launch_bounds__(256) void tile_offsets_kernel(BinArgs a)
 {
-    const int64_t T = (int64_t)a.tiles_x * a.tiles_y;
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= T) return;
-    const int r = (int)(t / a.tiles_x), x = (int)(t % a.tiles_x);
-    const uint32_t* base = a.info + kInfoRowChunks;
+    if (t >= a.tiles) return;
+    const ViewParams& vp = a.views[view_of_tile(a.views, a.n_views, (uint32_t)t)];
+    const int lt = (int)(t - vp.tile_base);
+    const int r = (int)vp.row_base + lt / vp.tiles_x, x = lt % vp.tiles_x;
+    const uint32_t* base = row_chunk_prefix(a);
     const uint32_t nch = base[r + 1] - base[r];
-    const int64_t start = (int64_t)base[r] * a.tiles_x;
+    const int64_t start = row_elem_prefix(a)[r];
     uint32_t off;
     if (nch > 0) off = a.counts2[start + (int64_t)x * nch];
     else if (start < (int64_t)a.info[kInfoC2Elems]) off = a.counts2[start];
-    else off = a.tile_offsets[T];
+    else off = a.tile_offsets[a.tiles];
     a.tile_offsets[t] = off;
 }
 
@@ -479,25 +527,26 @@ unsigned grid8(int g) { return (unsigned)(8 * ((g + 7) / 8)); }
 
 }  // namespace
 
-size_t bin_info_elems(int tiles_y) { return (size_t)(kInfoRowChunks + tiles_y + 2); }
+size_t bin_info_elems(int rows) { return (size_t)(kInfoRowChunks + 2 * (rows + 1) + 1); }
 int bin_level1_chunks(int64_t n) { return (int)((n + kChunk1 - 1) / kChunk1); }
-int bin_level2_chunk_bound(uint64_t row_entries, int tiles_y)
+int bin_level2_chunk_bound(uint64_t row_entries, int rows)
 {
-    return (int)std::min<uint64_t>(row_entries / kChunk2 + (uint64_t)tiles_y + 1, 1u << 30);
+    return (int)std::min<uint64_t>(row_entries / kChunk2 + (uint64_t)rows + 1, 1u << 30);
 }
 
-// Level 1 up to the row offsets (R = rows_off[tiles_y]) and the level-2
-// chunk table; no host dependence.
+// Level 1 up to the row offsets (R = rows_off[rows]) and the level-2 chunk
+// table; no host dependence.
 hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t s)
 {
     if (a.n == 0) {
-        hipError_t e = launch_fill_u32(a.rows_off, 0u, a.tiles_y + 1, s);
+        hipError_t e = launch_fill_u32(a.rows_off, 0u, a.rows + 1, s);
         if (e != hipSuccess) return e;
-        return launch_fill_u32(a.info, 0u, (int64_t)bin_info_elems(a.tiles_y), s);
+        return launch_fill_u32(a.info, 0u, (int64_t)bin_info_elems(a.rows), s);
     }
-    hipLaunchKernelGGL(level1_count_kernel, dim3(grid8(a.chunks1)), dim3(64), 0, s, a);
-    hipError_t e = launch_scan_exclusive(a.counts1, (int64_t)a.tiles_y * a.chunks1, scan_scratch, nullptr,
-                                         a.rows_off + a.tiles_y, a.overflow, s);
+    const int grid1 = a.chunks1 * a.n_views;
+    hipLaunchKernelGGL(level1_count_kernel, dim3(grid8(grid1)), dim3(64), 0, s, a);
+    hipError_t e = launch_scan_exclusive(a.counts1, (int64_t)a.rows * a.chunks1, scan_scratch, nullptr,
+                                         a.rows_off + a.rows, a.overflow, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(level2_table_kernel, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
@@ -506,20 +555,19 @@ hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t
 hipError_t launch_bin_row_scatter(const BinArgs& a, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(level1_scatter_kernel, dim3(grid8(bin_level1_chunks(a.n))), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(level1_scatter_kernel, dim3(grid8(a.chunks1 * a.n_views)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch, hipStream_t s)
 {
-    const int64_t T = (int64_t)a.tiles_x * a.tiles_y;
-    if (a.n == 0) return launch_fill_u32(a.tile_offsets, 0u, T + 1, s);
+    if (a.n == 0) return launch_fill_u32(a.tile_offsets, 0u, a.tiles + 1, s);
     if (grid2 > 0) hipLaunchKernelGGL(level2_count_kernel, dim3(grid8(grid2)), dim3(64), 0, s, a);
-    // the scan's length is C2 * tiles_x, read on the device (info[1])
-    hipError_t e = launch_scan_exclusive(a.counts2, (int64_t)grid2 * a.tiles_x, scan_scratch, nullptr,
-                                         a.tile_offsets + T, a.overflow, s, a.info + kInfoC2Elems);
+    // the scan's length E2 is read on the device (info[1])
+    hipError_t e = launch_scan_exclusive(a.counts2, (int64_t)a.counts2_capacity, scan_scratch, nullptr,
+                                         a.tile_offsets + a.tiles, a.overflow, s, a.info + kInfoC2Elems);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(tile_offsets_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(tile_offsets_kernel, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

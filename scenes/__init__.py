@@ -192,6 +192,17 @@ def make_cameras(config: str) -> list[dict]:
     return [default_camera(cfg["width"], cfg["height"])]
 
 
+def ring_cameras(count: int, width: int, height: int, radius: float = 3.0) -> list[dict]:
+    """``count`` look-at cameras evenly spaced on a circle of ``radius`` in the
+    xz-plane around the origin (the batched form of the C3 workload uses 8 at
+    1920x1080); the first sits at (0, 0, -radius), the default camera's eye."""
+    cams = []
+    for k in range(count):
+        a = 2.0 * math.pi * k / count
+        cams.append(look_at_camera((radius * math.sin(a), 0.0, -radius * math.cos(a)), width, height))
+    return cams
+
+
 def random_target(width: int, height: int, seed: int = 33) -> np.ndarray:
     """Uniform [0,1) target image ``[3, H, W]`` for an L2 loss."""
     return np.random.default_rng(seed).uniform(0.0, 1.0, (3, height, width)).astype(np.float32)

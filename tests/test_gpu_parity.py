@@ -251,3 +251,63 @@ def test_traced_render_is_identical_and_consistent(renderer):
     gpu_render(renderer, sc, cam)
     with pytest.raises(gs.GsError):
         renderer.blend_stats()
+
+
+def test_batched_views_equal_single_renders(renderer):
+    """gs_render_batched over views of mixed (and ragged) sizes returns, for
+    every view, the image, transmittance, n_contrib and per-tile lists of
+    that view rendered alone; the lists of view v hold items v * n + i."""
+    import torch
+    import paper_2607_15951_amd as gs
+    sc = scenes.make_scene("C2", n=30_000, seed=81)
+    n = sc["means"].shape[1]
+    rng = np.random.default_rng(82)
+    sizes = [(256, 256), (200, 120), (640, 480), (333, 197), (64, 48)]
+    cams = []
+    for (w, h) in sizes:
+        e = rng.standard_normal(3)
+        cams.append(scenes.look_at_camera(3.5 * e / np.linalg.norm(e), w, h))
+    cams.append(scenes.default_camera(300, 200))
+    singles = [gpu_render(renderer, sc, c) for c in cams]
+    dev = gs.scene_to_device(sc)
+    outs = renderer.render_batched(dev, cams)
+    torch.cuda.synchronize()
+    lists = renderer.lists(keys=True)
+    info = renderer.list_info()
+    assert info["num_views"] == len(cams)
+    values = lists["values"].cpu().numpy().view(np.uint32)
+    offsets = lists["tile_offsets"].cpu().numpy().view(np.uint32).astype(np.int64)
+    keys = lists["keys"].cpu().numpy().view(np.uint64)
+    tile_base = 0
+    for v, (c, o, g) in enumerate(zip(cams, outs, singles)):
+        say(f"[batched] view {v}: {c['width']}x{c['height']} K={g['num_pairs']}")
+        np.testing.assert_array_equal(o["image"].cpu().numpy(), g["image"].astype(np.float32))
+        np.testing.assert_array_equal(o["final_T"].cpu().numpy(), g["final_T"].astype(np.float32))
+        np.testing.assert_array_equal(o["n_contrib"].cpu().numpy(), g["n_contrib"])
+        T = ((c["width"] + 15) // 16) * ((c["height"] + 15) // 16)
+        off = offsets[tile_base:tile_base + T + 1]
+        np.testing.assert_array_equal(off - off[0], g["tile_offsets"].astype(np.int64))
+        got = values[off[0]:off[-1]]
+        np.testing.assert_array_equal(got, g["values"].astype(np.uint64) + np.uint64(v * n))
+        # keys carry the global tile index and the depth bits of the item
+        want_keys = g["keys"] + (np.uint64(tile_base) << np.uint64(32))
+        np.testing.assert_array_equal(keys[off[0]:off[-1]], want_keys)
+        tile_base += T
+    assert tile_base == info["num_tiles"]
+    assert info["num_pairs"] == sum(g["num_pairs"] for g in singles)
+
+
+def test_batched_rejects_bad_views(renderer):
+    import paper_2607_15951_amd as gs
+    sc = scenes.make_scene("C1", n=100, seed=83)
+    dev = gs.scene_to_device(sc)
+    good = scenes.default_camera(64, 64)
+    bad = dict(good)
+    bad["fx"] = np.float32(float("nan"))
+    with pytest.raises(gs.GsError):
+        renderer.render_batched(dev, [good, bad])
+    with pytest.raises(gs.GsError):
+        renderer.render_batched(dev, [])
+    # the context still renders afterwards
+    out = renderer.render_batched(dev, [good])
+    assert out[0]["image"].shape == (3, 64, 64)
