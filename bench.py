@@ -224,8 +224,9 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
 
 
 def time_batched(r, dev, cams, steps: int) -> dict:
-    """Views/s of one gs_render_batched call over ``cams`` per step, and of
-    the same views rendered by one gs_render call each."""
+    """Views/s of one gs_render_batched call over ``cams`` per step, of the
+    same batch replayed as a captured graph, and of the same views rendered by
+    one gs_render call each."""
     import torch
     outs = r.render_batched(dev, cams)
     torch.cuda.synchronize()
@@ -245,9 +246,21 @@ def time_batched(r, dev, cams, steps: int) -> dict:
             r.render(dev, c, c["width"], c["height"], out=o)
     torch.cuda.synchronize()
     ms_single = (time.perf_counter() - t0) * 1e3 / bsteps
+    # the same batch captured once into a graph (pair capacity 25% above this
+    # frame's K) and replayed
+    gr = r.graph(dev, cams, pair_capacity=int(info["num_pairs"] * 1.25) + 1024, outs=outs)
+    gr.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(bsteps):
+        gr.launch()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / bsteps
+    gr.close()
     pixels = sum(c["width"] * c["height"] for c in cams)
     return {"views": len(cams), "megapixels": round(pixels / 1e6, 2), "pairs": info["num_pairs"],
             "ms_per_batch": round(ms_batch, 3), "views_per_s": round(len(cams) * 1e3 / ms_batch, 1),
+            "ms_per_batch_graph": round(ms_graph, 3), "views_per_s_graph": round(len(cams) * 1e3 / ms_graph, 1),
             "ms_one_call_per_view": round(ms_single, 3),
             "views_per_s_one_call_per_view": round(len(cams) * 1e3 / ms_single, 1), "steps": bsteps}
 

@@ -158,6 +158,31 @@ typedef struct {
 gs_status gs_render_batched(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
                             const gs_render_opts* opts, void* stream);
 
+/* A batched render captured once into a HIP graph and replayed: the
+ * persistent form of gs_render_batched for callers that render the same set
+ * of view sizes frame after frame (every kernel of the render in one graph
+ * launch, no host round trip, no allocation).
+ *
+ * gs_graph_create renders once eagerly on `stream` (sizing the workspace
+ * from opts->pair_capacity, which must be > 0: the graph cannot read the
+ * pair count back), then captures the same render into a graph.  While the
+ * graph exists the context belongs to it: gs_render and gs_render_batched
+ * on ctx fail with GS_ERR_INVALID_ARGUMENT; the list and projection queries
+ * work on the last launch.  The scene pointers in g must stay valid and may
+ * change contents between launches.
+ * gs_graph_set_views replaces the cameras and output pointers (same count
+ * and sizes as at creation) by a small upload on `stream`; the next launch
+ * renders them.
+ * gs_graph_launch enqueues one render on `stream`; an overflow of
+ * pair_capacity is reported by gs_get_list_info after it.
+ * gs_graph_destroy releases the graph and frees the context (NULL-safe). */
+typedef struct gs_graph gs_graph;
+gs_status gs_graph_create(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
+                          const gs_render_opts* opts, void* stream, gs_graph** out);
+gs_status gs_graph_set_views(gs_graph* graph, const gs_view* views, int32_t n_views, void* stream);
+gs_status gs_graph_launch(gs_graph* graph, void* stream);
+void gs_graph_destroy(gs_graph* graph);
+
 /* Sizes of the last render's per-tile lists (host values; synchronises the
  * context's last stream). */
 typedef struct {

@@ -23,7 +23,8 @@ TILE = 16
 
 EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
             "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
-            "gs_get_blend_stats", "gs_get_blend_tile_work", "gs_render_batched"]
+            "gs_get_blend_stats", "gs_get_blend_tile_work", "gs_render_batched", "gs_graph_create",
+            "gs_graph_set_views", "gs_graph_launch", "gs_graph_destroy"]
 STAGES = ["project", "depth_sort", "bin_row_count", "bin_row_scatter", "bin_tile_count", "bin_tile_scatter",
           "blend"]
 
@@ -88,6 +89,15 @@ def load_library(path: str = LIB_PATH):
     L.gs_render_batched.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(gs_view), C.c_int32,
                                     C.POINTER(gs_render_opts), P]
     L.gs_render_batched.restype = C.c_int
+    L.gs_graph_create.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(gs_view), C.c_int32,
+                                  C.POINTER(gs_render_opts), P, C.POINTER(P)]
+    L.gs_graph_create.restype = C.c_int
+    L.gs_graph_set_views.argtypes = [P, C.POINTER(gs_view), C.c_int32, P]
+    L.gs_graph_set_views.restype = C.c_int
+    L.gs_graph_launch.argtypes = [P, P]
+    L.gs_graph_launch.restype = C.c_int
+    L.gs_graph_destroy.argtypes = [P]
+    L.gs_graph_destroy.restype = None
     L.gs_get_list_info.argtypes = [P, C.POINTER(gs_list_info)]
     L.gs_get_list_info.restype = C.c_int
     L.gs_copy_lists.argtypes = [P, P, P, P, P]
@@ -182,8 +192,11 @@ class Renderer:
             raise GsError(st, self._L.gs_last_error(None).decode())
         self.device = device
         self._last = None
+        self._graphs = []   # live RenderGraphs: closed before the context
 
     def close(self):
+        for gr in list(self._graphs):
+            gr.close()
         if self._ctx:
             self._L.gs_destroy(self._ctx)
             self._ctx = C.c_void_p()
@@ -227,6 +240,17 @@ class Renderer:
         per view, as render() does."""
         torch = _torch()
         dev = dev_scene["means"].device
+        views, outs = self._views(cameras, outs, dev, want_T, want_n_contrib)
+        g = make_gaussians(dev_scene)
+        opts = make_opts(background, pair_capacity)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        self._check(self._L.gs_render_batched(self._ctx, C.byref(g), views, len(cameras), C.byref(opts),
+                                              C.c_void_p(s)))
+        self._last = (dev, int(g.n) * len(cameras))
+        return outs
+
+    def _views(self, cameras, outs, dev, want_T=True, want_n_contrib=True):
+        torch = _torch()
         if outs is None:
             outs = []
             for c in cameras:
@@ -242,13 +266,25 @@ class Renderer:
             views[k].out_rgb = _ptr(o["image"])
             views[k].out_final_T = _ptr(o.get("final_T"))
             views[k].out_n_contrib = _ptr(o.get("n_contrib"))
+        return views, outs
+
+    def graph(self, dev_scene: dict, cameras: list, pair_capacity: int, background=(0.0, 0.0, 0.0), outs=None,
+              stream=None) -> "RenderGraph":
+        """Captures a batched render of ``cameras`` into a replayable graph
+        (gs_graph_create); the renderer belongs to it until it is closed."""
+        torch = _torch()
+        dev = dev_scene["means"].device
+        views, outs = self._views(cameras, outs, dev)
         g = make_gaussians(dev_scene)
         opts = make_opts(background, pair_capacity)
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-        self._check(self._L.gs_render_batched(self._ctx, C.byref(g), views, len(cameras), C.byref(opts),
-                                              C.c_void_p(s)))
+        h = C.c_void_p()
+        self._check(self._L.gs_graph_create(self._ctx, C.byref(g), views, len(cameras), C.byref(opts),
+                                            C.c_void_p(s), C.byref(h)))
         self._last = (dev, int(g.n) * len(cameras))
-        return outs
+        gr = RenderGraph(self, h, outs, dev)
+        self._graphs.append(gr)
+        return gr
 
     def set_profiling(self, stages: bool = True, blend_work: bool = False):
         """Tracing of the following renders: HIP events between the stages
@@ -317,3 +353,37 @@ class Renderer:
                                                             ("splats", "depth_key", "radius", "tiles_touched",
                                                              "rect")], C.c_void_p(s)))
         return {k: v[:n] for k, v in out.items()}
+
+
+class RenderGraph:
+    """A captured batched render (gs_graph_*): launch() replays it, set_views()
+    changes cameras and outputs of the same sizes between launches."""
+
+    def __init__(self, renderer: Renderer, handle, outs, dev):
+        self._r, self._h, self.outs, self._dev = renderer, handle, outs, dev
+
+    def launch(self, stream=None):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self._dev).cuda_stream
+        self._r._check(self._r._L.gs_graph_launch(self._h, C.c_void_p(s)))
+        return self.outs
+
+    def set_views(self, cameras: list, outs=None, stream=None):
+        torch = _torch()
+        views, outs = self._r._views(cameras, outs if outs is not None else self.outs, self._dev)
+        s = stream if stream is not None else torch.cuda.current_stream(self._dev).cuda_stream
+        self._r._check(self._r._L.gs_graph_set_views(self._h, views, len(cameras), C.c_void_p(s)))
+        self.outs = outs
+
+    def close(self):
+        if self._h:
+            self._r._L.gs_graph_destroy(self._h)
+            self._h = None
+            if self in self._r._graphs:
+                self._r._graphs.remove(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -56,6 +56,15 @@ struct gs_context {
     uint64_t capacity = 0;
     int sorted_in_b = 1;
     hipStream_t stream = nullptr;
+    gs_graph* graph = nullptr;   // a captured render owns the workspace
+};
+
+struct gs_graph {
+    gs_context* ctx = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<ViewParams> views;   // sizes and tile layout fixed at capture
 };
 
 namespace {
@@ -177,6 +186,17 @@ __global__ void write_views_kernel(ViewBatch b, int count, ViewParams* dst)
     for (int k = threadIdx.x; k < words; k += blockDim.x) out[k] = src[k];
 }
 
+hipError_t write_view_table(const std::vector<ViewParams>& hv, ViewParams* dst, hipStream_t s)
+{
+    for (size_t v0 = 0; v0 < hv.size(); v0 += kViewsPerLaunch) {
+        ViewBatch b;
+        const int cnt = (int)std::min<size_t>(kViewsPerLaunch, hv.size() - v0);
+        std::memcpy(b.v, hv.data() + v0, (size_t)cnt * sizeof(ViewParams));
+        hipLaunchKernelGGL(write_views_kernel, dim3(1), dim3(256), 0, s, b, cnt, dst + v0);
+    }
+    return hipGetLastError();
+}
+
 // tiles_x of every global tile row (rows of view v are [row_base, row_base + tiles_y))
 __global__ void row_table_kernel(const ViewParams* views, int n_views, uint32_t* row_tiles_x, int rows)
 {
@@ -193,8 +213,10 @@ __global__ void row_table_kernel(const ViewParams* views, int n_views, uint32_t*
 
 
 // One render of n_views views of the scene g (validated by the caller).
+// write_table: upload the view table first (false while a graph is captured:
+// the graph then reads the table its owner writes before each launch).
 gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector<ViewParams>& hv,
-                       const gs_render_opts* opts, hipStream_t s)
+                       const gs_render_opts* opts, hipStream_t s, bool write_table = true)
 {
     gs_status st;
     gs_render_opts o{};
@@ -237,12 +259,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     uint32_t* counters = static_cast<uint32_t*>(ctx->counters.p);
     uint32_t* view_counts = static_cast<uint32_t*>(ctx->view_counts.p);
     HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
-    for (int v0 = 0; v0 < V; v0 += kViewsPerLaunch) {
-        ViewBatch b;
-        const int cnt = std::min(kViewsPerLaunch, V - v0);
-        std::memcpy(b.v, hv.data() + v0, (size_t)cnt * sizeof(ViewParams));
-        hipLaunchKernelGGL(write_views_kernel, dim3(1), dim3(256), 0, s, b, cnt, views + v0);
-    }
+    if (write_table) HIP_TRY(write_view_table(hv, views, s), "view table");
     hipLaunchKernelGGL(row_table_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, (const ViewParams*)views,
                        V, static_cast<uint32_t*>(ctx->row_tiles_x.p), rows);
     HIP_TRY(hipGetLastError(), "view table");
@@ -389,6 +406,9 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     return GS_OK;
 }
 
+gs_status build_views(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
+                      const gs_render_opts* opts, std::vector<ViewParams>& hv);
+
 // The device-table entry of one view; tile_base / row_base follow the views
 // before it.
 ViewParams make_view(const gs_camera* cam, int32_t width, int32_t height, float* out_rgb, float* out_T,
@@ -445,6 +465,7 @@ gs_status gs_create(int device, gs_context** out)
 void gs_destroy(gs_context* ctx)
 {
     if (!ctx) return;
+    if (ctx->graph) gs_graph_destroy(ctx->graph);
     (void)hipSetDevice(ctx->device);
     DevBuf* bufs[] = {&ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
                       &ctx->sort_ka, &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb, &ctx->hist,
@@ -475,6 +496,7 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
                     void* stream)
 {
     if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (ctx->graph) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the context is bound to a render graph");
     gs_status st = validate(ctx, g, cam, width, height, opts, out_rgb);
     if (st != GS_OK) return st;
     std::vector<ViewParams> hv(1, make_view(cam, width, height, out_rgb, out_final_T, out_n_contrib, 0u, 0u));
@@ -485,6 +507,112 @@ gs_status gs_render_batched(gs_context* ctx, const gs_gaussians* g, const gs_vie
                             const gs_render_opts* opts, void* stream)
 {
     if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (ctx->graph) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the context is bound to a render graph");
+    std::vector<ViewParams> hv;
+    gs_status st = build_views(ctx, g, views, n_views, opts, hv);
+    if (st != GS_OK) return st;
+    return render_views(ctx, g, hv, opts, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_graph_create(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
+                          const gs_render_opts* opts, void* stream, gs_graph** out)
+{
+    if (!ctx || !out) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    *out = nullptr;
+    if (ctx->graph) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the context is bound to a render graph");
+    if (!opts || opts->pair_capacity == 0)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "a render graph needs opts->pair_capacity > 0");
+    std::vector<ViewParams> hv;
+    gs_status st = build_views(ctx, g, views, n_views, opts, hv);
+    if (st != GS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // an eager render sizes every buffer (capture must not allocate) and
+    // writes the view table
+    if ((st = render_views(ctx, g, hv, opts, s)) != GS_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    gs_graph* gr = new gs_graph();
+    gr->ctx = ctx;
+    gr->views = hv;
+    hipError_t e = hipStreamCreateWithFlags(&gr->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(gr->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        if (gr->capture) (void)hipStreamDestroy(gr->capture);
+        delete gr;
+        return hip_fail(ctx, e, "begin capture");
+    }
+    const uint32_t profiling = ctx->profiling;
+    ctx->profiling = 0;   // no event records inside the graph
+    st = render_views(ctx, g, hv, opts, gr->capture, false);
+    ctx->profiling = profiling;
+    e = hipStreamEndCapture(gr->capture, &gr->graph);
+    if (st == GS_OK && e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (st != GS_OK || e != hipSuccess) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        (void)hipStreamDestroy(gr->capture);
+        delete gr;
+        return st != GS_OK ? st : hip_fail(ctx, e, "capture");
+    }
+    ctx->graph = gr;
+    *out = gr;
+    return GS_OK;
+}
+
+gs_status gs_graph_set_views(gs_graph* graph, const gs_view* views, int32_t n_views, void* stream)
+{
+    if (!graph) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "graph is NULL");
+    gs_context* ctx = graph->ctx;
+    if (!views || n_views != (int32_t)graph->views.size())
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "n_views must equal the captured view count");
+    std::vector<ViewParams> hv = graph->views;
+    for (int v = 0; v < n_views; ++v) {
+        const gs_view& w = views[v];
+        gs_status st = validate_view(ctx, &w.camera, w.width, w.height, w.out_rgb);
+        if (st != GS_OK) return st;
+        if (w.width != hv[v].width || w.height != hv[v].height)
+            return fail(ctx, GS_ERR_INVALID_ARGUMENT, "view sizes must equal the captured ones");
+        hv[v] = make_view(&w.camera, w.width, w.height, w.out_rgb, w.out_final_T, w.out_n_contrib, hv[v].tile_base,
+                          hv[v].row_base);
+    }
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(write_view_table(hv, static_cast<ViewParams*>(ctx->views.p), static_cast<hipStream_t>(stream)),
+            "view table");
+    graph->views = hv;
+    return GS_OK;
+}
+
+gs_status gs_graph_launch(gs_graph* graph, void* stream)
+{
+    if (!graph) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "graph is NULL");
+    gs_context* ctx = graph->ctx;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_TRY(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+    ctx->stream = static_cast<hipStream_t>(stream);
+    ctx->have_render = true;
+    ctx->timed = false;
+    ctx->traced = false;
+    return GS_OK;
+}
+
+void gs_graph_destroy(gs_graph* graph)
+{
+    if (!graph) return;
+    (void)hipSetDevice(graph->ctx->device);
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    if (graph->capture) (void)hipStreamDestroy(graph->capture);
+    if (graph->ctx->graph == graph) graph->ctx->graph = nullptr;
+    delete graph;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validated views of a batched render with their tile and row bases.
+gs_status build_views(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
+                      const gs_render_opts* opts, std::vector<ViewParams>& hv)
+{
     gs_status st = validate_gaussians(ctx, g);
     if (st == GS_OK) st = validate_opts(ctx, opts);
     if (st != GS_OK) return st;
@@ -492,7 +620,7 @@ gs_status gs_render_batched(gs_context* ctx, const gs_gaussians* g, const gs_vie
     if (n_views < 1 || n_views > kMaxViews) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "n_views must lie in [1, 1024]");
     if ((int64_t)n_views * g->n > 0xFFFFFFFFll)
         return fail(ctx, GS_ERR_UNSUPPORTED, "n_views * n must stay below 2^32");
-    std::vector<ViewParams> hv;
+    hv.clear();
     hv.reserve((size_t)n_views);
     int64_t tile_base = 0, row_base = 0;
     for (int v = 0; v < n_views; ++v) {
@@ -505,8 +633,12 @@ gs_status gs_render_batched(gs_context* ctx, const gs_gaussians* g, const gs_vie
         if (row_base > kMaxTotalRows) return fail(ctx, GS_ERR_UNSUPPORTED, "more than 16384 tile rows over all views");
         if (tile_base >= (int64_t(1) << 31)) return fail(ctx, GS_ERR_UNSUPPORTED, "too many tiles over all views");
     }
-    return render_views(ctx, g, hv, opts, static_cast<hipStream_t>(stream));
+    return GS_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out)
 {

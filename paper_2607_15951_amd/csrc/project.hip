@@ -186,7 +186,9 @@ __device__ __forceinline__ bool project_view(const ViewParams& vp, double mx, do
     return true;
 }
 
-template <int DT, int DEG>
+// kOneView: the single-image render (one view, no loop-carried state, so the
+// compiler schedules it as straight-line code)
+template <int DT, int DEG, bool kOneView>
 __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 {
     constexpr int ncoef = (DEG + 1) * (DEG + 1);
@@ -215,7 +217,8 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
     const float opacity = 1.0f / (1.0f + __expf(-logit));
     __shared__ uint32_t s_vis[4], s_pairs[4];
 
-    for (int v = 0; v < a.n_views; ++v) {
+    const int n_views = kOneView ? 1 : a.n_views;
+    for (int v = 0; v < n_views; ++v) {
         const ViewParams& vp = a.views[v];
         Geometry g;
         const bool ok = cov_ok && project_view(vp, mxf, myf, mzf, Sg, g);
@@ -328,15 +331,22 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* _
     }
 }
 
-template <int DT>
+template <int DT, bool kOneView>
 void launch_project_dt(const ProjectArgs& a, unsigned blocks, hipStream_t s)
 {
     switch (a.sh_degree) {
-    case 0: hipLaunchKernelGGL((project_kernel<DT, 0>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((project_kernel<DT, 1>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((project_kernel<DT, 2>), dim3(blocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((project_kernel<DT, 3>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((project_kernel<DT, 0, kOneView>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((project_kernel<DT, 1, kOneView>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((project_kernel<DT, 2, kOneView>), dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((project_kernel<DT, 3, kOneView>), dim3(blocks), dim3(256), 0, s, a); break;
     }
+}
+
+template <int DT>
+void launch_project_views(const ProjectArgs& a, unsigned blocks, hipStream_t s)
+{
+    if (a.n_views == 1) launch_project_dt<DT, true>(a, blocks, s);
+    else launch_project_dt<DT, false>(a, blocks, s);
 }
 
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
@@ -345,9 +355,9 @@ hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
     if (a.n == 0) return launch_fill_u32(a.view_counts, 0u, (int64_t)kViewCounters * a.n_views, s);
     const unsigned blocks = (unsigned)((a.n + 255) / 256);
     switch (a.dtype) {
-    case 0: launch_project_dt<0>(a, blocks, s); break;
-    case 1: launch_project_dt<1>(a, blocks, s); break;
-    default: launch_project_dt<2>(a, blocks, s); break;
+    case 0: launch_project_views<0>(a, blocks, s); break;
+    case 1: launch_project_views<1>(a, blocks, s); break;
+    default: launch_project_views<2>(a, blocks, s); break;
     }
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)a.n_views), dim3(1024), 0, s,
                        (const uint32_t*)a.partials, (int)blocks, a.n_views, a.view_counts);

@@ -311,3 +311,61 @@ def test_batched_rejects_bad_views(renderer):
     # the context still renders afterwards
     out = renderer.render_batched(dev, [good])
     assert out[0]["image"].shape == (3, 64, 64)
+
+
+def test_graph_replays_match_eager_batched_render(renderer):
+    """A captured batched render (gs_graph_*) replayed several times, with
+    eager work and synchronisations between replays, returns the eager
+    batched render's images every time; new cameras of the same sizes take
+    effect on the next replay."""
+    import torch
+    import paper_2607_15951_amd as gs
+    sc = scenes.make_scene("C2", n=20_000, seed=91)
+    dev = gs.scene_to_device(sc)
+
+    def cams_at(seed_shift):
+        out = []
+        for k, (w, h) in enumerate([(320, 240), (200, 120), (256, 256)]):
+            e = np.random.default_rng(1000 * seed_shift + k).standard_normal(3)
+            out.append(scenes.look_at_camera(3.5 * e / np.linalg.norm(e), w, h))
+        return out
+
+    cams = cams_at(1)
+    ref = gs.Renderer(0)   # eager reference on its own context
+    try:
+        want = [{k: v.clone() for k, v in o.items()} for o in ref.render_batched(dev, cams)]
+        K = ref.list_info()["num_pairs"]
+        cams2 = cams_at(2)
+        want2 = [{k: v.clone() for k, v in o.items()} for o in ref.render_batched(dev, cams2)]
+        K2 = ref.list_info()["num_pairs"]
+    finally:
+        ref.close()
+    cap = int(1.5 * max(K, K2)) + 64
+    r = gs.Renderer(0)
+    try:
+        gr = r.graph(dev, cams, pair_capacity=cap)
+        with pytest.raises(gs.GsError):   # the context belongs to the graph
+            r.render(dev, cams[0], cams[0]["width"], cams[0]["height"])
+        for rep in range(3):
+            for o in gr.outs:
+                o["image"].fill_(-1.0)
+            torch.cuda.synchronize()
+            gr.launch()
+            torch.cuda.synchronize()
+            _ = torch.ones(1024, device="cuda").sum().item()   # eager work between replays
+            assert r.list_info()["num_pairs"] == K
+            for o, w in zip(gr.outs, want):
+                for k in ("image", "final_T", "n_contrib"):
+                    assert torch.equal(o[k], w[k]), f"replay {rep} {k}"
+        gr.set_views(cams2)
+        gr.launch()
+        torch.cuda.synchronize()
+        assert r.list_info()["num_pairs"] == K2
+        for o, w in zip(gr.outs, want2):
+            for k in ("image", "final_T", "n_contrib"):
+                assert torch.equal(o[k], w[k]), f"new views {k}"
+        gr.close()
+        # the context renders eagerly again once the graph is gone
+        r.render(dev, cams[0], cams[0]["width"], cams[0]["height"])
+    finally:
+        r.close()
