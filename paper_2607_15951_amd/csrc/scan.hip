@@ -12,6 +12,7 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int64_t kScanMaxGrid = 8192;   // tiles beyond it are taken by grid-stride loops
 
 __device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t v, uint64_t* sh, uint64_t* total)
 {
@@ -38,30 +39,37 @@ __device__ __forceinline__ int64_t scan_length(int64_t n, const uint32_t* n_dev)
     return d < n ? d : n;
 }
 
+// Tiles of kScanTile values; the grid strides over the tiles of the device
+// length (a grid sized for a bound then costs nothing past the real length).
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n_max,
                                                                     const uint32_t* n_dev,
                                                                     uint64_t* __restrict__ block_sums)
 {
     const int64_t n = scan_length(n_max, n_dev);
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
     __shared__ uint64_t sh[kScanThreads];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    uint64_t s = 0;
+    for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
+        const int64_t base = t * kScanTile;
+        uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k * kScanThreads + threadIdx.x;
-        if (i < n) s += in[i];
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t i = base + k * kScanThreads + threadIdx.x;
+            if (i < n) s += in[i];
+        }
+        uint64_t tot;
+        (void)block_exclusive_u64(s, sh, &tot);
+        if (threadIdx.x == 0) block_sums[t] = tot;
     }
-    uint64_t tot;
-    (void)block_exclusive_u64(s, sh, &tot);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-// exclusive scan of nb block sums by one block; writes the 64-bit total
-__global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(uint64_t* __restrict__ sums, int64_t nb,
-                                                                   uint64_t* total_out, uint32_t* total32,
-                                                                   uint32_t* overflow)
+// exclusive scan of the tiles' sums by one block; writes the 64-bit total
+__global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(uint64_t* __restrict__ sums, int64_t n_max,
+                                                                   const uint32_t* n_dev, uint64_t* total_out,
+                                                                   uint32_t* total32, uint32_t* overflow)
 {
     __shared__ uint64_t sh[kScanThreads];
+    const int64_t n = scan_length(n_max, n_dev);
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
     const int64_t per = (nb + kScanThreads - 1) / kScanThreads;
     const int64_t s = threadIdx.x * per, e = (s + per < nb) ? s + per : nb;
     uint64_t acc = 0;
@@ -85,23 +93,26 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __res
                                                                  const uint64_t* __restrict__ block_prefix)
 {
     const int64_t n = scan_length(n_max, n_dev);
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
     __shared__ uint64_t sh[kScanThreads];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    // thread t owns the kScanItems consecutive items [t*16, t*16+16) of the tile
-    uint32_t v[kScanItems];
-    const int64_t mine = base + (int64_t)threadIdx.x * kScanItems;
-    uint64_t s = 0;
+    for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
+        const int64_t base = t * kScanTile;
+        // thread i owns the kScanItems consecutive items [i*16, i*16+16) of the tile
+        uint32_t v[kScanItems];
+        const int64_t mine = base + (int64_t)threadIdx.x * kScanItems;
+        uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = (mine + k < n) ? data[mine + k] : 0u;
-        s += v[k];
-    }
-    uint64_t tot;
-    uint64_t run = block_exclusive_u64(s, sh, &tot) + block_prefix[blockIdx.x];
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = (mine + k < n) ? data[mine + k] : 0u;
+            s += v[k];
+        }
+        uint64_t tot;
+        uint64_t run = block_exclusive_u64(s, sh, &tot) + block_prefix[t];
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (mine + k < n) data[mine + k] = (uint32_t)run;
-        run += v[k];
+        for (int k = 0; k < kScanItems; ++k) {
+            if (mine + k < n) data[mine + k] = (uint32_t)run;
+            run += v[k];
+        }
     }
 }
 
@@ -119,17 +130,16 @@ hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scra
     if (n <= 0) {
         if (total64 || total32) {
             hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, block_scratch, (int64_t)0,
-                               total64, total32, overflow);
+                               (const uint32_t*)nullptr, total64, total32, overflow);
         }
         return hipGetLastError();
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, n_dev,
-                       block_scratch);
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, block_scratch, nb, total64, total32,
-                       overflow);
-    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, n_dev,
-                       block_scratch);
+    const unsigned grid = (unsigned)std::min<int64_t>(nb, kScanMaxGrid);
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch);
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, block_scratch, n, n_dev, total64,
+                       total32, overflow);
+    hipLaunchKernelGGL(scan_down_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch);
     return hipGetLastError();
 }
 

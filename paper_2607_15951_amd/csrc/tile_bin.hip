@@ -393,11 +393,9 @@ __device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, I
     return true;
 }
 
-__global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
+// One level-2 chunk's per-column counts.
+__device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int lane, uint32_t* diff)
 {
-    __shared__ uint32_t diff[kMaxBandTiles + 1];
-    const int lane = threadIdx.x, c = chunk_of_block();
-    if ((uint32_t)c >= a.info[kInfoC2]) return;
     int row;
     int64_t eb, ee;
     chunk2_range(a, c, lane, &row, &eb, &ee);
@@ -417,6 +415,17 @@ __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
     int64_t stride;
     uint32_t* dst = const_cast<uint32_t*>(level2_slot(a, row, c, &stride));
     counts_from_diff(diff, row_tx, dst, stride, lane);
+    __syncthreads();   // diff is reused by the next chunk
+}
+
+// The level-2 kernels stride over the device's chunk count, so a grid sized
+// for a bound (pair_capacity mode) costs nothing past the real chunks.
+__global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
+{
+    __shared__ uint32_t diff[kMaxBandTiles + 1];
+    const int lane = threadIdx.x;
+    const int c2 = (int)a.info[kInfoC2];
+    for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_count_chunk(a, c, lane, diff);
 }
 
 // The walk of one band over the n packed entries in LDS (s_g, s_x): batch
@@ -459,10 +468,8 @@ __device__ __forceinline__ void walk_band(const uint32_t* s_g, const uint32_t* s
 // reach band b are packed, in chunk order, into dense batches through LDS,
 // and only those batches walk the band's columns.  Inside a column the
 // entries keep their chunk order, so the output is that of the plain walk.
-__global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
+__device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, int lane, uint32_t* s_g, uint32_t* s_x)
 {
-    __shared__ uint32_t s_g[kChunk2], s_x[kChunk2];
-    const int lane = threadIdx.x, c = chunk_of_block();
     Items2 it;
     if (!load_items2(a, c, lane, it)) return;
     const int blo = it.lo / kBand, bhi = (it.hi + kBand - 1) / kBand;
@@ -502,6 +509,14 @@ __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
     }
 }
 
+__global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
+{
+    __shared__ uint32_t s_g[kChunk2], s_x[kChunk2];
+    const int lane = threadIdx.x;
+    const int c2 = (int)a.info[kInfoC2];
+    for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_scatter_chunk(a, c, lane, s_g, s_x);
+}
+
 // Tile offsets from the scanned level-2 counts: tile (r, x) starts at chunk
 // 0's cursor in column x of row r.  A row without chunks starts where the
 // next row's block starts (the scan's running total there), or at the total
@@ -524,6 +539,8 @@ __global__ __launch_bounds__(256) void tile_offsets_kernel(BinArgs a)
 }
 
 unsigned grid8(int g) { return (unsigned)(8 * ((g + 7) / 8)); }
+// level-2 waves launched at most (more chunks are taken in grid-stride turns)
+constexpr int kMaxGrid2 = 65536;
 
 }  // namespace
 
@@ -562,7 +579,7 @@ hipError_t launch_bin_row_scatter(const BinArgs& a, hipStream_t s)
 hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch, hipStream_t s)
 {
     if (a.n == 0) return launch_fill_u32(a.tile_offsets, 0u, a.tiles + 1, s);
-    if (grid2 > 0) hipLaunchKernelGGL(level2_count_kernel, dim3(grid8(grid2)), dim3(64), 0, s, a);
+    if (grid2 > 0) hipLaunchKernelGGL(level2_count_kernel, dim3(grid8(std::min(grid2, kMaxGrid2))), dim3(64), 0, s, a);
     // the scan's length E2 is read on the device (info[1])
     hipError_t e = launch_scan_exclusive(a.counts2, (int64_t)a.counts2_capacity, scan_scratch, nullptr,
                                          a.tile_offsets + a.tiles, a.overflow, s, a.info + kInfoC2Elems);
@@ -574,7 +591,7 @@ hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch,
 hipError_t launch_bin_tile_scatter(const BinArgs& a, int grid2, hipStream_t s)
 {
     if (a.n == 0 || grid2 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(level2_scatter_kernel, dim3(grid8(grid2)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(level2_scatter_kernel, dim3(grid8(std::min(grid2, kMaxGrid2))), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
