@@ -53,23 +53,34 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
     hist[row + (int64_t)tid * bpv] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
 }
 
+// Stable scatter of one block's items.  Item (round k, wave w, lane l) is
+// idx = begin + k * kSortBlock + 64 w + l, so the input order is (k, w, l).
+// Each wave ranks its items of a round among equal digits with eight ballots
+// (lanes holding the same digit) and records the group's size in
+// cnt[k][w][d]; one pass of 256 threads (one per digit) turns those counts
+// into exclusive offsets in (k, w) order, and every item lands at
+// base[d] + cnt[k][w][d] + (lanes of its group below it) -- two barriers per
+// block instead of a hand-over per (round, wave).
 __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, int64_t n, int shift, const uint32_t* __restrict__ offsets, int bpv)
 {
-    __shared__ uint32_t base[256];
+    __shared__ uint32_t cnt[kSortItems][4][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int64_t begin, end, row;
     sort_block_range(n, bpv, &begin, &end, &row);
-    base[tid] = offsets[row + (int64_t)tid * bpv];
+    for (int k = 0; k < kSortItems; ++k)
+        for (int w = 0; w < 4; ++w) cnt[k][w][tid] = 0u;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
+    uint32_t key[kSortItems], val[kSortItems], digit[kSortItems], rank[kSortItems];
+#pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = begin + k * kSortBlock + tid;
         const bool valid = idx < end;
-        const uint32_t key = valid ? keys_in[idx] : 0u;
-        const uint32_t val = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+        key[k] = valid ? keys_in[idx] : 0u;
+        val[k] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
+        const uint32_t d = (key[k] >> shift) & 255u;
         // lanes of this wave holding the same digit
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -78,20 +89,30 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
             const uint64_t bb = __ballot(bit);
             m &= bit ? bb : ~bb;
         }
-        const uint32_t rank = (uint32_t)__popcll(m & lt);
-        const uint32_t cnt = (uint32_t)__popcll(m);
-        uint32_t pos = 0;
-        // waves take their offsets in order so equal digits keep input order
-        for (int w = 0; w < 4; ++w) {
-            if (wave == w && valid) {
-                pos = base[d] + rank;
-                if (rank == 0) base[d] = pos + cnt;
+        digit[k] = valid ? d : 256u;
+        rank[k] = (uint32_t)__popcll(m & lt);
+        // the group's first lane records its size (groups are disjoint)
+        if (valid && rank[k] == 0) cnt[k][wave][d] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    {   // thread d: exclusive prefix of digit d over (round, wave), plus the block's base
+        uint32_t run = offsets[row + (int64_t)tid * bpv];
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t c = cnt[k][w][tid];
+                cnt[k][w][tid] = run;
+                run += c;
             }
-            __syncthreads();
-        }
-        if (valid) {
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        if (digit[k] < 256u) {
+            const uint32_t pos = cnt[k][wave][digit[k]] + rank[k];
+            keys_out[pos] = key[k];
+            vals_out[pos] = val[k];
         }
     }
 }

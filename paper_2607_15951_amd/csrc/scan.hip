@@ -1,6 +1,7 @@
-// scan.hip -- device-wide exclusive prefix sum of uint32 values (reduce, scan
-// of block sums, down-sweep), used by the depth sort's digit offsets and by
-// the per-band pair prefix of the binning.  Block sums and the total are
+// scan.hip -- device-wide exclusive prefix sum of uint32 values in two
+// launches (tile sums, then a down-sweep in which every tile adds the sums of
+// the tiles before it), used by the depth sort's digit offsets and by the
+// binning's count arrays.  Tile sums and the total are
 // accumulated in 64 bits; the total is written to *total (and an overflow
 // flag raised when it does not fit 32 bits).  With n_dev set, the length is
 // min(n, *n_dev), read on the device (no host sync).
@@ -88,14 +89,32 @@ __global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(uint64_t* __r
     }
 }
 
+// Down-sweep: every tile adds the sum of all tiles before it, computed by the
+// block itself from the tile sums (there are at most a few thousand), so the
+// scan needs no separate pass over the sums; the block of the last tile
+// writes the total.
 __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __restrict__ data, int64_t n_max,
                                                                  const uint32_t* n_dev,
-                                                                 const uint64_t* __restrict__ block_prefix)
+                                                                 const uint64_t* __restrict__ tile_sums,
+                                                                 uint64_t* total_out, uint32_t* total32,
+                                                                 uint32_t* overflow)
 {
     const int64_t n = scan_length(n_max, n_dev);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     __shared__ uint64_t sh[kScanThreads];
+    if (nb == 0 && blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            if (total_out) *total_out = 0;
+            if (total32) *total32 = 0;
+        }
+        return;
+    }
     for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
+        // prefix of the tile sums before t
+        uint64_t p = 0;
+        for (int64_t j = threadIdx.x; j < t; j += kScanThreads) p += tile_sums[j];
+        uint64_t before;
+        (void)block_exclusive_u64(p, sh, &before);
         const int64_t base = t * kScanTile;
         // thread i owns the kScanItems consecutive items [i*16, i*16+16) of the tile
         uint32_t v[kScanItems];
@@ -107,11 +126,17 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __res
             s += v[k];
         }
         uint64_t tot;
-        uint64_t run = block_exclusive_u64(s, sh, &tot) + block_prefix[t];
+        uint64_t run = block_exclusive_u64(s, sh, &tot) + before;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             if (mine + k < n) data[mine + k] = (uint32_t)run;
             run += v[k];
+        }
+        if (t == nb - 1 && threadIdx.x == 0) {
+            const uint64_t total = before + tot;
+            if (total_out) *total_out = total;
+            if (total32) *total32 = (uint32_t)total;
+            if (overflow && total > 0xFFFFFFFFull) *overflow = 1u;
         }
     }
 }
@@ -137,9 +162,8 @@ hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scra
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     const unsigned grid = (unsigned)std::min<int64_t>(nb, kScanMaxGrid);
     hipLaunchKernelGGL(scan_reduce_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch);
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, block_scratch, n, n_dev, total64,
-                       total32, overflow);
-    hipLaunchKernelGGL(scan_down_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch);
+    hipLaunchKernelGGL(scan_down_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch,
+                       total64, total32, overflow);
     return hipGetLastError();
 }
 
