@@ -171,14 +171,23 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
             s_mask[nk + tid] = 0u;
         }
         __syncthreads();
+        // this wave's entries of the batch: bit j of bits[j / 64] when entry j
+        // can reach the wave's quad (scalar registers, no per-entry LDS read)
+        uint64_t bits[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jj = q * 64 + lane;
+            bits[q] = __ballot(jj < nk && ((s_mask[jj] >> wave) & 1u));
+        }
         for (int j0 = 0; j0 < nk; j0 += kUnroll) {
             if (__ballot(!done) == 0) break;   // whole wave finished
+            const uint64_t word = bits[j0 >> 6] >> (j0 & 63);
+            if ((word & ((1u << kUnroll) - 1u)) == 0) continue;   // none of the next kUnroll reaches the quad
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const int j = j0 + u;
                 // an entry out of this quad's reach is skipped by the whole wave
-                const uint32_t qm = __builtin_amdgcn_readfirstlane(s_mask[j]);
-                if (!((qm >> wave) & 1u)) continue;
+                if (!((word >> u) & 1u)) continue;
                 if (kStats) ++bodies;
                 const float4 e0 = s0[j];
                 const float4 e1 = s1[j];
