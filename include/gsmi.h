@@ -183,6 +183,37 @@ gs_status gs_graph_set_views(gs_graph* graph, const gs_view* views, int32_t n_vi
 gs_status gs_graph_launch(gs_graph* graph, void* stream);
 void gs_graph_destroy(gs_graph* graph);
 
+/* Gradients of a scalar loss with respect to the Gaussian parameters, float32
+ * device arrays in the layouts of gs_gaussians (owned by the caller,
+ * overwritten): means [3][n], log_scales [3][n], quats [4][n] (of the raw,
+ * unnormalised quaternion), opacity_logits [n], sh [(deg+1)^2][3][n].  For
+ * BF16/FP16 storage they are the gradients at the stored values. */
+typedef struct {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* sh;
+} gs_gradients;
+
+/* Backward of the last render on ctx (gs_render or gs_render_batched; the
+ * differentiable part of Sec. 3.1 stages 1, 2 and 4 -- the tile lists and
+ * their order are held fixed, as are the 3-sigma rectangles): given
+ * dL/d(out_rgb) per view and optionally dL/d(out_final_T), writes dL/d(the
+ * Gaussian parameters) into grads.  The blend is recomputed front to back
+ * from the forward's own outputs (out_rgb, out_final_T, out_n_contrib of every
+ * view, which must have been requested and still hold that render's values)
+ * rather than stored; the alpha threshold, the 0.99 clamp and the early
+ * termination pass no gradient, nor does a colour clamped at 0.
+ *   g             the scene of that render (same pointers)
+ *   grad_rgb      host array [n_views] of device pointers, float [3][H][W]
+ *   grad_final_T  NULL, or host array [n_views] of device pointers (each
+ *                 float [H][W] or NULL)
+ * GS_ERR_INVALID_ARGUMENT when g differs from the last render's scene, an
+ * output of that render was not kept, or a pointer is NULL. */
+gs_status gs_render_backward(gs_context* ctx, const gs_gaussians* g, const float* const* grad_rgb,
+                             const float* const* grad_final_T, const gs_gradients* grads, void* stream);
+
 /* Sizes of the last render's per-tile lists (host values; synchronises the
  * context's last stream). */
 typedef struct {

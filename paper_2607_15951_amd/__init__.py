@@ -24,7 +24,7 @@ TILE = 16
 EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
             "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
             "gs_get_blend_stats", "gs_get_blend_tile_work", "gs_render_batched", "gs_graph_create",
-            "gs_graph_set_views", "gs_graph_launch", "gs_graph_destroy"]
+            "gs_graph_set_views", "gs_graph_launch", "gs_graph_destroy", "gs_render_backward"]
 STAGES = ["project", "depth_sort", "bin_row_count", "bin_row_scatter", "bin_tile_count", "bin_tile_scatter",
           "blend"]
 
@@ -55,6 +55,11 @@ class gs_list_info(C.Structure):
     _fields_ = [("num_pairs", C.c_uint64), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
                 ("n_visible", C.c_int64), ("num_row_entries", C.c_uint64), ("num_tiles", C.c_int64),
                 ("num_views", C.c_int32)]
+
+
+class gs_gradients(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logits", C.c_void_p), ("sh", C.c_void_p)]
 
 
 class gs_view(C.Structure):
@@ -98,6 +103,9 @@ def load_library(path: str = LIB_PATH):
     L.gs_graph_launch.restype = C.c_int
     L.gs_graph_destroy.argtypes = [P]
     L.gs_graph_destroy.restype = None
+    L.gs_render_backward.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.POINTER(gs_gradients), P]
+    L.gs_render_backward.restype = C.c_int
     L.gs_get_list_info.argtypes = [P, C.POINTER(gs_list_info)]
     L.gs_get_list_info.restype = C.c_int
     L.gs_copy_lists.argtypes = [P, P, P, P, P]
@@ -193,6 +201,7 @@ class Renderer:
         self.device = device
         self._last = None
         self._graphs = []   # live RenderGraphs: closed before the context
+        self.generation = 0   # counts renders: a pending backward needs the latest one
 
     def close(self):
         for gr in list(self._graphs):
@@ -231,6 +240,10 @@ class Renderer:
                                C.c_void_p(s))
         self._check(st)
         self._last = (dev, int(g.n))
+        # the backward reads these outputs: hold them so that the caching
+        # allocator does not hand their memory to another tensor meanwhile
+        self._last_out = out
+        self.generation += 1
         return out
 
     def render_batched(self, dev_scene: dict, cameras: list, background=(0.0, 0.0, 0.0), pair_capacity: int = 0,
@@ -247,6 +260,8 @@ class Renderer:
         self._check(self._L.gs_render_batched(self._ctx, C.byref(g), views, len(cameras), C.byref(opts),
                                               C.c_void_p(s)))
         self._last = (dev, int(g.n) * len(cameras))
+        self._last_out = outs
+        self.generation += 1
         return outs
 
     def _views(self, cameras, outs, dev, want_T=True, want_n_contrib=True):
@@ -285,6 +300,32 @@ class Renderer:
         gr = RenderGraph(self, h, outs, dev)
         self._graphs.append(gr)
         return gr
+
+    def backward(self, dev_scene: dict, grad_images: list, grad_T: list | None = None, stream=None) -> dict:
+        """Gradients of the Gaussian parameters (float32 tensors, input
+        layouts) for dL/d(image) of every view of the last render (and
+        optionally dL/d(final_T)); see gs_render_backward.  The backward
+        reads that render's image, final_T and n_contrib, which must not
+        have been written since (the renderer holds a reference to them)."""
+        torch = _torch()
+        dev = dev_scene["means"].device
+        n = dev_scene["means"].shape[1]
+        ncoef = dev_scene["sh"].shape[0]
+        out = {"means": torch.empty((3, n), dtype=torch.float32, device=dev),
+               "log_scales": torch.empty((3, n), dtype=torch.float32, device=dev),
+               "quats": torch.empty((4, n), dtype=torch.float32, device=dev),
+               "opacity_logits": torch.empty(n, dtype=torch.float32, device=dev),
+               "sh": torch.empty((ncoef, 3, n), dtype=torch.float32, device=dev)}
+        gi = [t.contiguous() for t in grad_images]
+        gt = [t.contiguous() if t is not None else None for t in grad_T] if grad_T is not None else None
+        arr_i = (C.c_void_p * len(gi))(*[_ptr(t) for t in gi])
+        arr_t = (C.c_void_p * len(gi))(*[_ptr(t) for t in gt]) if gt is not None else None
+        gr = gs_gradients(_ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
+                          _ptr(out["opacity_logits"]), _ptr(out["sh"]))
+        g = make_gaussians(dev_scene)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        self._check(self._L.gs_render_backward(self._ctx, C.byref(g), arr_i, arr_t, C.byref(gr), C.c_void_p(s)))
+        return out
 
     def set_profiling(self, stages: bool = True, blend_work: bool = False):
         """Tracing of the following renders: HIP events between the stages
@@ -387,3 +428,52 @@ class RenderGraph:
             self.close()
         except Exception:
             pass
+
+
+def render_autograd(renderer: Renderer, means, log_scales, quats, opacity_logits, sh, camera: dict, width: int,
+                    height: int, background=(0.0, 0.0, 0.0)):
+    """Differentiable render: (image [3,H,W], final_T [H,W]) with gradients
+    to the float32 parameter tensors through gs_render_backward.  The
+    renderer must not render again before the backward of this call."""
+    return _RenderFunction.apply(renderer, camera, int(width), int(height), tuple(background), means, log_scales,
+                                 quats, opacity_logits, sh)
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class RenderFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, renderer, camera, width, height, background, means, log_scales, quats, opacity_logits, sh):
+            ncoef = sh.shape[0]
+            deg = {1: 0, 4: 1, 9: 2, 16: 3}[ncoef]
+            scene = {"means": means.detach().contiguous(), "log_scales": log_scales.detach().contiguous(),
+                     "quats": quats.detach().contiguous(), "opacity_logits": opacity_logits.detach().contiguous(),
+                     "sh": sh.detach().contiguous(), "sh_degree": deg, "attr_dtype": GS_F32}
+            out = renderer.render(scene, camera, width, height, background=background)
+            ctx.renderer, ctx.scene, ctx.generation = renderer, scene, renderer.generation
+            ctx.out = out
+            return out["image"], out["final_T"]
+
+        @staticmethod
+        def backward(ctx, g_image, g_T):
+            if ctx.renderer.generation != ctx.generation:
+                raise RuntimeError("the renderer rendered again before this backward")
+            g_image = torch.zeros_like(ctx.out["image"]) if g_image is None else g_image
+            grads = ctx.renderer.backward(ctx.scene, [g_image], [g_T] if g_T is not None else None)
+            return (None, None, None, None, None, grads["means"], grads["log_scales"], grads["quats"],
+                    grads["opacity_logits"], grads["sh"])
+
+    return RenderFunction
+
+
+class _LazyFunction:
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFunction._fn is None:
+            _LazyFunction._fn = _autograd_function()
+        return _LazyFunction._fn.apply(*args)
+
+
+_RenderFunction = _LazyFunction()

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgsmi.so")
 
-SOURCES = ["project.hip", "scan.hip", "depth_sort.hip", "tile_bin.hip", "blend.hip", "api.hip"]
+SOURCES = ["project.hip", "scan.hip", "depth_sort.hip", "tile_bin.hip", "blend.hip", "blend_backward.hip", "api.hip"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

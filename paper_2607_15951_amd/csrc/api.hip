@@ -57,6 +57,10 @@ struct gs_context {
     int sorted_in_b = 1;
     hipStream_t stream = nullptr;
     gs_graph* graph = nullptr;   // a captured render owns the workspace
+    std::vector<ViewParams> last_views;   // view table of the last render
+    gs_gaussians last_g{};                // scene of the last render
+    float last_bg[3] = {0.f, 0.f, 0.f};
+    DevBuf grad2d;                        // backward: per-item blend gradients
 };
 
 struct gs_graph {
@@ -392,6 +396,9 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     STAGE_MARK(8);
 
     ctx->have_render = true;
+    ctx->last_views = hv;
+    ctx->last_g = *g;
+    for (int k = 0; k < 3; ++k) ctx->last_bg[k] = bl.bg[k];
     ctx->timed = (ctx->profiling & GS_PROFILE_STAGES) != 0;
     ctx->traced = bl.tile_work != nullptr;
     ctx->n = n;
@@ -467,7 +474,7 @@ void gs_destroy(gs_context* ctx)
     if (!ctx) return;
     if (ctx->graph) gs_graph_destroy(ctx->graph);
     (void)hipSetDevice(ctx->device);
-    DevBuf* bufs[] = {&ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
+    DevBuf* bufs[] = {&ctx->grad2d, &ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
                       &ctx->sort_ka, &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb, &ctx->hist,
                       &ctx->scan_scratch, &ctx->bin_info, &ctx->counts1, &ctx->rows_off, &ctx->row_ent,
                       &ctx->counts2, &ctx->partials, &ctx->views, &ctx->row_tiles_x, &ctx->view_counts,
@@ -639,6 +646,70 @@ gs_status build_views(gs_context* ctx, const gs_gaussians* g, const gs_view* vie
 }  // namespace
 
 extern "C" {
+
+gs_status gs_render_backward(gs_context* ctx, const gs_gaussians* g, const float* const* grad_rgb,
+                             const float* const* grad_final_T, const gs_gradients* grads, void* stream)
+{
+    if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (!g || !grad_rgb || !grads) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (!ctx->have_render) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "no render on this context yet");
+    const gs_gaussians& f = ctx->last_g;
+    if (g->n != f.n || g->sh_degree != f.sh_degree || g->attr_dtype != f.attr_dtype || g->means != f.means ||
+        g->log_scales != f.log_scales || g->quats != f.quats || g->opacity_logits != f.opacity_logits ||
+        g->sh != f.sh)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "g must be the scene of the last render on this context");
+    if (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "a gradient pointer is NULL");
+    std::vector<ViewParams> hv = ctx->last_views;
+    const int V = (int)hv.size();
+    for (int v = 0; v < V; ++v) {
+        if (!hv[v].out_T || !hv[v].out_nc)
+            return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the forward render must write out_final_T and out_n_contrib");
+        if (!grad_rgb[v]) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "grad_rgb holds a NULL view");
+        hv[v].grad_rgb = grad_rgb[v];
+        hv[v].grad_T = grad_final_T ? grad_final_T[v] : nullptr;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    gs_status st;
+    const int64_t items = ctx->n * V;
+    if ((st = ensure(ctx, ctx->grad2d, (size_t)std::max<int64_t>(items, 1) * kGrad2d * 4)) != GS_OK) return st;
+    ViewParams* views = static_cast<ViewParams*>(ctx->views.p);
+    HIP_TRY(write_view_table(hv, views, s), "view table");
+    float* grad2d = static_cast<float*>(ctx->grad2d.p);
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, items * kGrad2d, s), "clear gradients");
+    BlendBackArgs bb{};
+    bb.splats = static_cast<const Splat*>(ctx->splats.p);
+    bb.values = static_cast<const uint32_t*>(ctx->values.p);
+    bb.tile_offsets = static_cast<const uint32_t*>(ctx->tile_offsets.p);
+    bb.views = views;
+    bb.n_views = V;
+    bb.tiles = ctx->tiles;
+    for (int k = 0; k < 3; ++k) bb.bg[k] = ctx->last_bg[k];
+    bb.grad2d = grad2d;
+    HIP_TRY(launch_blend_backward(bb, ctx->capacity, s), "blend backward");
+    ProjectBackArgs pb{};
+    pb.n = g->n;
+    pb.sh_degree = g->sh_degree;
+    pb.dtype = g->attr_dtype;
+    pb.means = g->means;
+    pb.log_scales = g->log_scales;
+    pb.quats = g->quats;
+    pb.logits = g->opacity_logits;
+    pb.sh = g->sh;
+    pb.views = views;
+    pb.n_views = V;
+    pb.grad2d = grad2d;
+    pb.tiles_touched = static_cast<const uint32_t*>(ctx->tiles_touched.p);
+    pb.g_means = grads->means;
+    pb.g_log_scales = grads->log_scales;
+    pb.g_quats = grads->quats;
+    pb.g_logits = grads->opacity_logits;
+    pb.g_sh = grads->sh;
+    HIP_TRY(launch_project_backward(pb, s), "projection backward");
+    ctx->stream = s;
+    return GS_OK;
+}
 
 gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out)
 {

@@ -32,44 +32,12 @@
 // saturate walk their whole list), and contiguous bands per XCD would leave
 // the XCDs with the heavy bands running long after the others finish.
 #include "gs_internal.h"
+#include "blend_stage.h"
 
 namespace gsmi {
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kUnroll = 8;
-constexpr int kGroup = 16;   // consecutive tiles one XCD takes in turn
-
-// Smallest value of the quadratic form A x^2 + 2 B x y + C y^2 (positive
-// definite) over the box [x0, x0 + 7] x [y0, y0 + 7] of pixel offsets, made a
-// lower bound by subtracting 1e-5 of the size of its terms.  The form is
-// convex, so its minimum is 0 when the origin lies in the box and on an edge
-// otherwise; on an edge it is a 1D quadratic minimised in closed form.
-__device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, float B, float C)
-{
-    const float x1 = x0 + 7.0f, y1 = y0 + 7.0f;
-    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return 0.0f;
-    float q = INFINITY, S = 0.0f;
-    const float xs[2] = {x0, x1}, ys[2] = {y0, y1};
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const float xe = xs[e];
-        const float y = fminf(y1, fmaxf(y0, -B * xe / C));
-        const float qe = A * xe * xe + 2.0f * B * xe * y + C * y * y;
-        if (qe < q) {
-            q = qe;
-            S = A * xe * xe + 2.0f * fabsf(B * xe * y) + C * y * y;
-        }
-        const float ye = ys[e];
-        const float x = fminf(x1, fmaxf(x0, -B * ye / A));
-        const float qf = A * x * x + 2.0f * B * x * ye + C * ye * ye;
-        if (qf < q) {
-            q = qf;
-            S = A * x * x + 2.0f * fabsf(B * x * ye) + C * ye * ye;
-        }
-    }
-    return q - 1e-5f * (S + 1.0f);
-}
 
 // kStats: the tracing variant, which also records its work per tile
 // (a.tile_work)
@@ -81,8 +49,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     __shared__ float4 s2[256 + kUnroll];   // r, g, b, list position (int bits)
     __shared__ uint32_t s_mask[256 + kUnroll];   // quads (waves) the entry can reach
     __shared__ uint32_t s_wave_keep[4];
-    const int i = (int)(blockIdx.x >> 3);
-    const int tile = ((i / kGroup) * 8 + (int)(blockIdx.x & 7)) * kGroup + i % kGroup;
+    const int tile = blend_tile_of_block();
     if (tile >= a.tiles) return;
     // the view owning this global tile: its size, tile grid and outputs
     const ViewParams& vp = a.views[view_of_tile(a.views, a.n_views, (uint32_t)tile)];
@@ -135,20 +102,8 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
         uint32_t qmask = 0u;
         float4 v0, v1, v2;
         if (e < end) {
-            const double du = ((double)ra.x + (double)ra.z) - ox;
-            const double dv = ((double)ra.y + (double)ra.w) - oy;
-            const float du_hi = (float)du, dv_hi = (float)dv;
-            // reachable quads: alpha 1/255 is within reach somewhere in the quad
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float qmin =
-                    quad_min_over_box(du_hi - (float)((q & 1) * 8 + 7), dv_hi - (float)((q >> 1) * 8 + 7), rb.x, rb.y, rb.z);
-                if (rb.w * __expf(-0.5f * qmin) >= (1.0f / 255.0f) * (1.0f - 1e-5f)) qmask |= 1u << q;
-            }
+            qmask = stage_entry(ra, rb, rc, ox, oy, (uint32_t)(e - start), v0, v1, v2);
             keep = qmask != 0u;
-            v0 = make_float4(du_hi, dv_hi, (float)(du - (double)du_hi), (float)(dv - (double)dv_hi));
-            v1 = make_float4(-0.5f * kLog2e * rb.x, -kLog2e * rb.y, -0.5f * kLog2e * rb.z, rb.w);
-            v2 = make_float4(rc.x, rc.y, rc.z, __int_as_float((int)(e - start)));
         }
         // order-preserving compaction of the kept entries
         const uint64_t km = __ballot(keep);
@@ -273,7 +228,7 @@ hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s)
 {
     const int64_t T = a.tiles;
     if (T <= 0) return hipSuccess;
-    const int blocks = (int)(8 * kGroup * ((T + 8 * kGroup - 1) / (8 * kGroup)));
+    const int blocks = blend_blocks(T);
     if (a.tile_work) hipLaunchKernelGGL(blend_kernel<true>, dim3(blocks), dim3(256), 0, s, a, capacity);
     else hipLaunchKernelGGL(blend_kernel<false>, dim3(blocks), dim3(256), 0, s, a, capacity);
     return hipGetLastError();

@@ -1,0 +1,81 @@
+// blend_stage.h -- staging of one list entry for the per-tile blend, shared
+// by the forward (blend.hip) and backward (backward.hip) kernels so that both
+// see the same per-entry values and take the same inclusion decisions.
+#pragma once
+
+#include "gs_internal.h"
+
+namespace gsmi {
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Smallest value of the quadratic form A x^2 + 2 B x y + C y^2 (positive
+// definite) over the box [x0, x0 + 7] x [y0, y0 + 7] of pixel offsets, made a
+// lower bound by subtracting 1e-5 of the size of its terms.  The form is
+// convex, so its minimum is 0 when the origin lies in the box and on an edge
+// otherwise; on an edge it is a 1D quadratic minimised in closed form.
+__device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, float B, float C)
+{
+    const float x1 = x0 + 7.0f, y1 = y0 + 7.0f;
+    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return 0.0f;
+    float q = INFINITY, S = 0.0f;
+    const float xs[2] = {x0, x1}, ys[2] = {y0, y1};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float xe = xs[e];
+        const float y = fminf(y1, fmaxf(y0, -B * xe / C));
+        const float qe = A * xe * xe + 2.0f * B * xe * y + C * y * y;
+        if (qe < q) {
+            q = qe;
+            S = A * xe * xe + 2.0f * fabsf(B * xe * y) + C * y * y;
+        }
+        const float ye = ys[e];
+        const float x = fminf(x1, fmaxf(x0, -B * ye / A));
+        const float qf = A * x * x + 2.0f * B * x * ye + C * ye * ye;
+        if (qf < q) {
+            q = qf;
+            S = A * x * x + 2.0f * fabsf(B * x * ye) + C * ye * ye;
+        }
+    }
+    return q - 1e-5f * (S + 1.0f);
+}
+
+// Stages one entry (its 48-byte record ra, rb, rc) for the tile with origin
+// (ox, oy): v0 = centre - tile origin as a float hi/lo pair computed in double
+// precision, v1 = conic scaled by -0.5 log2(e) (so alpha = opacity *
+// exp2(A' dx^2 + B' dx dy + C' dy^2)) and opacity, v2 = colour and the list
+// position.  Returns the 4-bit mask of the tile's 8x8 quads in which the entry
+// can reach alpha 1/255 (a conservative bound: an entry outside it is skipped
+// by every pixel of the quad).
+__device__ __forceinline__ uint32_t stage_entry(const float4& ra, const float4& rb, const float4& rc, double ox,
+                                                double oy, uint32_t pos, float4& v0, float4& v1, float4& v2)
+{
+    const double du = ((double)ra.x + (double)ra.z) - ox;
+    const double dv = ((double)ra.y + (double)ra.w) - oy;
+    const float du_hi = (float)du, dv_hi = (float)dv;
+    uint32_t qmask = 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float qmin =
+            quad_min_over_box(du_hi - (float)((q & 1) * 8 + 7), dv_hi - (float)((q >> 1) * 8 + 7), rb.x, rb.y, rb.z);
+        if (rb.w * __expf(-0.5f * qmin) >= (1.0f / 255.0f) * (1.0f - 1e-5f)) qmask |= 1u << q;
+    }
+    v0 = make_float4(du_hi, dv_hi, (float)(du - (double)du_hi), (float)(dv - (double)dv_hi));
+    v1 = make_float4(-0.5f * kLog2e * rb.x, -kLog2e * rb.y, -0.5f * kLog2e * rb.z, rb.w);
+    v2 = make_float4(rc.x, rc.y, rc.z, __int_as_float((int)pos));
+    return qmask;
+}
+
+// Workgroup -> tile: tiles are cut into groups of kGroup consecutive tiles
+// (row-major), dealt to the 8 XCDs in turn (block b runs on XCD b % 8).
+constexpr int kGroup = 16;
+
+__device__ __forceinline__ int blend_tile_of_block()
+{
+    const int i = (int)(blockIdx.x >> 3);
+    return ((i / kGroup) * 8 + (int)(blockIdx.x & 7)) * kGroup + i % kGroup;
+}
+
+inline int blend_blocks(int64_t tiles) { return (int)(8 * kGroup * ((tiles + 8 * kGroup - 1) / (8 * kGroup))); }
+
+}  // namespace gsmi

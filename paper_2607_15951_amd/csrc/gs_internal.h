@@ -41,6 +41,9 @@ struct ViewParams {
     float* out_rgb;                 // [3][H][W]
     float* out_T;                   // [H][W] or null
     uint32_t* out_nc;               // [H][W] or null
+    // backward only: dL/d(out_rgb) [3][H][W] and dL/d(out_T) [H][W] or null
+    const float* grad_rgb;
+    const float* grad_T;
 };
 
 // Per-view counters written on the device: [0] visible Gaussians, [2..3]
@@ -153,6 +156,47 @@ struct BlendArgs {
 };
 
 hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s);
+
+// Backward of the blend: per list entry, dL/d(u, v, A, B, C, opacity, r, g, b)
+// summed over the pixels of every tile into grad2d[item][kGrad2d] (zeroed by
+// the caller).  Reads each view's forward outputs and dL/d(out_rgb, out_T)
+// from the view table.
+constexpr int kGrad2d = 9;
+struct BlendBackArgs {
+    const Splat* splats;
+    const uint32_t* values;
+    const uint32_t* tile_offsets;
+    const ViewParams* views;
+    int n_views;
+    int64_t tiles;
+    float bg[3];
+    float* grad2d;
+};
+hipError_t launch_blend_backward(const BlendBackArgs& a, uint64_t capacity, hipStream_t s);
+
+// Backward of the projection: from grad2d of every (view, Gaussian) item to
+// the gradients of the Gaussian parameters (float32, the input layouts),
+// summed over the views.
+struct ProjectBackArgs {
+    int64_t n;
+    int sh_degree;
+    int dtype;
+    const float* means;
+    const void* log_scales;
+    const void* quats;
+    const void* logits;
+    const void* sh;
+    const ViewParams* views;
+    int n_views;
+    const float* grad2d;            // [n_views * n][kGrad2d]
+    const uint32_t* tiles_touched;  // [n_views * n]: 0 for an item culled in its view
+    float* g_means;                 // [3][n]
+    float* g_log_scales;            // [3][n]
+    float* g_quats;                 // [4][n]
+    float* g_logits;                // [n]
+    float* g_sh;                    // [(deg+1)^2][3][n]
+};
+hipError_t launch_project_backward(const ProjectBackArgs& a, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_write_keys(const uint32_t* values, const uint32_t* tile_offsets,

@@ -298,6 +298,223 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
     }
 }
 
+// ---------------------------------------------------------------- backward
+// Gradient of the projection of one Gaussian, in double precision, from the
+// per-item gradient of the blend's inputs g9 = dL/d(u, v, A, B, C, opacity,
+// r, g, b).  The forward quantities are recomputed (the item was visible in
+// this view, so every cull passed).  Sums into gm (mean), gQ (rotation
+// matrix of the unit quaternion), gsc (scales exp(log_scale)), gY (SH basis
+// values) and gop (opacity).
+
+// d(real SH basis Y_k)/d(x, y, z) at an unnormalised point, k < (deg+1)^2
+__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, int k, double& gx, double& gy, double& gz)
+{
+    const double c1 = 0.48860251190291992, k4 = 1.0925484305920792, k6 = 0.31539156525252005,
+                 k8 = 0.54627421529603959, k9 = 0.59004358992664352, k10 = 2.8906114426405538,
+                 k11 = 0.45704579946446572, k12 = 0.37317633259011540, k14 = 1.4453057213202769;
+    gx = gy = gz = 0.0;
+    switch (k) {
+    case 1: gy = -c1; break;
+    case 2: gz = c1; break;
+    case 3: gx = -c1; break;
+    case 4: gx = k4 * y; gy = k4 * x; break;
+    case 5: gy = -k4 * z; gz = -k4 * y; break;
+    case 6: gx = -2.0 * k6 * x; gy = -2.0 * k6 * y; gz = 4.0 * k6 * z; break;
+    case 7: gx = -k4 * z; gz = -k4 * x; break;
+    case 8: gx = 2.0 * k8 * x; gy = -2.0 * k8 * y; break;
+    case 9: gx = -6.0 * k9 * x * y; gy = -3.0 * k9 * (x * x - y * y); break;
+    case 10: gx = k10 * y * z; gy = k10 * x * z; gz = k10 * x * y; break;
+    case 11: gx = 2.0 * k11 * x * y; gy = -k11 * (4.0 * z * z - x * x - 3.0 * y * y); gz = -8.0 * k11 * y * z; break;
+    case 12: gx = -6.0 * k12 * x * z; gy = -6.0 * k12 * y * z; gz = k12 * (6.0 * z * z - 3.0 * x * x - 3.0 * y * y); break;
+    case 13: gx = -k11 * (4.0 * z * z - 3.0 * x * x - y * y); gy = 2.0 * k11 * x * y; gz = -8.0 * k11 * x * z; break;
+    case 14: gx = 2.0 * k14 * x * z; gy = -2.0 * k14 * y * z; gz = k14 * (x * x - y * y); break;
+    case 15: gx = -3.0 * k9 * (x * x - y * y); gy = 6.0 * k9 * x * y; break;
+    default: break;
+    }
+}
+
+template <int DT, int DEG>
+__global__ __launch_bounds__(256) void project_backward_kernel(ProjectBackArgs a)
+{
+    constexpr int ncoef = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t n = a.n;
+    const double mx = a.means[i], my = a.means[n + i], mz = a.means[2 * n + i];
+    const double l[3] = {load_attr<DT>(a.log_scales, i), load_attr<DT>(a.log_scales, n + i),
+                         load_attr<DT>(a.log_scales, 2 * n + i)};
+    const double q4[4] = {load_attr<DT>(a.quats, i), load_attr<DT>(a.quats, n + i), load_attr<DT>(a.quats, 2 * n + i),
+                          load_attr<DT>(a.quats, 3 * n + i)};
+    const float logit = load_attr<DT>(a.logits, i);
+    float coef[3 * ncoef];
+#pragma unroll
+    for (int k = 0; k < 3 * ncoef; ++k) coef[k] = load_attr<DT>(a.sh, (int64_t)k * n + i);
+
+    // rotation Q of the unit quaternion, scales, M = Q diag(s), Sg = M M^T
+    const double qn = sqrt(((q4[0] * q4[0] + q4[1] * q4[1]) + q4[2] * q4[2]) + q4[3] * q4[3]);
+    double gm[3] = {0, 0, 0}, gQ[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gsc[3] = {0, 0, 0}, gop = 0.0;
+    float gcoef[3 * ncoef];   // float: per-view sums of a few terms
+#pragma unroll
+    for (int k = 0; k < 3 * ncoef; ++k) gcoef[k] = 0.0f;
+    double Sg[9];
+    const bool cov_ok = world_covariance(l[0], l[1], l[2], q4[0], q4[1], q4[2], q4[3], Sg);
+    const double w = cov_ok ? q4[0] / qn : 0.0, x = cov_ok ? q4[1] / qn : 0.0, y = cov_ok ? q4[2] / qn : 0.0,
+                 z = cov_ok ? q4[3] / qn : 0.0;
+    double Q[9];
+    Q[0] = 1.0 - 2.0 * (y * y + z * z);
+    Q[1] = 2.0 * (x * y - w * z);
+    Q[2] = 2.0 * (x * z + w * y);
+    Q[3] = 2.0 * (x * y + w * z);
+    Q[4] = 1.0 - 2.0 * (x * x + z * z);
+    Q[5] = 2.0 * (y * z - w * x);
+    Q[6] = 2.0 * (x * z - w * y);
+    Q[7] = 2.0 * (y * z + w * x);
+    Q[8] = 1.0 - 2.0 * (x * x + y * y);
+    const double sc[3] = {exp(l[0]), exp(l[1]), exp(l[2])};
+
+    for (int v = 0; cov_ok && v < a.n_views; ++v) {
+        const int64_t item = (int64_t)v * n + i;
+        if (a.tiles_touched[item] == 0) continue;
+        const float* g9 = a.grad2d + item * kGrad2d;
+        const double gu = g9[0], gv = g9[1], gA = g9[2], gB = g9[3], gC = g9[4], go = g9[5];
+        const ViewParams& vp = a.views[v];
+        const double* W = vp.R;
+        const double t0 = ((W[0] * mx + W[1] * my) + W[2] * mz) + vp.t[0];
+        const double t1 = ((W[3] * mx + W[4] * my) + W[5] * mz) + vp.t[1];
+        const double t2 = ((W[6] * mx + W[7] * my) + W[8] * mz) + vp.t[2];
+        // V = W Sg W^T
+        double L[9], V[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) L[3 * r + c] = W[3 * r] * Sg[c] + W[3 * r + 1] * Sg[3 + c] + W[3 * r + 2] * Sg[6 + c];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) V[3 * r + c] = L[3 * r] * W[3 * c] + L[3 * r + 1] * W[3 * c + 1] + L[3 * r + 2] * W[3 * c + 2];
+        const double limx = 1.3 * ((0.5 * (double)vp.width) / vp.fx), limy = 1.3 * ((0.5 * (double)vp.height) / vp.fy);
+        const double rx = t0 / t2, ry = t1 / t2;
+        const bool clx = rx < -limx || rx > limx, cly = ry < -limy || ry > limy;
+        const double xcl = fmin(limx, fmax(-limx, rx)) * t2, ycl = fmin(limy, fmax(-limy, ry)) * t2;
+        const double J[6] = {vp.fx / t2, 0.0, -(vp.fx * xcl) / (t2 * t2), 0.0, vp.fy / t2, -(vp.fy * ycl) / (t2 * t2)};
+        double JV[6];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 3; ++c) JV[3 * r + c] = J[3 * r] * V[c] + J[3 * r + 1] * V[3 + c] + J[3 * r + 2] * V[6 + c];
+        const double ca = (JV[0] * J[0] + JV[1] * J[1] + JV[2] * J[2]) + 0.3;
+        const double cb = JV[0] * J[3] + JV[1] * J[4] + JV[2] * J[5];
+        const double cc = (JV[3] * J[3] + JV[4] * J[4] + JV[5] * J[5]) + 0.3;
+        const double det = ca * cc - cb * cb;
+        const double A = cc / det, B = -cb / det, C = ca / det;
+        // conic -> 2D covariance: dL/dSigma'' = -Q G Q with G = [[gA, gB/2], [gB/2, gC]]
+        const double G01 = 0.5 * gB;
+        const double QG00 = A * gA + B * G01, QG01 = A * G01 + B * gC, QG10 = B * gA + C * G01, QG11 = B * G01 + C * gC;
+        const double gP00 = -(QG00 * A + QG01 * B), gP01 = -(QG00 * B + QG01 * C), gP11 = -(QG10 * B + QG11 * C);
+        // Sigma' = J V J^T: gV = J^T gP J, gJ = 2 gP J V (gP, V symmetric)
+        const double gP[4] = {gP00, gP01, gP01, gP11};
+        double gV[9], gJ[6];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                gV[3 * r + c] = J[r] * (gP[0] * J[c] + gP[1] * J[3 + c]) + J[3 + r] * (gP[2] * J[c] + gP[3] * J[3 + c]);
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 3; ++c) gJ[3 * r + c] = 2.0 * (gP[2 * r] * JV[c] + gP[2 * r + 1] * JV[3 + c]);
+        // camera-space position t: through J, and through the centre (u, v)
+        double gt0 = gu * vp.fx / t2, gt1 = gv * vp.fy / t2;
+        double gt2 = -gu * vp.fx * t0 / (t2 * t2) - gv * vp.fy * t1 / (t2 * t2);
+        gt2 += -gJ[0] * vp.fx / (t2 * t2) - gJ[4] * vp.fy / (t2 * t2);
+        if (!clx) {
+            gt0 += -gJ[2] * vp.fx / (t2 * t2);
+            gt2 += gJ[2] * 2.0 * vp.fx * t0 / (t2 * t2 * t2);
+        } else {
+            gt2 += gJ[2] * vp.fx * (xcl / t2) / (t2 * t2);
+        }
+        if (!cly) {
+            gt1 += -gJ[5] * vp.fy / (t2 * t2);
+            gt2 += gJ[5] * 2.0 * vp.fy * t1 / (t2 * t2 * t2);
+        } else {
+            gt2 += gJ[5] * vp.fy * (ycl / t2) / (t2 * t2);
+        }
+        for (int c = 0; c < 3; ++c) gm[c] += W[c] * gt0 + W[3 + c] * gt1 + W[6 + c] * gt2;
+        // V = W Sg W^T -> gSg = W^T gV W; Sg = M M^T -> gM = 2 gSg M; M = Q diag(s)
+        double gW1[9], gSg[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) gW1[3 * r + c] = gV[3 * r] * W[c] + gV[3 * r + 1] * W[3 + c] + gV[3 * r + 2] * W[6 + c];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) gSg[3 * r + c] = W[r] * gW1[c] + W[3 + r] * gW1[3 + c] + W[6 + r] * gW1[6 + c];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double gM = 0.0;
+                for (int k = 0; k < 3; ++k) gM += 2.0 * gSg[3 * r + k] * Q[3 * k + c] * sc[c];
+                gQ[3 * r + c] += gM * sc[c];
+                gsc[c] += gM * Q[3 * r + c];
+            }
+        gop += go;
+        // colour: rgb_c = max(0, sum_k f_kc Y_k(d) + 0.5), d the unit view direction
+        const double dxv = mx - vp.campos[0], dyv = my - vp.campos[1], dzv = mz - vp.campos[2];
+        const double dn = sqrt(dxv * dxv + dyv * dyv + dzv * dzv);
+        const double ux = dxv / dn, uy = dyv / dn, uz = dzv / dn;
+        float Yf[16];
+        sh_basis((float)ux, (float)uy, (float)uz, DEG, Yf);
+        float gY[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) gY[k] = 0.0f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float raw = 0.0f;   // the forward's colour sum
+#pragma unroll
+            for (int k = 0; k < ncoef; ++k) raw += coef[k * 3 + ch] * Yf[k];
+            if (!(raw + 0.5f > 0.0f)) continue;   // clamped at 0
+            const float gc = g9[6 + ch];
+#pragma unroll
+            for (int k = 0; k < ncoef; ++k) {
+                gcoef[k * 3 + ch] += gc * Yf[k];
+                gY[k] += gc * coef[k * 3 + ch];
+            }
+        }
+        double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
+        for (int k = 1; k < ncoef; ++k) {
+            double hx, hy, hz;
+            sh_basis_grad(ux, uy, uz, k, hx, hy, hz);
+            gd0 += gY[k] * hx;
+            gd1 += gY[k] * hy;
+            gd2 += gY[k] * hz;
+        }
+        const double dot = ux * gd0 + uy * gd1 + uz * gd2;
+        gm[0] += (gd0 - ux * dot) / dn;
+        gm[1] += (gd1 - uy * dot) / dn;
+        gm[2] += (gd2 - uz * dot) / dn;
+    }
+
+    // quaternion: through the rotation matrix of q / |q|
+    double gw = 2.0 * (-z * gQ[1] + y * gQ[2] + z * gQ[3] - x * gQ[5] - y * gQ[6] + x * gQ[7]);
+    double gx = 2.0 * (y * gQ[1] + z * gQ[2] + y * gQ[3] - 2.0 * x * gQ[4] - w * gQ[5] + z * gQ[6] + w * gQ[7] -
+                       2.0 * x * gQ[8]);
+    double gy = 2.0 * (-2.0 * y * gQ[0] + x * gQ[1] + w * gQ[2] + x * gQ[3] + z * gQ[5] - w * gQ[6] + z * gQ[7] -
+                       2.0 * y * gQ[8]);
+    double gz = 2.0 * (-2.0 * z * gQ[0] - w * gQ[1] + x * gQ[2] + w * gQ[3] - 2.0 * z * gQ[4] + y * gQ[5] + x * gQ[6] +
+                       y * gQ[7]);
+    const double qd = w * gw + x * gx + y * gy + z * gz;
+    const double inv_qn = cov_ok ? 1.0 / qn : 0.0;
+    a.g_quats[i] = (float)((gw - w * qd) * inv_qn);
+    a.g_quats[n + i] = (float)((gx - x * qd) * inv_qn);
+    a.g_quats[2 * n + i] = (float)((gy - y * qd) * inv_qn);
+    a.g_quats[3 * n + i] = (float)((gz - z * qd) * inv_qn);
+    for (int c = 0; c < 3; ++c) {
+        a.g_means[(int64_t)c * n + i] = (float)gm[c];
+        a.g_log_scales[(int64_t)c * n + i] = (float)(gsc[c] * sc[c]);
+    }
+    const double sig = 1.0 / (1.0 + exp(-(double)logit));
+    a.g_logits[i] = (float)(gop * sig * (1.0 - sig));
+#pragma unroll
+    for (int k = 0; k < 3 * ncoef; ++k) a.g_sh[(int64_t)k * n + i] = gcoef[k];
+}
+
+template <int DT>
+void launch_project_backward_dt(const ProjectBackArgs& a, unsigned blocks, hipStream_t s)
+{
+    switch (a.sh_degree) {
+    case 0: hipLaunchKernelGGL((project_backward_kernel<DT, 0>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((project_backward_kernel<DT, 1>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((project_backward_kernel<DT, 2>), dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((project_backward_kernel<DT, 3>), dim3(blocks), dim3(256), 0, s, a); break;
+    }
+}
+
 }  // namespace
 
 // Per view (one block each): visible Gaussians and pairs, summed over the
@@ -347,6 +564,18 @@ void launch_project_views(const ProjectArgs& a, unsigned blocks, hipStream_t s)
 {
     if (a.n_views == 1) launch_project_dt<DT, true>(a, blocks, s);
     else launch_project_dt<DT, false>(a, blocks, s);
+}
+
+hipError_t launch_project_backward(const ProjectBackArgs& a, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((a.n + 255) / 256);
+    switch (a.dtype) {
+    case 0: launch_project_backward_dt<0>(a, blocks, s); break;
+    case 1: launch_project_backward_dt<1>(a, blocks, s); break;
+    default: launch_project_backward_dt<2>(a, blocks, s); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
