@@ -52,7 +52,8 @@ def attr_bytes(dtype: int) -> int:
 
 def algorithmic_bytes(stage: str, n: int, n_vis: int, K: int, R: int, deg: int, dtype: int, W: int, H: int,
                       stats: dict) -> float:
-    """HBM bytes one launch of a single-kernel stage must move."""
+    """HBM bytes one launch of a single-kernel stage must move: its compulsory
+    reads and writes, each input and output once."""
     tx, ty = (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
     if stage == "project":
         per_in = 12 + attr_bytes(dtype) * (3 + 4 + 1 + 3 * (deg + 1) ** 2)
@@ -265,6 +266,36 @@ def time_batched(r, dev, cams, steps: int) -> dict:
             "views_per_s_one_call_per_view": round(len(cams) * 1e3 / ms_single, 1), "steps": bsteps}
 
 
+def time_backward(r, dev, cam, W: int, H: int, steps: int, out) -> dict:
+    """Device time of gs_render_backward for the frame (seeded dL/d(image) and
+    dL/d(final_T) in [0, 1)), alone and after its render (one training
+    step's rasterizer work)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1234)
+    gi = torch.rand((3, H, W), device="cuda", generator=g)
+    gt = torch.rand((H, W), device="cuda", generator=g)
+    r.render(dev, cam, W, H, out=out)
+    r.backward(dev, [gi], [gt])
+    torch.cuda.synchronize()
+    bsteps = max(3, min(steps, 20))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(bsteps):
+        r.backward(dev, [gi], [gt])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_bwd = e0.elapsed_time(e1) / bsteps
+    t0 = time.perf_counter()
+    for _ in range(bsteps):
+        r.render(dev, cam, W, H, out=out)
+        r.backward(dev, [gi], [gt])
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / bsteps
+    return {"ms_backward": round(ms_bwd, 4), "ms_forward_backward": round(ms_step, 4),
+            "forward_backward_per_s": round(1e3 / ms_step, 1), "steps": bsteps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,7 +323,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this single-GPU build "
-              "(the render shards by camera or screen tiles, see DESIGN.md)", file=sys.stderr)
+              "(the render would shard by camera or by screen tiles)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -374,6 +405,9 @@ def main():
                               "project_algorithmic_GBps": round(pb / (vst["project"] * 1e-3) / 1e9, 1)}
             del vdev
             log(f"[bench] variant {name}: " + json.dumps(variants[name]))
+        if dtype == gs.GS_F32:
+            variants["backward"] = time_backward(r, dev, cam, W, H, args.steps, out)
+            log("[bench] variant backward: " + json.dumps(variants["backward"]))
         # batched: the same frame's scene from 8 cameras on a ring (1080p each),
         # and the 64-camera mixed-resolution workload, each one
         # gs_render_batched call per step, against the same views rendered one

@@ -15,9 +15,10 @@
 //
 // Layout as the forward: one workgroup of four waves per 16x16 tile, one pixel
 // per lane, entries staged through LDS with the same per-quad reach masks.
-// Per entry, each wave sums its 64 pixels' nine gradients and adds them into
-// an LDS row of the staged entry; after the batch every row with a
-// contribution goes to HBM with nine atomic adds (once per tile and entry).
+// Per entry, each wave sums its 64 pixels' nine gradients (a transposed
+// butterfly, below) and adds them into an LDS row of the staged entry; after
+// the batch every row with a contribution goes to HBM with nine atomic adds
+// (once per tile and entry).
 #include "blend_stage.h"
 
 namespace gsmi {
@@ -25,10 +26,52 @@ namespace {
 
 constexpr float kLn2 = 0.69314718055994531f;
 
-__device__ __forceinline__ float wave_sum(float v)
+// The value of the lane whose index differs in bit kBit: DPP quad
+// permutations for bits 0 and 1, ds_swizzle (bit-mask mode, within 32 lanes)
+// for bits 2 to 4, ds_bpermute across the two halves for bit 5.
+template <int kBit>
+__device__ __forceinline__ float lane_xor(float v)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const int x = __float_as_int(v);
+    if constexpr (kBit == 0) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+    else if constexpr (kBit == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+    else if constexpr (kBit < 5) return __int_as_float(__builtin_amdgcn_ds_swizzle(x, 0x1F | ((1 << kBit) << 10)));
+    else return __shfl_xor(v, 32, 64);
+}
+
+// One butterfly step over lane bit kBit for pairs (lo, hi): a lane whose bit
+// is clear keeps lo plus its partner's lo, the other keeps hi plus its
+// partner's hi, so one move per pair halves the values each lane carries.
+template <int kBit>
+__device__ __forceinline__ float trade(float lo, float hi, bool upper)
+{
+    return (upper ? hi : lo) + lane_xor<kBit>(upper ? lo : hi);
+}
+
+// Wave sums of the nine values g[0..8] of every lane, with 13 cross-lane moves
+// instead of 9 x 6: four trading steps over lane bits 0-3 leave each lane one
+// value summed over its 16-lane row, two plain steps over bits 4-5 finish the
+// sum.  Returns the sum a lane holds and sets slot to the index of its value,
+// or to -1 for a padding slot; lanes 0-15 hold each of the nine sums once.
+__device__ __forceinline__ float wave_sum9(const float g[kGrad2d], int lane, int& slot)
+{
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
+    float a[6], c[4], d[2];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) a[i] = trade<0>(g[i], i < 4 ? g[5 + i] : 0.0f, b0);   // g0-4 | g5-8, 0
+    a[5] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) c[i] = trade<1>(a[i], a[3 + i], b1);
+    c[3] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) d[i] = trade<2>(c[i], c[2 + i], b2);
+    float e = trade<3>(d[0], d[1], b3);
+    e += lane_xor<4>(e);
+    e += lane_xor<5>(e);
+    const int ic = (b2 ? 2 : 0) + (b3 ? 1 : 0);    // index into c
+    const int real = b1 ? (b0 ? 1 : 2) : 3;         // c entries that hold a value
+    slot = (lane < 16 && ic < real) ? (b0 ? 5 : 0) + (b1 ? 3 : 0) + ic : -1;
+    return e;
 }
 
 __global__ __launch_bounds__(256) void blend_backward_kernel(BlendBackArgs a, uint64_t capacity)
@@ -136,7 +179,7 @@ __global__ __launch_bounds__(256) void blend_backward_kernel(BlendBackArgs a, ui
                 g[6] = G0 * w;
                 g[7] = G1 * w;
                 g[8] = G2 * w;
-                const float inv = 1.0f / (1.0f - al);
+                const float inv = __builtin_amdgcn_rcpf(1.0f - al);   // 1 - al >= 0.01
                 const float ga = (G0 * e2.x + G1 * e2.y + G2 * e2.z) * Tr -
                                  (G0 * S0 + G1 * S1 + G2 * S2 + Gbg * Tf) * inv;
                 if (araw <= 0.99f) {
@@ -152,11 +195,9 @@ __global__ __launch_bounds__(256) void blend_backward_kernel(BlendBackArgs a, ui
                 Tr = Tr * (1.0f - al);
             }
             if (__ballot(take) != 0) {
-#pragma unroll
-                for (int k = 0; k < kGrad2d; ++k) {
-                    const float v = wave_sum(g[k]);
-                    if (lane == 0) atomicAdd(&s_acc[j][k], v);
-                }
+                int slot;
+                const float v = wave_sum9(g, lane, slot);
+                if (slot >= 0) atomicAdd(&s_acc[j][slot], v);
             }
         }
         __syncthreads();

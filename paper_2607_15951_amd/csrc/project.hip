@@ -299,44 +299,119 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 }
 
 // ---------------------------------------------------------------- backward
-// Gradient of the projection of one Gaussian, in double precision, from the
-// per-item gradient of the blend's inputs g9 = dL/d(u, v, A, B, C, opacity,
-// r, g, b).  The forward quantities are recomputed (the item was visible in
-// this view, so every cull passed).  Sums into gm (mean), gQ (rotation
-// matrix of the unit quaternion), gsc (scales exp(log_scale)), gY (SH basis
-// values) and gop (opacity).
+// Gradient of the projection from the per-item gradient of the blend's inputs
+// g9 = dL/d(u, v, A, B, C, opacity, r, g, b), summed over the views that show
+// the Gaussian.  The forward quantities are recomputed (an item with tiles was
+// visible in its view, so every cull passed).  Two kernels: the colour (SH)
+// part in float and the geometry part in double precision, so that neither
+// holds the other's registers.
 
-// d(real SH basis Y_k)/d(x, y, z) at an unnormalised point, k < (deg+1)^2
-__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, int k, double& gx, double& gy, double& gz)
+// d(real SH basis Y_k)/d(x, y, z), k < (deg+1)^2, of the polynomial forms
+// that sh_basis evaluates (equal to the basis on the unit sphere; only the
+// tangential part of this gradient is used)
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int k, float& gx, float& gy, float& gz)
 {
-    const double c1 = 0.48860251190291992, k4 = 1.0925484305920792, k6 = 0.31539156525252005,
-                 k8 = 0.54627421529603959, k9 = 0.59004358992664352, k10 = 2.8906114426405538,
-                 k11 = 0.45704579946446572, k12 = 0.37317633259011540, k14 = 1.4453057213202769;
-    gx = gy = gz = 0.0;
+    const float c1 = 0.48860251190291992f, k4 = 1.0925484305920792f, k6 = 0.31539156525252005f,
+                k8 = 0.54627421529603959f, k9 = 0.59004358992664352f, k10 = 2.8906114426405538f,
+                k11 = 0.45704579946446572f, k12 = 0.37317633259011540f, k14 = 1.4453057213202769f;
+    gx = gy = gz = 0.0f;
     switch (k) {
     case 1: gy = -c1; break;
     case 2: gz = c1; break;
     case 3: gx = -c1; break;
     case 4: gx = k4 * y; gy = k4 * x; break;
     case 5: gy = -k4 * z; gz = -k4 * y; break;
-    case 6: gx = -2.0 * k6 * x; gy = -2.0 * k6 * y; gz = 4.0 * k6 * z; break;
+    case 6: gx = -2.0f * k6 * x; gy = -2.0f * k6 * y; gz = 4.0f * k6 * z; break;
     case 7: gx = -k4 * z; gz = -k4 * x; break;
-    case 8: gx = 2.0 * k8 * x; gy = -2.0 * k8 * y; break;
-    case 9: gx = -6.0 * k9 * x * y; gy = -3.0 * k9 * (x * x - y * y); break;
+    case 8: gx = 2.0f * k8 * x; gy = -2.0f * k8 * y; break;
+    case 9: gx = -6.0f * k9 * x * y; gy = -3.0f * k9 * (x * x - y * y); break;
     case 10: gx = k10 * y * z; gy = k10 * x * z; gz = k10 * x * y; break;
-    case 11: gx = 2.0 * k11 * x * y; gy = -k11 * (4.0 * z * z - x * x - 3.0 * y * y); gz = -8.0 * k11 * y * z; break;
-    case 12: gx = -6.0 * k12 * x * z; gy = -6.0 * k12 * y * z; gz = k12 * (6.0 * z * z - 3.0 * x * x - 3.0 * y * y); break;
-    case 13: gx = -k11 * (4.0 * z * z - 3.0 * x * x - y * y); gy = 2.0 * k11 * x * y; gz = -8.0 * k11 * x * z; break;
-    case 14: gx = 2.0 * k14 * x * z; gy = -2.0 * k14 * y * z; gz = k14 * (x * x - y * y); break;
-    case 15: gx = -3.0 * k9 * (x * x - y * y); gy = 6.0 * k9 * x * y; break;
+    case 11: gx = 2.0f * k11 * x * y; gy = -k11 * (4.0f * z * z - x * x - 3.0f * y * y); gz = -8.0f * k11 * y * z; break;
+    case 12: gx = -6.0f * k12 * x * z; gy = -6.0f * k12 * y * z; gz = k12 * (6.0f * z * z - 3.0f * x * x - 3.0f * y * y); break;
+    case 13: gx = -k11 * (4.0f * z * z - 3.0f * x * x - y * y); gy = 2.0f * k11 * x * y; gz = -8.0f * k11 * x * z; break;
+    case 14: gx = 2.0f * k14 * x * z; gy = -2.0f * k14 * y * z; gz = k14 * (x * x - y * y); break;
+    case 15: gx = -3.0f * k9 * (x * x - y * y); gy = 6.0f * k9 * x * y; break;
     default: break;
     }
 }
 
+// Colour part of the backward, one thread per Gaussian, in float as the
+// forward evaluates it: rgb_c = max(0, sum_k f_kc Y_k(d) + 0.5) with d the
+// unit view direction.  Writes the SH coefficient gradients (summed over the
+// views, zero where no view shows the Gaussian) and the mean's gradient
+// through d; the geometry kernel adds the rest of the mean's gradient
+// afterwards.  Channels outer, views inner: only one channel's coefficients
+// and gradient sums are live, and d and Y(d) are recomputed per channel (a few
+// dozen flops) rather than held.  The mean's gradient through d is linear in
+// dL/dY = sum_c gc_c f_kc, so it is summed channel by channel.
 template <int DT, int DEG>
-__global__ __launch_bounds__(256) void project_backward_kernel(ProjectBackArgs a)
+__global__ __launch_bounds__(256) void project_backward_color_kernel(ProjectBackArgs a)
 {
     constexpr int ncoef = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t n = a.n;
+    const float mx = a.means[i], my = a.means[n + i], mz = a.means[2 * n + i];
+    float gm0 = 0.0f, gm1 = 0.0f, gm2 = 0.0f;
+#pragma unroll 1
+    for (int ch = 0; ch < 3; ++ch) {
+        float f[ncoef], gf[ncoef];
+#pragma unroll
+        for (int k = 0; k < ncoef; ++k) {
+            f[k] = load_attr<DT>(a.sh, (int64_t)(k * 3 + ch) * n + i);
+            gf[k] = 0.0f;
+        }
+        for (int v = 0; v < a.n_views; ++v) {
+            const int64_t item = (int64_t)v * n + i;
+            if (a.tiles_touched[item] == 0) continue;
+            const ViewParams& vp = a.views[v];
+            float dx = mx - vp.campos[0], dy = my - vp.campos[1], dz = mz - vp.campos[2];
+            const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            dx *= inv;
+            dy *= inv;
+            dz *= inv;
+            float Y[16];
+            sh_basis(dx, dy, dz, DEG, Y);
+            float raw = 0.0f;   // the forward's colour sum
+#pragma unroll
+            for (int k = 0; k < ncoef; ++k) raw += f[k] * Y[k];
+            if (!(raw + 0.5f > 0.0f)) continue;   // clamped at 0: no gradient
+            const float gc = a.grad2d[item * kGrad2d + 6 + ch];
+            float gd0 = 0.0f, gd1 = 0.0f, gd2 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < ncoef; ++k) {
+                gf[k] += gc * Y[k];
+                if (k > 0) {
+                    float hx, hy, hz;
+                    sh_basis_grad(dx, dy, dz, k, hx, hy, hz);
+                    const float gy = gc * f[k];
+                    gd0 += gy * hx;
+                    gd1 += gy * hy;
+                    gd2 += gy * hz;
+                }
+            }
+            // d = (m - campos) / |m - campos|: the tangential part over the length
+            const float dot = dx * gd0 + dy * gd1 + dz * gd2;
+            gm0 += (gd0 - dx * dot) * inv;
+            gm1 += (gd1 - dy * dot) * inv;
+            gm2 += (gd2 - dz * dot) * inv;
+        }
+#pragma unroll
+        for (int k = 0; k < ncoef; ++k) a.g_sh[(int64_t)(k * 3 + ch) * n + i] = gf[k];
+    }
+    a.g_means[i] = gm0;
+    a.g_means[n + i] = gm1;
+    a.g_means[2 * n + i] = gm2;
+}
+
+// Geometry part, one thread per Gaussian, in double precision: from
+// dL/d(u, v, A, B, C, opacity) of every view through the conic inverse, the
+// EWA Jacobian (guard-band clamp included), the world covariance, the scales,
+// the normalised quaternion and the sigmoid.  Adds to the mean's gradient
+// that the colour kernel wrote.
+template <int DT, bool kOneView>
+__global__ __launch_bounds__(256) void project_backward_geometry_kernel(ProjectBackArgs a)
+{
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     const int64_t n = a.n;
@@ -346,20 +421,14 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjectBackArgs a
     const double q4[4] = {load_attr<DT>(a.quats, i), load_attr<DT>(a.quats, n + i), load_attr<DT>(a.quats, 2 * n + i),
                           load_attr<DT>(a.quats, 3 * n + i)};
     const float logit = load_attr<DT>(a.logits, i);
-    float coef[3 * ncoef];
-#pragma unroll
-    for (int k = 0; k < 3 * ncoef; ++k) coef[k] = load_attr<DT>(a.sh, (int64_t)k * n + i);
 
     // rotation Q of the unit quaternion, scales, M = Q diag(s), Sg = M M^T
     const double qn = sqrt(((q4[0] * q4[0] + q4[1] * q4[1]) + q4[2] * q4[2]) + q4[3] * q4[3]);
     double gm[3] = {0, 0, 0}, gQ[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gsc[3] = {0, 0, 0}, gop = 0.0;
-    float gcoef[3 * ncoef];   // float: per-view sums of a few terms
-#pragma unroll
-    for (int k = 0; k < 3 * ncoef; ++k) gcoef[k] = 0.0f;
     double Sg[9];
     const bool cov_ok = world_covariance(l[0], l[1], l[2], q4[0], q4[1], q4[2], q4[3], Sg);
-    const double w = cov_ok ? q4[0] / qn : 0.0, x = cov_ok ? q4[1] / qn : 0.0, y = cov_ok ? q4[2] / qn : 0.0,
-                 z = cov_ok ? q4[3] / qn : 0.0;
+    const double inv_qn = cov_ok ? 1.0 / qn : 0.0;
+    const double w = q4[0] * inv_qn, x = q4[1] * inv_qn, y = q4[2] * inv_qn, z = q4[3] * inv_qn;
     double Q[9];
     Q[0] = 1.0 - 2.0 * (y * y + z * z);
     Q[1] = 2.0 * (x * y - w * z);
@@ -372,12 +441,14 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjectBackArgs a
     Q[8] = 1.0 - 2.0 * (x * x + y * y);
     const double sc[3] = {exp(l[0]), exp(l[1]), exp(l[2])};
 
-    for (int v = 0; cov_ok && v < a.n_views; ++v) {
+    const int n_views = kOneView ? 1 : a.n_views;
+    for (int v = 0; cov_ok && v < n_views; ++v) {
         const int64_t item = (int64_t)v * n + i;
         if (a.tiles_touched[item] == 0) continue;
         const float* g9 = a.grad2d + item * kGrad2d;
-        const double gu = g9[0], gv = g9[1], gA = g9[2], gB = g9[3], gC = g9[4], go = g9[5];
         const ViewParams& vp = a.views[v];
+        const double gu = g9[0], gv = g9[1], gA = g9[2], gB = g9[3], gC = g9[4];
+        gop += g9[5];
         const double* W = vp.R;
         const double t0 = ((W[0] * mx + W[1] * my) + W[2] * mz) + vp.t[0];
         const double t1 = ((W[3] * mx + W[4] * my) + W[5] * mz) + vp.t[1];
@@ -388,19 +459,21 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjectBackArgs a
             for (int c = 0; c < 3; ++c) L[3 * r + c] = W[3 * r] * Sg[c] + W[3 * r + 1] * Sg[3 + c] + W[3 * r + 2] * Sg[6 + c];
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) V[3 * r + c] = L[3 * r] * W[3 * c] + L[3 * r + 1] * W[3 * c + 1] + L[3 * r + 2] * W[3 * c + 2];
-        const double limx = 1.3 * ((0.5 * (double)vp.width) / vp.fx), limy = 1.3 * ((0.5 * (double)vp.height) / vp.fy);
-        const double rx = t0 / t2, ry = t1 / t2;
+        const double fx = vp.fx, fy = vp.fy;
+        const double limx = 1.3 * ((0.5 * (double)vp.width) / fx), limy = 1.3 * ((0.5 * (double)vp.height) / fy);
+        const double rx = t0 / t2, ry = t1 / t2;   // divided as the forward divides: same clamp decisions
         const bool clx = rx < -limx || rx > limx, cly = ry < -limy || ry > limy;
         const double xcl = fmin(limx, fmax(-limx, rx)) * t2, ycl = fmin(limy, fmax(-limy, ry)) * t2;
-        const double J[6] = {vp.fx / t2, 0.0, -(vp.fx * xcl) / (t2 * t2), 0.0, vp.fy / t2, -(vp.fy * ycl) / (t2 * t2)};
+        const double it = 1.0 / t2, it2 = it * it, it3 = it2 * it;
+        const double J[6] = {fx * it, 0.0, -(fx * xcl) * it2, 0.0, fy * it, -(fy * ycl) * it2};
         double JV[6];
         for (int r = 0; r < 2; ++r)
             for (int c = 0; c < 3; ++c) JV[3 * r + c] = J[3 * r] * V[c] + J[3 * r + 1] * V[3 + c] + J[3 * r + 2] * V[6 + c];
         const double ca = (JV[0] * J[0] + JV[1] * J[1] + JV[2] * J[2]) + 0.3;
         const double cb = JV[0] * J[3] + JV[1] * J[4] + JV[2] * J[5];
         const double cc = (JV[3] * J[3] + JV[4] * J[4] + JV[5] * J[5]) + 0.3;
-        const double det = ca * cc - cb * cb;
-        const double A = cc / det, B = -cb / det, C = ca / det;
+        const double idet = 1.0 / (ca * cc - cb * cb);
+        const double A = cc * idet, B = -cb * idet, C = ca * idet;
         // conic -> 2D covariance: dL/dSigma'' = -Q G Q with G = [[gA, gB/2], [gB/2, gC]]
         const double G01 = 0.5 * gB;
         const double QG00 = A * gA + B * G01, QG01 = A * G01 + B * gC, QG10 = B * gA + C * G01, QG11 = B * G01 + C * gC;
@@ -414,20 +487,20 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjectBackArgs a
         for (int r = 0; r < 2; ++r)
             for (int c = 0; c < 3; ++c) gJ[3 * r + c] = 2.0 * (gP[2 * r] * JV[c] + gP[2 * r + 1] * JV[3 + c]);
         // camera-space position t: through J, and through the centre (u, v)
-        double gt0 = gu * vp.fx / t2, gt1 = gv * vp.fy / t2;
-        double gt2 = -gu * vp.fx * t0 / (t2 * t2) - gv * vp.fy * t1 / (t2 * t2);
-        gt2 += -gJ[0] * vp.fx / (t2 * t2) - gJ[4] * vp.fy / (t2 * t2);
+        double gt0 = gu * fx * it, gt1 = gv * fy * it;
+        double gt2 = -(gu * fx * t0 + gv * fy * t1) * it2;
+        gt2 += -(gJ[0] * fx + gJ[4] * fy) * it2;
         if (!clx) {
-            gt0 += -gJ[2] * vp.fx / (t2 * t2);
-            gt2 += gJ[2] * 2.0 * vp.fx * t0 / (t2 * t2 * t2);
+            gt0 += -gJ[2] * fx * it2;
+            gt2 += gJ[2] * 2.0 * fx * t0 * it3;
         } else {
-            gt2 += gJ[2] * vp.fx * (xcl / t2) / (t2 * t2);
+            gt2 += gJ[2] * fx * xcl * it3;
         }
         if (!cly) {
-            gt1 += -gJ[5] * vp.fy / (t2 * t2);
-            gt2 += gJ[5] * 2.0 * vp.fy * t1 / (t2 * t2 * t2);
+            gt1 += -gJ[5] * fy * it2;
+            gt2 += gJ[5] * 2.0 * fy * t1 * it3;
         } else {
-            gt2 += gJ[5] * vp.fy * (ycl / t2) / (t2 * t2);
+            gt2 += gJ[5] * fy * ycl * it3;
         }
         for (int c = 0; c < 3; ++c) gm[c] += W[c] * gt0 + W[3 + c] * gt1 + W[6 + c] * gt2;
         // V = W Sg W^T -> gSg = W^T gV W; Sg = M M^T -> gM = 2 gSg M; M = Q diag(s)
@@ -443,41 +516,6 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjectBackArgs a
                 gQ[3 * r + c] += gM * sc[c];
                 gsc[c] += gM * Q[3 * r + c];
             }
-        gop += go;
-        // colour: rgb_c = max(0, sum_k f_kc Y_k(d) + 0.5), d the unit view direction
-        const double dxv = mx - vp.campos[0], dyv = my - vp.campos[1], dzv = mz - vp.campos[2];
-        const double dn = sqrt(dxv * dxv + dyv * dyv + dzv * dzv);
-        const double ux = dxv / dn, uy = dyv / dn, uz = dzv / dn;
-        float Yf[16];
-        sh_basis((float)ux, (float)uy, (float)uz, DEG, Yf);
-        float gY[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) gY[k] = 0.0f;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float raw = 0.0f;   // the forward's colour sum
-#pragma unroll
-            for (int k = 0; k < ncoef; ++k) raw += coef[k * 3 + ch] * Yf[k];
-            if (!(raw + 0.5f > 0.0f)) continue;   // clamped at 0
-            const float gc = g9[6 + ch];
-#pragma unroll
-            for (int k = 0; k < ncoef; ++k) {
-                gcoef[k * 3 + ch] += gc * Yf[k];
-                gY[k] += gc * coef[k * 3 + ch];
-            }
-        }
-        double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
-        for (int k = 1; k < ncoef; ++k) {
-            double hx, hy, hz;
-            sh_basis_grad(ux, uy, uz, k, hx, hy, hz);
-            gd0 += gY[k] * hx;
-            gd1 += gY[k] * hy;
-            gd2 += gY[k] * hz;
-        }
-        const double dot = ux * gd0 + uy * gd1 + uz * gd2;
-        gm[0] += (gd0 - ux * dot) / dn;
-        gm[1] += (gd1 - uy * dot) / dn;
-        gm[2] += (gd2 - uz * dot) / dn;
     }
 
     // quaternion: through the rotation matrix of q / |q|
@@ -489,30 +527,30 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjectBackArgs a
     double gz = 2.0 * (-2.0 * z * gQ[0] - w * gQ[1] + x * gQ[2] + w * gQ[3] - 2.0 * z * gQ[4] + y * gQ[5] + x * gQ[6] +
                        y * gQ[7]);
     const double qd = w * gw + x * gx + y * gy + z * gz;
-    const double inv_qn = cov_ok ? 1.0 / qn : 0.0;
     a.g_quats[i] = (float)((gw - w * qd) * inv_qn);
     a.g_quats[n + i] = (float)((gx - x * qd) * inv_qn);
     a.g_quats[2 * n + i] = (float)((gy - y * qd) * inv_qn);
     a.g_quats[3 * n + i] = (float)((gz - z * qd) * inv_qn);
     for (int c = 0; c < 3; ++c) {
-        a.g_means[(int64_t)c * n + i] = (float)gm[c];
+        a.g_means[(int64_t)c * n + i] = (float)((double)a.g_means[(int64_t)c * n + i] + gm[c]);
         a.g_log_scales[(int64_t)c * n + i] = (float)(gsc[c] * sc[c]);
     }
     const double sig = 1.0 / (1.0 + exp(-(double)logit));
     a.g_logits[i] = (float)(gop * sig * (1.0 - sig));
-#pragma unroll
-    for (int k = 0; k < 3 * ncoef; ++k) a.g_sh[(int64_t)k * n + i] = gcoef[k];
 }
 
 template <int DT>
 void launch_project_backward_dt(const ProjectBackArgs& a, unsigned blocks, hipStream_t s)
 {
     switch (a.sh_degree) {
-    case 0: hipLaunchKernelGGL((project_backward_kernel<DT, 0>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((project_backward_kernel<DT, 1>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((project_backward_kernel<DT, 2>), dim3(blocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((project_backward_kernel<DT, 3>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((project_backward_color_kernel<DT, 0>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((project_backward_color_kernel<DT, 1>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((project_backward_color_kernel<DT, 2>), dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((project_backward_color_kernel<DT, 3>), dim3(blocks), dim3(256), 0, s, a); break;
     }
+    // one view: no loop, fewer live registers in the geometry kernel
+    if (a.n_views == 1) hipLaunchKernelGGL((project_backward_geometry_kernel<DT, true>), dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((project_backward_geometry_kernel<DT, false>), dim3(blocks), dim3(256), 0, s, a);
 }
 
 }  // namespace
