@@ -224,11 +224,12 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
 
 
-def time_batched(r, dev, cams, steps: int) -> dict:
+def time_batched(r, dev, cams, steps: int, autotune: bool = True) -> dict:
     """Views/s of one gs_render_batched call over ``cams`` per step, of the
     same batch replayed as a captured graph, and of the same views rendered by
-    one gs_render call each."""
+    one gs_render call each (launch shapes autotuned for the batch first)."""
     import torch
+    tuning = r.autotune(dev, cams, reps=3)["tuning"] if autotune else r.tuning()
     outs = r.render_batched(dev, cams)
     torch.cuda.synchronize()
     bsteps = max(3, min(steps, 10))
@@ -263,7 +264,8 @@ def time_batched(r, dev, cams, steps: int) -> dict:
             "ms_per_batch": round(ms_batch, 3), "views_per_s": round(len(cams) * 1e3 / ms_batch, 1),
             "ms_per_batch_graph": round(ms_graph, 3), "views_per_s_graph": round(len(cams) * 1e3 / ms_graph, 1),
             "ms_one_call_per_view": round(ms_single, 3),
-            "views_per_s_one_call_per_view": round(len(cams) * 1e3 / ms_single, 1), "steps": bsteps}
+            "views_per_s_one_call_per_view": round(len(cams) * 1e3 / ms_single, 1), "steps": bsteps,
+            "tuning": tuning}
 
 
 def time_backward(r, dev, cam, W: int, H: int, steps: int, out) -> dict:
@@ -305,6 +307,7 @@ def main():
     ap.add_argument("--variant", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the BF16/FP16 storage variants")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV",
@@ -345,6 +348,13 @@ def main():
     out = {"image": torch.empty((3, H, W), dtype=torch.float32, device="cuda"),
            "final_T": torch.empty((H, W), dtype=torch.float32, device="cuda"),
            "n_contrib": torch.empty((H, W), dtype=torch.int32, device="cuda")}
+    # launch shapes for this workload (speed only: every shape renders the
+    # same bits), chosen before the timed region like the warm-up
+    tune = None
+    if not args.no_autotune:
+        log("[bench] autotune")
+        tune = r.autotune(dev, [cam], reps=5)
+        log("[bench] tuning " + json.dumps(tune["tuning"]))
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
         r.render(dev, cam, W, H, out=out)
@@ -473,6 +483,7 @@ def main():
         "blend_work": {**stats, "tflops": round((FLOPS_EVAL * stats["evaluations"] + FLOPS_COMPOSITE *
                                                  stats["composited"]) / (stage_ms["blend"] * 1e-3) / 1e12, 3)},
         "roofline": roof,
+        "tuning": tune,
         "variants": variants,
         "cpu_baseline": cpu,
     }

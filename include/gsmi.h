@@ -304,6 +304,51 @@ gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats4);
  * GS_ERR_INVALID_ARGUMENT if the render was not counted or tiles differs. */
 gs_status gs_get_blend_tile_work(gs_context* ctx, uint64_t* work, int64_t tiles);
 
+/* Launch shapes of the render, chosen per workload: the tile size (16, which
+ * the keys of Sec. 3.1 and the lists depend on) is fixed, but how many items
+ * a thread or wavefront carries in each stage, and how the blend's tiles are
+ * dealt to the XCDs, change only speed.  Every supported value gives the same
+ * image, final T, n_contrib, lists and projection, bit for bit.
+ *   sort_items        keys per thread of a depth-sort block: 4, 8 or 16
+ *   bin_row_items     depth-sorted Gaussians per lane of a row-binning
+ *                     wavefront: 4, 8 or 16
+ *   bin_tile_items    row entries per lane of a tile-binning wavefront:
+ *                     8, 16 or 32
+ *   blend_tile_group  consecutive tiles (row-major) dealt to one XCD by the
+ *                     blend and its backward: 1 .. 64
+ * A new context starts at {8, 8, 16, 16}.  gs_set_tuning applies to the
+ * following renders and backwards (a backward uses its render's shapes; a
+ * captured graph keeps those of its capture); GS_ERR_INVALID_ARGUMENT for an
+ * unsupported value, leaving the tuning unchanged. */
+typedef struct {
+    int32_t sort_items;
+    int32_t bin_row_items;
+    int32_t bin_tile_items;
+    int32_t blend_tile_group;
+} gs_tuning;
+
+gs_status gs_set_tuning(gs_context* ctx, const gs_tuning* tuning);
+gs_status gs_get_tuning(gs_context* ctx, gs_tuning* out);
+
+/* Autotuner: renders the given views (as gs_render_batched, whose outputs
+ * it overwrites) with each candidate shape, one parameter at a time from the
+ * context's current tuning -- sort_items judged by the depth-sort stage time,
+ * bin_row_items and bin_tile_items by the four binning stages,
+ * blend_tile_group by the blend -- each candidate once untimed and then reps
+ * times timed by the stage events, keeps the fastest value of each parameter
+ * before tuning the next, and leaves the result as the context's tuning.
+ *   out     the chosen tuning (may be NULL)
+ *   out_ms  NULL, or host array [GS_TUNE_CANDIDATES]: the mean judged time
+ *           of every candidate in the order sort_items 4, 8, 16;
+ *           bin_row_items 4, 8, 16; bin_tile_items 8, 16, 32;
+ *           blend_tile_group 1, 2, 4, 8, 16, 32, 64
+ * Profiling flags are restored afterwards.  Errors as gs_render_batched,
+ * GS_ERR_INVALID_ARGUMENT for reps outside [1, 1000] or a context bound to a
+ * graph; on error the tuning is left as it was. */
+#define GS_TUNE_CANDIDATES 16
+gs_status gs_autotune(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
+                      const gs_render_opts* opts, int32_t reps, void* stream, gs_tuning* out, float* out_ms);
+
 #ifdef __cplusplus
 }
 #endif

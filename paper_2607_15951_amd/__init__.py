@@ -24,7 +24,8 @@ TILE = 16
 EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
             "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
             "gs_get_blend_stats", "gs_get_blend_tile_work", "gs_render_batched", "gs_graph_create",
-            "gs_graph_set_views", "gs_graph_launch", "gs_graph_destroy", "gs_render_backward"]
+            "gs_graph_set_views", "gs_graph_launch", "gs_graph_destroy", "gs_render_backward", "gs_set_tuning",
+            "gs_get_tuning", "gs_autotune"]
 STAGES = ["project", "depth_sort", "bin_row_count", "bin_row_scatter", "bin_tile_count", "bin_tile_scatter",
           "blend"]
 
@@ -60,6 +61,15 @@ class gs_list_info(C.Structure):
 class gs_gradients(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
                 ("opacity_logits", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class gs_tuning(C.Structure):
+    _fields_ = [("sort_items", C.c_int32), ("bin_row_items", C.c_int32), ("bin_tile_items", C.c_int32),
+                ("blend_tile_group", C.c_int32)]
+
+
+TUNE_CANDIDATES = [("sort_items", v) for v in (4, 8, 16)] + [("bin_row_items", v) for v in (4, 8, 16)] + \
+    [("bin_tile_items", v) for v in (8, 16, 32)] + [("blend_tile_group", v) for v in (1, 2, 4, 8, 16, 32, 64)]
 
 
 class gs_view(C.Structure):
@@ -106,6 +116,13 @@ def load_library(path: str = LIB_PATH):
     L.gs_render_backward.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(gs_gradients), P]
     L.gs_render_backward.restype = C.c_int
+    L.gs_set_tuning.argtypes = [P, C.POINTER(gs_tuning)]
+    L.gs_set_tuning.restype = C.c_int
+    L.gs_get_tuning.argtypes = [P, C.POINTER(gs_tuning)]
+    L.gs_get_tuning.restype = C.c_int
+    L.gs_autotune.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(gs_view), C.c_int32, C.POINTER(gs_render_opts),
+                              C.c_int32, P, C.POINTER(gs_tuning), C.POINTER(C.c_float)]
+    L.gs_autotune.restype = C.c_int
     L.gs_get_list_info.argtypes = [P, C.POINTER(gs_list_info)]
     L.gs_get_list_info.restype = C.c_int
     L.gs_copy_lists.argtypes = [P, P, P, P, P]
@@ -300,6 +317,38 @@ class Renderer:
         gr = RenderGraph(self, h, outs, dev)
         self._graphs.append(gr)
         return gr
+
+    def tuning(self) -> dict:
+        t = gs_tuning()
+        self._check(self._L.gs_get_tuning(self._ctx, C.byref(t)))
+        return {k: int(getattr(t, k)) for k, _ in gs_tuning._fields_}
+
+    def set_tuning(self, **kw):
+        """Changes launch shapes (gs_set_tuning); unnamed fields keep their value."""
+        cur = self.tuning()
+        cur.update(kw)
+        t = gs_tuning(**cur)
+        self._check(self._L.gs_set_tuning(self._ctx, C.byref(t)))
+
+    def autotune(self, dev_scene: dict, cameras: list, reps: int = 3, background=(0.0, 0.0, 0.0),
+                 pair_capacity: int = 0, stream=None) -> dict:
+        """gs_autotune over a batched render of ``cameras``: returns the chosen
+        tuning and the judged milliseconds of every candidate."""
+        torch = _torch()
+        dev = dev_scene["means"].device
+        views, outs = self._views(cameras, None, dev)
+        g = make_gaussians(dev_scene)
+        opts = make_opts(background, pair_capacity)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        t = gs_tuning()
+        ms = (C.c_float * len(TUNE_CANDIDATES))()
+        self._check(self._L.gs_autotune(self._ctx, C.byref(g), views, len(cameras), C.byref(opts), int(reps),
+                                        C.c_void_p(s), C.byref(t), ms))
+        self._last = (dev, int(g.n) * len(cameras))
+        self._last_out = outs
+        self.generation += 1
+        return {"tuning": {k: int(getattr(t, k)) for k, _ in gs_tuning._fields_},
+                "candidates_ms": [(name, v, round(float(ms[i]), 4)) for i, (name, v) in enumerate(TUNE_CANDIDATES)]}
 
     def backward(self, dev_scene: dict, grad_images: list, grad_T: list | None = None, stream=None) -> dict:
         """Gradients of the Gaussian parameters (float32 tensors, input

@@ -61,6 +61,8 @@ struct gs_context {
     gs_gaussians last_g{};                // scene of the last render
     float last_bg[3] = {0.f, 0.f, 0.f};
     DevBuf grad2d;                        // backward: per-item blend gradients
+    Tuning tuning = kDefaultTuning;       // launch shapes of the next render
+    Tuning last_tuning = kDefaultTuning;  // launch shapes of the last render
 };
 
 struct gs_graph {
@@ -237,7 +239,8 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     int max_tx = 0;
     for (const ViewParams& v : hv) max_tx = std::max(max_tx, v.tiles_x);
     const size_t ni = (size_t)(items > 0 ? items : 1);
-    const int chunks1 = std::max(bin_level1_chunks(n), 1);
+    const Tuning tu = ctx->tuning;
+    const int chunks1 = std::max(bin_level1_chunks(n, tu.bin1_items), 1);
 
     if ((st = ensure(ctx, ctx->splats, ni * sizeof(Splat))) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->depth_key, ni * 4)) != GS_OK) return st;
@@ -299,6 +302,8 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ba.row_tiles_x = static_cast<const uint32_t*>(ctx->row_tiles_x.p);
     ba.rows = rows;
     ba.tiles = T;
+    ba.items1 = tu.bin1_items;
+    ba.items2 = tu.bin2_items;
     ba.chunks1 = chunks1;
     ba.info = static_cast<uint32_t*>(ctx->bin_info.p);
     ba.counts1 = static_cast<uint32_t*>(ctx->counts1.p);
@@ -310,7 +315,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     // (row entries <= pairs); else the host reads K, R and the level-2 sizes
     // once
     ba.row_capacity = capacity ? capacity : ~0ull;
-    ba.max_chunks2 = capacity ? bin_level2_chunk_bound(capacity, rows) : (1 << 30);
+    ba.max_chunks2 = capacity ? bin_level2_chunk_bound(capacity, rows, tu.bin2_items) : (1 << 30);
     ba.counts2_capacity = capacity ? (uint64_t)ba.max_chunks2 * max_tx : ~0ull;
     // scan lengths: depth-sort digit counts, level-1 counts, tile offsets and
     // (pair_capacity > 0) the level-2 counts; the eager path grows the scratch
@@ -323,7 +328,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
                               static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
                               static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p),
-                              scan_scratch, n, V, &in_b, s),
+                              scan_scratch, n, V, tu.sort_items, &in_b, s),
             "depth sort");
     ba.sorted_idx = static_cast<const uint32_t*>(in_b ? ctx->sort_vb.p : ctx->sort_va.p);
     STAGE_MARK(2);
@@ -383,6 +388,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     bl.views = views;
     bl.n_views = V;
     bl.tiles = T;
+    bl.group = tu.blend_group;
     const float zero_bg[3] = {0.f, 0.f, 0.f};
     const float* bg = opts ? o.background : zero_bg;
     for (int k = 0; k < 3; ++k) bl.bg[k] = bg[k];
@@ -396,6 +402,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     STAGE_MARK(8);
 
     ctx->have_render = true;
+    ctx->last_tuning = tu;
     ctx->last_views = hv;
     ctx->last_g = *g;
     for (int k = 0; k < 3; ++k) ctx->last_bg[k] = bl.bg[k];
@@ -685,6 +692,7 @@ gs_status gs_render_backward(gs_context* ctx, const gs_gaussians* g, const float
     bb.views = views;
     bb.n_views = V;
     bb.tiles = ctx->tiles;
+    bb.group = ctx->last_tuning.blend_group;
     for (int k = 0; k < 3; ++k) bb.bg[k] = ctx->last_bg[k];
     bb.grad2d = grad2d;
     HIP_TRY(launch_blend_backward(bb, ctx->capacity, s), "blend backward");
@@ -805,6 +813,109 @@ gs_status gs_get_stage_times(gs_context* ctx, float* ms, int32_t count)
     const int to[GS_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 8};
     for (int k = 0; k < GS_NUM_STAGES; ++k)
         HIP_TRY(hipEventElapsedTime(&ms[k], ctx->ev[from[k]], ctx->ev[to[k]]), "hipEventElapsedTime");
+    return GS_OK;
+}
+
+namespace {
+
+Tuning from_abi(const gs_tuning& t) { return Tuning{t.sort_items, t.bin_row_items, t.bin_tile_items, t.blend_tile_group}; }
+
+gs_tuning to_abi(const Tuning& t)
+{
+    gs_tuning o;
+    o.sort_items = t.sort_items;
+    o.bin_row_items = t.bin1_items;
+    o.bin_tile_items = t.bin2_items;
+    o.blend_tile_group = t.blend_group;
+    return o;
+}
+
+// The candidates gs_autotune tries, in the order of its out_ms array: each
+// parameter of Tuning with the stages whose time it is judged by (indices
+// into the GS_NUM_STAGES stage times).
+struct TuneParam {
+    int Tuning::*field;
+    int values[8];
+    int count;
+    int stage_lo, stage_hi;   // stages [lo, hi]
+};
+const TuneParam kTuneParams[] = {
+    {&Tuning::sort_items, {4, 8, 16}, 3, 1, 1},
+    {&Tuning::bin1_items, {4, 8, 16}, 3, 2, 5},
+    {&Tuning::bin2_items, {8, 16, 32}, 3, 2, 5},
+    {&Tuning::blend_group, {1, 2, 4, 8, 16, 32, 64}, 7, 6, 6},
+};
+
+}  // namespace
+
+gs_status gs_set_tuning(gs_context* ctx, const gs_tuning* tuning)
+{
+    if (!ctx || !tuning) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    const Tuning t = from_abi(*tuning);
+    if (!tuning_supported(t))
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT,
+                    "unsupported tuning: sort_items and bin_row_items take 4, 8 or 16, bin_tile_items 8, 16 or 32, "
+                    "blend_tile_group 1..64");
+    ctx->tuning = t;
+    return GS_OK;
+}
+
+gs_status gs_get_tuning(gs_context* ctx, gs_tuning* out)
+{
+    if (!ctx || !out) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    *out = to_abi(ctx->tuning);
+    return GS_OK;
+}
+
+gs_status gs_autotune(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
+                      const gs_render_opts* opts, int32_t reps, void* stream, gs_tuning* out, float* out_ms)
+{
+    if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (ctx->graph) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the context is bound to a render graph");
+    if (reps < 1 || reps > 1000) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "reps must lie in [1, 1000]");
+    std::vector<ViewParams> hv;
+    gs_status st = build_views(ctx, g, views, n_views, opts, hv);
+    if (st != GS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint32_t saved_flags = ctx->profiling;
+    const Tuning start = ctx->tuning;
+    Tuning cur = start;
+    if ((st = gs_set_profiling(ctx, GS_PROFILE_STAGES)) != GS_OK) return st;   // creates the stage events
+    int k_out = 0;
+    for (const TuneParam& p : kTuneParams) {
+        float best_ms = INFINITY;
+        int best = cur.*p.field;
+        for (int c = 0; c < p.count; ++c) {
+            Tuning t = cur;
+            t.*p.field = p.values[c];
+            ctx->tuning = t;
+            float sum = 0.f;
+            // one untimed render sizes the buffers this shape needs
+            for (int r = 0; r <= reps && st == GS_OK; ++r) {
+                st = render_views(ctx, g, hv, opts, s);
+                float ms[GS_NUM_STAGES];
+                if (st == GS_OK) st = gs_get_stage_times(ctx, ms, GS_NUM_STAGES);
+                if (st == GS_OK && r > 0)
+                    for (int k = p.stage_lo; k <= p.stage_hi; ++k) sum += ms[k];
+            }
+            if (st != GS_OK) {
+                ctx->tuning = start;
+                ctx->profiling = saved_flags;
+                return st;
+            }
+            const float avg = sum / (float)reps;
+            if (out_ms) out_ms[k_out] = avg;
+            ++k_out;
+            if (avg < best_ms) {
+                best_ms = avg;
+                best = p.values[c];
+            }
+        }
+        cur.*p.field = best;
+    }
+    ctx->tuning = cur;
+    ctx->profiling = saved_flags;
+    if (out) *out = to_abi(cur);
     return GS_OK;
 }
 

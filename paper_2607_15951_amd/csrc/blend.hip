@@ -24,7 +24,8 @@
 //
 // Workgroup -> tile mapping is XCD-aware: the dispatcher deals consecutive
 // workgroups round-robin to the 8 XCDs, so block b runs on XCD b % 8.  Tiles
-// are cut into groups of kGroup consecutive tiles (row-major), dealt to the XCDs
+// are cut into groups of a.group consecutive tiles (row-major; the autotuner
+// picks the group size), dealt to the XCDs
 // in turn: XCD x takes groups x, x + 8, x + 16, ... in screen order.  Each
 // group's tiles share Gaussians in one L2, and every XCD gets an even share of
 // every part of the screen: blend work per tile varies by an order of
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
     __shared__ float4 s2[256 + kUnroll];   // r, g, b, list position (int bits)
     __shared__ uint32_t s_mask[256 + kUnroll];   // quads (waves) the entry can reach
     __shared__ uint32_t s_wave_keep[4];
-    const int tile = blend_tile_of_block();
+    const int tile = blend_tile_of_block(a.group);
     if (tile >= a.tiles) return;
     // the view owning this global tile: its size, tile grid and outputs
     const ViewParams& vp = a.views[view_of_tile(a.views, a.n_views, (uint32_t)tile)];
@@ -228,7 +229,7 @@ hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s)
 {
     const int64_t T = a.tiles;
     if (T <= 0) return hipSuccess;
-    const int blocks = blend_blocks(T);
+    const int blocks = blend_blocks(T, a.group);
     if (a.tile_work) hipLaunchKernelGGL(blend_kernel<true>, dim3(blocks), dim3(256), 0, s, a, capacity);
     else hipLaunchKernelGGL(blend_kernel<false>, dim3(blocks), dim3(256), 0, s, a, capacity);
     return hipGetLastError();

@@ -66,16 +66,18 @@ __device__ __forceinline__ uint32_t stage_entry(const float4& ra, const float4& 
     return qmask;
 }
 
-// Workgroup -> tile: tiles are cut into groups of kGroup consecutive tiles
-// (row-major), dealt to the 8 XCDs in turn (block b runs on XCD b % 8).
-constexpr int kGroup = 16;
-
-__device__ __forceinline__ int blend_tile_of_block()
+// Workgroup -> tile: tiles are cut into groups of `group` consecutive tiles
+// (row-major), dealt to the 8 XCDs in turn (block b runs on XCD b % 8), so
+// neighbouring tiles, which share list entries, share an XCD's L2.
+__device__ __forceinline__ int blend_tile_of_block(int group)
 {
     const int i = (int)(blockIdx.x >> 3);
-    return ((i / kGroup) * 8 + (int)(blockIdx.x & 7)) * kGroup + i % kGroup;
+    return ((i / group) * 8 + (int)(blockIdx.x & 7)) * group + i % group;
 }
 
-inline int blend_blocks(int64_t tiles) { return (int)(8 * kGroup * ((tiles + 8 * kGroup - 1) / (8 * kGroup))); }
+inline int blend_blocks(int64_t tiles, int group)
+{
+    return (int)(8 * group * ((tiles + 8 * group - 1) / (8 * group)));
+}
 
 }  // namespace gsmi

@@ -13,11 +13,18 @@ constexpr int kTile = 16;                 // screen tile edge in pixels
 constexpr int kTilePixels = kTile * kTile;
 constexpr int kMaxBandTiles = 2048;       // LDS cursors per binning wave
 constexpr int kSortBlock = 256;           // threads of a depth-sort block
-constexpr int kSortItems = 8;             // keys per thread per depth-sort block
-constexpr int kSortTile = kSortBlock * kSortItems;
-constexpr int kItemsL1 = 8;               // depth-sorted Gaussians per lane of a level-1 binning wave
-constexpr int kItemsL2 = 16;              // row entries per lane of a level-2 binning wave
 constexpr int kTileWorkFields = 6;        // u64 fields of a per-tile blend trace record
+
+// Launch shapes that change speed but never results (every choice gives the
+// same image, lists and counts): chosen per workload by the autotuner.
+struct Tuning {
+    int sort_items;    // keys per thread of a depth-sort block: 4, 8, 16
+    int bin1_items;    // depth-sorted Gaussians per lane of a level-1 binning wave: 4, 8, 16
+    int bin2_items;    // row entries per lane of a level-2 binning wave: 8, 16, 32
+    int blend_group;   // consecutive tiles dealt to one XCD by the blend: 1 .. 64
+};
+constexpr Tuning kDefaultTuning = {8, 8, 16, 16};
+bool tuning_supported(const Tuning& t);
 constexpr int kMaxRows = 2048;            // tile rows per image (height <= 32768)
 constexpr int kMaxTotalRows = 16384;      // tile rows over all views of one render
 
@@ -90,10 +97,11 @@ hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
 // each, four 8-bit passes, every segment sorted on its own (values start as
 // the item index v * n + i); *result_in_b tells which ping-pong buffer pair
 // holds the result.
-size_t depth_sort_hist_elems(int64_t n, int n_views);
+bool depth_sort_items_supported(int items);
+size_t depth_sort_hist_elems(int64_t n, int n_views);   // enough for every supported width
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a,
                              uint32_t* keys_b, uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch,
-                             int64_t n, int n_views, int* result_in_b, hipStream_t s);
+                             int64_t n, int n_views, int items, int* result_in_b, hipStream_t s);
 
 struct BinArgs {
     const uint32_t* sorted_idx;   // [n_views * n] items (v * n + i), each view's segment in (depth, index) order
@@ -105,7 +113,8 @@ struct BinArgs {
     const uint32_t* row_tiles_x;  // [rows] tiles_x of each global tile row
     int rows;                     // global tile rows (sum of the views' tiles_y)
     int64_t tiles;                // global tiles (sum of the views' tiles)
-    int chunks1;                  // level-1 chunks per view, bin_level1_chunks(n)
+    int items1, items2;           // items per lane of a level-1 / level-2 wave (Tuning)
+    int chunks1;                  // level-1 chunks per view, bin_level1_chunks(n, items1)
     uint32_t* info;               // level-2 chunk table (bin_info_elems(rows))
     uint32_t* counts1;            // [rows][chunks1] counts -> exclusive scan = cursors
     uint32_t* rows_off;           // [rows + 1] row-list offsets; [rows] = R
@@ -121,8 +130,9 @@ struct BinArgs {
 };
 
 size_t bin_info_elems(int rows);
-int bin_level1_chunks(int64_t n);
-int bin_level2_chunk_bound(uint64_t row_entries, int rows);
+bool bin_items_supported(int items1, int items2);
+int bin_level1_chunks(int64_t n, int items1);
+int bin_level2_chunk_bound(uint64_t row_entries, int rows, int items2);
 hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t s);
 hipError_t launch_bin_row_scatter(const BinArgs& a, hipStream_t s);
 hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch, hipStream_t s);
@@ -147,6 +157,7 @@ struct BlendArgs {
     const ViewParams* views;   // device table: sizes, tile bases, outputs
     int n_views;
     int64_t tiles;             // global tiles
+    int group;                 // tiles per XCD group (Tuning::blend_group)
     float bg[3];
     // per-tile trace when tracing (else null), [T][kTileWorkFields]: start
     // and end of the tile's workgroup (s_memrealtime, 100 MHz), entries
@@ -169,6 +180,7 @@ struct BlendBackArgs {
     const ViewParams* views;
     int n_views;
     int64_t tiles;
+    int group;
     float bg[3];
     float* grad2d;
 };

@@ -13,7 +13,7 @@
 //   level 2  every row entry is copied to the list of each tile of that row
 //            its column span covers: the pair values.
 // A wavefront owns a chunk of consecutive items (Gaussians, or one row's
-// entries), kept in registers, kItemsL* per lane.  It walks the buckets
+// entries), kept in registers, a few per lane (the autotuner picks how many).  It walks the buckets
 // (rows, or the row's tile columns) in order; for bucket x every item of a
 // batch of 64 tests whether its span covers x, M = ballot(covers), and the
 // covering lanes write at cursor[x] + (number of covering lanes below them),
@@ -29,11 +29,11 @@
 //   scatter  the walk from those cursors.
 #include "gs_internal.h"
 
+#include <type_traits>
+
 namespace gsmi {
 namespace {
 
-constexpr int kChunk1 = kItemsL1 * 64;   // Gaussians per level-1 wave
-constexpr int kChunk2 = kItemsL2 * 64;   // row entries per level-2 wave
 constexpr int kBand = 16;                // tile columns per band of the level-2 walk
 
 // info[] layout (uint32): [0] level-2 chunks C2, [1] level-2 count elements
@@ -88,9 +88,10 @@ __device__ __forceinline__ int wave_max(int v)
 // payload (item, x-span).  Level-1 chunk c belongs to view c / chunks1 and is
 // part c % chunks1 of that view's visible items (which open its segment).
 
+template <int kItems>
 struct Items1 {
     // rows [y0, y0 + h) covered (rows of the view); h = 0 for padding lanes
-    uint32_t y0[kItemsL1], h[kItemsL1], xs[kItemsL1], g[kItemsL1];
+    uint32_t y0[kItems], h[kItems], xs[kItems], g[kItems];
     int lo, hi;        // rows spanned by the chunk
     int view, part;    // view, chunk index within the view
 };
@@ -104,18 +105,19 @@ __device__ __forceinline__ bool chunk1_range(const BinArgs& a, int c, int* view,
     if (*view >= a.n_views) return false;
     const int64_t seg = (int64_t)(*view) * a.n;
     const int64_t nv = (int64_t)a.view_counts[(int64_t)kViewCounters * (*view)];
-    *start = seg + (int64_t)(*part) * kChunk1;
+    *start = seg + (int64_t)(*part) * (a.items1 * 64);
     *end = seg + nv;
     return *start < *end;
 }
 
-__device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, Items1& it)
+template <int kItems>
+__device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, Items1<kItems>& it)
 {
     int64_t start, end;
     if (!chunk1_range(a, c, &it.view, &it.part, &start, &end)) return false;
     int lo = 1 << 30, hi = 0;
 #pragma unroll
-    for (int b = 0; b < kItemsL1; ++b) {
+    for (int b = 0; b < kItems; ++b) {
         const int64_t k = start + b * 64 + lane;
         ushort4 r = make_ushort4(0, 0, 0, 0);
         uint32_t g = 0;
@@ -159,6 +161,7 @@ __device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, ui
 
 // Counting needs no order: each span adds +1 at its first bucket and -1 past
 // its last in an LDS difference array (two atomics per item), summed at the end.
+template <int kItems>
 __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
 {
     __shared__ uint32_t diff[kMaxRows + 1];
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
     int64_t start = 0, end = 0;
     (void)chunk1_range(a, c, &v2, &p2, &start, &end);
 #pragma unroll
-    for (int b = 0; b < kItemsL1; ++b) {
+    for (int b = 0; b < kItems; ++b) {
         const int64_t k = start + b * 64 + lane;
         if (k < end) {
             const ushort4 r = a.rect[a.sorted_idx[k]];
@@ -225,33 +228,35 @@ __device__ __forceinline__ void walk_bucket(uint32_t bucket, uint32_t cur, const
         walk_run<true>(bucket, cur, first, span, payload, out, capacity);
 }
 
+template <int kItems>
 __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
 {
     const int lane = threadIdx.x, c = chunk_of_block();
-    Items1 it;
+    Items1<kItems> it;
     if (!load_items1(a, c, lane, it)) return;
     // row r of the view: cursor[r * chunks1]
     const uint32_t* cursor = a.counts1 + (int64_t)a.views[it.view].row_base * a.chunks1 + it.part;
-    uint2 payload[kItemsL1];
+    uint2 payload[kItems];
 #pragma unroll
-    for (int b = 0; b < kItemsL1; ++b) payload[b] = make_uint2(it.g[b], it.xs[b]);
+    for (int b = 0; b < kItems; ++b) payload[b] = make_uint2(it.g[b], it.xs[b]);
     for (int w0 = it.lo; w0 < it.hi; w0 += kWindow) {
         const int ra = w0 + lane, rb = w0 + 64 + lane;
         const uint32_t cur_a = ra < it.hi ? cursor[(int64_t)ra * a.chunks1] : 0u;
         const uint32_t cur_b = rb < it.hi ? cursor[(int64_t)rb * a.chunks1] : 0u;
         const int e0 = min(it.hi, w0 + 64), e1 = min(it.hi, w0 + kWindow);
         for (int r = w0; r < e0; ++r)
-            walk_bucket<kItemsL1>((uint32_t)r, __builtin_amdgcn_readlane(cur_a, r - w0), it.y0, it.h, payload,
+            walk_bucket<kItems>((uint32_t)r, __builtin_amdgcn_readlane(cur_a, r - w0), it.y0, it.h, payload,
                                   a.row_ent, a.row_capacity);
         for (int r = w0 + 64; r < e1; ++r)
-            walk_bucket<kItemsL1>((uint32_t)r, __builtin_amdgcn_readlane(cur_b, r - w0 - 64), it.y0, it.h, payload,
+            walk_bucket<kItems>((uint32_t)r, __builtin_amdgcn_readlane(cur_b, r - w0 - 64), it.y0, it.h, payload,
                                   a.row_ent, a.row_capacity);
     }
 }
 
 // Row offsets and the level-2 chunk table (one 1024-thread block, a run of
 // rows per thread).  The scanned level-1 counts give rows_off[r] (chunk 0's
-// cursor in row r); row r owns ceil(len_r / kChunk2) level-2 chunks and
+// cursor in row r); row r owns ceil(len_r / chunk2) level-2 chunks (chunk2 =
+// 64 items2 entries) and
 // tiles_x(r) count elements per chunk; info holds both prefixes.  On
 // overflow every row gets zero chunks.
 constexpr int kTableRowsPerThread = kMaxTotalRows / 1024;
@@ -261,6 +266,7 @@ __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
     __shared__ uint32_t part_c[1024], part_e[1024];
     __shared__ uint32_t s_total_c, s_total_e;
     const int tid = threadIdx.x, rows = a.rows;
+    const uint32_t chunk2 = (uint32_t)a.items2 * 64u;
     const int r0 = tid * kTableRowsPerThread;
     for (int k = 0; k < kTableRowsPerThread; ++k) {
         const int r = r0 + k;
@@ -272,7 +278,7 @@ __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
         const int r = r0 + k;
         if (r < rows) {
             const uint32_t len = a.rows_off[r + 1] - a.rows_off[r];
-            const uint32_t ch = (len + kChunk2 - 1) / kChunk2;
+            const uint32_t ch = (len + chunk2 - 1) / chunk2;
             sc += ch;
             se += ch * a.row_tiles_x[r];
         }
@@ -309,7 +315,7 @@ __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
             cpre[r] = run_c;
             epre[r] = run_e;
             if (ok) {
-                const uint32_t ch = (a.rows_off[r + 1] - a.rows_off[r] + kChunk2 - 1) / kChunk2;
+                const uint32_t ch = (a.rows_off[r + 1] - a.rows_off[r] + chunk2 - 1) / chunk2;
                 run_c += ch;
                 run_e += ch * a.row_tiles_x[r];
             }
@@ -326,9 +332,10 @@ __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
 // ------------------------------------------------------------------ level 2
 // items: one row's entries; buckets: that row's tile columns; payload: index
 
+template <int kItems>
 struct Items2 {
     // columns [x0, x0 + w) covered; w = 0 for padding lanes
-    uint32_t x0[kItemsL2], w[kItemsL2], g[kItemsL2];
+    uint32_t x0[kItems], w[kItems], g[kItems];
     int row, lo, hi;   // row, columns spanned by the chunk
     const uint32_t* cursor;   // column x's cursor at cursor[x * stride]
     int64_t stride;           // the row's level-2 chunks
@@ -362,19 +369,21 @@ __device__ __forceinline__ void chunk2_range(const BinArgs& a, int c, int lane, 
         L = nl;
     }
     *row = __builtin_amdgcn_readfirstlane(L);
-    *eb = (int64_t)a.rows_off[*row] + (int64_t)((uint32_t)c - base[*row]) * kChunk2;
+    const int64_t chunk2 = (int64_t)a.items2 * 64;
+    *eb = (int64_t)a.rows_off[*row] + (int64_t)((uint32_t)c - base[*row]) * chunk2;
     const int64_t end_row = a.rows_off[*row + 1];
-    *ee = (*eb + kChunk2 < end_row) ? *eb + kChunk2 : end_row;
+    *ee = (*eb + chunk2 < end_row) ? *eb + chunk2 : end_row;
 }
 
-__device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, Items2& it)
+template <int kItems>
+__device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, Items2<kItems>& it)
 {
     if ((uint32_t)c >= a.info[kInfoC2]) return false;
     int64_t eb, ee;
     chunk2_range(a, c, lane, &it.row, &eb, &ee);
     int lo = 1 << 30, hi = 0;
 #pragma unroll
-    for (int b = 0; b < kItemsL2; ++b) {
+    for (int b = 0; b < kItems; ++b) {
         const int64_t e = eb + b * 64 + lane;
         uint2 ent = make_uint2(0u, 0u);
         if (e < ee) {
@@ -394,6 +403,7 @@ __device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, I
 }
 
 // One level-2 chunk's per-column counts.
+template <int kItems>
 __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int lane, uint32_t* diff)
 {
     int row;
@@ -403,7 +413,7 @@ __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int 
     for (int x = lane; x <= row_tx; x += 64) diff[x] = 0u;
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < kItemsL2; ++b) {
+    for (int b = 0; b < kItems; ++b) {
         const int64_t e = eb + b * 64 + lane;
         if (e < ee) {
             const uint32_t xs = a.row_ent[e].y;
@@ -420,12 +430,13 @@ __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int 
 
 // The level-2 kernels stride over the device's chunk count, so a grid sized
 // for a bound (pair_capacity mode) costs nothing past the real chunks.
+template <int kItems>
 __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
 {
     __shared__ uint32_t diff[kMaxBandTiles + 1];
     const int lane = threadIdx.x;
     const int c2 = (int)a.info[kInfoC2];
-    for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_count_chunk(a, c, lane, diff);
+    for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_count_chunk<kItems>(a, c, lane, diff);
 }
 
 // The walk of one band over the n packed entries in LDS (s_g, s_x): batch
@@ -468,9 +479,10 @@ __device__ __forceinline__ void walk_band(const uint32_t* s_g, const uint32_t* s
 // reach band b are packed, in chunk order, into dense batches through LDS,
 // and only those batches walk the band's columns.  Inside a column the
 // entries keep their chunk order, so the output is that of the plain walk.
+template <int kItems>
 __device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, int lane, uint32_t* s_g, uint32_t* s_x)
 {
-    Items2 it;
+    Items2<kItems> it;
     if (!load_items2(a, c, lane, it)) return;
     const int blo = it.lo / kBand, bhi = (it.hi + kBand - 1) / kBand;
     const int row_tx = (int)a.row_tiles_x[it.row];
@@ -486,7 +498,7 @@ __device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, in
         // pack the entries reaching the band, clipped to it, in chunk order
         uint32_t n = 0;
 #pragma unroll
-        for (int j = 0; j < kItemsL2; ++j) {
+        for (int j = 0; j < kItems; ++j) {
             const uint32_t e0 = max(it.x0[j], bx0), e1 = min(it.x0[j] + it.w[j], bx1);
             const bool reach = e1 > e0;
             const uint64_t m = __ballot(reach);
@@ -509,12 +521,13 @@ __device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, in
     }
 }
 
+template <int kItems>
 __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
 {
-    __shared__ uint32_t s_g[kChunk2], s_x[kChunk2];
+    __shared__ uint32_t s_g[kItems * 64], s_x[kItems * 64];
     const int lane = threadIdx.x;
     const int c2 = (int)a.info[kInfoC2];
-    for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_scatter_chunk(a, c, lane, s_g, s_x);
+    for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_scatter_chunk<kItems>(a, c, lane, s_g, s_x);
 }
 
 // Tile offsets from the scanned level-2 counts: tile (r, x) starts at chunk
@@ -545,11 +558,41 @@ constexpr int kMaxGrid2 = 65536;
 }  // namespace
 
 size_t bin_info_elems(int rows) { return (size_t)(kInfoRowChunks + 2 * (rows + 1) + 1); }
-int bin_level1_chunks(int64_t n) { return (int)((n + kChunk1 - 1) / kChunk1); }
-int bin_level2_chunk_bound(uint64_t row_entries, int rows)
+bool bin_items_supported(int items1, int items2)
 {
-    return (int)std::min<uint64_t>(row_entries / kChunk2 + (uint64_t)rows + 1, 1u << 30);
+    return (items1 == 4 || items1 == 8 || items1 == 16) && (items2 == 8 || items2 == 16 || items2 == 32);
 }
+bool tuning_supported(const Tuning& t)
+{
+    return depth_sort_items_supported(t.sort_items) && bin_items_supported(t.bin1_items, t.bin2_items) &&
+           t.blend_group >= 1 && t.blend_group <= 64;
+}
+int bin_level1_chunks(int64_t n, int items1) { return (int)((n + (int64_t)items1 * 64 - 1) / ((int64_t)items1 * 64)); }
+int bin_level2_chunk_bound(uint64_t row_entries, int rows, int items2)
+{
+    return (int)std::min<uint64_t>(row_entries / ((uint64_t)items2 * 64) + (uint64_t)rows + 1, 1u << 30);
+}
+
+namespace {
+template <typename F>
+void with_items1(int items, F f)
+{
+    switch (items) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    default: f(std::integral_constant<int, 16>{}); break;
+    }
+}
+template <typename F>
+void with_items2(int items, F f)
+{
+    switch (items) {
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 32>{}); break;
+    }
+}
+}  // namespace
 
 // Level 1 up to the row offsets (R = rows_off[rows]) and the level-2 chunk
 // table; no host dependence.
@@ -560,8 +603,11 @@ hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t
         if (e != hipSuccess) return e;
         return launch_fill_u32(a.info, 0u, (int64_t)bin_info_elems(a.rows), s);
     }
+    if (!bin_items_supported(a.items1, a.items2)) return hipErrorInvalidValue;
     const int grid1 = a.chunks1 * a.n_views;
-    hipLaunchKernelGGL(level1_count_kernel, dim3(grid8(grid1)), dim3(64), 0, s, a);
+    with_items1(a.items1, [&](auto I) {
+        hipLaunchKernelGGL(level1_count_kernel<decltype(I)::value>, dim3(grid8(grid1)), dim3(64), 0, s, a);
+    });
     hipError_t e = launch_scan_exclusive(a.counts1, (int64_t)a.rows * a.chunks1, scan_scratch, nullptr,
                                          a.rows_off + a.rows, a.overflow, s);
     if (e != hipSuccess) return e;
@@ -572,14 +618,23 @@ hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t
 hipError_t launch_bin_row_scatter(const BinArgs& a, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(level1_scatter_kernel, dim3(grid8(a.chunks1 * a.n_views)), dim3(64), 0, s, a);
+    if (!bin_items_supported(a.items1, a.items2)) return hipErrorInvalidValue;
+    with_items1(a.items1, [&](auto I) {
+        hipLaunchKernelGGL(level1_scatter_kernel<decltype(I)::value>, dim3(grid8(a.chunks1 * a.n_views)), dim3(64), 0,
+                           s, a);
+    });
     return hipGetLastError();
 }
 
 hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch, hipStream_t s)
 {
     if (a.n == 0) return launch_fill_u32(a.tile_offsets, 0u, a.tiles + 1, s);
-    if (grid2 > 0) hipLaunchKernelGGL(level2_count_kernel, dim3(grid8(std::min(grid2, kMaxGrid2))), dim3(64), 0, s, a);
+    if (!bin_items_supported(a.items1, a.items2)) return hipErrorInvalidValue;
+    if (grid2 > 0)
+        with_items2(a.items2, [&](auto I) {
+            hipLaunchKernelGGL(level2_count_kernel<decltype(I)::value>, dim3(grid8(std::min(grid2, kMaxGrid2))),
+                               dim3(64), 0, s, a);
+        });
     // the scan's length E2 is read on the device (info[1])
     hipError_t e = launch_scan_exclusive(a.counts2, (int64_t)a.counts2_capacity, scan_scratch, nullptr,
                                          a.tile_offsets + a.tiles, a.overflow, s, a.info + kInfoC2Elems);
@@ -591,7 +646,11 @@ hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch,
 hipError_t launch_bin_tile_scatter(const BinArgs& a, int grid2, hipStream_t s)
 {
     if (a.n == 0 || grid2 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(level2_scatter_kernel, dim3(grid8(std::min(grid2, kMaxGrid2))), dim3(64), 0, s, a);
+    if (!bin_items_supported(a.items1, a.items2)) return hipErrorInvalidValue;
+    with_items2(a.items2, [&](auto I) {
+        hipLaunchKernelGGL(level2_scatter_kernel<decltype(I)::value>, dim3(grid8(std::min(grid2, kMaxGrid2))),
+                           dim3(64), 0, s, a);
+    });
     return hipGetLastError();
 }
 

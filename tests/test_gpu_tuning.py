@@ -1,0 +1,157 @@
+"""Launch-shape tuning (gs_set_tuning, gs_autotune) on the GPU.
+
+Every supported shape must give the same render bit for bit (image, final T,
+n_contrib, tile offsets and values), eager and with a pair capacity, single
+and batched; the default shape is the one the oracle parity tests check.
+The autotuner must return one of its candidates and leave the results
+unchanged.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+CANDIDATES = {"sort_items": (4, 8, 16), "bin_row_items": (4, 8, 16), "bin_tile_items": (8, 16, 32),
+              "blend_tile_group": (1, 2, 4, 8, 16, 32, 64)}
+DEFAULT = {"sort_items": 8, "bin_row_items": 8, "bin_tile_items": 16, "blend_tile_group": 16}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def renderer():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_15951_amd as gs
+    r = gs.Renderer(0)
+    yield r
+    r.close()
+
+
+def snapshot(renderer, outs):
+    import torch
+    torch.cuda.synchronize()
+    lists = renderer.lists(keys=False)
+    res = {"offsets": lists["tile_offsets"].cpu().numpy().copy(), "values": lists["values"].cpu().numpy().copy()}
+    for v, o in enumerate(outs):
+        res[f"image{v}"] = o["image"].cpu().numpy().view(np.uint32).copy()
+        res[f"T{v}"] = o["final_T"].cpu().numpy().view(np.uint32).copy()
+        res[f"nc{v}"] = o["n_contrib"].cpu().numpy().copy()
+    return res
+
+
+def render_all(renderer, dev, cams, capacity):
+    if len(cams) == 1:
+        c = cams[0]
+        return [renderer.render(dev, c, c["width"], c["height"], pair_capacity=capacity)]
+    return renderer.render_batched(dev, cams, pair_capacity=capacity)
+
+
+def shapes():
+    out = []
+    for k, vals in CANDIDATES.items():
+        for v in vals:
+            if v != DEFAULT[k]:
+                out.append({k: v})
+    out.append({k: vals[0] for k, vals in CANDIDATES.items()})
+    out.append({k: vals[-1] for k, vals in CANDIDATES.items()})
+    return out
+
+
+CASES = {
+    "C2-dist 40k 333x197": lambda: (scenes.make_scene("C2", n=40_000, seed=21), [scenes.default_camera(333, 197)]),
+    "C3-dist 60k rotated 400x240": lambda: (scenes.make_scene("C3", n=60_000, seed=31),
+                                            [scenes.look_at_camera([1.2, -0.8, -2.7], 400, 240)]),
+    "batched 3 views": lambda: (scenes.make_scene("C2", n=30_000, seed=23),
+                                [scenes.default_camera(200, 120), scenes.look_at_camera([1.5, -0.4, -2.4], 96, 64),
+                                 scenes.look_at_camera([-2.0, 0.3, -2.0], 300, 180)]),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("capacity", [0, 1], ids=["eager", "capacity"])
+def test_every_shape_gives_identical_results(renderer, case, capacity):
+    import paper_2607_15951_amd as gs
+    sc, cams = CASES[case]()
+    dev = gs.scene_to_device(sc)
+    renderer.set_tuning(**DEFAULT)
+    cap = 0
+    if capacity:
+        render_all(renderer, dev, cams, 0)
+        cap = int(renderer.list_info()["num_pairs"] * 1.3) + 1024
+    outs = render_all(renderer, dev, cams, cap)
+    want = snapshot(renderer, outs)
+    say(f"[tuning] {case} capacity={cap}: {len(want['values'])} pairs, {len(shapes())} shapes")
+    try:
+        for sh in shapes():
+            renderer.set_tuning(**DEFAULT)
+            renderer.set_tuning(**sh)
+            got = snapshot(renderer, render_all(renderer, dev, cams, cap))
+            for k in want:
+                assert np.array_equal(got[k], want[k]), f"{case}: {k} differs with {sh}"
+    finally:
+        renderer.set_tuning(**DEFAULT)
+
+
+def test_set_tuning_rejects_unsupported_values(renderer):
+    renderer.set_tuning(**DEFAULT)
+    for bad in ({"sort_items": 5}, {"bin_row_items": 32}, {"bin_tile_items": 4}, {"blend_tile_group": 0},
+                {"blend_tile_group": 65}):
+        with pytest.raises(RuntimeError):
+            renderer.set_tuning(**bad)
+        assert renderer.tuning() == DEFAULT
+
+
+def test_autotune_returns_a_candidate_and_keeps_results(renderer):
+    import paper_2607_15951_amd as gs
+    sc, cams = CASES["batched 3 views"]()
+    dev = gs.scene_to_device(sc)
+    renderer.set_tuning(**DEFAULT)
+    want = snapshot(renderer, render_all(renderer, dev, cams, 0))
+    try:
+        res = renderer.autotune(dev, cams, reps=2)
+        say(f"[tuning] autotune: {res['tuning']}")
+        for k, v in res["tuning"].items():
+            assert v in CANDIDATES[k], (k, v)
+        assert renderer.tuning() == res["tuning"]
+        assert len(res["candidates_ms"]) == len(gs.TUNE_CANDIDATES)
+        assert all(ms > 0 for _, _, ms in res["candidates_ms"])
+        got = snapshot(renderer, render_all(renderer, dev, cams, 0))
+        for k in want:
+            assert np.array_equal(got[k], want[k]), f"{k} differs after autotune"
+    finally:
+        renderer.set_tuning(**DEFAULT)
+
+
+def test_backward_with_other_tile_groups(renderer):
+    """The backward deals tiles like its render; gradients agree to float
+    atomics' reordering."""
+    import paper_2607_15951_amd as gs
+    import torch
+    sc = scenes.make_scene("C2", n=5_000, seed=24, sh_degree=1)
+    cam = scenes.default_camera(160, 96)
+    dev = gs.scene_to_device(sc)
+    rng = np.random.default_rng(3)
+    gi = torch.from_numpy(rng.uniform(-1, 1, (3, 96, 160)).astype(np.float32)).cuda()
+    ref = None
+    try:
+        for group in (16, 1, 64):
+            renderer.set_tuning(blend_tile_group=group)
+            renderer.render(dev, cam, 160, 96)
+            g = {k: v.cpu().numpy() for k, v in renderer.backward(dev, [gi]).items()}
+            if ref is None:
+                ref = g
+                continue
+            for k in g:
+                scale = float(np.abs(ref[k]).max()) or 1.0
+                assert float(np.abs(g[k] - ref[k]).max()) <= 1e-5 * scale, (group, k)
+    finally:
+        renderer.set_tuning(**DEFAULT)
