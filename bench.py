@@ -115,15 +115,28 @@ KERNEL_SOURCES = {
     "level2_scatter_kernel": ["tile_bin.hip", "gs_internal.h"],
     "blend_kernel": ["blend.hip", "gs_internal.h"],
 }
-STAGE_KERNEL = {"project": "project_kernel", "bin_row_scatter": "level1_scatter_kernel",
-                "bin_tile_scatter": "level2_scatter_kernel", "blend": "blend_kernel"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt")
+
+
+def stage_kernel(stage: str, dtype: int, deg: int, tuning: dict) -> str:
+    """The instantiation a single-kernel stage launches for one view, as the
+    profiler names it (template arguments follow the storage dtype, the SH
+    degree and the launch shapes)."""
+    if stage == "project":
+        return f"project_kernel<{dtype}, {deg}, true>"
+    if stage == "bin_row_scatter":
+        return f"level1_scatter_kernel<{tuning['bin_row_items']}>"
+    if stage == "bin_tile_scatter":
+        return f"level2_scatter_kernel<{tuning['bin_tile_items']}>"
+    if stage == "blend":
+        return "blend_kernel<false>"
+    raise KeyError(stage)
 
 
 def source_digest(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[kernel]:
+    for f in KERNEL_SOURCES[kernel.split("<")[0]]:
         with open(os.path.join(ROOT, "paper_2607_15951_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -139,8 +152,10 @@ def read_traffic(kernel: str, workload: str, variant: str):
         for line in fh:
             parts = line.split()
             if len(parts) >= 6 and parts[0] == "kernel":
-                # kernel <name> <workload> <variant> <digest> <fetch_bytes> <write_bytes>
+                # kernel <name> <workload> <variant> <digest> <fetch_bytes> <write_bytes>; the name
+                # keeps its template arguments with the spaces taken out
                 rec[(parts[1], parts[2], parts[3])] = (parts[4], float(parts[5]), float(parts[6]))
+    kernel = kernel.replace(" ", "")
     r = rec.get((kernel, workload, variant))
     if r is None or r[0] != source_digest(kernel):
         return None
@@ -182,7 +197,7 @@ def _pmc_avg(path: str, counter: str) -> dict:
         # the work-counting blend variant (one launch per bench run) is not the timed kernel
         if r["Counter_Name"] != counter or "blend_kernel<true>" in kernel_short_name(r["Kernel_Name"]):
             continue
-        k = kernel_short_name(r["Kernel_Name"], templates=False)
+        k = kernel_short_name(r["Kernel_Name"]).replace(" ", "")
         acc.setdefault(k, []).append(float(r["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
@@ -201,8 +216,8 @@ def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_writ
     lines = [f"# copy calibration: {cf[0]} FETCH_SIZE {cf[1]:.0f} KiB, WRITE_SIZE {cw[1]:.0f} KiB for "
              f"{copy_bytes} B read and written -> factors fetch {f_fac:.3f}, write {w_fac:.3f}",
              "# kernel <name> <workload> <variant> <source digest> <fetch bytes/launch> <write bytes/launch>"]
-    for k in sorted(KERNEL_SOURCES):
-        if k in fetch and k in write:
+    for k in sorted(set(fetch) & set(write)):
+        if k.split("<")[0] in KERNEL_SOURCES:
             lines.append(f"kernel {k} {workload} {variant} {source_digest(k)} {fetch[k] * 1024 * f_fac:.0f} "
                          f"{write[k] * 1024 * w_fac:.0f}")
     for k in sorted(set(fetch) | set(write)):
@@ -355,6 +370,7 @@ def main():
         log("[bench] autotune")
         tune = r.autotune(dev, [cam], reps=5)
         log("[bench] tuning " + json.dumps(tune["tuning"]))
+    main_tuning = r.tuning()   # the shapes of the timed frames (later variants retune)
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
         r.render(dev, cam, W, H, out=out)
@@ -434,22 +450,25 @@ def main():
             del dev4
 
     K, n_vis, R = info["num_pairs"], info["n_visible"], info["num_row_entries"]
+    tuned = main_tuning
     single = ["project", "bin_row_scatter", "bin_tile_scatter", "blend"]
     dom = max(single, key=lambda k: stage_ms[k])
     if dom == "blend":
         flops = FLOPS_EVAL * stats["evaluations"] + FLOPS_COMPOSITE * stats["composited"]
         achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "blend_kernel", "bound": "alu", "achieved": round(achieved, 3),
+        kname = stage_kernel(dom, dtype, deg, tuned)
+        roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": read_traffic("blend_kernel", args.workload, args.variant), "work": {"evaluations": stats["evaluations"], "composited": stats["composited"],
+                "traffic": read_traffic(kname, args.workload, args.variant), "work": {"evaluations": stats["evaluations"], "composited": stats["composited"],
                                           "flops_per_evaluation": FLOPS_EVAL,
                                           "flops_per_composite": FLOPS_COMPOSITE}}
     else:
         by = algorithmic_bytes(dom, n, n_vis, K, R, deg, dtype, W, H, stats)
         achieved = by / (stage_ms[dom] * 1e-3) / 1e9
-        roof = {"kernel": STAGE_KERNEL[dom], "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        kname = stage_kernel(dom, dtype, deg, tuned)
+        roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": read_traffic(STAGE_KERNEL[dom], args.workload, args.variant),
+                "traffic": read_traffic(kname, args.workload, args.variant),
                 "bytes_per_launch": int(by)}
     stage_gbs = {}
     for k in single:
