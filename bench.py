@@ -313,6 +313,50 @@ def time_backward(r, dev, cam, W: int, H: int, steps: int, out) -> dict:
             "forward_backward_per_s": round(1e3 / ms_step, 1), "steps": bsteps}
 
 
+def time_reuse(r, dev, W: int, H: int, frames: int = 16) -> dict:
+    """Orbits of several step sizes around the scene (the camera motions of
+    the paper's churn table): frame time with and without
+    GS_RENDER_REUSE_ORDER, the depth-sort stage time with it, how many frames
+    kept the previous order, the order's descents, and the churn -- the
+    share of Gaussians whose tile rectangle changed since the last frame."""
+    import torch
+    import scenes
+    out = {}
+    for step in (0.0, 0.001, 0.01, 0.05, 0.1, 0.5, 2.0):
+        cams = [scenes.orbit_camera(step * f, W, H) for f in range(frames + 1)]
+        o = r.render(dev, cams[0], W, H)
+        timed = {}
+        for reuse in (True, False):
+            r.render(dev, cams[0], W, H, out=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c in cams[1:]:
+                r.render(dev, c, W, H, out=o, reuse_order=reuse)
+            torch.cuda.synchronize()
+            timed[reuse] = (time.perf_counter() - t0) * 1e3 / frames
+        r.render(dev, cams[0], W, H, out=o)
+        prev = r.projection()["rect"].clone()
+        r.set_profiling(stages=True)
+        sort_ms = kept = desc = 0.0
+        moved = 0
+        for c in cams[1:]:
+            r.render(dev, c, W, H, out=o, reuse_order=True)
+            sort_ms += r.stage_times()["depth_sort"]
+            rep = r.order_reuse()
+            kept += rep["reused"]
+            desc += rep["descents"]
+            rect = r.projection()["rect"]
+            moved += int((rect != prev).any(dim=1).sum())
+            prev = rect.clone()
+        r.set_profiling(stages=False)
+        n = int(prev.shape[0])
+        out[f"orbit_{step}deg"] = {
+            "ms_per_frame_reuse": round(timed[True], 4), "ms_per_frame_plain": round(timed[False], 4),
+            "depth_sort_ms_reuse": round(sort_ms / frames, 4), "frames_reused": int(kept), "frames": frames,
+            "descents_per_frame": round(desc / frames, 1), "churn_pct": round(100.0 * moved / (frames * n), 3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +478,8 @@ def main():
         if dtype == gs.GS_F32:
             variants["backward"] = time_backward(r, dev, cam, W, H, args.steps, out)
             log("[bench] variant backward: " + json.dumps(variants["backward"]))
+            variants["reuse_order"] = time_reuse(r, dev, W, H)
+            log("[bench] variant reuse_order: " + json.dumps(variants["reuse_order"]))
         # batched: the same frame's scene from 8 cameras on a ring (1080p each),
         # and the 64-camera mixed-resolution workload, each one
         # gs_render_batched call per step, against the same views rendered one

@@ -94,13 +94,27 @@ typedef struct {
  *                  out-of-bounds write, the image is then unspecified, and
  *                  gs_get_list_info (hence gs_copy_lists) returns
  *                  GS_ERR_CAPACITY for that render
- *   flags          reserved, must be 0 */
+ *   flags          0 or GS_RENDER_REUSE_ORDER (below); other bits give
+ *                  GS_ERR_INVALID_ARGUMENT */
 typedef struct {
     float background[3];
     int32_t tile_size;
     uint64_t pair_capacity;
     uint32_t flags;
 } gs_render_opts;
+
+/* GS_RENDER_REUSE_ORDER: frame-to-frame reuse of the depth order, after the
+ * data locality of Sec. 5.7 (Table 5).  When the previous render on the
+ * context was a single view of as many Gaussians, the depth sort first
+ * re-keys that render's order with this frame's depths and counts the
+ * adjacent pairs it puts out of order.  None (a static camera, changes of
+ * colour or opacity only): the radix sort is skipped.  At most n/256: runs
+ * of 8192 are sorted in on-chip memory twice (the second time shifted by
+ * half a run) and, if the result checks out on the device, the radix sort is
+ * skipped.  Otherwise the radix sort runs as usual.  The order, hence every
+ * output, is the same as without the flag; only the time differs.  Ignored
+ * for batched renders and for the first render on a context. */
+#define GS_RENDER_REUSE_ORDER 1u
 
 /* Creates a context on HIP device `device`; *out receives it. */
 gs_status gs_create(int device, gs_context** out);
@@ -245,8 +259,10 @@ gs_status gs_copy_lists(gs_context* ctx, uint32_t* values, uint32_t* tile_offset
  *                  opacity, r, g, b, depth, where the 2D centre is
  *                  u = u_hi + u_lo (float32 pair of the double value) and
  *                  the EWA falloff is exp(-0.5(A dx^2 + C dy^2) - B dx dy)
- *   depth_key      uint32 [n] float32 bits of depth; 0xFFFFFFFF for a
- *                  Gaussian that overlaps no tile
+ *   depth_key      uint32 [n] float32 bits of the camera-space depth t_z
+ *                  (the low half of every pair key of the Gaussian); every
+ *                  Gaussian with a finite t_z has one, also when it is culled
+ *                  or off screen and has no pair; 0xFFFFFFFF otherwise
  *   radius         int32 [n] 3-sigma radius in pixels, 0 if no tile
  *   tiles_touched  uint32 [n]
  *   rect           uint16 [n][4] tile rectangle x0, y0, x1, y1 (exclusive) */
@@ -303,6 +319,14 @@ gs_status gs_get_blend_stats(gs_context* ctx, uint64_t* stats4);
  * Table 2.  gs_get_blend_stats holds the sums over tiles.
  * GS_ERR_INVALID_ARGUMENT if the render was not counted or tiles differs. */
 gs_status gs_get_blend_tile_work(gs_context* ctx, uint64_t* work, int64_t tiles);
+
+/* Outcome of the last render's GS_RENDER_REUSE_ORDER attempt (host array of
+ * 2, synchronises with that render): [0] 1 if the reused order held and the
+ * radix sort was skipped, 0 if it ran; [1] the number of adjacent pairs of
+ * the previous order that this frame's depths put out of order (the order's
+ * churn between the two frames).  GS_ERR_INVALID_ARGUMENT if the last render
+ * did not start from a previous order. */
+gs_status gs_get_order_reuse(gs_context* ctx, uint32_t* out2);
 
 /* Launch shapes of the render, chosen per workload: the tile size (16, which
  * the keys of Sec. 3.1 and the lists depend on) is fixed, but how many items

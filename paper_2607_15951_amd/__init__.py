@@ -19,13 +19,14 @@ LIB_PATH = os.path.join(_PKG, "libgsmi.so")
 GS_OK, GS_ERR_INVALID_ARGUMENT, GS_ERR_OUT_OF_MEMORY, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = range(6)
 GS_F32, GS_BF16, GS_F16 = 0, 1, 2
 PROFILE_STAGES, PROFILE_BLEND_WORK = 1, 2
+RENDER_REUSE_ORDER = 1
 TILE = 16
 
 EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
             "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
             "gs_get_blend_stats", "gs_get_blend_tile_work", "gs_render_batched", "gs_graph_create",
             "gs_graph_set_views", "gs_graph_launch", "gs_graph_destroy", "gs_render_backward", "gs_set_tuning",
-            "gs_get_tuning", "gs_autotune"]
+            "gs_get_tuning", "gs_autotune", "gs_get_order_reuse"]
 STAGES = ["project", "depth_sort", "bin_row_count", "bin_row_scatter", "bin_tile_count", "bin_tile_scatter",
           "blend"]
 
@@ -116,6 +117,8 @@ def load_library(path: str = LIB_PATH):
     L.gs_render_backward.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(gs_gradients), P]
     L.gs_render_backward.restype = C.c_int
+    L.gs_get_order_reuse.argtypes = [P, C.POINTER(C.c_uint32)]
+    L.gs_get_order_reuse.restype = C.c_int
     L.gs_set_tuning.argtypes = [P, C.POINTER(gs_tuning)]
     L.gs_set_tuning.restype = C.c_int
     L.gs_get_tuning.argtypes = [P, C.POINTER(gs_tuning)]
@@ -154,13 +157,13 @@ def make_camera(cam: dict) -> gs_camera:
     return c
 
 
-def make_opts(background=(0.0, 0.0, 0.0), pair_capacity: int = 0) -> gs_render_opts:
+def make_opts(background=(0.0, 0.0, 0.0), pair_capacity: int = 0, flags: int = 0) -> gs_render_opts:
     o = gs_render_opts()
     for k in range(3):
         o.background[k] = float(background[k])
     o.tile_size = TILE
     o.pair_capacity = int(pair_capacity)
-    o.flags = 0
+    o.flags = int(flags)
     return o
 
 
@@ -239,8 +242,10 @@ class Renderer:
 
     def render(self, dev_scene: dict, camera: dict, width: int, height: int, background=(0.0, 0.0, 0.0),
                pair_capacity: int = 0, out=None, want_T: bool = True, want_n_contrib: bool = True,
-               stream=None):
-        """Renders into (new or given) tensors: rgb [3,H,W], final_T [H,W], n_contrib [H,W]."""
+               stream=None, reuse_order: bool = False):
+        """Renders into (new or given) tensors: rgb [3,H,W], final_T [H,W], n_contrib [H,W].
+        reuse_order: start the depth sort from the previous render's order
+        (GS_RENDER_REUSE_ORDER; same results, less work between nearby frames)."""
         torch = _torch()
         dev = dev_scene["means"].device
         if out is None:
@@ -250,7 +255,7 @@ class Renderer:
                    if want_n_contrib else None}
         g = make_gaussians(dev_scene)
         cam = make_camera(camera)
-        opts = make_opts(background, pair_capacity)
+        opts = make_opts(background, pair_capacity, RENDER_REUSE_ORDER if reuse_order else 0)
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         st = self._L.gs_render(self._ctx, C.byref(g), C.byref(cam), int(width), int(height), C.byref(opts),
                                _ptr(out["image"]), _ptr(out.get("final_T")), _ptr(out.get("n_contrib")),
@@ -301,14 +306,14 @@ class Renderer:
         return views, outs
 
     def graph(self, dev_scene: dict, cameras: list, pair_capacity: int, background=(0.0, 0.0, 0.0), outs=None,
-              stream=None) -> "RenderGraph":
+              stream=None, reuse_order: bool = False) -> "RenderGraph":
         """Captures a batched render of ``cameras`` into a replayable graph
         (gs_graph_create); the renderer belongs to it until it is closed."""
         torch = _torch()
         dev = dev_scene["means"].device
         views, outs = self._views(cameras, outs, dev)
         g = make_gaussians(dev_scene)
-        opts = make_opts(background, pair_capacity)
+        opts = make_opts(background, pair_capacity, RENDER_REUSE_ORDER if reuse_order else 0)
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         h = C.c_void_p()
         self._check(self._L.gs_graph_create(self._ctx, C.byref(g), views, len(cameras), C.byref(opts),
@@ -317,6 +322,14 @@ class Renderer:
         gr = RenderGraph(self, h, outs, dev)
         self._graphs.append(gr)
         return gr
+
+    def order_reuse(self) -> dict:
+        """Outcome of the last render's reuse of the previous depth order
+        (gs_get_order_reuse): whether the radix sort was skipped, and the
+        descents of the previous order under the new depths."""
+        w = (C.c_uint32 * 2)()
+        self._check(self._L.gs_get_order_reuse(self._ctx, w))
+        return {"reused": bool(w[0]), "descents": int(w[1])}
 
     def tuning(self) -> dict:
         t = gs_tuning()

@@ -63,6 +63,9 @@ struct gs_context {
     DevBuf grad2d;                        // backward: per-item blend gradients
     Tuning tuning = kDefaultTuning;       // launch shapes of the next render
     Tuning last_tuning = kDefaultTuning;  // launch shapes of the last render
+    int64_t order_n = -1;     // items of the depth order the sort buffers hold (one view), -1 if none
+    bool last_reuse = false;  // the last render started from the previous order
+    DevBuf reuse_words;       // [kReuseWords] outcome of that attempt
 };
 
 struct gs_graph {
@@ -130,7 +133,8 @@ gs_status validate_opts(gs_context* ctx, const gs_render_opts* opts)
 {
     if (opts) {
         if (opts->tile_size != kTile) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "tile_size must be 16");
-        if (opts->flags != 0) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "flags must be 0");
+        if (opts->flags & ~GS_RENDER_REUSE_ORDER)
+            return fail(ctx, GS_ERR_INVALID_ARGUMENT, "unknown flag in opts->flags");
         if (!finite_all(opts->background, 3))
             return fail(ctx, GS_ERR_INVALID_ARGUMENT, "background holds a non-finite value");
     }
@@ -230,6 +234,8 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     if (opts) o = *opts;
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     ctx->have_render = false;
+    const int64_t prev_order_n = ctx->order_n;
+    ctx->order_n = -1;   // valid again only once this render has completed its sort
 
     const int V = (int)hv.size();
     const int64_t n = g->n;
@@ -325,10 +331,21 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     if ((st = ensure(ctx, ctx->scan_scratch, scan_scratch_elems(scan_max) * 8)) != GS_OK) return st;
     uint64_t* scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
     int in_b = 1;
+    // one view of the same Gaussians as the last render: start from its order
+    const bool reuse = (o.flags & GS_RENDER_REUSE_ORDER) && V == 1 && n > 0 && prev_order_n == n;
+    uint32_t* reuse_words = nullptr;
+    if (reuse) {
+        if ((st = ensure(ctx, ctx->reuse_words, kReuseWords * 4)) != GS_OK) return st;
+        reuse_words = static_cast<uint32_t*>(ctx->reuse_words.p);
+        HIP_TRY(launch_order_reuse(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
+                                   static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
+                                   static_cast<uint32_t*>(ctx->sort_vb.p), n, tu.sort_items, reuse_words, s),
+                "order reuse");
+    }
     HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
                               static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
                               static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p),
-                              scan_scratch, n, V, tu.sort_items, &in_b, s),
+                              scan_scratch, n, V, tu.sort_items, reuse_words, &in_b, s),
             "depth sort");
     ba.sorted_idx = static_cast<const uint32_t*>(in_b ? ctx->sort_vb.p : ctx->sort_va.p);
     STAGE_MARK(2);
@@ -403,6 +420,8 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
 
     ctx->have_render = true;
     ctx->last_tuning = tu;
+    ctx->order_n = (V == 1 && in_b) ? n : -1;
+    ctx->last_reuse = reuse;
     ctx->last_views = hv;
     ctx->last_g = *g;
     for (int k = 0; k < 3; ++k) ctx->last_bg[k] = bl.bg[k];
@@ -716,6 +735,20 @@ gs_status gs_render_backward(gs_context* ctx, const gs_gaussians* g, const float
     pb.g_sh = grads->sh;
     HIP_TRY(launch_project_backward(pb, s), "projection backward");
     ctx->stream = s;
+    return GS_OK;
+}
+
+gs_status gs_get_order_reuse(gs_context* ctx, uint32_t* out2)
+{
+    if (!ctx || !out2) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (!ctx->have_render || !ctx->last_reuse)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render did not start from the previous order");
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    uint32_t w[kReuseWords];
+    HIP_TRY(hipMemcpyAsync(w, ctx->reuse_words.p, sizeof w, hipMemcpyDeviceToHost, ctx->stream), "read reuse words");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    out2[0] = w[0];
+    out2[1] = w[1];
     return GS_OK;
 }
 

@@ -13,9 +13,10 @@
 // Each 8-bit pass is reduce-then-scan: an LDS histogram per block, one
 // exclusive scan of the digit-major [segment][digit][block] table, and a stable
 // scatter that ranks equal digits with wavefront ballots (lower lanes and
-// earlier waves first).  Keys of Gaussians that overlap no tile are
-// 0xFFFFFFFF and sink to the end; values start as the Gaussian index, so ties
-// in depth stay in index order.
+// earlier waves first).  Digits are taken from sort_key(key), which orders
+// depths as numbers (negative ones, behind the camera, first); keys of
+// Gaussians without a finite depth are 0xFFFFFFFF and sink to the end.
+// Values start as the Gaussian index, so ties in depth stay in index order.
 #include "gs_internal.h"
 
 namespace gsmi {
@@ -36,10 +37,23 @@ __device__ __forceinline__ void sort_block_range(int64_t n, int bpv, int64_t* be
     *row = (int64_t)v * 256 * bpv + lb;   // table index of digit 0; digit d adds d * bpv
 }
 
+// Order-preserving map of a depth key to the sort key: float bits compare as
+// unsigned integers only among non-negative floats, so negative depths
+// (Gaussians behind the camera) are flipped below them; 0xFFFFFFFF (no finite
+// depth) stays last.  On the non-negative depths of the pairs it keeps the
+// order of the bits themselves.
+__device__ __forceinline__ uint32_t sort_key(uint32_t b)
+{
+    if (b == 0xFFFFFFFFu) return b;
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
 template <int kItems>
 __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
-                                                                 int shift, uint32_t* __restrict__ hist, int bpv)
+                                                                 int shift, uint32_t* __restrict__ hist, int bpv,
+                                                                 const uint32_t* skip)
 {
+    if (skip && *skip) return;   // the previous frame's order was reused
     __shared__ uint32_t h[4][256];   // one private histogram per wave
     const int tid = threadIdx.x, wave = tid >> 6;
 #pragma unroll
@@ -50,7 +64,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int64_t idx = begin + k * kSortBlock + tid;
-        if (idx < end) atomicAdd(&h[wave][(keys[idx] >> shift) & 255u], 1u);
+        if (idx < end) atomicAdd(&h[wave][(sort_key(keys[idx]) >> shift) & 255u], 1u);
     }
     __syncthreads();
     hist[row + (int64_t)tid * bpv] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
@@ -67,8 +81,10 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
 template <int kItems>
 __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, int64_t n, int shift, const uint32_t* __restrict__ offsets, int bpv)
+    uint32_t* __restrict__ vals_out, int64_t n, int shift, const uint32_t* __restrict__ offsets, int bpv,
+    const uint32_t* skip)
 {
+    if (skip && *skip) return;
     __shared__ uint32_t cnt[kItems][4][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int64_t begin, end, row;
@@ -84,7 +100,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
         const bool valid = idx < end;
         key[k] = valid ? keys_in[idx] : 0u;
         val[k] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
-        const uint32_t d = (key[k] >> shift) & 255u;
+        const uint32_t d = (sort_key(key[k]) >> shift) & 255u;
         // lanes of this wave holding the same digit
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -123,13 +139,162 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
 
 template <int kItems>
 void launch_sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* hist,
-                      int64_t n, int shift, int bpv, unsigned nblocks, bool histogram_only, hipStream_t s)
+                      int64_t n, int shift, int bpv, unsigned nblocks, bool histogram_only, const uint32_t* skip,
+                      hipStream_t s)
 {
     if (histogram_only)
-        hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, hist, bpv);
+        hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, hist, bpv,
+                           skip);
     else
         hipLaunchKernelGGL(radix_scatter_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
-                           n, shift, hist, bpv);
+                           n, shift, hist, bpv, skip);
+}
+
+// ------------------------------------------------- reuse of the previous order
+// Between nearby frames few Gaussians change their tile (the data locality of
+// Sec. 5.7, Table 5), but their depth order is another matter: a dense scene
+// has depth gaps far below the depth change of a small camera step, so most
+// adjacent pairs swap.  The previous frame's order (one view, same Gaussians)
+// is therefore only tried, and cheaply: each item gets this frame's key in
+// that order and the descents (adjacent pairs out of order) are counted.
+//   no descent       the order holds (static camera, appearance-only
+//                    changes): the radix passes are skipped;
+//   a few descents   runs of kReuseBlock items are sorted in LDS twice
+//                    (aligned, then shifted by half a run) and the result is
+//                    checked; the passes are skipped if it holds;
+//   more             the radix passes sort from scratch.
+// Every decision is taken on the device (flags the kernels read), so the
+// frame needs no host read and can be captured.  Whatever path runs, the
+// order is the stable (depth, index) order: the check compares the composite
+// (sort key << 32 | index), a strict total order.
+constexpr int kReuseThreads = 1024;
+constexpr int kReuseItems = 8;
+constexpr int kReuseBlock = kReuseThreads * kReuseItems;   // items sorted together in LDS
+
+// The gathered keys are sort keys (sort_key), as the radix passes compare.
+// words[0] = 1 while the reused order holds (the radix passes' skip flag),
+// words[1] = descents of the gathered previous order (churn), words[2] = the
+// radix scans' length (0 when skipped), words[3] = 1 when the local repair
+// runs.  A repair is tried for at most n / kRepairFraction descents.
+constexpr int64_t kRepairFraction = 256;
+// Grid-stride, so that the descent count takes one atomic per block: an
+// atomic per wave on one counter serialises when most pairs swap.
+constexpr int kGatherBlocks = 2048;
+__global__ __launch_bounds__(256) void order_gather_kernel(const uint32_t* __restrict__ keys,
+                                                           const uint32_t* __restrict__ prev, int64_t n,
+                                                           uint32_t* __restrict__ k_out, uint32_t* __restrict__ v_out,
+                                                           uint32_t* words)
+{
+    uint32_t descents = 0u;
+    bool invalid = false;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+        uint32_t p = prev[j];
+        if (p >= (uint32_t)n) {   // not an order of these items: sort from scratch
+            invalid = true;
+            p = 0u;
+        }
+        const uint32_t k = sort_key(keys[p]);
+        k_out[j] = k;
+        v_out[j] = p;
+        if (j + 1 < n) {
+            uint32_t p1 = prev[j + 1];
+            p1 = p1 < (uint32_t)n ? p1 : 0u;
+            const uint64_t a = ((uint64_t)k << 32) | p, b = ((uint64_t)sort_key(keys[p1]) << 32) | p1;
+            descents += a > b ? 1u : 0u;
+        }
+    }
+    if (invalid) words[0] = 0u;
+    __shared__ uint32_t s_d[4];
+    for (int o = 32; o > 0; o >>= 1) descents += __shfl_xor(descents, o, 64);
+    if ((threadIdx.x & 63) == 0) s_d[threadIdx.x >> 6] = descents;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t d = s_d[0] + s_d[1] + s_d[2] + s_d[3];
+        if (d) atomicAdd(&words[1], d);
+    }
+}
+
+// Sorts runs of kReuseBlock composite keys in LDS (bitonic network).  Run b
+// covers [offset + b * kReuseBlock, ...); with kShifted the runs start half a
+// run in, and one extra block copies the first half run unchanged.
+// (The unshifted pass sorts in place: in and out may be the same arrays.)
+template <bool kShifted>
+__global__ __launch_bounds__(kReuseThreads) void order_local_sort_kernel(const uint32_t* k_in, const uint32_t* v_in,
+                                                                        int64_t n, uint32_t* k_out, uint32_t* v_out,
+                                                                        const uint32_t* words)
+{
+    if (!words[3]) return;   // no repair this frame
+    __shared__ uint64_t s[kReuseBlock];
+    const int tid = threadIdx.x;
+    const int64_t half = kReuseBlock / 2;
+    if (kShifted && blockIdx.x == gridDim.x - 1) {   // the head, already in place
+        for (int64_t i = tid; i < half && i < n; i += kReuseThreads) {
+            k_out[i] = k_in[i];
+            v_out[i] = v_in[i];
+        }
+        return;
+    }
+    const int64_t base = (kShifted ? half : 0) + (int64_t)blockIdx.x * kReuseBlock;
+#pragma unroll
+    for (int k = 0; k < kReuseItems; ++k) {
+        const int64_t i = base + k * kReuseThreads + tid;
+        s[k * kReuseThreads + tid] = i < n ? (((uint64_t)k_in[i] << 32) | v_in[i]) : ~0ull;   // pads sort last
+    }
+    __syncthreads();
+    for (int size = 2; size <= kReuseBlock; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+            for (int k = 0; k < kReuseBlock / 2 / kReuseThreads; ++k) {
+                const int c = k * kReuseThreads + tid;   // pair index
+                const int lo = 2 * stride * (c / stride) + (c % stride), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t a = s[lo], b = s[hi];
+                if ((a > b) == up) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kReuseItems; ++k) {
+        const int64_t i = base + k * kReuseThreads + tid;
+        if (i < n) {
+            const uint64_t c = s[k * kReuseThreads + tid];
+            k_out[i] = (uint32_t)(c >> 32);
+            v_out[i] = (uint32_t)c;
+        }
+    }
+}
+
+// After the gather: no descent keeps the order as it is (the previous order
+// in vals_b is this frame's order), a few start the repair, more give up.
+__global__ void order_plan_kernel(uint32_t* words, int64_t n)
+{
+    if (threadIdx.x != 0) return;
+    const uint32_t d = words[1];
+    const bool valid = words[0] != 0u;
+    const bool repair = valid && d > 0u && (int64_t)d <= n / kRepairFraction;
+    words[3] = repair ? 1u : 0u;
+    words[0] = (valid && (d == 0u || repair)) ? 1u : 0u;
+}
+
+// Clears words[0] at any descent left after the two local sorts.
+__global__ __launch_bounds__(256) void order_check_kernel(const uint32_t* __restrict__ k, const uint32_t* __restrict__ v,
+                                                          int64_t n, uint32_t* words)
+{
+    if (!words[3]) return;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j + 1 < n) {
+        const uint64_t a = ((uint64_t)k[j] << 32) | v[j], b = ((uint64_t)k[j + 1] << 32) | v[j + 1];
+        if (a > b) words[0] = 0u;
+    }
+}
+
+__global__ void order_decide_kernel(uint32_t* words, uint32_t scan_len)
+{
+    if (threadIdx.x == 0) words[2] = words[0] ? 0u : scan_len;
 }
 
 }  // namespace
@@ -145,13 +310,42 @@ size_t depth_sort_hist_elems(int64_t n, int n_views)
     return (size_t)(256 * (nb > 0 ? nb : 1));
 }
 
+hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                              uint32_t* vals_b, int64_t n, int items, uint32_t* words, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipError_t e = launch_fill_u32(words, 0u, kReuseWords, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(words, 1u, 1, s);
+    if (e != hipSuccess) return e;
+    const unsigned g256 = (unsigned)((n + 255) / 256);
+    // previous order (vals_b) -> (this frame's keys, items) in a
+    hipLaunchKernelGGL(order_gather_kernel, dim3((unsigned)std::min<int64_t>(g256, kGatherBlocks)), dim3(256), 0, s,
+                       keys, (const uint32_t*)vals_b, n, keys_a, vals_a, words);
+    hipLaunchKernelGGL(order_plan_kernel, dim3(1), dim3(64), 0, s, words, n);
+    const int64_t half = kReuseBlock / 2;
+    const unsigned runs = (unsigned)((n + kReuseBlock - 1) / kReuseBlock);
+    const unsigned runs_shifted = (unsigned)(n > half ? (n - half + kReuseBlock - 1) / kReuseBlock : 0) + 1u;
+    hipLaunchKernelGGL(order_local_sort_kernel<false>, dim3(runs), dim3(kReuseThreads), 0, s, (const uint32_t*)keys_a,
+                       (const uint32_t*)vals_a, n, keys_a, vals_a, (const uint32_t*)words);
+    hipLaunchKernelGGL(order_local_sort_kernel<true>, dim3(runs_shifted), dim3(kReuseThreads), 0, s,
+                       (const uint32_t*)keys_a, (const uint32_t*)vals_a, n, keys_b, vals_b, (const uint32_t*)words);
+    hipLaunchKernelGGL(order_check_kernel, dim3(g256), dim3(256), 0, s, (const uint32_t*)keys_b, (const uint32_t*)vals_b,
+                       n, words);
+    const int64_t tile = (int64_t)kSortBlock * items;
+    const uint32_t scan_len = (uint32_t)(256 * ((n + tile - 1) / tile));
+    hipLaunchKernelGGL(order_decide_kernel, dim3(1), dim3(64), 0, s, words, scan_len);
+    return hipGetLastError();
+}
+
 // Sorts each of the n_views segments keys_in[v * n .. (v + 1) * n) (not
 // modified) with values v * n + i, items keys per thread of a block.  Four
 // passes: in -> a -> b -> a -> b, so the sorted keys/values end in (keys_b,
-// vals_b).
+// vals_b).  With reuse_words (one view, after launch_order_reuse) every pass
+// reads words[0] on the device and does nothing when the reused order holds.
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
                              uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch, int64_t n, int n_views,
-                             int items, int* result_in_b, hipStream_t s)
+                             int items, const uint32_t* reuse_words, int* result_in_b, hipStream_t s)
 {
     *result_in_b = 1;
     if (n == 0 || n_views <= 0) return hipSuccess;
@@ -163,17 +357,20 @@ hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t
     const uint32_t* vin = nullptr;
     uint32_t* kout = keys_a;
     uint32_t* vout = vals_a;
+    const uint32_t* skip = reuse_words;
+    const uint32_t* scan_len = reuse_words ? reuse_words + 2 : nullptr;   // 0 when skipped
     auto pass_launch = [&](int shift, bool hist_only) {
         switch (items) {
-        case 4: launch_sort_pass<4>(kin, vin, kout, vout, hist, n, shift, bpv, nblocks, hist_only, s); break;
-        case 8: launch_sort_pass<8>(kin, vin, kout, vout, hist, n, shift, bpv, nblocks, hist_only, s); break;
-        default: launch_sort_pass<16>(kin, vin, kout, vout, hist, n, shift, bpv, nblocks, hist_only, s); break;
+        case 4: launch_sort_pass<4>(kin, vin, kout, vout, hist, n, shift, bpv, nblocks, hist_only, skip, s); break;
+        case 8: launch_sort_pass<8>(kin, vin, kout, vout, hist, n, shift, bpv, nblocks, hist_only, skip, s); break;
+        default: launch_sort_pass<16>(kin, vin, kout, vout, hist, n, shift, bpv, nblocks, hist_only, skip, s); break;
         }
     };
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
         pass_launch(shift, true);
-        hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblocks, scan_scratch, nullptr, nullptr, nullptr, s);
+        hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblocks, scan_scratch, nullptr, nullptr, nullptr, s,
+                                             scan_len);
         if (e != hipSuccess) return e;
         pass_launch(shift, false);
         kin = kout;

@@ -53,8 +53,10 @@ struct ViewParams {
     const float* grad_T;
 };
 
-// Per-view counters written on the device: [0] visible Gaussians, [2..3]
-// pairs K of the view (u64).
+// Per-view counters written on the device: [0] Gaussians on screen (at least
+// one tile), [1] Gaussians with a finite depth key (they sort first in a
+// view's depth order; those culled or off screen have an empty rectangle),
+// [2..3] pairs K of the view (u64).
 constexpr int kViewCounters = 4;
 
 // Finds the view owning global tile t (views hold ascending tile bases).
@@ -87,7 +89,7 @@ struct ProjectArgs {
     uint32_t* tiles_touched;
     ushort4* rect;
     uint32_t* view_counts;        // [n_views][kViewCounters]
-    uint32_t* partials;           // [blocks][n_views][2] per-block visible count and pairs
+    uint32_t* partials;           // [blocks][n_views][4] per-block counts: on screen, pairs, keyed
 };
 
 size_t project_partials_elems(int64_t n, int n_views);
@@ -101,11 +103,21 @@ bool depth_sort_items_supported(int items);
 size_t depth_sort_hist_elems(int64_t n, int n_views);   // enough for every supported width
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a,
                              uint32_t* keys_b, uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch,
-                             int64_t n, int n_views, int items, int* result_in_b, hipStream_t s);
+                             int64_t n, int n_views, int items, const uint32_t* reuse_words, int* result_in_b,
+                             hipStream_t s);
+// Reuse of the previous frame's order (one view, n items): reads the previous
+// order from vals_b and this frame's keys; leaves in vals_b this frame's
+// order when it can reach it cheaply, and in words[kReuseWords]: [0] 1 when
+// vals_b holds the sorted order (launch_depth_sort then skips its passes),
+// [1] descents of the previous order under this frame's keys, [2] the radix
+// scans' length (0 when skipped), [3] 1 when the local repair ran.
+constexpr int kReuseWords = 4;
+hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                              uint32_t* vals_b, int64_t n, int items, uint32_t* words, hipStream_t s);
 
 struct BinArgs {
     const uint32_t* sorted_idx;   // [n_views * n] items (v * n + i), each view's segment in (depth, index) order
-    const uint32_t* view_counts;  // device [n_views][kViewCounters]; visible items sort first in a segment
+    const uint32_t* view_counts;  // device [n_views][kViewCounters]; keyed items sort first in a segment
     const ushort4* rect;          // [n_views * n] tile rectangle of each item in its view
     int64_t n;                    // Gaussians per view
     int n_views;

@@ -70,7 +70,7 @@ struct Geometry {
 
 size_t project_partials_elems(int64_t n, int n_views)
 {
-    return (size_t)(2 * ((n + 255) / 256 + 1) * (size_t)(n_views > 0 ? n_views : 1));
+    return (size_t)(4 * ((n + 255) / 256 + 1) * (size_t)(n_views > 0 ? n_views : 1));
 }
 
 namespace {
@@ -215,13 +215,20 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
     double Sg[9];
     const bool cov_ok = world_covariance(l0, l1, l2, qw, qx, qy, qz, Sg);
     const float opacity = 1.0f / (1.0f + __expf(-logit));
-    __shared__ uint32_t s_vis[4], s_pairs[4];
+    __shared__ uint32_t s_vis[4], s_pairs[4], s_front[4];
 
     const int n_views = kOneView ? 1 : a.n_views;
     for (int v = 0; v < n_views; ++v) {
         const ViewParams& vp = a.views[v];
         Geometry g;
         const bool ok = cov_ok && project_view(vp, mxf, myf, mzf, Sg, g);
+        // the depth key: every Gaussian with a finite depth keeps one, on
+        // screen or not, culled or not (an off-screen or culled Gaussian
+        // yields no pair), so the depth order changes little between nearby
+        // frames even where Gaussians cross the screen edge or the near plane
+        // (see launch_order_reuse); t_z as project_view computes it
+        const double tz_key = ((vp.R[6] * (double)mxf + vp.R[7] * (double)myf) + vp.R[8] * (double)mzf) + vp.t[2];
+        const bool keyed = isfinite(tz_key);
 
         uint32_t tiles = 0;
         ushort4 rc = make_ushort4(0, 0, 0, 0);
@@ -272,7 +279,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
             dst[0] = sp.a;
             dst[1] = sp.b;
             dst[2] = sp.c;
-            a.depth_key[o] = tiles > 0 ? __float_as_uint((float)g.tz) : 0xFFFFFFFFu;
+            a.depth_key[o] = keyed ? __float_as_uint((float)tz_key) : 0xFFFFFFFFu;
             a.radius[o] = tiles > 0 ? g.radius : 0;
             a.tiles_touched[o] = tiles;
             a.rect[o] = rc;
@@ -282,17 +289,20 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
         // single counter hit by every wave serialises); reduce_partials_kernel
         // sums them
         const uint64_t vis = __ballot(tiles > 0);
+        const uint64_t front = __ballot(valid && keyed);
         uint32_t wave_pairs = tiles;
         for (int o = 32; o > 0; o >>= 1) wave_pairs += __shfl_xor(wave_pairs, o, 64);
         if ((threadIdx.x & 63) == 0) {
             s_vis[threadIdx.x >> 6] = (uint32_t)__popcll(vis);
             s_pairs[threadIdx.x >> 6] = wave_pairs;
+            s_front[threadIdx.x >> 6] = (uint32_t)__popcll(front);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            uint32_t* pp = a.partials + 2 * ((int64_t)blockIdx.x * a.n_views + v);
+            uint32_t* pp = a.partials + 4 * ((int64_t)blockIdx.x * a.n_views + v);
             pp[0] = s_vis[0] + s_vis[1] + s_vis[2] + s_vis[3];
             pp[1] = s_pairs[0] + s_pairs[1] + s_pairs[2] + s_pairs[3];
+            pp[2] = s_front[0] + s_front[1] + s_front[2] + s_front[3];
         }
         __syncthreads();   // s_vis / s_pairs are reused by the next view
     }
@@ -555,32 +565,36 @@ void launch_project_backward_dt(const ProjectBackArgs& a, unsigned blocks, hipSt
 
 }  // namespace
 
-// Per view (one block each): visible Gaussians and pairs, summed over the
-// projection blocks' partials.
+// Per view (one block each): Gaussians on screen, pairs and Gaussians with a
+// depth key (past the culls), summed over the projection blocks' partials.
 __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* __restrict__ partials, int blocks,
                                                                int n_views, uint32_t* view_counts)
 {
-    __shared__ unsigned long long sv[1024], sp[1024];
+    __shared__ unsigned long long sv[1024], sp[1024], sf[1024];
     const int v = blockIdx.x;
-    unsigned long long vis = 0, pairs = 0;
+    unsigned long long vis = 0, pairs = 0, front = 0;
     for (int b = threadIdx.x; b < blocks; b += 1024) {
-        vis += partials[2 * ((int64_t)b * n_views + v)];
-        pairs += partials[2 * ((int64_t)b * n_views + v) + 1];
+        const uint32_t* pp = partials + 4 * ((int64_t)b * n_views + v);
+        vis += pp[0];
+        pairs += pp[1];
+        front += pp[2];
     }
     sv[threadIdx.x] = vis;
     sp[threadIdx.x] = pairs;
+    sf[threadIdx.x] = front;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) {
             sv[threadIdx.x] += sv[threadIdx.x + o];
             sp[threadIdx.x] += sp[threadIdx.x + o];
+            sf[threadIdx.x] += sf[threadIdx.x + o];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         uint32_t* c = view_counts + (int64_t)kViewCounters * v;
         c[0] = (uint32_t)sv[0];
-        c[1] = 0u;
+        c[1] = (uint32_t)sf[0];
         c[2] = (uint32_t)sp[0];
         c[3] = (uint32_t)(sp[0] >> 32);
     }

@@ -86,7 +86,8 @@ __device__ __forceinline__ int wave_max(int v)
 // ------------------------------------------------------------------ level 1
 // items: depth-sorted Gaussians of one view; buckets: that view's tile rows;
 // payload (item, x-span).  Level-1 chunk c belongs to view c / chunks1 and is
-// part c % chunks1 of that view's visible items (which open its segment).
+// part c % chunks1 of that view's keyed items (which open its segment; those
+// culled or off screen have an empty rectangle).
 
 template <int kItems>
 struct Items1 {
@@ -96,7 +97,7 @@ struct Items1 {
     int view, part;    // view, chunk index within the view
 };
 
-// Visible-item range [start, end) of level-1 chunk c; false when empty.
+// Keyed-item range [start, end) of level-1 chunk c; false when empty.
 __device__ __forceinline__ bool chunk1_range(const BinArgs& a, int c, int* view, int* part, int64_t* start,
                                              int64_t* end)
 {
@@ -104,7 +105,9 @@ __device__ __forceinline__ bool chunk1_range(const BinArgs& a, int c, int* view,
     *part = c % a.chunks1;
     if (*view >= a.n_views) return false;
     const int64_t seg = (int64_t)(*view) * a.n;
-    const int64_t nv = (int64_t)a.view_counts[(int64_t)kViewCounters * (*view)];
+    // the view's keyed items (finite depth) open its segment; the culled or
+    // off-screen ones among them have an empty rectangle and yield no entry
+    const int64_t nv = (int64_t)a.view_counts[(int64_t)kViewCounters * (*view) + 1];
     *start = seg + (int64_t)(*part) * (a.items1 * 64);
     *end = seg + nv;
     return *start < *end;
@@ -124,8 +127,10 @@ __device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, I
         if (k < end) {
             g = a.sorted_idx[k];
             r = a.rect[g];
-            lo = (int)r.y < lo ? (int)r.y : lo;
-            hi = (int)r.w > hi ? (int)r.w : hi;
+            if (r.w > r.y) {   // an off-screen item spans no row
+                lo = (int)r.y < lo ? (int)r.y : lo;
+                hi = (int)r.w > hi ? (int)r.w : hi;
+            }
         }
         it.y0[b] = r.y;
         it.h[b] = (uint32_t)r.w - (uint32_t)r.y;
@@ -179,8 +184,10 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
         const int64_t k = start + b * 64 + lane;
         if (k < end) {
             const ushort4 r = a.rect[a.sorted_idx[k]];
-            atomicAdd(&diff[r.y], 1u);
-            atomicSub(&diff[r.w], 1u);
+            if (r.w > r.y) {
+                atomicAdd(&diff[r.y], 1u);
+                atomicSub(&diff[r.w], 1u);
+            }
         }
     }
     __syncthreads();

@@ -203,6 +203,14 @@ def ring_cameras(count: int, width: int, height: int, radius: float = 3.0) -> li
     return cams
 
 
+def orbit_camera(angle_deg: float, width: int, height: int, radius: float = 3.0) -> dict:
+    """Look-at camera on the same circle as ring_cameras at ``angle_deg``
+    degrees (0 = the default camera's eye): frames of an orbit, as in the
+    churn measurements of Sec. 5.7 (Table 5)."""
+    a = math.radians(angle_deg)
+    return look_at_camera((radius * math.sin(a), 0.0, -radius * math.cos(a)), width, height)
+
+
 def random_target(width: int, height: int, seed: int = 33) -> np.ndarray:
     """Uniform [0,1) target image ``[3, H, W]`` for an L2 loss."""
     return np.random.default_rng(seed).uniform(0.0, 1.0, (3, height, width)).astype(np.float32)

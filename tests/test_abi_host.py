@@ -56,6 +56,12 @@ def test_validate_accepts_good_arguments(lib):
     assert gs.validate(g, cam, 1, 1, opts, C.c_void_p(0x2000)) == gs.GS_OK
 
 
+def test_validate_accepts_the_reuse_flag(lib):
+    g, cam, opts = _valid_args()
+    opts.flags = gs.RENDER_REUSE_ORDER
+    assert gs.validate(g, cam, 64, 48, opts, C.c_void_p(0x2000)) == gs.GS_OK
+
+
 @pytest.mark.parametrize("case", ["null_out", "neg_n", "huge_n", "deg4", "deg_neg", "dtype", "null_attr",
                                   "w0", "h0", "w_big", "nan_cam", "inf_t", "fx0", "near0", "tile8",
                                   "flags", "nan_bg"])
@@ -94,7 +100,7 @@ def test_validate_rejects(lib, case):
     elif case == "tile8":
         opts.tile_size = 8
     elif case == "flags":
-        opts.flags = 1
+        opts.flags = 2          # only GS_RENDER_REUSE_ORDER (1) is defined
     elif case == "nan_bg":
         opts.background[1] = float("nan")
     st = gs.validate(g, cam, W, H, opts, out)
