@@ -13,8 +13,11 @@ constexpr float kLog2e = 1.4426950408889634f;
 // definite) over the box [x0, x0 + 7] x [y0, y0 + 7] of pixel offsets, made a
 // lower bound by subtracting 1e-5 of the size of its terms.  The form is
 // convex, so its minimum is 0 when the origin lies in the box and on an edge
-// otherwise; on an edge it is a 1D quadratic minimised in closed form.
-__device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, float B, float C)
+// otherwise; on an edge it is a 1D quadratic minimised in closed form, at
+// y = -(B / C) x or x = -(B / A) y (bc = B / C and ba = B / A, computed once
+// per entry: the rounding of the minimiser moves the value by a term
+// quadratic in that rounding, far inside the margin).
+__device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, float B, float C, float bc, float ba)
 {
     const float x1 = x0 + 7.0f, y1 = y0 + 7.0f;
     if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return 0.0f;
@@ -23,14 +26,14 @@ __device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, 
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         const float xe = xs[e];
-        const float y = fminf(y1, fmaxf(y0, -B * xe / C));
+        const float y = fminf(y1, fmaxf(y0, -bc * xe));
         const float qe = A * xe * xe + 2.0f * B * xe * y + C * y * y;
         if (qe < q) {
             q = qe;
             S = A * xe * xe + 2.0f * fabsf(B * xe * y) + C * y * y;
         }
         const float ye = ys[e];
-        const float x = fminf(x1, fmaxf(x0, -B * ye / A));
+        const float x = fminf(x1, fmaxf(x0, -ba * ye));
         const float qf = A * x * x + 2.0f * B * x * ye + C * ye * ye;
         if (qf < q) {
             q = qf;
@@ -54,10 +57,11 @@ __device__ __forceinline__ uint32_t stage_entry(const float4& ra, const float4& 
     const double dv = ((double)ra.y + (double)ra.w) - oy;
     const float du_hi = (float)du, dv_hi = (float)dv;
     uint32_t qmask = 0u;
+    const float bc = rb.y / rb.z, ba = rb.y / rb.x;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float qmin =
-            quad_min_over_box(du_hi - (float)((q & 1) * 8 + 7), dv_hi - (float)((q >> 1) * 8 + 7), rb.x, rb.y, rb.z);
+        const float qmin = quad_min_over_box(du_hi - (float)((q & 1) * 8 + 7), dv_hi - (float)((q >> 1) * 8 + 7), rb.x,
+                                             rb.y, rb.z, bc, ba);
         if (rb.w * __expf(-0.5f * qmin) >= (1.0f / 255.0f) * (1.0f - 1e-5f)) qmask |= 1u << q;
     }
     v0 = make_float4(du_hi, dv_hi, (float)(du - (double)du_hi), (float)(dv - (double)dv_hi));
