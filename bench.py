@@ -113,7 +113,7 @@ KERNEL_SOURCES = {
     "project_kernel": ["project.hip", "gs_internal.h"],
     "level1_scatter_kernel": ["tile_bin.hip", "gs_internal.h"],
     "level2_scatter_kernel": ["tile_bin.hip", "gs_internal.h"],
-    "blend_kernel": ["blend.hip", "gs_internal.h"],
+    "blend_kernel": ["blend.hip", "blend_stage.h", "gs_internal.h"],
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt")
 
