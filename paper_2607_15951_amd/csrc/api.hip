@@ -32,7 +32,7 @@ struct gs_context {
     std::string err;
     DevBuf splats, depth_key, radius, tiles_touched, rect;
     DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist, scan_scratch;
-    DevBuf bin_info, counts1, rows_off, row_ent, counts2, partials;
+    DevBuf bin_info, counts1, rows_off, row_ent, counts2, partials, sorted_rect;
     DevBuf views, row_tiles_x;   // device view table and tiles_x of every global tile row
     DevBuf view_counts;          // [n_views][kViewCounters] visible Gaussians and pairs per view
     DevBuf counters;             // [1] capacity overflow flag
@@ -253,6 +253,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     if ((st = ensure(ctx, ctx->radius, ni * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->tiles_touched, ni * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->rect, ni * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, ctx->sorted_rect, ni * 8)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->sort_ka, ni * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->sort_va, ni * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, ctx->sort_kb, ni * 4)) != GS_OK) return st;
@@ -302,6 +303,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     BinArgs ba{};
     ba.view_counts = view_counts;
     ba.rect = pa.rect;
+    ba.sorted_rect = static_cast<ushort4*>(ctx->sorted_rect.p);
     ba.n = n;
     ba.n_views = V;
     ba.views = views;
@@ -504,7 +506,8 @@ void gs_destroy(gs_context* ctx)
                       &ctx->sort_ka, &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb, &ctx->hist,
                       &ctx->scan_scratch, &ctx->bin_info, &ctx->counts1, &ctx->rows_off, &ctx->row_ent,
                       &ctx->counts2, &ctx->partials, &ctx->views, &ctx->row_tiles_x, &ctx->view_counts,
-                      &ctx->counters, &ctx->tile_offsets, &ctx->values, &ctx->tile_work};
+                      &ctx->counters, &ctx->tile_offsets, &ctx->values, &ctx->tile_work, &ctx->sorted_rect,
+                      &ctx->reuse_words};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->host_info) (void)hipHostFree(ctx->host_info);

@@ -119,6 +119,7 @@ struct BinArgs {
     const uint32_t* sorted_idx;   // [n_views * n] items (v * n + i), each view's segment in (depth, index) order
     const uint32_t* view_counts;  // device [n_views][kViewCounters]; keyed items sort first in a segment
     const ushort4* rect;          // [n_views * n] tile rectangle of each item in its view
+    ushort4* sorted_rect;         // [n_views * n] the same in depth order (keyed items; written by the row count)
     int64_t n;                    // Gaussians per view
     int n_views;
     const ViewParams* views;      // device table

@@ -126,7 +126,7 @@ __device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, I
         uint32_t g = 0;
         if (k < end) {
             g = a.sorted_idx[k];
-            r = a.rect[g];
+            r = a.sorted_rect[k];
             if (r.w > r.y) {   // an off-screen item spans no row
                 lo = (int)r.y < lo ? (int)r.y : lo;
                 hi = (int)r.w > hi ? (int)r.w : hi;
@@ -183,7 +183,9 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
     for (int b = 0; b < kItems; ++b) {
         const int64_t k = start + b * 64 + lane;
         if (k < end) {
+            // the rectangles in depth order, for the scatter to stream
             const ushort4 r = a.rect[a.sorted_idx[k]];
+            a.sorted_rect[k] = r;
             if (r.w > r.y) {
                 atomicAdd(&diff[r.y], 1u);
                 atomicSub(&diff[r.w], 1u);
