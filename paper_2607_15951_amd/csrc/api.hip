@@ -32,7 +32,7 @@ struct gs_context {
     std::string err;
     DevBuf splats, depth_key, radius, tiles_touched, rect;
     DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist, scan_scratch;
-    DevBuf bin_info, counts1, rows_off, row_ent, counts2, partials, sorted_rect;
+    DevBuf bin_info, counts1, rows_off, row_ent, counts2, partials, sorted_rect, readback;
     DevBuf views, row_tiles_x;   // device view table and tiles_x of every global tile row
     DevBuf view_counts;          // [n_views][kViewCounters] visible Gaussians and pairs per view
     DevBuf counters;             // [1] capacity overflow flag
@@ -208,6 +208,19 @@ hipError_t write_view_table(const std::vector<ViewParams>& hv, ViewParams* dst, 
 }
 
 // tiles_x of every global tile row (rows of view v are [row_base, row_base + tiles_y))
+// The eager render's host read gathered for one copy: the view counters
+// ([n][kViewCounters]), then counters[0..3], R and the level-2 chunk and
+// count-element totals.
+constexpr int kReadbackTail = 7;
+__global__ void pack_readback_kernel(const uint32_t* view_counts, int n_vc, const uint32_t* counters,
+                                     const uint32_t* r_total, const uint32_t* info, uint32_t* out)
+{
+    for (int i = threadIdx.x; i < n_vc + kReadbackTail; i += blockDim.x) {
+        const int t = i - n_vc;
+        out[i] = i < n_vc ? view_counts[i] : (t < 4 ? counters[t] : (t == 4 ? *r_total : info[t - 5]));
+    }
+}
+
 __global__ void row_table_kernel(const ViewParams* views, int n_views, uint32_t* row_tiles_x, int rows)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -356,15 +369,18 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
 
     int grid2 = ba.max_chunks2;
     if (capacity == 0) {
-        // eager: one host read of the per-view pairs, R and the level-2 sizes
+        // eager: one host read (one copy) of the per-view pairs, R and the
+        // level-2 sizes
         uint32_t* hi = ctx->host_info;
-        HIP_TRY(hipMemcpyAsync(hi, view_counts, (size_t)V * kViewCounters * 4, hipMemcpyDeviceToHost, s),
-                "read view counts");
-        uint32_t* tail = hi + (size_t)kMaxViews * kViewCounters;
-        HIP_TRY(hipMemcpyAsync(tail, counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read counters");
-        HIP_TRY(hipMemcpyAsync(tail + 4, ba.rows_off + rows, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read R");
-        HIP_TRY(hipMemcpyAsync(tail + 5, ba.info, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read sizes");
+        const int n_vc = V * kViewCounters;
+        if ((st = ensure(ctx, ctx->readback, (size_t)(n_vc + kReadbackTail) * 4)) != GS_OK) return st;
+        uint32_t* rb = static_cast<uint32_t*>(ctx->readback.p);
+        hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, s, (const uint32_t*)view_counts, n_vc,
+                           (const uint32_t*)counters, (const uint32_t*)(ba.rows_off + rows), (const uint32_t*)ba.info,
+                           rb);
+        HIP_TRY(hipMemcpyAsync(hi, rb, (size_t)(n_vc + kReadbackTail) * 4, hipMemcpyDeviceToHost, s), "read sizes");
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        uint32_t* tail = hi + n_vc;
         uint64_t K64 = 0;
         for (int v = 0; v < V; ++v) {
             const uint32_t* c = hi + (size_t)v * kViewCounters;
@@ -507,7 +523,7 @@ void gs_destroy(gs_context* ctx)
                       &ctx->scan_scratch, &ctx->bin_info, &ctx->counts1, &ctx->rows_off, &ctx->row_ent,
                       &ctx->counts2, &ctx->partials, &ctx->views, &ctx->row_tiles_x, &ctx->view_counts,
                       &ctx->counters, &ctx->tile_offsets, &ctx->values, &ctx->tile_work, &ctx->sorted_rect,
-                      &ctx->reuse_words};
+                      &ctx->reuse_words, &ctx->readback};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->host_info) (void)hipHostFree(ctx->host_info);
