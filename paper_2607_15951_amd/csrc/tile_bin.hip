@@ -453,7 +453,7 @@ __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
 // every column's cursor stays in a scalar register.  cur_b holds the cursors
 // (lane q: column bx0 + q).
 template <bool kChecked>
-__device__ __forceinline__ void walk_band(const uint32_t* s_g, const uint32_t* s_x, uint32_t n, uint32_t bx0,
+__device__ __forceinline__ void walk_band(const uint32_t* s_g, const uint16_t* s_x, uint32_t n, uint32_t bx0,
                                           uint32_t cur_b, uint32_t* __restrict__ out, uint64_t capacity, int lane)
 {
     uint32_t cur[kBand];
@@ -466,12 +466,12 @@ __device__ __forceinline__ void walk_band(const uint32_t* s_g, const uint32_t* s
             xs = s_x[k];
             g = s_g[k];
         }
-        const uint32_t x0 = xs & 0xFFFFu, w = (xs >> 16) - x0;
-        // all kBand columns: packed entries are clipped to the band and to
-        // the image, so a column outside them is never covered
+        // band-relative span [x0, x0 + w): packed entries are clipped to the
+        // band and to the image, so a column outside them is never covered
+        const uint32_t x0 = xs & 31u, w = (xs >> 5) - x0;
 #pragma unroll
         for (int q = 0; q < kBand; ++q) {
-            const bool cover = bx0 + q - x0 < w;
+            const bool cover = (uint32_t)q - x0 < w;
             const uint64_t m = __ballot(cover);
             if (cover) {
                 const uint32_t pos = cur[q] + lanes_below(m);
@@ -489,7 +489,7 @@ __device__ __forceinline__ void walk_band(const uint32_t* s_g, const uint32_t* s
 // and only those batches walk the band's columns.  Inside a column the
 // entries keep their chunk order, so the output is that of the plain walk.
 template <int kItems>
-__device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, int lane, uint32_t* s_g, uint32_t* s_x)
+__device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, int lane, uint32_t* s_g, uint16_t* s_x)
 {
     Items2<kItems> it;
     if (!load_items2(a, c, lane, it)) return;
@@ -514,7 +514,7 @@ __device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, in
             if (reach) {
                 const uint32_t slot = n + lanes_below(m);
                 s_g[slot] = it.g[j];
-                s_x[slot] = e0 | (e1 << 16);
+                s_x[slot] = (uint16_t)((e0 - bx0) | ((e1 - bx0) << 5));   // 0 <= e0 < e1 <= kBand
             }
             n += (uint32_t)__popcll(m);
         }
@@ -533,7 +533,8 @@ __device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, in
 template <int kItems>
 __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
 {
-    __shared__ uint32_t s_g[kItems * 64], s_x[kItems * 64];
+    __shared__ uint32_t s_g[kItems * 64];
+    __shared__ uint16_t s_x[kItems * 64];
     const int lane = threadIdx.x;
     const int c2 = (int)a.info[kInfoC2];
     for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_scatter_chunk<kItems>(a, c, lane, s_g, s_x);
