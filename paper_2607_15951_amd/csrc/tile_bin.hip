@@ -343,8 +343,8 @@ __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
 
 template <int kItems>
 struct Items2 {
-    // columns [x0, x0 + w) covered; w = 0 for padding lanes
-    uint32_t x0[kItems], w[kItems], g[kItems];
+    // columns [x0, x1) covered, packed x0 | x1 << 16; empty for padding lanes
+    uint32_t xs[kItems], g[kItems];
     int row, lo, hi;   // row, columns spanned by the chunk
     const uint32_t* cursor;   // column x's cursor at cursor[x * stride]
     int64_t stride;           // the row's level-2 chunks
@@ -401,8 +401,7 @@ __device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, I
             lo = x0 < lo ? x0 : lo;
             hi = x1 > hi ? x1 : hi;
         }
-        it.x0[b] = ent.y & 0xFFFFu;
-        it.w[b] = (ent.y >> 16) - (ent.y & 0xFFFFu);
+        it.xs[b] = ent.y;
         it.g[b] = ent.x;
     }
     it.lo = __builtin_amdgcn_readfirstlane(wave_min(lo));   // uniform: keep it scalar
@@ -508,7 +507,7 @@ __device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, in
         uint32_t n = 0;
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
-            const uint32_t e0 = max(it.x0[j], bx0), e1 = min(it.x0[j] + it.w[j], bx1);
+            const uint32_t e0 = max(it.xs[j] & 0xFFFFu, bx0), e1 = min(it.xs[j] >> 16, bx1);
             const bool reach = e1 > e0;
             const uint64_t m = __ballot(reach);
             if (reach) {
