@@ -255,8 +255,11 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     const int64_t items = n * V;
     const int rows = (int)(hv.back().row_base + hv.back().tiles_y);
     const int64_t T = (int64_t)hv.back().tile_base + (int64_t)hv.back().tiles_x * hv.back().tiles_y;
-    int max_tx = 0;
-    for (const ViewParams& v : hv) max_tx = std::max(max_tx, v.tiles_x);
+    int max_tx = 0, max_ty = 0;
+    for (const ViewParams& v : hv) {
+        max_tx = std::max(max_tx, v.tiles_x);
+        max_ty = std::max(max_ty, v.tiles_y);
+    }
     const size_t ni = (size_t)(items > 0 ? items : 1);
     const Tuning tu = ctx->tuning;
     const int chunks1 = std::max(bin_level1_chunks(n, tu.bin1_items), 1);
@@ -322,6 +325,8 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ba.views = views;
     ba.row_tiles_x = static_cast<const uint32_t*>(ctx->row_tiles_x.p);
     ba.rows = rows;
+    ba.max_tiles_x = max_tx;
+    ba.max_tiles_y = max_ty;
     ba.tiles = T;
     ba.items1 = tu.bin1_items;
     ba.items2 = tu.bin2_items;

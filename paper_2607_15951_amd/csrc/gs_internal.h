@@ -11,7 +11,7 @@ namespace gsmi {
 
 constexpr int kTile = 16;                 // screen tile edge in pixels
 constexpr int kTilePixels = kTile * kTile;
-constexpr int kMaxBandTiles = 2048;       // LDS cursors per binning wave
+constexpr int kMaxBandTiles = 2048;       // tile columns per image (width <= 32768)
 constexpr int kSortBlock = 256;           // threads of a depth-sort block
 constexpr int kTileWorkFields = 6;        // u64 fields of a per-tile blend trace record
 
@@ -125,6 +125,7 @@ struct BinArgs {
     const ViewParams* views;      // device table
     const uint32_t* row_tiles_x;  // [rows] tiles_x of each global tile row
     int rows;                     // global tile rows (sum of the views' tiles_y)
+    int max_tiles_x, max_tiles_y; // largest tiles_x and tiles_y of the views
     int64_t tiles;                // global tiles (sum of the views' tiles)
     int items1, items2;           // items per lane of a level-1 / level-2 wave (Tuning)
     int chunks1;                  // level-1 chunks per view, bin_level1_chunks(n, items1)

@@ -169,7 +169,7 @@ __device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, ui
 template <int kItems>
 __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
 {
-    __shared__ uint32_t diff[kMaxRows + 1];
+    extern __shared__ uint32_t diff[];   // [max_tiles_y + 1], sized at launch
     const int lane = threadIdx.x, c = chunk_of_block();
     const int view = c / a.chunks1, part = c % a.chunks1;
     if (view >= a.n_views) return;
@@ -441,7 +441,7 @@ __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int 
 template <int kItems>
 __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
 {
-    __shared__ uint32_t diff[kMaxBandTiles + 1];
+    extern __shared__ uint32_t diff[];   // [max_tiles_x + 1], sized at launch: more waves fit
     const int lane = threadIdx.x;
     const int c2 = (int)a.info[kInfoC2];
     for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_count_chunk<kItems>(a, c, lane, diff);
@@ -615,7 +615,8 @@ hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t
     if (!bin_items_supported(a.items1, a.items2)) return hipErrorInvalidValue;
     const int grid1 = a.chunks1 * a.n_views;
     with_items1(a.items1, [&](auto I) {
-        hipLaunchKernelGGL(level1_count_kernel<decltype(I)::value>, dim3(grid8(grid1)), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(level1_count_kernel<decltype(I)::value>, dim3(grid8(grid1)), dim3(64),
+                           (a.max_tiles_y + 1) * sizeof(uint32_t), s, a);
     });
     hipError_t e = launch_scan_exclusive(a.counts1, (int64_t)a.rows * a.chunks1, scan_scratch, nullptr,
                                          a.rows_off + a.rows, a.overflow, s);
@@ -642,7 +643,7 @@ hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch,
     if (grid2 > 0)
         with_items2(a.items2, [&](auto I) {
             hipLaunchKernelGGL(level2_count_kernel<decltype(I)::value>, dim3(grid8(std::min(grid2, kMaxGrid2))),
-                               dim3(64), 0, s, a);
+                               dim3(64), (a.max_tiles_x + 1) * sizeof(uint32_t), s, a);
         });
     // the scan's length E2 is read on the device (info[1])
     hipError_t e = launch_scan_exclusive(a.counts2, (int64_t)a.counts2_capacity, scan_scratch, nullptr,
