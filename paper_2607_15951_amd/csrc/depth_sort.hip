@@ -75,9 +75,12 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
 // Each wave ranks its items of a round among equal digits with eight ballots
 // (lanes holding the same digit) and records the group's size in
 // cnt[k][w][d]; one pass of 256 threads (one per digit) turns those counts
-// into exclusive offsets in (k, w) order, and every item lands at
-// base[d] + cnt[k][w][d] + (lanes of its group below it) -- two barriers per
-// block instead of a hand-over per (round, wave).
+// into exclusive offsets in (k, w) order and the digits' totals into the
+// block's digit starts.  Every item is then placed in LDS at its position in
+// the block's stable digit order, and the block writes that order out with
+// consecutive threads on consecutive positions of each digit's run: item i of
+// digit d goes to base[d] + (i - start[d]).  The global writes come as whole
+// runs instead of one scattered word per lane.
 template <int kItems>
 __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
@@ -85,7 +88,8 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint32_t* skip)
 {
     if (skip && *skip) return;
-    __shared__ uint32_t cnt[kItems][4][256];
+    __shared__ uint32_t cnt[kItems][4][256];   // then the block's keys and values in digit order
+    __shared__ uint32_t s_start[256], s_base[256], s_wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int64_t begin, end, row;
     sort_block_range<kItems>(n, bpv, &begin, &end, &row);
@@ -115,8 +119,9 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
         if (valid && rank[k] == 0) cnt[k][wave][d] = (uint32_t)__popcll(m);
     }
     __syncthreads();
-    {   // thread d: exclusive prefix of digit d over (round, wave), plus the block's base
-        uint32_t run = offsets[row + (int64_t)tid * bpv];
+    {   // thread d: exclusive offsets of digit d over (round, wave), its total,
+        // and the block's digit start (exclusive prefix of the totals)
+        uint32_t run = 0u;
 #pragma unroll
         for (int k = 0; k < kItems; ++k)
 #pragma unroll
@@ -125,15 +130,42 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
                 cnt[k][w][tid] = run;
                 run += c;
             }
+        uint32_t incl = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) s_wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0u;
+        for (int w = 0; w < wave; ++w) before += s_wsum[w];
+        s_start[tid] = before + incl - run;
+        s_base[tid] = offsets[row + (int64_t)tid * bpv];
     }
     __syncthreads();
+    uint32_t local[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        local[k] = digit[k] < 256u ? s_start[digit[k]] + cnt[k][wave][digit[k]] + rank[k] : ~0u;
+    __syncthreads();   // cnt is reused below
+    uint32_t* s_key = &cnt[0][0][0];
+    uint32_t* s_val = s_key + kItems * kSortBlock;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        if (digit[k] < 256u) {
-            const uint32_t pos = cnt[k][wave][digit[k]] + rank[k];
-            keys_out[pos] = key[k];
-            vals_out[pos] = val[k];
+        if (local[k] != ~0u) {
+            s_key[local[k]] = key[k];
+            s_val[local[k]] = val[k];
         }
+    }
+    __syncthreads();
+    const int count = (int)(end - begin);
+    for (int i = tid; i < count; i += kSortBlock) {
+        const uint32_t kk = s_key[i];
+        const uint32_t d = (sort_key(kk) >> shift) & 255u;
+        const uint32_t pos = s_base[d] + ((uint32_t)i - s_start[d]);
+        keys_out[pos] = kk;
+        vals_out[pos] = s_val[i];
     }
 }
 
