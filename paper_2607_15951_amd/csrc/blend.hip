@@ -148,23 +148,21 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
                 const float4 e0 = s0[j];
                 const float4 e1 = s1[j];
                 const float4 e2 = s2[j];
-                const float dx = (e0.x - fx) + e0.z;
-                const float dy = (e0.y - fy) + e0.w;
-                const float pw = fmaf(e1.x * dx, dx, fmaf(e1.z * dy, dy, (e1.y * dx) * dy));
-                const float al = fminf(0.99f, e1.w * __builtin_amdgcn_exp2f(pw));
+                float dx, dy, E;
+                const float al = entry_alpha(e0, e1, fx, fy, dx, dy, E);
                 const float tn = Tr * (1.0f - al);
                 const bool pass = al >= 1.0f / 255.0f;
                 const bool stop = pass && tn < 1e-4f && !done;
                 const bool take = pass && !stop && !done;
-                const uint32_t pos = (uint32_t)__float_as_int(e2.w);
-                if (kStats) term = stop ? pos + 1u : term;
+                const uint32_t pos1 = (uint32_t)__float_as_int(e2.w);   // list position + 1
+                if (kStats) term = stop ? pos1 : term;
                 done = done || stop;
                 const float wgt = take ? al * Tr : 0.0f;
                 c0 = fmaf(wgt, e2.x, c0);
                 c1 = fmaf(wgt, e2.y, c1);
                 c2 = fmaf(wgt, e2.z, c2);
                 Tr = take ? tn : Tr;
-                last = take ? pos + 1u : last;
+                last = take ? pos1 : last;
                 if (kStats) composited += take ? 1u : 0u;
             }
         }

@@ -159,14 +159,11 @@ __global__ __launch_bounds__(256) void blend_backward_kernel(BlendBackArgs a, ui
             if (!((bits[j >> 6] >> (j & 63)) & 1u)) continue;
             if (__ballot(!done) == 0) break;   // every pixel of the wave is past its last entry
             const float4 e0 = s0[j], e1 = s1[j], e2 = s2[j];
-            const uint32_t pos = (uint32_t)__float_as_int(e2.w);
-            if (!done && pos >= nc) done = true;
-            const float dx = (e0.x - fx) + e0.z;
-            const float dy = (e0.y - fy) + e0.w;
-            const float pw = fmaf(e1.x * dx, dx, fmaf(e1.z * dy, dy, (e1.y * dx) * dy));
-            const float E = __builtin_amdgcn_exp2f(pw);
+            const uint32_t pos1 = (uint32_t)__float_as_int(e2.w);   // list position + 1
+            if (!done && pos1 > nc) done = true;                      // past the pixel's last entry
+            float dx, dy, E;
+            const float al = entry_alpha(e0, e1, fx, fy, dx, dy, E);
             const float araw = e1.w * E;
-            const float al = fminf(0.99f, araw);
             const bool take = !done && al >= 1.0f / 255.0f;
             float g[kGrad2d];
 #pragma unroll

@@ -49,7 +49,8 @@ __device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, 
 // exp2(A' dx^2 + B' dx dy + C' dy^2)) and opacity, v2 = colour and the list
 // position.  Returns the 4-bit mask of the tile's 8x8 quads in which the entry
 // can reach alpha 1/255 (a conservative bound: an entry outside it is skipped
-// by every pixel of the quad).
+// by every pixel of the quad).  v2.w holds the list position plus one (the
+// n_contrib a pixel reports when this is its last composited entry).
 __device__ __forceinline__ uint32_t stage_entry(const float4& ra, const float4& rb, const float4& rc, double ox,
                                                 double oy, uint32_t pos, float4& v0, float4& v1, float4& v2)
 {
@@ -66,8 +67,23 @@ __device__ __forceinline__ uint32_t stage_entry(const float4& ra, const float4& 
     }
     v0 = make_float4(du_hi, dv_hi, (float)(du - (double)du_hi), (float)(dv - (double)dv_hi));
     v1 = make_float4(-0.5f * kLog2e * rb.x, -kLog2e * rb.y, -0.5f * kLog2e * rb.z, rb.w);
-    v2 = make_float4(rc.x, rc.y, rc.z, __int_as_float((int)pos));
+    v2 = make_float4(rc.x, rc.y, rc.z, __int_as_float((int)(pos + 1u)));
     return qmask;
+}
+
+// Alpha of a staged entry (e0, e1) at the pixel with tile offset (fx, fy),
+// shared by the forward and the backward so that both take the same
+// decisions: the offset to the centre as (hi - pixel) + lo, then
+// opacity * E with E = exp2(dx (A' dx + B' dy) + C' dy^2), clamped to 0.99.
+// Returns alpha; dx, dy and the falloff E (for the backward) on the side.
+__device__ __forceinline__ float entry_alpha(const float4& e0, const float4& e1, float fx, float fy, float& dx,
+                                             float& dy, float& E)
+{
+    dx = (e0.x - fx) + e0.z;
+    dy = (e0.y - fy) + e0.w;
+    const float pw = fmaf(fmaf(e1.x, dx, e1.y * dy), dx, (e1.z * dy) * dy);
+    E = __builtin_amdgcn_exp2f(pw);
+    return fminf(0.99f, e1.w * E);
 }
 
 // Workgroup -> tile: tiles are cut into groups of `group` consecutive tiles
