@@ -343,10 +343,10 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ba.row_capacity = capacity ? capacity : ~0ull;
     ba.max_chunks2 = capacity ? bin_level2_chunk_bound(capacity, rows, tu.bin2_items) : (1 << 30);
     ba.counts2_capacity = capacity ? (uint64_t)ba.max_chunks2 * max_tx : ~0ull;
-    // scan lengths: depth-sort digit counts, level-1 counts, tile offsets and
+    // scan lengths: level-1 counts, tile offsets and
     // (pair_capacity > 0) the level-2 counts; the eager path grows the scratch
     // for the level-2 counts after its host read
-    int64_t scan_max = std::max<int64_t>({T + 1, (int64_t)depth_sort_hist_elems(n, V), (int64_t)rows * chunks1});
+    int64_t scan_max = std::max<int64_t>(T + 1, (int64_t)rows * chunks1);
     if (capacity) scan_max = std::max<int64_t>(scan_max, (int64_t)ba.counts2_capacity);
     if ((st = ensure(ctx, ctx->scan_scratch, scan_scratch_elems(scan_max) * 8)) != GS_OK) return st;
     uint64_t* scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
@@ -359,13 +359,13 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
         reuse_words = static_cast<uint32_t*>(ctx->reuse_words.p);
         HIP_TRY(launch_order_reuse(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
                                    static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
-                                   static_cast<uint32_t*>(ctx->sort_vb.p), n, tu.sort_items, reuse_words, s),
+                                   static_cast<uint32_t*>(ctx->sort_vb.p), n, reuse_words, s),
                 "order reuse");
     }
     HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
                               static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
-                              static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p),
-                              scan_scratch, n, V, tu.sort_items, reuse_words, &in_b, s),
+                              static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p), n, V,
+                              tu.sort_items, reuse_words, &in_b, s),
             "depth sort");
     ba.sorted_idx = static_cast<const uint32_t*>(in_b ? ctx->sort_vb.p : ctx->sort_va.p);
     STAGE_MARK(2);

@@ -10,10 +10,13 @@
 // Several views are sorted at once as segments of one array (one segment per
 // view, items v * n + i); no block straddles two segments.
 //
-// Each 8-bit pass is reduce-then-scan: an LDS histogram per block, one
-// exclusive scan of the digit-major [segment][digit][block] table, and a stable
-// scatter that ranks equal digits with wavefront ballots (lower lanes and
-// earlier waves first).  Digits are taken from sort_key(key), which orders
+// Each 8-bit pass is reduce-then-scan in three launches: an LDS histogram
+// per block into the digit-major [segment][digit][block] table, one
+// workgroup per (segment, digit) that scans its row of the table and records
+// the digit's total, and a stable scatter that ranks equal digits with
+// wavefront ballots (lower lanes and earlier waves first) and places digit d
+// of segment v at v * n + (totals of the smaller digits) + (its row's
+// exclusive prefix).  Digits are taken from sort_key(key), which orders
 // depths as numbers (negative ones, behind the camera, first); keys of
 // Gaussians without a finite depth are 0xFFFFFFFF and sink to the end.
 // Values start as the Gaussian index, so ties in depth stay in index order.
@@ -24,8 +27,8 @@ namespace {
 
 // Block b sorts part lb = b % bpv of segment v = b / bpv: items
 // [v * n + lb * tile, min(.. + tile, (v + 1) * n)), tile = kSortBlock * kItems.
-// The digit table is [segment][digit][part], so its exclusive scan keeps the
-// segments apart and stable within each.
+// The count buffer holds the digit totals [segment][digit] (kDigitTotals
+// per segment) followed by the digit table [segment][digit][part].
 template <int kItems>
 __device__ __forceinline__ void sort_block_range(int64_t n, int bpv, int64_t* begin, int64_t* end, int64_t* row)
 {
@@ -55,7 +58,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
 {
     if (skip && *skip) return;   // the previous frame's order was reused
     __shared__ uint32_t h[4][256];   // one private histogram per wave
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 #pragma unroll
     for (int w = 0; w < 4; ++w) h[w][tid] = 0;
     __syncthreads();
@@ -64,10 +67,65 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int64_t idx = begin + k * kSortBlock + tid;
-        if (idx < end) atomicAdd(&h[wave][(sort_key(keys[idx]) >> shift) & 255u], 1u);
+        const bool valid = idx < end;
+        const uint32_t d = valid ? (sort_key(keys[idx]) >> shift) & 255u : 0u;
+        const uint64_t m = __ballot(valid);
+        if (m == 0) continue;
+        // the high digits of nearby depths are mostly one value: a wave whose
+        // items share it counts them with one atomic instead of 64 colliding
+        const int first = __ffsll((long long)m) - 1;
+        const uint32_t d0 = (uint32_t)__shfl((int)d, first, 64);
+        if (__ballot(valid && d != d0) == 0) {
+            if (lane == first) atomicAdd(&h[wave][d0], (uint32_t)__popcll(m));
+        } else if (valid) {
+            atomicAdd(&h[wave][d], 1u);
+        }
     }
     __syncthreads();
     hist[row + (int64_t)tid * bpv] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+}
+
+// Workgroup (v, d): exclusive scan, in place, of digit d's row of segment v
+// (bpv block counts), and the digit's total in totals[v * 256 + d].  Counts
+// fit 32 bits (n_views * n < 2^32).
+constexpr int kScanRowItems = 8;
+__global__ __launch_bounds__(256) void radix_row_scan_kernel(uint32_t* __restrict__ table, uint32_t* __restrict__ totals,
+                                                              int bpv, const uint32_t* skip)
+{
+    if (skip && *skip) return;
+    __shared__ uint32_t s_wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t* row = table + (int64_t)blockIdx.x * bpv;
+    uint32_t carry = 0u;
+    for (int base = 0; base < bpv; base += 256 * kScanRowItems) {
+        uint32_t x[kScanRowItems], run = 0u;
+        const int j0 = base + tid * kScanRowItems;   // this thread's consecutive counts
+#pragma unroll
+        for (int k = 0; k < kScanRowItems; ++k) {
+            x[k] = (j0 + k < bpv) ? row[j0 + k] : 0u;
+            run += x[k];
+        }
+        uint32_t incl = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) s_wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += s_wsum[w];
+        const uint32_t chunk_total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+        uint32_t acc = before + incl - run;
+#pragma unroll
+        for (int k = 0; k < kScanRowItems; ++k) {
+            if (j0 + k < bpv) row[j0 + k] = acc;
+            acc += x[k];
+        }
+        carry += chunk_total;
+        __syncthreads();   // s_wsum is reused by the next chunk
+    }
+    if (tid == 0) totals[blockIdx.x] = carry;
 }
 
 // Stable scatter of one block's items.  Item (round k, wave w, lane l) is
@@ -84,12 +142,12 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
 template <int kItems>
 __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, int64_t n, int shift, const uint32_t* __restrict__ offsets, int bpv,
-    const uint32_t* skip)
+    uint32_t* __restrict__ vals_out, int64_t n, int shift, const uint32_t* __restrict__ offsets,
+    const uint32_t* __restrict__ totals, int bpv, const uint32_t* skip)
 {
     if (skip && *skip) return;
     __shared__ uint32_t cnt[kItems][4][256];   // then the block's keys and values in digit order
-    __shared__ uint32_t s_start[256], s_base[256], s_wsum[4];
+    __shared__ uint32_t s_start[256], s_base[256], s_wsum[4], s_ssum[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int64_t begin, end, row;
     sort_block_range<kItems>(n, bpv, &begin, &end, &row);
@@ -120,7 +178,10 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     }
     __syncthreads();
     {   // thread d: exclusive offsets of digit d over (round, wave), its total,
-        // and the block's digit start (exclusive prefix of the totals)
+        // and the block's digit start (exclusive prefix of the totals); then
+        // the segment's start of digit d (exclusive prefix of its totals)
+        const int v = (int)(blockIdx.x / (unsigned)bpv);
+        const uint32_t seg_total = totals[v * 256 + tid];
         uint32_t run = 0u;
 #pragma unroll
         for (int k = 0; k < kItems; ++k)
@@ -130,18 +191,27 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
                 cnt[k][w][tid] = run;
                 run += c;
             }
-        uint32_t incl = run;
+        uint32_t incl = run, seg_incl = seg_total;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t t = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += t;
+            const uint32_t t = __shfl_up(incl, o, 64), u = __shfl_up(seg_incl, o, 64);
+            if (lane >= o) {
+                incl += t;
+                seg_incl += u;
+            }
         }
-        if (lane == 63) s_wsum[wave] = incl;
+        if (lane == 63) {
+            s_wsum[wave] = incl;
+            s_ssum[wave] = seg_incl;
+        }
         __syncthreads();
-        uint32_t before = 0u;
-        for (int w = 0; w < wave; ++w) before += s_wsum[w];
+        uint32_t before = 0u, seg_before = (uint32_t)((int64_t)v * n);
+        for (int w = 0; w < wave; ++w) {
+            before += s_wsum[w];
+            seg_before += s_ssum[w];
+        }
         s_start[tid] = before + incl - run;
-        s_base[tid] = offsets[row + (int64_t)tid * bpv];
+        s_base[tid] = seg_before + seg_incl - seg_total + offsets[row + (int64_t)tid * bpv];
     }
     __syncthreads();
     uint32_t local[kItems];
@@ -169,17 +239,21 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     }
 }
 
+// One 8-bit pass: histogram, row scans, scatter.  counts = totals
+// [n_views][256] then the table.
 template <int kItems>
-void launch_sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* hist,
-                      int64_t n, int shift, int bpv, unsigned nblocks, bool histogram_only, const uint32_t* skip,
+void launch_sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* counts,
+                      int64_t n, int n_views, int shift, int bpv, unsigned nblocks, const uint32_t* skip,
                       hipStream_t s)
 {
-    if (histogram_only)
-        hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, hist, bpv,
-                           skip);
-    else
-        hipLaunchKernelGGL(radix_scatter_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
-                           n, shift, hist, bpv, skip);
+    uint32_t* totals = counts;
+    uint32_t* table = counts + (int64_t)256 * n_views;
+    hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, table, bpv,
+                       skip);
+    hipLaunchKernelGGL(radix_row_scan_kernel, dim3(256u * (unsigned)n_views), dim3(256), 0, s, table, totals, bpv,
+                       skip);
+    hipLaunchKernelGGL(radix_scatter_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n,
+                       shift, (const uint32_t*)table, (const uint32_t*)totals, bpv, skip);
 }
 
 // ------------------------------------------------- reuse of the previous order
@@ -205,9 +279,8 @@ constexpr int kReuseBlock = kReuseThreads * kReuseItems;   // items sorted toget
 
 // The gathered keys are sort keys (sort_key), as the radix passes compare.
 // words[0] = 1 while the reused order holds (the radix passes' skip flag),
-// words[1] = descents of the gathered previous order (churn), words[2] = the
-// radix scans' length (0 when skipped), words[3] = 1 when the local repair
-// runs.  A repair is tried for at most n / kRepairFraction descents.
+// words[1] = descents of the gathered previous order (churn), words[2] = 1
+// when the local repair runs.  A repair is tried for at most n / kRepairFraction descents.
 constexpr int64_t kRepairFraction = 256;
 // Grid-stride, so that the descent count takes one atomic per block: an
 // atomic per wave on one counter serialises when most pairs swap.
@@ -255,7 +328,7 @@ __global__ __launch_bounds__(kReuseThreads) void order_local_sort_kernel(const u
                                                                         int64_t n, uint32_t* k_out, uint32_t* v_out,
                                                                         const uint32_t* words)
 {
-    if (!words[3]) return;   // no repair this frame
+    if (!words[2]) return;   // no repair this frame
     __shared__ uint64_t s[kReuseBlock];
     const int tid = threadIdx.x;
     const int64_t half = kReuseBlock / 2;
@@ -308,7 +381,7 @@ __global__ void order_plan_kernel(uint32_t* words, int64_t n)
     const uint32_t d = words[1];
     const bool valid = words[0] != 0u;
     const bool repair = valid && d > 0u && (int64_t)d <= n / kRepairFraction;
-    words[3] = repair ? 1u : 0u;
+    words[2] = repair ? 1u : 0u;
     words[0] = (valid && (d == 0u || repair)) ? 1u : 0u;
 }
 
@@ -316,17 +389,12 @@ __global__ void order_plan_kernel(uint32_t* words, int64_t n)
 __global__ __launch_bounds__(256) void order_check_kernel(const uint32_t* __restrict__ k, const uint32_t* __restrict__ v,
                                                           int64_t n, uint32_t* words)
 {
-    if (!words[3]) return;
+    if (!words[2]) return;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j + 1 < n) {
         const uint64_t a = ((uint64_t)k[j] << 32) | v[j], b = ((uint64_t)k[j + 1] << 32) | v[j + 1];
         if (a > b) words[0] = 0u;
     }
-}
-
-__global__ void order_decide_kernel(uint32_t* words, uint32_t scan_len)
-{
-    if (threadIdx.x == 0) words[2] = words[0] ? 0u : scan_len;
 }
 
 }  // namespace
@@ -335,15 +403,17 @@ bool depth_sort_items_supported(int items) { return items == 4 || items == 8 || 
 
 size_t depth_sort_hist_elems(int64_t n, int n_views)
 {
-    // sized for the smallest block (the most blocks) any supported width uses
+    // digit totals, then the table sized for the smallest block (the most
+    // blocks) any supported width uses
     const int64_t tile = (int64_t)kSortBlock * 4;
     const int64_t bpv = (n + tile - 1) / tile;
-    const int64_t nb = bpv * (n_views > 0 ? n_views : 1);
-    return (size_t)(256 * (nb > 0 ? nb : 1));
+    const int64_t V = n_views > 0 ? n_views : 1;
+    const int64_t nb = bpv * V;
+    return (size_t)(256 * (V + (nb > 0 ? nb : 1)));
 }
 
 hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
-                              uint32_t* vals_b, int64_t n, int items, uint32_t* words, hipStream_t s)
+                              uint32_t* vals_b, int64_t n, uint32_t* words, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e = launch_fill_u32(words, 0u, kReuseWords, s);
@@ -364,9 +434,6 @@ hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* 
                        (const uint32_t*)keys_a, (const uint32_t*)vals_a, n, keys_b, vals_b, (const uint32_t*)words);
     hipLaunchKernelGGL(order_check_kernel, dim3(g256), dim3(256), 0, s, (const uint32_t*)keys_b, (const uint32_t*)vals_b,
                        n, words);
-    const int64_t tile = (int64_t)kSortBlock * items;
-    const uint32_t scan_len = (uint32_t)(256 * ((n + tile - 1) / tile));
-    hipLaunchKernelGGL(order_decide_kernel, dim3(1), dim3(64), 0, s, words, scan_len);
     return hipGetLastError();
 }
 
@@ -376,8 +443,8 @@ hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* 
 // vals_b).  With reuse_words (one view, after launch_order_reuse) every pass
 // reads words[0] on the device and does nothing when the reused order holds.
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
-                             uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch, int64_t n, int n_views,
-                             int items, const uint32_t* reuse_words, int* result_in_b, hipStream_t s)
+                             uint32_t* vals_b, uint32_t* counts, int64_t n, int n_views, int items,
+                             const uint32_t* reuse_words, int* result_in_b, hipStream_t s)
 {
     *result_in_b = 1;
     if (n == 0 || n_views <= 0) return hipSuccess;
@@ -390,21 +457,13 @@ hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t
     uint32_t* kout = keys_a;
     uint32_t* vout = vals_a;
     const uint32_t* skip = reuse_words;
-    const uint32_t* scan_len = reuse_words ? reuse_words + 2 : nullptr;   // 0 when skipped
-    auto pass_launch = [&](int shift, bool hist_only) {
-        switch (items) {
-        case 4: launch_sort_pass<4>(kin, vin, kout, vout, hist, n, shift, bpv, nblocks, hist_only, skip, s); break;
-        case 8: launch_sort_pass<8>(kin, vin, kout, vout, hist, n, shift, bpv, nblocks, hist_only, skip, s); break;
-        default: launch_sort_pass<16>(kin, vin, kout, vout, hist, n, shift, bpv, nblocks, hist_only, skip, s); break;
-        }
-    };
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
-        pass_launch(shift, true);
-        hipError_t e = launch_scan_exclusive(hist, (int64_t)256 * nblocks, scan_scratch, nullptr, nullptr, nullptr, s,
-                                             scan_len);
-        if (e != hipSuccess) return e;
-        pass_launch(shift, false);
+        switch (items) {
+        case 4: launch_sort_pass<4>(kin, vin, kout, vout, counts, n, n_views, shift, bpv, nblocks, skip, s); break;
+        case 8: launch_sort_pass<8>(kin, vin, kout, vout, counts, n, n_views, shift, bpv, nblocks, skip, s); break;
+        default: launch_sort_pass<16>(kin, vin, kout, vout, counts, n, n_views, shift, bpv, nblocks, skip, s); break;
+        }
         kin = kout;
         vin = vout;
         if (pass % 2 == 0) {

@@ -102,18 +102,17 @@ hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
 bool depth_sort_items_supported(int items);
 size_t depth_sort_hist_elems(int64_t n, int n_views);   // enough for every supported width
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a,
-                             uint32_t* keys_b, uint32_t* vals_b, uint32_t* hist, uint64_t* scan_scratch,
-                             int64_t n, int n_views, int items, const uint32_t* reuse_words, int* result_in_b,
-                             hipStream_t s);
+                             uint32_t* keys_b, uint32_t* vals_b, uint32_t* counts, int64_t n, int n_views, int items,
+                             const uint32_t* reuse_words, int* result_in_b, hipStream_t s);
 // Reuse of the previous frame's order (one view, n items): reads the previous
 // order from vals_b and this frame's keys; leaves in vals_b this frame's
 // order when it can reach it cheaply, and in words[kReuseWords]: [0] 1 when
 // vals_b holds the sorted order (launch_depth_sort then skips its passes),
-// [1] descents of the previous order under this frame's keys, [2] the radix
-// scans' length (0 when skipped), [3] 1 when the local repair ran.
-constexpr int kReuseWords = 4;
+// [1] descents of the previous order under this frame's keys, [2] 1 when the
+// local repair ran.
+constexpr int kReuseWords = 3;
 hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
-                              uint32_t* vals_b, int64_t n, int items, uint32_t* words, hipStream_t s);
+                              uint32_t* vals_b, int64_t n, uint32_t* words, hipStream_t s);
 
 struct BinArgs {
     const uint32_t* sorted_idx;   // [n_views * n] items (v * n + i), each view's segment in (depth, index) order
