@@ -10,27 +10,28 @@
 namespace gsmi {
 namespace {
 
-constexpr int kScanThreads = 256;
+constexpr int kScanThreads = 256;   // four waves (block_exclusive_u64)
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int64_t kScanMaxGrid = 8192;   // tiles beyond it are taken by grid-stride loops
 
 __device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t v, uint64_t* sh, uint64_t* total)
 {
-    // Hillis-Steele over 256 lanes in LDS (once per block, not per item)
-    const int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int o = 1; o < kScanThreads; o <<= 1) {
-        const uint64_t t = tid >= o ? sh[tid - o] : 0ull;
-        __syncthreads();
-        sh[tid] += t;
-        __syncthreads();
+    // inclusive scan in each wave by shuffles, then the 4 wave totals in LDS
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
     }
-    const uint64_t incl = sh[tid];
-    *total = sh[kScanThreads - 1];
+    if (lane == 63) sh[wave] = incl;
     __syncthreads();
-    return incl - v;
+    uint64_t before = 0;
+    for (int w = 0; w < wave; ++w) before += sh[w];
+    *total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();   // sh is reused by the next call
+    return before + incl - v;
 }
 
 __device__ __forceinline__ int64_t scan_length(int64_t n, const uint32_t* n_dev)
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_
 {
     const int64_t n = scan_length(n_max, n_dev);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    __shared__ uint64_t sh[kScanThreads];
+    __shared__ uint64_t sh[kScanThreads / 64];
     for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
         const int64_t base = t * kScanTile;
         uint64_t s = 0;
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(uint64_t* __r
                                                                    const uint32_t* n_dev, uint64_t* total_out,
                                                                    uint32_t* total32, uint32_t* overflow)
 {
-    __shared__ uint64_t sh[kScanThreads];
+    __shared__ uint64_t sh[kScanThreads / 64];
     const int64_t n = scan_length(n_max, n_dev);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     const int64_t per = (nb + kScanThreads - 1) / kScanThreads;
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __res
 {
     const int64_t n = scan_length(n_max, n_dev);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    __shared__ uint64_t sh[kScanThreads];
+    __shared__ uint64_t sh[kScanThreads / 64];
     if (nb == 0 && blockIdx.x == 0) {
         if (threadIdx.x == 0) {
             if (total_out) *total_out = 0;

@@ -263,27 +263,28 @@ __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
 }
 
 // Row offsets and the level-2 chunk table (one 1024-thread block, a run of
-// rows per thread).  The scanned level-1 counts give rows_off[r] (chunk 0's
+// ceil(rows / 1024) rows per thread, so a few rows take one step each).  The scanned level-1 counts give rows_off[r] (chunk 0's
 // cursor in row r); row r owns ceil(len_r / chunk2) level-2 chunks (chunk2 =
 // 64 items2 entries) and
 // tiles_x(r) count elements per chunk; info holds both prefixes.  On
 // overflow every row gets zero chunks.
-constexpr int kTableRowsPerThread = kMaxTotalRows / 1024;
+static_assert(kMaxTotalRows % 1024 == 0, "rows per thread of the chunk table");
 
 __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
 {
-    __shared__ uint32_t part_c[1024], part_e[1024];
+    __shared__ uint32_t wave_c[16], wave_e[16];
     __shared__ uint32_t s_total_c, s_total_e;
-    const int tid = threadIdx.x, rows = a.rows;
+    const int tid = threadIdx.x, rows = a.rows, lane = tid & 63, wave = tid >> 6;
     const uint32_t chunk2 = (uint32_t)a.items2 * 64u;
-    const int r0 = tid * kTableRowsPerThread;
-    for (int k = 0; k < kTableRowsPerThread; ++k) {
+    const int per = (rows + 1023) / 1024;   // at most kMaxTotalRows / 1024
+    const int r0 = tid * per;
+    for (int k = 0; k < per; ++k) {
         const int r = r0 + k;
         if (r < rows) a.rows_off[r] = a.counts1[(int64_t)r * a.chunks1];
     }
     __syncthreads();   // rows_off[rows] (= R) was written by the scan
     uint32_t sc = 0, se = 0;
-    for (int k = 0; k < kTableRowsPerThread; ++k) {
+    for (int k = 0; k < per; ++k) {
         const int r = r0 + k;
         if (r < rows) {
             const uint32_t len = a.rows_off[r + 1] - a.rows_off[r];
@@ -292,19 +293,27 @@ __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
             se += ch * a.row_tiles_x[r];
         }
     }
-    part_c[tid] = sc;
-    part_e[tid] = se;
+    // inclusive prefixes over the threads: in the wave, then over the waves
+    uint32_t ic = sc, ie = se;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t tc = __shfl_up(ic, o, 64), te = __shfl_up(ie, o, 64);
+        if (lane >= o) {
+            ic += tc;
+            ie += te;
+        }
+    }
+    if (lane == 63) {
+        wave_c[wave] = ic;
+        wave_e[wave] = ie;
+    }
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t tc = tid >= o ? part_c[tid - o] : 0u;
-        const uint32_t te = tid >= o ? part_e[tid - o] : 0u;
-        __syncthreads();
-        part_c[tid] += tc;
-        part_e[tid] += te;
-        __syncthreads();
+    for (int w = 0; w < wave; ++w) {
+        ic += wave_c[w];
+        ie += wave_e[w];
     }
     if (tid == 1023) {
-        uint32_t tc = part_c[1023], te = part_e[1023];
+        uint32_t tc = ic, te = ie;
         if ((int64_t)tc > (int64_t)a.max_chunks2 || (uint64_t)te > a.counts2_capacity ||
             (uint64_t)a.rows_off[rows] > a.row_capacity) {
             *a.overflow = 1u;
@@ -315,10 +324,10 @@ __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
     }
     __syncthreads();
     const bool ok = s_total_c != 0u;
-    uint32_t run_c = ok ? part_c[tid] - sc : 0u, run_e = ok ? part_e[tid] - se : 0u;
+    uint32_t run_c = ok ? ic - sc : 0u, run_e = ok ? ie - se : 0u;
     uint32_t* cpre = a.info + kInfoRowChunks;
     uint32_t* epre = a.info + kInfoRowChunks + rows + 1;
-    for (int k = 0; k < kTableRowsPerThread; ++k) {
+    for (int k = 0; k < per; ++k) {
         const int r = r0 + k;
         if (r < rows) {
             cpre[r] = run_c;
