@@ -11,12 +11,14 @@
 // view, items v * n + i); no block straddles two segments.
 //
 // Each 8-bit pass is reduce-then-scan in three launches: an LDS histogram
-// per block into the digit-major [segment][digit][block] table, one
-// workgroup per (segment, digit) that scans its row of the table and records
-// the digit's total, and a stable scatter that ranks equal digits with
-// wavefront ballots (lower lanes and earlier waves first) and places digit d
-// of segment v at v * n + (totals of the smaller digits) + (its row's
-// exclusive prefix).  Digits are taken from sort_key(key), which orders
+// per block, written as the block's 256 contiguous counts (whole cache
+// lines; a digit-major table would take 256 scattered partial-line writes
+// per block); one workgroup per (segment, digit) that gathers its digit's
+// counts over the blocks, scans them into the digit-major
+// [segment][digit][block] offset table and records the digit's total; and a
+// stable scatter that ranks equal digits with wavefront ballots (lower lanes
+// and earlier waves first) and places digit d of segment v at v * n +
+// (totals of the smaller digits) + (its row's exclusive prefix).  Digits are taken from sort_key(key), which orders
 // depths as numbers (negative ones, behind the camera, first); keys of
 // Gaussians without a finite depth are 0xFFFFFFFF and sink to the end.
 // Values start as the Gaussian index, so ties in depth stay in index order.
@@ -27,8 +29,8 @@ namespace {
 
 // Block b sorts part lb = b % bpv of segment v = b / bpv: items
 // [v * n + lb * tile, min(.. + tile, (v + 1) * n)), tile = kSortBlock * kItems.
-// The count buffer holds the digit totals [segment][digit] (kDigitTotals
-// per segment) followed by the digit table [segment][digit][part].
+// The count buffer holds the digit totals [segment][digit], the offset
+// table [segment][digit][part], then the block histograms [block][digit].
 template <int kItems>
 __device__ __forceinline__ void sort_block_range(int64_t n, int bpv, int64_t* begin, int64_t* end, int64_t* row)
 {
@@ -82,19 +84,25 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
         }
     }
     __syncthreads();
-    hist[row + (int64_t)tid * bpv] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+    (void)row;
+    hist[(int64_t)blockIdx.x * 256 + tid] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
 }
 
-// Workgroup (v, d): exclusive scan, in place, of digit d's row of segment v
-// (bpv block counts), and the digit's total in totals[v * 256 + d].  Counts
-// fit 32 bits (n_views * n < 2^32).
+// Workgroup (v, d): exclusive scan of digit d's counts over the bpv blocks of
+// segment v (hist[(v * bpv + b) * 256 + d]) into row (v, d) of the offset
+// table, and the digit's total in totals[v * 256 + d].  Counts fit 32 bits
+// (n_views * n < 2^32).
 constexpr int kScanRowItems = 8;
-__global__ __launch_bounds__(256) void radix_row_scan_kernel(uint32_t* __restrict__ table, uint32_t* __restrict__ totals,
-                                                              int bpv, const uint32_t* skip)
+__global__ __launch_bounds__(256) void radix_row_scan_kernel(const uint32_t* __restrict__ hist,
+                                                              uint32_t* __restrict__ table,
+                                                              uint32_t* __restrict__ totals, int bpv,
+                                                              const uint32_t* skip)
 {
     if (skip && *skip) return;
     __shared__ uint32_t s_wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int v = (int)(blockIdx.x >> 8), d = (int)(blockIdx.x & 255u);
+    const uint32_t* col = hist + (int64_t)v * bpv * 256 + d;   // block b's count at col[b * 256]
     uint32_t* row = table + (int64_t)blockIdx.x * bpv;
     uint32_t carry = 0u;
     for (int base = 0; base < bpv; base += 256 * kScanRowItems) {
@@ -102,7 +110,7 @@ __global__ __launch_bounds__(256) void radix_row_scan_kernel(uint32_t* __restric
         const int j0 = base + tid * kScanRowItems;   // this thread's consecutive counts
 #pragma unroll
         for (int k = 0; k < kScanRowItems; ++k) {
-            x[k] = (j0 + k < bpv) ? row[j0 + k] : 0u;
+            x[k] = (j0 + k < bpv) ? col[(int64_t)(j0 + k) * 256] : 0u;
             run += x[k];
         }
         uint32_t incl = run;
@@ -240,7 +248,8 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
 }
 
 // One 8-bit pass: histogram, row scans, scatter.  counts = totals
-// [n_views][256] then the table.
+// [n_views][256], the offset table [n_views][256][bpv], the block
+// histograms [nblocks][256].
 template <int kItems>
 void launch_sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* counts,
                       int64_t n, int n_views, int shift, int bpv, unsigned nblocks, const uint32_t* skip,
@@ -248,10 +257,11 @@ void launch_sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
 {
     uint32_t* totals = counts;
     uint32_t* table = counts + (int64_t)256 * n_views;
-    hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, table, bpv,
+    uint32_t* hist = table + (int64_t)256 * nblocks;
+    hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, hist, bpv,
                        skip);
-    hipLaunchKernelGGL(radix_row_scan_kernel, dim3(256u * (unsigned)n_views), dim3(256), 0, s, table, totals, bpv,
-                       skip);
+    hipLaunchKernelGGL(radix_row_scan_kernel, dim3(256u * (unsigned)n_views), dim3(256), 0, s,
+                       (const uint32_t*)hist, table, totals, bpv, skip);
     hipLaunchKernelGGL(radix_scatter_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n,
                        shift, (const uint32_t*)table, (const uint32_t*)totals, bpv, skip);
 }
@@ -403,13 +413,13 @@ bool depth_sort_items_supported(int items) { return items == 4 || items == 8 || 
 
 size_t depth_sort_hist_elems(int64_t n, int n_views)
 {
-    // digit totals, then the table sized for the smallest block (the most
-    // blocks) any supported width uses
+    // digit totals, then the offset table and the block histograms, both
+    // sized for the smallest block (the most blocks) any supported width uses
     const int64_t tile = (int64_t)kSortBlock * 4;
     const int64_t bpv = (n + tile - 1) / tile;
     const int64_t V = n_views > 0 ? n_views : 1;
     const int64_t nb = bpv * V;
-    return (size_t)(256 * (V + (nb > 0 ? nb : 1)));
+    return (size_t)(256 * (V + 2 * (nb > 0 ? nb : 1)));
 }
 
 hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
