@@ -570,33 +570,41 @@ void launch_project_backward_dt(const ProjectBackArgs& a, unsigned blocks, hipSt
 __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* __restrict__ partials, int blocks,
                                                                int n_views, uint32_t* view_counts)
 {
-    __shared__ unsigned long long sv[1024], sp[1024], sf[1024];
-    const int v = blockIdx.x;
+    // 64-bit sums: in each thread over a stride of blocks, in each wave by
+    // shuffles, then over the 16 waves in LDS
+    __shared__ unsigned long long sv[16], sp[16], sf[16];
+    const int v = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long vis = 0, pairs = 0, front = 0;
+#pragma unroll 4
     for (int b = threadIdx.x; b < blocks; b += 1024) {
-        const uint32_t* pp = partials + 4 * ((int64_t)b * n_views + v);
-        vis += pp[0];
-        pairs += pp[1];
-        front += pp[2];
+        const uint4 pp = *reinterpret_cast<const uint4*>(partials + 4 * ((int64_t)b * n_views + v));
+        vis += pp.x;
+        pairs += pp.y;
+        front += pp.z;
     }
-    sv[threadIdx.x] = vis;
-    sp[threadIdx.x] = pairs;
-    sf[threadIdx.x] = front;
+    for (int o = 32; o > 0; o >>= 1) {
+        vis += __shfl_xor(vis, o, 64);
+        pairs += __shfl_xor(pairs, o, 64);
+        front += __shfl_xor(front, o, 64);
+    }
+    if (lane == 0) {
+        sv[wave] = vis;
+        sp[wave] = pairs;
+        sf[wave] = front;
+    }
     __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            sv[threadIdx.x] += sv[threadIdx.x + o];
-            sp[threadIdx.x] += sp[threadIdx.x + o];
-            sf[threadIdx.x] += sf[threadIdx.x + o];
-        }
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
+        unsigned long long tv = 0, tp = 0, tf = 0;
+        for (int w = 0; w < 16; ++w) {
+            tv += sv[w];
+            tp += sp[w];
+            tf += sf[w];
+        }
         uint32_t* c = view_counts + (int64_t)kViewCounters * v;
-        c[0] = (uint32_t)sv[0];
-        c[1] = (uint32_t)sf[0];
-        c[2] = (uint32_t)sp[0];
-        c[3] = (uint32_t)(sp[0] >> 32);
+        c[0] = (uint32_t)tv;
+        c[1] = (uint32_t)tf;
+        c[2] = (uint32_t)tp;
+        c[3] = (uint32_t)(tp >> 32);
     }
 }
 
