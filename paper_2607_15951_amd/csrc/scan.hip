@@ -34,6 +34,10 @@ __device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t v, uint64_t* sh
     return before + incl - v;
 }
 
+// LDS index of tile word e, one word of padding per 32 so that a thread's
+// 16 consecutive words and a wave's 64 striped words spread over the banks
+__device__ __forceinline__ int padded(int e) { return e + (e >> 5); }
+
 __device__ __forceinline__ int64_t scan_length(int64_t n, const uint32_t* n_dev)
 {
     if (!n_dev) return n;
@@ -103,6 +107,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __res
     const int64_t n = scan_length(n_max, n_dev);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     __shared__ uint64_t sh[kScanThreads / 64];
+    __shared__ uint32_t s_tile[kScanTile + kScanTile / 32];
     if (nb == 0 && blockIdx.x == 0) {
         if (threadIdx.x == 0) {
             if (total_out) *total_out = 0;
@@ -117,22 +122,37 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __res
         uint64_t before;
         (void)block_exclusive_u64(p, sh, &before);
         const int64_t base = t * kScanTile;
-        // thread i owns the kScanItems consecutive items [i*16, i*16+16) of the tile
+        // thread i scans the kScanItems consecutive items [16 i, 16 i + 16) of
+        // the tile; the tile moves between HBM and LDS in striped order
+        // (consecutive lanes on consecutive words: whole cache lines) and is
+        // regrouped in LDS
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int e = k * kScanThreads + threadIdx.x;
+            s_tile[padded(e)] = (base + e < n) ? data[base + e] : 0u;
+        }
+        __syncthreads();
         uint32_t v[kScanItems];
-        const int64_t mine = base + (int64_t)threadIdx.x * kScanItems;
         uint64_t s = 0;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
-            v[k] = (mine + k < n) ? data[mine + k] : 0u;
+            v[k] = s_tile[padded(threadIdx.x * kScanItems + k)];
             s += v[k];
         }
         uint64_t tot;
         uint64_t run = block_exclusive_u64(s, sh, &tot) + before;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
-            if (mine + k < n) data[mine + k] = (uint32_t)run;
+            s_tile[padded(threadIdx.x * kScanItems + k)] = (uint32_t)run;
             run += v[k];
         }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int e = k * kScanThreads + threadIdx.x;
+            if (base + e < n) data[base + e] = s_tile[padded(e)];
+        }
+        __syncthreads();   // s_tile is reused by the next tile
         if (t == nb - 1 && threadIdx.x == 0) {
             const uint64_t total = before + tot;
             if (total_out) *total_out = total;
