@@ -150,14 +150,15 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
                 const float4 e2 = s2[j];
                 float dx, dy, E;
                 const float al = entry_alpha(e0, e1, fx, fy, dx, dy, E);
-                const float tn = Tr * (1.0f - al);
+                const float wt = al * Tr;
+                const float tn = fmaf(-al, Tr, Tr);   // Tr (1 - al), rounded once
                 const bool pass = al >= 1.0f / 255.0f;
                 const bool stop = pass && tn < 1e-4f && !done;
                 const bool take = pass && !stop && !done;
                 const uint32_t pos1 = (uint32_t)__float_as_int(e2.w);   // list position + 1
                 if (kStats) term = stop ? pos1 : term;
                 done = done || stop;
-                const float wgt = take ? al * Tr : 0.0f;
+                const float wgt = take ? wt : 0.0f;
                 c0 = fmaf(wgt, e2.x, c0);
                 c1 = fmaf(wgt, e2.y, c1);
                 c2 = fmaf(wgt, e2.z, c2);

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void blend_backward_kernel(BlendBackArgs a, ui
                     g[0] = gp * kLn2 * (2.0f * e1.x * dx + e1.y * dy);
                     g[1] = gp * kLn2 * (2.0f * e1.z * dy + e1.y * dx);
                 }
-                Tr = Tr * (1.0f - al);
+                Tr = fmaf(-al, Tr, Tr);   // as the forward: Tr (1 - al), rounded once
             }
             if (__ballot(take) != 0) {
                 int slot;
