@@ -179,12 +179,22 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
     int v2, p2;
     int64_t start = 0, end = 0;
     (void)chunk1_range(a, c, &v2, &p2, &start, &end);
+    // the rectangles in depth order, for the scatter to stream: all index
+    // loads, then all gathers, then the counting (see load_items2)
+    uint32_t idx[kItems];
+#pragma unroll
+    for (int b = 0; b < kItems; ++b) {
+        const int64_t k = start + b * 64 + lane;
+        idx[b] = k < end ? a.sorted_idx[k] : 0u;
+    }
+    ushort4 rr[kItems];
+#pragma unroll
+    for (int b = 0; b < kItems; ++b) rr[b] = a.rect[idx[b]];
 #pragma unroll
     for (int b = 0; b < kItems; ++b) {
         const int64_t k = start + b * 64 + lane;
         if (k < end) {
-            // the rectangles in depth order, for the scatter to stream
-            const ushort4 r = a.rect[a.sorted_idx[k]];
+            const ushort4 r = rr[b];
             a.sorted_rect[k] = r;
             if (r.w > r.y) {
                 atomicAdd(&diff[r.y], 1u);
@@ -399,19 +409,27 @@ __device__ __forceinline__ bool load_items2(const BinArgs& a, int c, int lane, I
     if ((uint32_t)c >= a.info[kInfoC2]) return false;
     int64_t eb, ee;
     chunk2_range(a, c, lane, &it.row, &eb, &ee);
-    int lo = 1 << 30, hi = 0;
+    // every load is issued before any is used (a load under its own branch
+    // would be waited for before the next is issued); lanes past the chunk
+    // load entry eb, which exists, and drop it
+    uint2 ent[kItems];
 #pragma unroll
     for (int b = 0; b < kItems; ++b) {
         const int64_t e = eb + b * 64 + lane;
-        uint2 ent = make_uint2(0u, 0u);
-        if (e < ee) {
-            ent = a.row_ent[e];
-            const int x0 = (int)(ent.y & 0xFFFFu), x1 = (int)(ent.y >> 16);
+        ent[b] = a.row_ent[e < ee ? e : eb];
+    }
+    int lo = 1 << 30, hi = 0;
+#pragma unroll
+    for (int b = 0; b < kItems; ++b) {
+        const bool in = eb + b * 64 + lane < ee;
+        const uint32_t xs = in ? ent[b].y : 0u;
+        if (in) {
+            const int x0 = (int)(xs & 0xFFFFu), x1 = (int)(xs >> 16);
             lo = x0 < lo ? x0 : lo;
             hi = x1 > hi ? x1 : hi;
         }
-        it.xs[b] = ent.y;
-        it.g[b] = ent.x;
+        it.xs[b] = xs;
+        it.g[b] = in ? ent[b].x : 0u;
     }
     it.lo = __builtin_amdgcn_readfirstlane(wave_min(lo));   // uniform: keep it scalar
     it.hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
@@ -429,13 +447,18 @@ __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int 
     const int row_tx = (int)a.row_tiles_x[row];
     for (int x = lane; x <= row_tx; x += 64) diff[x] = 0u;
     __syncthreads();
+    // all loads first (see load_items2), then the counting
+    uint32_t xs[kItems];
 #pragma unroll
     for (int b = 0; b < kItems; ++b) {
         const int64_t e = eb + b * 64 + lane;
-        if (e < ee) {
-            const uint32_t xs = a.row_ent[e].y;
-            atomicAdd(&diff[xs & 0xFFFFu], 1u);
-            atomicSub(&diff[xs >> 16], 1u);
+        xs[b] = a.row_ent[e < ee ? e : eb].y;
+    }
+#pragma unroll
+    for (int b = 0; b < kItems; ++b) {
+        if (eb + b * 64 + lane < ee) {
+            atomicAdd(&diff[xs[b] & 0xFFFFu], 1u);
+            atomicSub(&diff[xs[b] >> 16], 1u);
         }
     }
     __syncthreads();
