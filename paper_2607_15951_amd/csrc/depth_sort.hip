@@ -66,11 +66,20 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
     __syncthreads();
     int64_t begin, end, row;
     sort_block_range<kItems>(n, bpv, &begin, &end, &row);
+    // every key load issued before any is used (a load under its own branch
+    // is waited for before the next one issues); past end, key begin is
+    // loaded and dropped
+    uint32_t kk[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t idx = begin + k * kSortBlock + tid;
+        kk[k] = keys[idx < end ? idx : begin];
+    }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int64_t idx = begin + k * kSortBlock + tid;
         const bool valid = idx < end;
-        const uint32_t d = valid ? (sort_key(keys[idx]) >> shift) & 255u : 0u;
+        const uint32_t d = valid ? (sort_key(kk[k]) >> shift) & 255u : 0u;
         const uint64_t m = __ballot(valid);
         if (m == 0) continue;
         // the high digits of nearby depths are mostly one value: a wave whose
@@ -164,12 +173,19 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
     uint32_t key[kItems], val[kItems], digit[kItems], rank[kItems];
+    // all loads first (see radix_hist_kernel)
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t idx = begin + k * kSortBlock + tid;
+        const int64_t ic = idx < end ? idx : begin;
+        key[k] = keys_in[ic];
+        val[k] = vals_in ? vals_in[ic] : (uint32_t)idx;
+    }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int64_t idx = begin + k * kSortBlock + tid;
         const bool valid = idx < end;
-        key[k] = valid ? keys_in[idx] : 0u;
-        val[k] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
+        if (!valid) key[k] = val[k] = 0u;
         const uint32_t d = (sort_key(key[k]) >> shift) & 255u;
         // lanes of this wave holding the same digit
         uint64_t m = __ballot(valid);

@@ -56,12 +56,19 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_
     __shared__ uint64_t sh[kScanThreads / 64];
     for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
         const int64_t base = t * kScanTile;
-        uint64_t s = 0;
+        // every load issued before any is used (a load under its own branch
+        // is waited for before the next one issues); past n, word base (< n)
+        // is loaded and dropped
+        uint32_t x[kScanItems];
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             const int64_t i = base + k * kScanThreads + threadIdx.x;
-            if (i < n) s += in[i];
+            x[k] = in[i < n ? i : base];
         }
+        uint64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k * kScanThreads + threadIdx.x < n) s += x[k];
         uint64_t tot;
         (void)block_exclusive_u64(s, sh, &tot);
         if (threadIdx.x == 0) block_sums[t] = tot;
@@ -126,10 +133,16 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __res
         // the tile; the tile moves between HBM and LDS in striped order
         // (consecutive lanes on consecutive words: whole cache lines) and is
         // regrouped in LDS
+        uint32_t x[kScanItems];   // all loads first, as in scan_reduce_kernel
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t i = base + k * kScanThreads + threadIdx.x;
+            x[k] = data[i < n ? i : base];
+        }
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             const int e = k * kScanThreads + threadIdx.x;
-            s_tile[padded(e)] = (base + e < n) ? data[base + e] : 0u;
+            s_tile[padded(e)] = (base + e < n) ? x[k] : 0u;
         }
         __syncthreads();
         uint32_t v[kScanItems];
