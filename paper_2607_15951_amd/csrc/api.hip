@@ -355,7 +355,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     const bool reuse = (o.flags & GS_RENDER_REUSE_ORDER) && V == 1 && n > 0 && prev_order_n == n;
     uint32_t* reuse_words = nullptr;
     if (reuse) {
-        if ((st = ensure(ctx, ctx->reuse_words, kReuseWords * 4)) != GS_OK) return st;
+        if ((st = ensure(ctx, ctx->reuse_words, order_reuse_words(n) * 4)) != GS_OK) return st;
         reuse_words = static_cast<uint32_t*>(ctx->reuse_words.p);
         HIP_TRY(launch_order_reuse(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
                                    static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),

@@ -308,41 +308,44 @@ constexpr int kReuseBlock = kReuseThreads * kReuseItems;   // items sorted toget
 // words[1] = descents of the gathered previous order (churn), words[2] = 1
 // when the local repair runs.  A repair is tried for at most n / kRepairFraction descents.
 constexpr int64_t kRepairFraction = 256;
-// Grid-stride, so that the descent count takes one atomic per block: an
-// atomic per wave on one counter serialises when most pairs swap.
-constexpr int kGatherBlocks = 2048;
+// One item per thread: item j takes this frame's key of prev[j], and each
+// block counts its descents (pairs (j, j + 1) out of order, the pair across
+// its end included) into partial[block].  No counter is shared: one atomic
+// counter hit by every block serialises when most pairs swap.  The successor
+// of lane l is lane l + 1's item; lane 63 loads its own.
 __global__ __launch_bounds__(256) void order_gather_kernel(const uint32_t* __restrict__ keys,
                                                            const uint32_t* __restrict__ prev, int64_t n,
                                                            uint32_t* __restrict__ k_out, uint32_t* __restrict__ v_out,
-                                                           uint32_t* words)
+                                                           uint32_t* words, uint32_t* __restrict__ partial)
 {
-    uint32_t descents = 0u;
-    bool invalid = false;
-    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
-        uint32_t p = prev[j];
-        if (p >= (uint32_t)n) {   // not an order of these items: sort from scratch
-            invalid = true;
-            p = 0u;
-        }
-        const uint32_t k = sort_key(keys[p]);
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool in = j < n;
+    uint32_t p = prev[in ? j : 0];
+    const bool tail = lane == 63 && j + 1 < n;
+    uint32_t p1 = tail ? prev[j + 1] : 0u;
+    const bool invalid = in && p >= (uint32_t)n;   // not an order of these items: sort from scratch
+    p = p < (uint32_t)n ? p : 0u;
+    p1 = p1 < (uint32_t)n ? p1 : 0u;
+    const uint32_t k = sort_key(keys[p]);
+    const uint32_t k1 = tail ? sort_key(keys[p1]) : 0u;
+    if (in) {
         k_out[j] = k;
         v_out[j] = p;
-        if (j + 1 < n) {
-            uint32_t p1 = prev[j + 1];
-            p1 = p1 < (uint32_t)n ? p1 : 0u;
-            const uint64_t a = ((uint64_t)k << 32) | p, b = ((uint64_t)sort_key(keys[p1]) << 32) | p1;
-            descents += a > b ? 1u : 0u;
-        }
     }
+    uint32_t kn = __shfl_down(k, 1, 64), pn = __shfl_down(p, 1, 64);
+    if (lane == 63) {
+        kn = k1;
+        pn = p1;
+    }
+    const uint64_t cur = ((uint64_t)k << 32) | p, next = ((uint64_t)kn << 32) | pn;
+    uint32_t descents = (j + 1 < n && cur > next) ? 1u : 0u;
     if (invalid) words[0] = 0u;
     __shared__ uint32_t s_d[4];
     for (int o = 32; o > 0; o >>= 1) descents += __shfl_xor(descents, o, 64);
-    if ((threadIdx.x & 63) == 0) s_d[threadIdx.x >> 6] = descents;
+    if (lane == 0) s_d[threadIdx.x >> 6] = descents;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t d = s_d[0] + s_d[1] + s_d[2] + s_d[3];
-        if (d) atomicAdd(&words[1], d);
-    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s_d[0] + s_d[1] + s_d[2] + s_d[3];
 }
 
 // Sorts runs of kReuseBlock composite keys in LDS (bitonic network).  Run b
@@ -401,10 +404,21 @@ __global__ __launch_bounds__(kReuseThreads) void order_local_sort_kernel(const u
 
 // After the gather: no descent keeps the order as it is (the previous order
 // in vals_b is this frame's order), a few start the repair, more give up.
-__global__ void order_plan_kernel(uint32_t* words, int64_t n)
+__global__ __launch_bounds__(1024) void order_plan_kernel(uint32_t* words, const uint32_t* __restrict__ partial,
+                                                           int blocks, int64_t n)
 {
+    // the descents: the gather blocks' counts summed
+    __shared__ unsigned long long s_sum[16];
+    unsigned long long t = 0;
+    for (int b = threadIdx.x; b < blocks; b += 1024) t += partial[b];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = t;
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    const uint32_t d = words[1];
+    unsigned long long total = 0;
+    for (int w = 0; w < 16; ++w) total += s_sum[w];
+    const uint32_t d = (uint32_t)total;   // at most n - 1 < 2^32
+    words[1] = d;
     const bool valid = words[0] != 0u;
     const bool repair = valid && d > 0u && (int64_t)d <= n / kRepairFraction;
     words[2] = repair ? 1u : 0u;
@@ -427,6 +441,8 @@ __global__ __launch_bounds__(256) void order_check_kernel(const uint32_t* __rest
 
 bool depth_sort_items_supported(int items) { return items == 4 || items == 8 || items == 16; }
 
+size_t order_reuse_words(int64_t n) { return (size_t)(kReuseWords + (n + 255) / 256); }
+
 size_t depth_sort_hist_elems(int64_t n, int n_views)
 {
     // digit totals, then the offset table and the block histograms, both
@@ -448,9 +464,10 @@ hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* 
     if (e != hipSuccess) return e;
     const unsigned g256 = (unsigned)((n + 255) / 256);
     // previous order (vals_b) -> (this frame's keys, items) in a
-    hipLaunchKernelGGL(order_gather_kernel, dim3((unsigned)std::min<int64_t>(g256, kGatherBlocks)), dim3(256), 0, s,
-                       keys, (const uint32_t*)vals_b, n, keys_a, vals_a, words);
-    hipLaunchKernelGGL(order_plan_kernel, dim3(1), dim3(64), 0, s, words, n);
+    uint32_t* partial = words + kReuseWords;
+    hipLaunchKernelGGL(order_gather_kernel, dim3(g256), dim3(256), 0, s, keys, (const uint32_t*)vals_b, n, keys_a,
+                       vals_a, words, partial);
+    hipLaunchKernelGGL(order_plan_kernel, dim3(1), dim3(1024), 0, s, words, (const uint32_t*)partial, (int)g256, n);
     const int64_t half = kReuseBlock / 2;
     const unsigned runs = (unsigned)((n + kReuseBlock - 1) / kReuseBlock);
     const unsigned runs_shifted = (unsigned)(n > half ? (n - half + kReuseBlock - 1) / kReuseBlock : 0) + 1u;

@@ -111,6 +111,7 @@ hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t
 // [1] descents of the previous order under this frame's keys, [2] 1 when the
 // local repair ran.
 constexpr int kReuseWords = 3;
+size_t order_reuse_words(int64_t n);   // words and the gather's per-block counts
 hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
                               uint32_t* vals_b, int64_t n, uint32_t* words, hipStream_t s);
 
