@@ -163,13 +163,19 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ totals, int bpv, const uint32_t* skip)
 {
     if (skip && *skip) return;
-    __shared__ uint32_t cnt[kItems][4][256];   // then the block's keys and values in digit order
+    // the block's keys and values in digit order; before that, the 16-bit
+    // ranking counts cnt[k][w][d] (at most kItems * kSortBlock) in the same
+    // bytes, which keeps the block's LDS at 8 bytes per item
+    __shared__ uint32_t s_buf[2 * kItems * kSortBlock];
+    uint16_t(*cnt)[4][256] = reinterpret_cast<uint16_t(*)[4][256]>(s_buf);
+    static_assert(kItems * 4 * 256 * sizeof(uint16_t) <= sizeof(s_buf), "ranking counts fit the key buffer");
+    static_assert(kItems * kSortBlock <= 65535, "16-bit ranking offsets");
     __shared__ uint32_t s_start[256], s_base[256], s_wsum[4], s_ssum[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int64_t begin, end, row;
     sort_block_range<kItems>(n, bpv, &begin, &end, &row);
     for (int k = 0; k < kItems; ++k)
-        for (int w = 0; w < 4; ++w) cnt[k][w][tid] = 0u;
+        for (int w = 0; w < 4; ++w) cnt[k][w][tid] = 0;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
     uint32_t key[kItems], val[kItems], digit[kItems], rank[kItems];
@@ -198,7 +204,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
         digit[k] = valid ? d : 256u;
         rank[k] = (uint32_t)__popcll(m & lt);
         // the group's first lane records its size (groups are disjoint)
-        if (valid && rank[k] == 0) cnt[k][wave][d] = (uint32_t)__popcll(m);
+        if (valid && rank[k] == 0) cnt[k][wave][d] = (uint16_t)__popcll(m);
     }
     __syncthreads();
     {   // thread d: exclusive offsets of digit d over (round, wave), its total,
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
                 const uint32_t c = cnt[k][w][tid];
-                cnt[k][w][tid] = run;
+                cnt[k][w][tid] = (uint16_t)run;
                 run += c;
             }
         uint32_t incl = run, seg_incl = seg_total;
@@ -243,7 +249,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     for (int k = 0; k < kItems; ++k)
         local[k] = digit[k] < 256u ? s_start[digit[k]] + cnt[k][wave][digit[k]] + rank[k] : ~0u;
     __syncthreads();   // cnt is reused below
-    uint32_t* s_key = &cnt[0][0][0];
+    uint32_t* s_key = s_buf;
     uint32_t* s_val = s_key + kItems * kSortBlock;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
