@@ -142,6 +142,23 @@ __device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, I
     return true;
 }
 
+// Difference arrays in LDS are kept in kDiffCopies interleaved copies, bucket
+// x of copy c at x * kDiffCopies + c, and lane l adds to copy l % kDiffCopies:
+// lanes that hit the same bucket mostly hit different words, so the atomics
+// of a wave collide less.
+constexpr int kDiffCopies = 4;
+__device__ __forceinline__ uint32_t* diff_slot(uint32_t* diff, uint32_t x, int lane)
+{
+    return diff + x * kDiffCopies + (lane & (kDiffCopies - 1));
+}
+__device__ __forceinline__ uint32_t diff_at(const uint32_t* diff, int x)
+{
+    uint32_t v = 0;
+#pragma unroll
+    for (int c = 0; c < kDiffCopies; ++c) v += diff[x * kDiffCopies + c];
+    return v;
+}
+
 // Exclusive-then-inclusive sum of a difference array diff[0..m) (LDS) by one
 // wave: dst[x * stride] = diff[0] + ... + diff[x], the count of spans covering x.
 __device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, uint32_t* dst, int64_t stride,
@@ -150,7 +167,7 @@ __device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, ui
     const int per = (m + 63) / 64;
     const int b = lane * per, e = (b + per < m) ? b + per : m;
     uint32_t s = 0;
-    for (int k = b; k < e; ++k) s += diff[k];
+    for (int k = b; k < e; ++k) s += diff_at(diff, k);
     uint32_t run = s;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -159,7 +176,7 @@ __device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, ui
     }
     run -= s;
     for (int k = b; k < e; ++k) {
-        run += diff[k];
+        run += diff_at(diff, k);
         dst[k * stride] = run;
     }
 }
@@ -169,12 +186,12 @@ __device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, ui
 template <int kItems>
 __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
 {
-    extern __shared__ uint32_t diff[];   // [max_tiles_y + 1], sized at launch
+    extern __shared__ uint32_t diff[];   // [max_tiles_y + 1][kDiffCopies], sized at launch
     const int lane = threadIdx.x, c = chunk_of_block();
     const int view = c / a.chunks1, part = c % a.chunks1;
     if (view >= a.n_views) return;
     const ViewParams& vp = a.views[view];
-    for (int r = lane; r <= vp.tiles_y; r += 64) diff[r] = 0u;
+    for (int r = lane; r < (vp.tiles_y + 1) * kDiffCopies; r += 64) diff[r] = 0u;
     __syncthreads();
     int v2, p2;
     int64_t start = 0, end = 0;
@@ -197,8 +214,8 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
             const ushort4 r = rr[b];
             a.sorted_rect[k] = r;
             if (r.w > r.y) {
-                atomicAdd(&diff[r.y], 1u);
-                atomicSub(&diff[r.w], 1u);
+                atomicAdd(diff_slot(diff, r.y, lane), 1u);
+                atomicSub(diff_slot(diff, r.w, lane), 1u);
             }
         }
     }
@@ -445,7 +462,7 @@ __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int 
     int64_t eb, ee;
     chunk2_range(a, c, lane, &row, &eb, &ee);
     const int row_tx = (int)a.row_tiles_x[row];
-    for (int x = lane; x <= row_tx; x += 64) diff[x] = 0u;
+    for (int x = lane; x < (row_tx + 1) * kDiffCopies; x += 64) diff[x] = 0u;
     __syncthreads();
     // all loads first (see load_items2), then the counting
     uint32_t xs[kItems];
@@ -457,8 +474,8 @@ __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int 
 #pragma unroll
     for (int b = 0; b < kItems; ++b) {
         if (eb + b * 64 + lane < ee) {
-            atomicAdd(&diff[xs[b] & 0xFFFFu], 1u);
-            atomicSub(&diff[xs[b] >> 16], 1u);
+            atomicAdd(diff_slot(diff, xs[b] & 0xFFFFu, lane), 1u);
+            atomicSub(diff_slot(diff, xs[b] >> 16, lane), 1u);
         }
     }
     __syncthreads();
@@ -473,7 +490,7 @@ __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int 
 template <int kItems>
 __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
 {
-    extern __shared__ uint32_t diff[];   // [max_tiles_x + 1], sized at launch: more waves fit
+    extern __shared__ uint32_t diff[];   // [max_tiles_x + 1][kDiffCopies], sized at launch: more waves fit
     const int lane = threadIdx.x;
     const int c2 = (int)a.info[kInfoC2];
     for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_count_chunk<kItems>(a, c, lane, diff);
@@ -648,7 +665,7 @@ hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t
     const int grid1 = a.chunks1 * a.n_views;
     with_items1(a.items1, [&](auto I) {
         hipLaunchKernelGGL(level1_count_kernel<decltype(I)::value>, dim3(grid8(grid1)), dim3(64),
-                           (a.max_tiles_y + 1) * sizeof(uint32_t), s, a);
+                           (a.max_tiles_y + 1) * kDiffCopies * sizeof(uint32_t), s, a);
     });
     hipError_t e = launch_scan_exclusive(a.counts1, (int64_t)a.rows * a.chunks1, scan_scratch, nullptr,
                                          a.rows_off + a.rows, a.overflow, s);
@@ -675,7 +692,7 @@ hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch,
     if (grid2 > 0)
         with_items2(a.items2, [&](auto I) {
             hipLaunchKernelGGL(level2_count_kernel<decltype(I)::value>, dim3(grid8(std::min(grid2, kMaxGrid2))),
-                               dim3(64), (a.max_tiles_x + 1) * sizeof(uint32_t), s, a);
+                               dim3(64), (a.max_tiles_x + 1) * kDiffCopies * sizeof(uint32_t), s, a);
         });
     // the scan's length E2 is read on the device (info[1])
     hipError_t e = launch_scan_exclusive(a.counts2, (int64_t)a.counts2_capacity, scan_scratch, nullptr,
