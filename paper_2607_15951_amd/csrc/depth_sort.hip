@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t* 
         }
     }
     __syncthreads();
-    (void)row;
+    (void)row;   // the histogram goes to the block's own row of 256 counts, not to the offset table
     hist[(int64_t)blockIdx.x * 256 + tid] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
 }
 
