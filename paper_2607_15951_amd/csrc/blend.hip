@@ -38,7 +38,9 @@
 namespace gsmi {
 namespace {
 
-constexpr int kUnroll = 8;
+constexpr int kUnroll = 16;   // entries per unrolled group (a divisor of 64)
+static_assert(64 % kUnroll == 0, "groups do not straddle a 64-entry mask word");
+constexpr uint64_t kGroupMask = kUnroll == 64 ? ~0ull : ((1ull << kUnroll) - 1ull);
 
 // kStats: the tracing variant, which also records its work per tile
 // (a.tile_work)
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capaci
         for (int j0 = 0; j0 < nk; j0 += kUnroll) {
             if (__ballot(!done) == 0) break;   // whole wave finished
             const uint64_t word = bits[j0 >> 6] >> (j0 & 63);
-            if ((word & ((1u << kUnroll) - 1u)) == 0) continue;   // none of the next kUnroll reaches the quad
+            if ((word & kGroupMask) == 0) continue;   // none of the next kUnroll reaches the quad
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const int j = j0 + u;
