@@ -223,69 +223,90 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
     counts_from_diff(diff, vp.tiles_y, a.counts1 + (int64_t)vp.row_base * a.chunks1 + part, a.chunks1, lane);
 }
 
-// Cursor windows: bucket cursors are loaded 128 at a time into two VGPRs
-// (lane l holds buckets w0 + l and w0 + 64 + l) and read back as scalars, so
-// a bucket's walk starts without a dependent memory load.
-constexpr int kWindow = 128;
+// The row walk goes band by band (kRowBand rows): the chunk's items that
+// reach band b are packed, in chunk order, into dense batches in LDS (payload
+// and their rows inside the band), and only those batches walk the band's
+// rows.  An item covers a few of the view's rows, so a plain walk of every
+// row against every batch would mostly test items that miss the row.  Inside
+// a row the items keep their chunk order, so the output is that of the plain
+// walk.  Cursors of a band's rows are loaded into one VGPR (lane q: row
+// b0 + q) and read back as scalars.
+constexpr int kRowBand = 8;   // measured: 4 and 12 were slower
+static_assert(kRowBand <= 15, "band-relative rows in 4 bits");
 
-// The walk of one bucket: for each batch of 64 items, covering lanes write
-// their payload at cur + (covering lanes below them).  The base pointer and
-// cursor are wave-uniform (scalar registers).  A bucket whose run cannot pass
-// the capacity (cur + every item of the chunk) takes the walk without the
-// per-lane bound test.
-template <bool kChecked, int kItems, typename P>
-__device__ __forceinline__ void walk_run(uint32_t bucket, uint32_t cur, const uint32_t (&first)[kItems],
-                                         const uint32_t (&span)[kItems], const P (&payload)[kItems],
-                                         P* __restrict__ out, uint64_t capacity)
+template <bool kChecked>
+__device__ __forceinline__ void walk_row_band(const uint2* s_p, const uint8_t* s_r, uint32_t n, uint32_t cur_b,
+                                              uint2* __restrict__ out, uint64_t capacity, int lane)
 {
-    P* base = out + cur;
+    uint32_t cur[kRowBand];
 #pragma unroll
-    for (int b = 0; b < kItems; ++b) {
-        const bool cover = bucket - first[b] < span[b];
-        const uint64_t m = __ballot(cover);
-        if (cover) {
-            const uint32_t below = lanes_below(m);
-            if (!kChecked || (uint64_t)cur + below < capacity) base[below] = payload[b];
+    for (int q = 0; q < kRowBand; ++q) cur[q] = __builtin_amdgcn_readlane(cur_b, q);
+    for (uint32_t k0 = 0; k0 < n; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        uint32_t rs = 0u;
+        uint2 p = make_uint2(0u, 0u);
+        if (k < n) {
+            rs = s_r[k];
+            p = s_p[k];
         }
-        const uint32_t n = (uint32_t)__popcll(m);
-        cur += n;
-        base += n;
+        // band-relative rows [r0, r0 + w): packed items are clipped to the
+        // band and to the view, so a row outside them is never covered
+        const uint32_t r0 = rs & 15u, w = (rs >> 4) - r0;
+#pragma unroll
+        for (int q = 0; q < kRowBand; ++q) {
+            const bool cover = (uint32_t)q - r0 < w;
+            const uint64_t m = __ballot(cover);
+            if (cover) {
+                const uint32_t pos = cur[q] + lanes_below(m);
+                if (!kChecked || pos < capacity) out[pos] = p;
+            }
+            cur[q] += (uint32_t)__popcll(m);
+        }
     }
-}
-
-template <int kItems, typename P>
-__device__ __forceinline__ void walk_bucket(uint32_t bucket, uint32_t cur, const uint32_t (&first)[kItems],
-                                            const uint32_t (&span)[kItems], const P (&payload)[kItems],
-                                            P* __restrict__ out, uint64_t capacity)
-{
-    if ((uint64_t)cur + kItems * 64 <= capacity)
-        walk_run<false>(bucket, cur, first, span, payload, out, capacity);
-    else
-        walk_run<true>(bucket, cur, first, span, payload, out, capacity);
 }
 
 template <int kItems>
 __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
 {
+    __shared__ uint2 s_p[kItems * 64];
+    __shared__ uint8_t s_r[kItems * 64];
     const int lane = threadIdx.x, c = chunk_of_block();
     Items1<kItems> it;
     if (!load_items1(a, c, lane, it)) return;
     // row r of the view: cursor[r * chunks1]
     const uint32_t* cursor = a.counts1 + (int64_t)a.views[it.view].row_base * a.chunks1 + it.part;
-    uint2 payload[kItems];
+    auto band_cursors = [&](int b0) -> uint32_t {
+        const int r = b0 + lane;
+        return (lane < kRowBand && r < it.hi) ? cursor[(int64_t)r * a.chunks1] : 0u;
+    };
+    const int blo = it.lo / kRowBand * kRowBand;
+    uint32_t cur_b = blo < it.hi ? band_cursors(blo) : 0u;
+    for (int b0 = blo; b0 < it.hi; b0 += kRowBand) {
+        const uint32_t by0 = (uint32_t)b0, by1 = min((uint32_t)(b0 + kRowBand), (uint32_t)it.hi);
+        const uint32_t cur_next = (b0 + kRowBand < it.hi) ? band_cursors(b0 + kRowBand) : 0u;   // prefetch
+        // pack the items reaching the band, clipped to it, in chunk order
+        uint32_t n = 0;
 #pragma unroll
-    for (int b = 0; b < kItems; ++b) payload[b] = make_uint2(it.g[b], it.xs[b]);
-    for (int w0 = it.lo; w0 < it.hi; w0 += kWindow) {
-        const int ra = w0 + lane, rb = w0 + 64 + lane;
-        const uint32_t cur_a = ra < it.hi ? cursor[(int64_t)ra * a.chunks1] : 0u;
-        const uint32_t cur_b = rb < it.hi ? cursor[(int64_t)rb * a.chunks1] : 0u;
-        const int e0 = min(it.hi, w0 + 64), e1 = min(it.hi, w0 + kWindow);
-        for (int r = w0; r < e0; ++r)
-            walk_bucket<kItems>((uint32_t)r, __builtin_amdgcn_readlane(cur_a, r - w0), it.y0, it.h, payload,
-                                  a.row_ent, a.row_capacity);
-        for (int r = w0 + 64; r < e1; ++r)
-            walk_bucket<kItems>((uint32_t)r, __builtin_amdgcn_readlane(cur_b, r - w0 - 64), it.y0, it.h, payload,
-                                  a.row_ent, a.row_capacity);
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t e0 = max(it.y0[j], by0), e1 = min(it.y0[j] + it.h[j], by1);
+            const bool reach = e1 > e0;
+            const uint64_t m = __ballot(reach);
+            if (reach) {
+                const uint32_t slot = n + lanes_below(m);
+                s_p[slot] = make_uint2(it.g[j], it.xs[j]);
+                s_r[slot] = (uint8_t)((e0 - by0) | ((e1 - by0) << 4));   // 0 <= e0 < e1 <= kRowBand
+            }
+            n += (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        // row cursors increase down the view: the band's last one bounds them all
+        const uint32_t cur_last = __builtin_amdgcn_readlane(cur_b, (int)(by1 - by0) - 1);
+        if ((uint64_t)cur_last + n <= a.row_capacity)
+            walk_row_band<false>(s_p, s_r, n, cur_b, a.row_ent, a.row_capacity, lane);
+        else
+            walk_row_band<true>(s_p, s_r, n, cur_b, a.row_ent, a.row_capacity, lane);
+        __syncthreads();   // the LDS is free for the next band
+        cur_b = cur_next;
     }
 }
 
