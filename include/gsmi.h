@@ -39,7 +39,7 @@ typedef enum {
     GS_ERR_OUT_OF_MEMORY = 2,    /* device allocation of the workspace failed */
     GS_ERR_CAPACITY = 3,         /* more (Gaussian, tile) pairs than allowed */
     GS_ERR_HIP = 4,              /* a HIP runtime call failed (message says which) */
-    GS_ERR_UNSUPPORTED = 5       /* valid request outside what this build handles */
+    GS_ERR_UNSUPPORTED = 5       /* valid request outside what the library supports */
 } gs_status;
 
 typedef enum { GS_F32 = 0, GS_BF16 = 1, GS_F16 = 2 } gs_dtype;
@@ -356,13 +356,13 @@ gs_status gs_get_tuning(gs_context* ctx, gs_tuning* out);
 
 /* Autotuner: renders the given views (as gs_render_batched, whose outputs
  * it overwrites) with each candidate shape, one parameter at a time from the
- * context's current tuning -- sort_items judged by the depth-sort stage time,
+ * context's current tuning -- sort_items scored by the depth-sort stage time,
  * bin_row_items and bin_tile_items by the four binning stages,
  * blend_tile_group by the blend -- each candidate once untimed and then reps
  * times timed by the stage events, keeps the fastest value of each parameter
  * before tuning the next, and leaves the result as the context's tuning.
  *   out     the chosen tuning (may be NULL)
- *   out_ms  NULL, or host array [GS_TUNE_CANDIDATES]: the mean judged time
+ *   out_ms  NULL, or host array [GS_TUNE_CANDIDATES]: the mean scored time
  *           of every candidate in the order sort_items 4, 8, 16;
  *           bin_row_items 4, 8, 16; bin_tile_items 8, 16, 32;
  *           blend_tile_group 1, 2, 4, 8, 16, 32, 64

@@ -346,7 +346,7 @@ class Renderer:
     def autotune(self, dev_scene: dict, cameras: list, reps: int = 3, background=(0.0, 0.0, 0.0),
                  pair_capacity: int = 0, stream=None) -> dict:
         """gs_autotune over a batched render of ``cameras``: returns the chosen
-        tuning and the judged milliseconds of every candidate."""
+        tuning and the scored milliseconds of every candidate."""
         torch = _torch()
         dev = dev_scene["means"].device
         views, outs = self._views(cameras, None, dev)

@@ -888,7 +888,7 @@ gs_tuning to_abi(const Tuning& t)
 }
 
 // The candidates gs_autotune tries, in the order of its out_ms array: each
-// parameter of Tuning with the stages whose time it is judged by (indices
+// parameter of Tuning with the stages whose time scores it (indices
 // into the GS_NUM_STAGES stage times).
 struct TuneParam {
     int Tuning::*field;
