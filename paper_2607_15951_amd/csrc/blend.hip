@@ -43,9 +43,14 @@ static_assert(64 % kUnroll == 0, "groups do not straddle a 64-entry mask word");
 constexpr uint64_t kGroupMask = kUnroll == 64 ? ~0ull : ((1ull << kUnroll) - 1ull);
 
 // kStats: the tracing variant, which also records its work per tile
-// (a.tile_work)
+// (a.tile_work).  The plain kernel asks for 7 waves per SIMD (at most 72
+// VGPRs; it needs no spills there): its batches wait on gathers and barriers,
+// and more resident tiles hide more of that (measured: 5 and 6 waves ran
+// alike, 7 ran 4% faster, 8 spilled and ran slower).  The tracing kernel keeps
+// the compiler's own budget, where its counters need no spills.
 template <bool kStats>
-__global__ __launch_bounds__(256) void blend_kernel(BlendArgs a, uint64_t capacity)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 : 7))) void blend_kernel(
+    BlendArgs a, uint64_t capacity)
 {
     __shared__ float4 s0[256 + kUnroll];   // du_hi, dv_hi, du_lo, dv_lo  (centre - tile origin)
     __shared__ float4 s1[256 + kUnroll];   // A', B', C', opacity  (A' = -0.5 log2(e) A, ...)

@@ -74,7 +74,10 @@ __device__ __forceinline__ float wave_sum9(const float g[kGrad2d], int lane, int
     return e;
 }
 
-__global__ __launch_bounds__(256) void blend_backward_kernel(BlendBackArgs a, uint64_t capacity)
+// 6 waves per SIMD (79 VGPRs, no spills; the compiler's own budget of 84
+// leaves 5): its 23.8 KB of LDS also allows 6 tiles per CU
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void blend_backward_kernel(
+    BlendBackArgs a, uint64_t capacity)
 {
     __shared__ float4 s0[256];   // du_hi, dv_hi, du_lo, dv_lo
     __shared__ float4 s1[256];   // A', B', C', opacity
