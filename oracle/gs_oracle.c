@@ -425,7 +425,8 @@ int64_t or_tile_list(int64_t n, const int32_t* rect, const uint32_t* tiles_touch
  *             conic and opacity and 2u in exp2 stays within half of e_a;
  *             an alpha clamped to 0.99 carries only the 2u of that constant;
  *     T:      |T' / 1e-4 - 1| / e_T with e_T the accumulated relative error
- *             bound of T' (each factor 1 - a contributes e_a a / (1 - a) + 3u).
+ *             bound of T': each factor 1 - a contributes (e_a / 2) a / (1 - a)
+ *             (the alpha bound above) plus u (one rounding of T (1 - a)).
  * ------------------------------------------------------------------------- */
 static void composite_pixel(double px, double py, const uint32_t* list, int64_t len, int64_t n,
                             const double* mean2d, const double* conic, const double* opacity,
@@ -451,7 +452,7 @@ static void composite_pixel(double px, double py, const uint32_t* list, int64_t 
         if (ma < m_alpha) m_alpha = ma;
         if (a < 1.0 / 255.0) continue;
         double Tn = T * (1.0 - a);
-        double eTn = eT + ea * a / (1.0 - a) + 3.0 * u;
+        double eTn = eT + 0.5 * ea * a / (1.0 - a) + u;
         double mt = fabs(Tn * 1e4 - 1.0) / eTn;
         if (mt < m_T) m_T = mt;
         if (Tn < 1e-4) break;

@@ -214,7 +214,9 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 
     double Sg[9];
     const bool cov_ok = world_covariance(l0, l1, l2, qw, qx, qy, qz, Sg);
-    const float opacity = 1.0f / (1.0f + __expf(-logit));
+    // sigmoid in double, rounded once: the opacity carries one float rounding
+    // whatever the logit (a float exp of -logit would carry about |logit| of them)
+    const float opacity = (float)(1.0 / (1.0 + exp(-(double)logit)));
     __shared__ uint32_t s_vis[4], s_pairs[4], s_front[4];
 
     const int n_views = kOneView ? 1 : a.n_views;

@@ -94,7 +94,13 @@ def check_projection(g, p, label=""):
     return amb
 
 
-def check_image(g, o, label="", tol=IMAGE_TOL, max_ambiguous_frac=5e-3):
+# Ambiguous pixels observed on the seeded parity scenes (whole images) reach
+# 1.2e-3 of the pixels (the 500k-Gaussian 1280x720 mixture, 1088 pixels);
+# the cap is about twice that.
+MAX_AMBIGUOUS_FRAC = 2.5e-3
+
+
+def check_image(g, o, label="", tol=IMAGE_TOL, max_ambiguous_frac=MAX_AMBIGUOUS_FRAC):
     """Image, final T and n_contrib against the oracle composite."""
     amb = oracle.ambiguous_mask(o)
     P = amb.size
@@ -120,12 +126,31 @@ def psnr(a, b):
     return math.inf if mse == 0 else 10 * math.log10(1.0 / mse)
 
 
-def check_lists_full(g, o, label=""):
-    """Whole sorted lists against the oracle's qsort of the emitted pairs."""
-    assert g["num_pairs"] == len(o["keys"]), label
-    counts = (o["ranges"][:, 1] - o["ranges"][:, 0]).astype(np.uint64)
-    want_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.uint32)
-    np.testing.assert_array_equal(g["tile_offsets"], want_off, err_msg=label)
-    np.testing.assert_array_equal(g["values"], o["values"], err_msg=label)
+def check_lists_full(g, o, label="", exclude=()):
+    """Whole sorted lists against the oracle's qsort of the emitted pairs.
+
+    ``exclude``: Gaussians whose 3-sigma radius sits within rounding of an
+    integer (check_projection's radius-ambiguous set), whose rectangles may
+    legitimately differ.  Their pairs are removed from both sides and every
+    other pair is compared in order, tile by tile; returns the number of
+    pairs removed (GPU side, oracle side)."""
+    exclude = np.asarray(exclude, np.int64)
+    if exclude.size == 0:
+        assert g["num_pairs"] == len(o["keys"]), label
+        counts = (o["ranges"][:, 1] - o["ranges"][:, 0]).astype(np.uint64)
+        want_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.uint32)
+        np.testing.assert_array_equal(g["tile_offsets"], want_off, err_msg=label)
+        np.testing.assert_array_equal(g["values"], o["values"], err_msg=label)
+        if "keys" in g:
+            np.testing.assert_array_equal(g["keys"], o["keys"], err_msg=label)
+        return 0, 0
+    T = len(g["tile_offsets"]) - 1
+    g_tile = np.repeat(np.arange(T, dtype=np.int64), np.diff(g["tile_offsets"].astype(np.int64)))
+    keep_g = ~np.isin(g["values"], exclude)
+    o_tile = (o["keys"] >> np.uint64(32)).astype(np.int64)
+    keep_o = ~np.isin(o["values"], exclude)
+    np.testing.assert_array_equal(g_tile[keep_g], o_tile[keep_o], err_msg=f"{label} tiles of kept pairs")
+    np.testing.assert_array_equal(g["values"][keep_g], o["values"][keep_o], err_msg=f"{label} kept pairs")
     if "keys" in g:
-        np.testing.assert_array_equal(g["keys"], o["keys"], err_msg=label)
+        np.testing.assert_array_equal(g["keys"][keep_g], o["keys"][keep_o], err_msg=f"{label} kept keys")
+    return int((~keep_g).sum()), int((~keep_o).sum())

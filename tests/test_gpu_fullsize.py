@@ -34,11 +34,10 @@ pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
 
 TILE = 16
 IMAGE_TOL = 1e-4
-# The sample is biased toward the heaviest tiles, where pixels composite the
-# most entries and the transmittance error bound (which grows with every
-# composited entry) leaves more pixels within reach of a threshold; the
-# whole-image tests on small scenes keep 5e-3.
-MAX_AMBIGUOUS_FRAC = 1e-2
+# Ambiguous pixels of the sampled tiles, as the oracle marks them for these
+# seeded scenes: C3 fp32 2 of 4224, C3 bf16 8 of 3712, C5 bf16 17 of 3584,
+# C5 fp16 11 of 3584; each case is capped at about twice its count.
+MAX_AMBIGUOUS = {"C3/fp32": 4, "C3/bf16": 16, "C5/bf16": 34, "C5/fp16": 22}
 
 
 def say(msg):
@@ -141,6 +140,9 @@ def fullsize_case(renderer, workload: str, dtype: int, n_random: int):
         want = oracle.tile_list(p, t)
         if not differ:
             np.testing.assert_array_equal(got, want, err_msg=f"{label} tile {t} list")
+        else:   # every pair of the Gaussians binned alike, in order
+            np.testing.assert_array_equal(got[~np.isin(got, differ)], want[~np.isin(want, differ)],
+                                          err_msg=f"{label} tile {t} list")
         xs, ys = tile_pixels(t, tx, W, H)
         o5, marg = oracle.composite_pixels(p, xs, ys, want)
         amb_px = (marg[:, 0] < oracle.ALPHA_MARGIN) | (marg[:, 1] < oracle.T_MARGIN)
@@ -171,7 +173,7 @@ def fullsize_case(renderer, workload: str, dtype: int, n_random: int):
                    psnr_vs_fp64_master_db=(math.inf if mse == 0 else 10 * math.log10(1.0 / mse)))
     say("[fullsize] " + json.dumps(rep))
     assert worst <= IMAGE_TOL, f"{label}: max-abs {worst:.3e} on unambiguous sampled pixels"
-    assert n_amb <= max(4, MAX_AMBIGUOUS_FRAC * n_pix), f"{label}: {n_amb} ambiguous of {n_pix}"
+    assert n_amb <= MAX_AMBIGUOUS[label], f"{label}: {n_amb} ambiguous of {n_pix}"
     return rep
 
 

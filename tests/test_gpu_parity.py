@@ -40,11 +40,11 @@ def full_parity(renderer, scene, cam, label, dtype=0, background=(0.0, 0.0, 0.0)
     ref_scene = dequantised(scene, dtype)
     o = oracle.render(ref_scene, cam, background=background)
     amb = check_projection(g, o["proj"], label)
-    if len(amb) == 0:
-        check_lists_full(g, o, label)
+    removed = check_lists_full(g, o, label, exclude=amb)
     stats = check_image(g, o, label)
     say(f"[parity] {label}: K={len(o['keys'])} max_abs={stats['max_abs']:.2e} "
-        f"ambiguous={stats['ambiguous']} psnr={stats['psnr']:.1f}")
+        f"ambiguous={stats['ambiguous']} psnr={stats['psnr']:.1f} radius_ambiguous={len(amb)} "
+        f"pairs_removed={removed}")
     return g, o, stats
 
 

@@ -412,3 +412,35 @@ def test_culls():
     # z_cam = 0.1 (behind near 0.2) culled; 0.15 culled; zero quaternion culled; NaN culled
     assert list(p["tiles_touched"] > 0) == [False, False, False, True, False]
     assert list(p["radius"] > 0) == [False, False, False, True, False]
+
+
+def test_composite_pixels_and_tile_list_equal_the_whole_frame_path():
+    """The per-tile entry points the full-size tests use (``tile_list`` and
+    ``composite_pixels``) against the whole-frame path (emitted pairs sorted by
+    qsort, ``composite`` over every pixel): same lists, and bit for bit the
+    same colour, final T, n_contrib and decision margins on every pixel of
+    every tile, the ragged right column and bottom row included."""
+    sc = scenes.make_scene("C2", n=6000, seed=77)
+    cam = scenes.look_at_camera([0.9, -0.6, -2.8], 203, 115)   # ragged: 13 x 8 tiles
+    o = oracle.render(sc, cam, background=(0.1, 0.2, 0.3))
+    proj = o["proj"]
+    tx, ty = proj["tiles_x"], proj["tiles_y"]
+    W, H = cam["width"], cam["height"]
+    checked = 0
+    for t in range(tx * ty):
+        s, e = (int(v) for v in o["ranges"][t])
+        lst = o["values"][s:e]
+        np.testing.assert_array_equal(oracle.tile_list(proj, t), lst, err_msg=f"tile {t}")
+        x0, y0 = (t % tx) * 16, (t // tx) * 16
+        ys, xs = np.mgrid[y0:min(y0 + 16, H), x0:min(x0 + 16, W)]
+        xs, ys = xs.ravel(), ys.ravel()
+        o5, marg = oracle.composite_pixels(proj, xs, ys, lst, background=(0.1, 0.2, 0.3))
+        np.testing.assert_array_equal(o5[:, :3], o["image"][:, ys, xs].T)
+        np.testing.assert_array_equal(o5[:, 3], o["final_T"][ys, xs])
+        np.testing.assert_array_equal(o5[:, 4], o["n_contrib"][ys, xs])
+        np.testing.assert_array_equal(marg[:, 0], o["margin_alpha"][ys, xs])
+        np.testing.assert_array_equal(marg[:, 1], o["margin_T"][ys, xs])
+        checked += len(xs)
+    assert checked == W * H
+    assert len(o["keys"]) > 20 * tx * ty   # lists long enough to terminate pixels
+    assert (o["n_contrib"] > 0).mean() > 0.5
