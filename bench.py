@@ -39,7 +39,11 @@ TILE = 16
 # transmittance update (2) and the weighted colour accumulation (1 + 3 x 2).
 FLOPS_EVAL = 13
 FLOPS_COMPOSITE = 9
-CHUNK_ENTRIES = 1024  # row entries per second-level binning wave
+# MI355X FP32 vector peak without packed FP32 (the library is built without
+# packed-FP32 instruction selection): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x
+# 2.4 GHz
+FP32_VECTOR_NONPACKED_TFLOPS = 78.6
+SORT_PASSES = 4       # 8-bit LSD passes of the depth sort
 
 
 def log(msg):
@@ -51,18 +55,28 @@ def attr_bytes(dtype: int) -> int:
 
 
 def algorithmic_bytes(stage: str, n: int, n_vis: int, K: int, R: int, deg: int, dtype: int, W: int, H: int,
-                      stats: dict) -> float:
-    """HBM bytes one launch of a single-kernel stage must move: its compulsory
-    reads and writes, each input and output once."""
+                      stats: dict, tuning: dict | None = None) -> float:
+    """HBM bytes one frame's launches of a stage must move: each input and
+    output once (the per-unit figures below, times the units of the frame).
+    ``tuning`` gives the chunk sizes of the binning (count arrays and cursors
+    scale with them)."""
+    tu = tuning or {"bin_row_items": 8, "bin_tile_items": 16}
     tx, ty = (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
+    chunks1 = (n + 64 * tu["bin_row_items"] - 1) // (64 * tu["bin_row_items"])
+    chunks2 = R // (64 * tu["bin_tile_items"]) + ty
     if stage == "project":
         per_in = 12 + attr_bytes(dtype) * (3 + 4 + 1 + 3 * (deg + 1) ** 2)
         per_out = 48 + 4 + 4 + 4 + 8
         return n * (per_in + per_out)
-    if stage == "bin_row_scatter":   # sorted index + rectangle per Gaussian, 8-byte row entries out
-        return n_vis * (4 + 8) + R * 8 + ((n + 511) // 512) * ty * 4
+    if stage == "depth_sort":        # per 8-bit pass: keys read for the digit counts, keys + values read and written
+        return SORT_PASSES * n * (4 + 8 + 8)
+    if stage == "bin_row_count":     # sorted index + rectangle per Gaussian; per (row, chunk) count written and scanned
+        return n * (4 + 8) + ty * chunks1 * (4 + 8)
+    if stage == "bin_row_scatter":   # sorted index + rectangle per visible Gaussian, 8-byte row entries out
+        return n_vis * (4 + 8) + R * 8 + chunks1 * ty * 4
+    if stage == "bin_tile_count":    # row entries in; per (chunk, column) count written and scanned; tile offsets
+        return R * 8 + chunks2 * tx * (4 + 8) + (tx * ty + 1) * 4
     if stage == "bin_tile_scatter":  # row entries in, chunk prefixes, the values out
-        chunks2 = R // CHUNK_ENTRIES + ty
         return R * 8 + chunks2 * tx * 4 * 2 + K * 4
     if stage == "blend":             # list entry + 48-byte record per staged entry; rgb, T, n_contrib per pixel
         return stats["staged"] * (4 + 48) + W * H * 20
@@ -142,6 +156,36 @@ def source_digest(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
+def library_digest() -> str:
+    """Digest of every library source: a frame's counter reading stays valid
+    while none of them changes."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2607_15951_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_frame_traffic(workload: str, variant: str):
+    """(fetch, write) HBM bytes per frame over all kernels from the committed
+    counter summary, with the launch shapes they were taken with, or None
+    when there is none or a library source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            parts = line.split()
+            # frame <workload> <variant> <library digest> <fetch bytes> <write bytes> <tuning>
+            if len(parts) >= 7 and parts[0] == "frame" and parts[1] == workload and parts[2] == variant:
+                if parts[3] != library_digest():
+                    return None
+                return {"fetch": float(parts[4]), "write": float(parts[5]), "tuning": parts[6]}
+    return None
+
+
 def read_traffic(kernel: str, workload: str, variant: str):
     """HBM bytes per launch of ``kernel`` from the committed counter summary,
     or None when there is none or the kernel's sources changed since."""
@@ -203,7 +247,7 @@ def _pmc_avg(path: str, counter: str) -> dict:
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str, workload: str,
-                  variant: str) -> str:
+                  variant: str, tuning: str | None = None) -> str:
     """HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
     each scaled by the reading of a plain copy of known size."""
     copy_bytes = 1 << 30
@@ -223,7 +267,34 @@ def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_writ
     for k in sorted(set(fetch) | set(write)):
         lines.append(f"# raw {k}: FETCH_SIZE {fetch.get(k, float('nan')):.0f} KiB, "
                      f"WRITE_SIZE {write.get(k, float('nan')):.0f} KiB per dispatch")
+    if tuning:
+        # a --frames-only run renders whole frames and nothing else: every
+        # dispatch belongs to one, and the projection runs once per frame
+        ff = _pmc_total(fetch_csv, "FETCH_SIZE")
+        ww = _pmc_total(write_csv, "WRITE_SIZE")
+        frames = ff["frames"]
+        lines.append(f"# frame totals over {frames} frames (every dispatch of a --frames-only run), "
+                     "bytes per frame: frame <workload> <variant> <library digest> <fetch> <write> <tuning>")
+        lines.append(f"frame {workload} {variant} {library_digest()} {ff['kib'] * 1024 * f_fac / frames:.0f} "
+                     f"{ww['kib'] * 1024 * w_fac / frames:.0f} {tuning}")
     return "\n".join(lines)
+
+
+def _pmc_total(path: str, counter: str) -> dict:
+    """Sum of one counter over every dispatch of a run, and the number of
+    frames (projection dispatches) it covers."""
+    kib, frames = 0.0, 0
+    seen = set()
+    for r in _csv_rows(path):
+        if r["Counter_Name"] != counter:
+            continue
+        kib += float(r["Counter_Value"])
+        name = kernel_short_name(r["Kernel_Name"], templates=False)
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id") or id(r)
+        if name == "project_kernel" and key not in seen:
+            seen.add(key)
+            frames += 1
+    return {"kib": kib, "frames": max(frames, 1)}
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
@@ -369,6 +440,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--tuning", metavar="SORT,ROW,TILE,GROUP",
+                    help="launch shapes to use instead of autotuning (sort_items, bin_row_items, bin_tile_items, "
+                         "blend_tile_group)")
+    ap.add_argument("--frames-only", type=int, metavar="F",
+                    help="render F frames of the workload (after one warm-up frame) and nothing else, for "
+                         "per-frame counter totals; prints one JSON line")
     ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV",
                     help="print a rocprofv3 --stats kernel summary as a markdown table, then exit")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -381,7 +458,8 @@ def main():
         print(summarize_stats(args.summarize_stats))
         return
     if args.summarize_pmc:
-        print(summarize_pmc(*args.summarize_pmc, workload=args.workload, variant=args.variant))
+        print(summarize_pmc(*args.summarize_pmc, workload=args.workload, variant=args.variant,
+                            tuning=args.tuning))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this single-GPU build "
@@ -410,11 +488,22 @@ def main():
     # launch shapes for this workload (speed only: every shape renders the
     # same bits), chosen before the timed region like the warm-up
     tune = None
-    if not args.no_autotune:
+    if args.tuning:
+        vals = [int(v) for v in args.tuning.split(",")]
+        r.set_tuning(sort_items=vals[0], bin_row_items=vals[1], bin_tile_items=vals[2], blend_tile_group=vals[3])
+    elif not args.no_autotune and not args.frames_only:
         log("[bench] autotune")
         tune = r.autotune(dev, [cam], reps=5)
         log("[bench] tuning " + json.dumps(tune["tuning"]))
     main_tuning = r.tuning()   # the shapes of the timed frames (later variants retune)
+    if args.frames_only:
+        for _ in range(args.frames_only + 1):
+            r.render(dev, cam, W, H, out=out)
+        torch.cuda.synchronize()
+        r.close()
+        print(json.dumps({"frames": args.frames_only + 1, "workload": args.workload, "tuning": main_tuning}),
+              flush=True)
+        return
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
         r.render(dev, cam, W, H, out=out)
@@ -509,7 +598,7 @@ def main():
                                           "flops_per_evaluation": FLOPS_EVAL,
                                           "flops_per_composite": FLOPS_COMPOSITE}}
     else:
-        by = algorithmic_bytes(dom, n, n_vis, K, R, deg, dtype, W, H, stats)
+        by = algorithmic_bytes(dom, n, n_vis, K, R, deg, dtype, W, H, stats, tuned)
         achieved = by / (stage_ms[dom] * 1e-3) / 1e9
         kname = stage_kernel(dom, dtype, deg, tuned)
         roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -517,9 +606,32 @@ def main():
                 "traffic": read_traffic(kname, args.workload, args.variant),
                 "bytes_per_launch": int(by)}
     stage_gbs = {}
-    for k in single:
-        by = algorithmic_bytes(k, n, n_vis, K, R, deg, dtype, W, H, stats)
+    stage_bytes = {}
+    for k in gs.STAGES:
+        by = algorithmic_bytes(k, n, n_vis, K, R, deg, dtype, W, H, stats, tuned)
+        stage_bytes[k] = by
         stage_gbs[k] = round(by / (stage_ms[k] * 1e-3) / 1e9, 1) if stage_ms[k] > 0 else None
+    # the whole frame: every stage's algorithmic bytes over the frame time
+    frame_bytes = sum(stage_bytes.values())
+    frame_gbs = frame_bytes / (ms_per_step * 1e-3) / 1e9
+    ft = read_frame_traffic(args.workload, args.variant)
+    frame = {"algorithmic_bytes": int(frame_bytes), "achieved_GBps": round(frame_gbs, 1), "peak_GBps": HBM_PEAK_GBS,
+             "frac": round(frame_gbs / HBM_PEAK_GBS, 4),
+             "stage_algorithmic_bytes": {k: int(v) for k, v in stage_bytes.items()},
+             "counter_bytes": None if ft is None else int(ft["fetch"] + ft["write"]),
+             "counter_GBps": None if ft is None else round((ft["fetch"] + ft["write"]) / (ms_per_step * 1e-3) / 1e9, 1),
+             "counter_tuning": None if ft is None else ft["tuning"]}
+    # blend work: the evaluations Eq. 1 needs (each pixel up to its
+    # termination) and the lane evaluations the kernel executed (64 per wave
+    # and staged entry it did not skip)
+    blend_s = stage_ms["blend"] * 1e-3
+    blend_work = {**stats,
+                  "tflops": round((FLOPS_EVAL * stats["evaluations"] + FLOPS_COMPOSITE * stats["composited"])
+                                  / blend_s / 1e12, 3),
+                  "tflops_executed": round((FLOPS_EVAL * stats["lane_evaluations"] + FLOPS_COMPOSITE *
+                                            stats["composited"]) / blend_s / 1e12, 3),
+                  "peak_tflops_nonpacked": FP32_VECTOR_NONPACKED_TFLOPS}
+    blend_work["frac_executed"] = round(blend_work["tflops_executed"] / FP32_VECTOR_NONPACKED_TFLOPS, 4)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -545,8 +657,8 @@ def main():
                    "row_entries": R, "visible": n_vis},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stages_algorithmic_GBps": stage_gbs,
-        "blend_work": {**stats, "tflops": round((FLOPS_EVAL * stats["evaluations"] + FLOPS_COMPOSITE *
-                                                 stats["composited"]) / (stage_ms["blend"] * 1e-3) / 1e12, 3)},
+        "frame_hbm": frame,
+        "blend_work": blend_work,
         "roofline": roof,
         "tuning": tune,
         "variants": variants,

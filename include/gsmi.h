@@ -210,8 +210,10 @@ typedef struct {
     float* sh;
 } gs_gradients;
 
-/* Backward of the last render on ctx (gs_render or gs_render_batched; the
- * differentiable part of Sec. 3.1 stages 1, 2 and 4 -- the tile lists and
+/* Backward of the last render on ctx (gs_render, gs_render_batched, or the
+ * last gs_graph_launch of a graph on ctx, with the cameras and outputs that
+ * launch rendered; the differentiable part of Sec. 3.1 stages 1, 2 and 4 --
+ * the tile lists and
  * their order are held fixed, as are the 3-sigma rectangles): given
  * dL/d(out_rgb) per view and optionally dL/d(out_final_T), writes dL/d(the
  * Gaussian parameters) into grads.  The blend is recomputed front to back
@@ -339,8 +341,15 @@ gs_status gs_get_order_reuse(gs_context* ctx, uint32_t* out2);
  *   bin_tile_items    row entries per lane of a tile-binning wavefront:
  *                     8, 16 or 32
  *   blend_tile_group  consecutive tiles (row-major) dealt to one XCD by the
- *                     blend and its backward: 1 .. 64
- * A new context starts at {8, 8, 16, 16}.  gs_set_tuning applies to the
+ *                     blend and its backward: 1 .. 64; or 0: every tile's
+ *                     workgroup is dispatched heaviest first, by the work
+ *                     (list entries walked) each tile took in the last
+ *                     render on the context when it had the same tile
+ *                     layout, else by list length -- the frame-to-frame
+ *                     coherence of Sec. 5.7 applied to the load imbalance of
+ *                     the per-tile blend (Sec. 6); the backward follows its
+ *                     render's order
+ * A new context starts at {8, 8, 16, 0}.  gs_set_tuning applies to the
  * following renders and backwards (a backward uses its render's shapes; a
  * captured graph keeps those of its capture); GS_ERR_INVALID_ARGUMENT for an
  * unsupported value, leaving the tuning unchanged. */
@@ -365,11 +374,11 @@ gs_status gs_get_tuning(gs_context* ctx, gs_tuning* out);
  *   out_ms  NULL, or host array [GS_TUNE_CANDIDATES]: the mean scored time
  *           of every candidate in the order sort_items 4, 8, 16;
  *           bin_row_items 4, 8, 16; bin_tile_items 8, 16, 32;
- *           blend_tile_group 1, 2, 4, 8, 16, 32, 64
+ *           blend_tile_group 0, 1, 2, 4, 8, 16, 32, 64
  * Profiling flags are restored afterwards.  Errors as gs_render_batched,
  * GS_ERR_INVALID_ARGUMENT for reps outside [1, 1000] or a context bound to a
  * graph; on error the tuning is left as it was. */
-#define GS_TUNE_CANDIDATES 16
+#define GS_TUNE_CANDIDATES 17
 gs_status gs_autotune(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
                       const gs_render_opts* opts, int32_t reps, void* stream, gs_tuning* out, float* out_ms);
 

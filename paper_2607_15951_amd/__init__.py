@@ -70,7 +70,7 @@ class gs_tuning(C.Structure):
 
 
 TUNE_CANDIDATES = [("sort_items", v) for v in (4, 8, 16)] + [("bin_row_items", v) for v in (4, 8, 16)] + \
-    [("bin_tile_items", v) for v in (8, 16, 32)] + [("blend_tile_group", v) for v in (1, 2, 4, 8, 16, 32, 64)]
+    [("bin_tile_items", v) for v in (8, 16, 32)] + [("blend_tile_group", v) for v in (0, 1, 2, 4, 8, 16, 32, 64)]
 
 
 class gs_view(C.Structure):
@@ -188,11 +188,48 @@ def scene_to_device(scene: dict, dtype: int = GS_F32, device="cuda"):
     return out
 
 
+def _check_tensor(t, name: str, shape: tuple, dtype, device):
+    """The C ABI takes bare device pointers and cannot see a tensor's device,
+    dtype, layout or size: they are checked here, before any call."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a cuda tensor (got {t.device})")
+    if t.device != device:
+        raise ValueError(f"{name} must live on {device} (got {t.device})")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _attr_torch_dtype(attr_dtype: int):
+    torch = _torch()
+    return {GS_F32: torch.float32, GS_BF16: torch.bfloat16, GS_F16: torch.float16}[attr_dtype]
+
+
 def make_gaussians(dev_scene: dict) -> gs_gaussians:
+    torch = _torch()
+    means = dev_scene["means"]
+    if not isinstance(means, torch.Tensor) or means.dim() != 2 or means.shape[0] != 3:
+        raise ValueError("means must be a [3, n] tensor")
+    n = int(means.shape[1])
+    deg = int(dev_scene["sh_degree"])
+    attr = int(dev_scene.get("attr_dtype", GS_F32))
+    if deg not in (0, 1, 2, 3) or attr not in (GS_F32, GS_BF16, GS_F16):
+        raise ValueError("sh_degree must be 0..3 and attr_dtype GS_F32, GS_BF16 or GS_F16")
+    adt = _attr_torch_dtype(attr)
+    _check_tensor(means, "means", (3, n), torch.float32, means.device)
+    for k, shape in (("log_scales", (3, n)), ("quats", (4, n)), ("opacity_logits", (n,)),
+                     ("sh", ((deg + 1) ** 2, 3, n))):
+        _check_tensor(dev_scene[k], k, shape, adt, means.device)
     g = gs_gaussians()
-    g.n = int(dev_scene["means"].shape[1])
-    g.sh_degree = int(dev_scene["sh_degree"])
-    g.attr_dtype = int(dev_scene.get("attr_dtype", GS_F32))
+    g.n = n
+    g.sh_degree = deg
+    g.attr_dtype = attr
     g.means = dev_scene["means"].data_ptr()
     g.log_scales = dev_scene["log_scales"].data_ptr()
     g.quats = dev_scene["quats"].data_ptr()
@@ -207,6 +244,17 @@ def validate(gaussians: gs_gaussians, camera: gs_camera, width: int, height: int
     L = load_library()
     return int(L.gs_validate(C.byref(gaussians), C.byref(camera), int(width), int(height),
                              C.byref(opts) if opts is not None else None, out_rgb_ptr))
+
+
+def _check_outputs(out: dict, width: int, height: int, device):
+    """Caller-given output tensors of one view: rgb [3,H,W] float32, final_T
+    [H,W] float32 or None, n_contrib [H,W] int32 or None."""
+    torch = _torch()
+    _check_tensor(out["image"], "image", (3, height, width), torch.float32, device)
+    if out.get("final_T") is not None:
+        _check_tensor(out["final_T"], "final_T", (height, width), torch.float32, device)
+    if out.get("n_contrib") is not None:
+        _check_tensor(out["n_contrib"], "n_contrib", (height, width), torch.int32, device)
 
 
 class Renderer:
@@ -253,6 +301,8 @@ class Renderer:
                    "final_T": torch.empty((height, width), dtype=torch.float32, device=dev) if want_T else None,
                    "n_contrib": torch.empty((height, width), dtype=torch.int32, device=dev)
                    if want_n_contrib else None}
+        else:
+            _check_outputs(out, int(width), int(height), dev)
         g = make_gaussians(dev_scene)
         cam = make_camera(camera)
         opts = make_opts(background, pair_capacity, RENDER_REUSE_ORDER if reuse_order else 0)
@@ -296,6 +346,11 @@ class Renderer:
                              "final_T": torch.empty((H, W), dtype=torch.float32, device=dev) if want_T else None,
                              "n_contrib": torch.empty((H, W), dtype=torch.int32, device=dev)
                              if want_n_contrib else None})
+        else:
+            if len(outs) != len(cameras):
+                raise ValueError("outs must hold one output dict per camera")
+            for c, o in zip(cameras, outs):
+                _check_outputs(o, int(c["width"]), int(c["height"]), dev)
         views = (gs_view * len(cameras))()
         for k, (c, o) in enumerate(zip(cameras, outs)):
             views[k].camera = make_camera(c)
@@ -373,6 +428,14 @@ class Renderer:
         dev = dev_scene["means"].device
         n = dev_scene["means"].shape[1]
         ncoef = dev_scene["sh"].shape[0]
+        if self._last is None or self._last[0] != dev:
+            raise ValueError("the scene must live where the last render ran")
+        for k, t in enumerate(grad_images):
+            o = self._last_out[k] if isinstance(self._last_out, list) else self._last_out
+            _check_tensor(t.contiguous(), f"grad_images[{k}]", tuple(o["image"].shape), torch.float32, dev)
+            if grad_T is not None and grad_T[k] is not None:
+                _check_tensor(grad_T[k].contiguous(), f"grad_T[{k}]", tuple(o["image"].shape[1:]), torch.float32,
+                              dev)
         out = {"means": torch.empty((3, n), dtype=torch.float32, device=dev),
                "log_scales": torch.empty((3, n), dtype=torch.float32, device=dev),
                "quats": torch.empty((4, n), dtype=torch.float32, device=dev),
@@ -469,6 +532,9 @@ class RenderGraph:
         torch = _torch()
         s = stream if stream is not None else torch.cuda.current_stream(self._dev).cuda_stream
         self._r._check(self._r._L.gs_graph_launch(self._h, C.c_void_p(s)))
+        # a backward now differentiates this launch, whose outputs it reads
+        self._r._last_out = self.outs
+        self._r.generation += 1
         return self.outs
 
     def set_views(self, cameras: list, outs=None, stream=None):
@@ -514,14 +580,17 @@ def _autograd_function():
                      "sh": sh.detach().contiguous(), "sh_degree": deg, "attr_dtype": GS_F32}
             out = renderer.render(scene, camera, width, height, background=background)
             ctx.renderer, ctx.scene, ctx.generation = renderer, scene, renderer.generation
-            ctx.out = out
+            # the backward reads these outputs through the library: saved here,
+            # autograd refuses the backward if they were modified in place
+            ctx.save_for_backward(out["image"], out["final_T"])
             return out["image"], out["final_T"]
 
         @staticmethod
         def backward(ctx, g_image, g_T):
+            image, _final_T = ctx.saved_tensors   # raises if either was modified in place
             if ctx.renderer.generation != ctx.generation:
                 raise RuntimeError("the renderer rendered again before this backward")
-            g_image = torch.zeros_like(ctx.out["image"]) if g_image is None else g_image
+            g_image = torch.zeros_like(image) if g_image is None else g_image
             grads = ctx.renderer.backward(ctx.scene, [g_image], [g_T] if g_T is not None else None)
             return (None, None, None, None, None, grads["means"], grads["log_scales"], grads["quats"],
                     grads["opacity_logits"], grads["sh"])

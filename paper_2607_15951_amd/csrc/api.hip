@@ -61,11 +61,15 @@ struct gs_context {
     gs_gaussians last_g{};                // scene of the last render
     float last_bg[3] = {0.f, 0.f, 0.f};
     DevBuf grad2d;                        // backward: per-item blend gradients
+    DevBuf back_views;                    // backward: its own view table (a captured graph reads `views`)
     Tuning tuning = kDefaultTuning;       // launch shapes of the next render
     Tuning last_tuning = kDefaultTuning;  // launch shapes of the last render
     int64_t order_n = -1;     // items of the depth order the sort buffers hold (one view), -1 if none
     bool last_reuse = false;  // the last render started from the previous order
     DevBuf reuse_words;       // [kReuseWords] outcome of that attempt
+    // per-tile blend work of the last render, and the blend's dispatch order
+    DevBuf tile_cost, tile_order;
+    std::vector<int> cost_layout;   // tiles_x, tiles_y of every view whose work tile_cost holds
 };
 
 struct gs_graph {
@@ -438,8 +442,28 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
             return st;
         bl.tile_work = static_cast<unsigned long long*>(ctx->tile_work.p);
     }
+    // every blend records its tiles' work; with blend_group 0 it is dispatched
+    // heaviest first, by the last render's work when that render had the same
+    // tile layout, else by list length
+    std::vector<int> layout;
+    for (const ViewParams& v : hv) {
+        layout.push_back(v.tiles_x);
+        layout.push_back(v.tiles_y);
+    }
+    const void* cost_before = ctx->tile_cost.p;
+    if ((st = ensure(ctx, ctx->tile_cost, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
+    const bool history = cost_before == ctx->tile_cost.p && ctx->cost_layout == layout;
+    bl.tile_cost = static_cast<uint32_t*>(ctx->tile_cost.p);
+    bl.order = nullptr;
+    if (tu.blend_group == 0) {
+        if ((st = ensure(ctx, ctx->tile_order, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
+        uint32_t* order = static_cast<uint32_t*>(ctx->tile_order.p);
+        HIP_TRY(launch_blend_order(history ? bl.tile_cost : nullptr, bl.tile_offsets, T, order, s), "blend order");
+        bl.order = order;
+    }
     HIP_TRY(launch_blend(bl, capacity, s), "blend");
     STAGE_MARK(8);
+    ctx->cost_layout = layout;
 
     ctx->have_render = true;
     ctx->last_tuning = tu;
@@ -523,12 +547,12 @@ void gs_destroy(gs_context* ctx)
     if (!ctx) return;
     if (ctx->graph) gs_graph_destroy(ctx->graph);
     (void)hipSetDevice(ctx->device);
-    DevBuf* bufs[] = {&ctx->grad2d, &ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
+    DevBuf* bufs[] = {&ctx->grad2d, &ctx->back_views, &ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
                       &ctx->sort_ka, &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb, &ctx->hist,
                       &ctx->scan_scratch, &ctx->bin_info, &ctx->counts1, &ctx->rows_off, &ctx->row_ent,
                       &ctx->counts2, &ctx->partials, &ctx->views, &ctx->row_tiles_x, &ctx->view_counts,
                       &ctx->counters, &ctx->tile_offsets, &ctx->values, &ctx->tile_work, &ctx->sorted_rect,
-                      &ctx->reuse_words, &ctx->readback};
+                      &ctx->reuse_words, &ctx->readback, &ctx->tile_cost, &ctx->tile_order};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->host_info) (void)hipHostFree(ctx->host_info);
@@ -645,6 +669,9 @@ gs_status gs_graph_launch(gs_graph* graph, void* stream)
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_TRY(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
     ctx->stream = static_cast<hipStream_t>(stream);
+    // the launch rendered the graph's current cameras into its current
+    // outputs: a backward now differentiates that render
+    ctx->last_views = graph->views;
     ctx->have_render = true;
     ctx->timed = false;
     ctx->traced = false;
@@ -724,7 +751,9 @@ gs_status gs_render_backward(gs_context* ctx, const gs_gaussians* g, const float
     gs_status st;
     const int64_t items = ctx->n * V;
     if ((st = ensure(ctx, ctx->grad2d, (size_t)std::max<int64_t>(items, 1) * kGrad2d * 4)) != GS_OK) return st;
-    ViewParams* views = static_cast<ViewParams*>(ctx->views.p);
+    if ((st = ensure(ctx, ctx->back_views, (size_t)V * sizeof(ViewParams))) != GS_OK) return st;
+    // a table of its own: the render's table stays as a captured graph reads it
+    ViewParams* views = static_cast<ViewParams*>(ctx->back_views.p);
     HIP_TRY(write_view_table(hv, views, s), "view table");
     float* grad2d = static_cast<float*>(ctx->grad2d.p);
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, items * kGrad2d, s), "clear gradients");
@@ -736,6 +765,8 @@ gs_status gs_render_backward(gs_context* ctx, const gs_gaussians* g, const float
     bb.n_views = V;
     bb.tiles = ctx->tiles;
     bb.group = ctx->last_tuning.blend_group;
+    // the forward's dispatch order (its buffer is rewritten only by a forward)
+    bb.order = bb.group == 0 ? static_cast<const uint32_t*>(ctx->tile_order.p) : nullptr;
     for (int k = 0; k < 3; ++k) bb.bg[k] = ctx->last_bg[k];
     bb.grad2d = grad2d;
     HIP_TRY(launch_blend_backward(bb, ctx->capacity, s), "blend backward");
@@ -900,7 +931,7 @@ const TuneParam kTuneParams[] = {
     {&Tuning::sort_items, {4, 8, 16}, 3, 1, 1},
     {&Tuning::bin1_items, {4, 8, 16}, 3, 2, 5},
     {&Tuning::bin2_items, {8, 16, 32}, 3, 2, 5},
-    {&Tuning::blend_group, {1, 2, 4, 8, 16, 32, 64}, 7, 6, 6},
+    {&Tuning::blend_group, {0, 1, 2, 4, 8, 16, 32, 64}, 8, 6, 6},
 };
 
 }  // namespace
@@ -912,7 +943,7 @@ gs_status gs_set_tuning(gs_context* ctx, const gs_tuning* tuning)
     if (!tuning_supported(t))
         return fail(ctx, GS_ERR_INVALID_ARGUMENT,
                     "unsupported tuning: sort_items and bin_row_items take 4, 8 or 16, bin_tile_items 8, 16 or 32, "
-                    "blend_tile_group 1..64");
+                    "blend_tile_group 0..64");
     ctx->tuning = t;
     return GS_OK;
 }

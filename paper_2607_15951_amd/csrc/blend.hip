@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 
     __shared__ float4 s2[256 + kUnroll];   // r, g, b, list position (int bits)
     __shared__ uint32_t s_mask[256 + kUnroll];   // quads (waves) the entry can reach
     __shared__ uint32_t s_wave_keep[4];
-    const int tile = blend_tile_of_block(a.group);
+    const int tile = blend_tile(a.order, a.group);
     if (tile >= a.tiles) return;
     // the view owning this global tile: its size, tile grid and outputs
     const ViewParams& vp = a.views[view_of_tile(a.views, a.n_views, (uint32_t)tile)];
@@ -93,7 +93,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 
         nb = rec[1];
         nc = rec[2];
     }
-    for (uint64_t b0 = start; b0 < end; b0 += 256) {
+    uint64_t b0 = start;
+    for (; b0 < end; b0 += 256) {
         if (__syncthreads_count(!done) == 0) break;
         const float4 ra = na, rb = nb, rc = nc;
         if (b0 + 256 + tid < end) {
@@ -201,6 +202,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 
             w[5] = s_co[0] + s_co[1] + s_co[2] + s_co[3];
         }
     }
+    // the work of this tile, for the next frame's dispatch order: list
+    // entries walked before every pixel had terminated
+    if (a.tile_cost && tid == 0) a.tile_cost[tile] = (uint32_t)((b0 < end ? b0 : end) - start);
     if (!inside) return;
     const int64_t P = (int64_t)width * height;
     const int64_t p = (int64_t)py * width + px;
@@ -210,6 +214,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 
     out_rgb[2 * P + p] = fmaf(Tr, a.bg[2], c2);
     if (vp.out_T) vp.out_T[p] = Tr;
     if (vp.out_nc) vp.out_nc[p] = last;
+}
+
+// Log-scale bucket of a tile's cost: exact below 128, then 32 buckets per
+// octave (costs within about 3% share one); 0 .. 927.
+constexpr int kOrderBuckets = 1024;
+__device__ __forceinline__ int cost_bucket(uint32_t c)
+{
+    if (c < 128u) return (int)c;
+    const int e = 31 - __clz(c);   // 7 .. 31
+    return 128 + (e - 7) * 32 + (int)((c >> (e - 5)) & 31u);
+}
+
+// One 1024-thread workgroup: a counting sort of the tiles by descending cost
+// bucket.  Within a bucket the order is whatever the LDS atomics give: the
+// order only decides when each tile's workgroup starts, never what it
+// computes.
+__global__ __launch_bounds__(1024) void blend_order_kernel(const uint32_t* __restrict__ cost,
+                                                           const uint32_t* __restrict__ offsets, int64_t tiles,
+                                                           uint32_t* __restrict__ order)
+{
+    __shared__ uint32_t hist[kOrderBuckets];
+    __shared__ uint32_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    hist[tid] = 0u;
+    __syncthreads();
+    for (int64_t t = tid; t < tiles; t += 1024) {
+        const uint32_t c = cost ? cost[t] : offsets[t + 1] - offsets[t];
+        atomicAdd(&hist[cost_bucket(c)], 1u);
+    }
+    __syncthreads();
+    // start of each bucket in descending bucket order: thread k holds bucket
+    // 1023 - k, scanned inclusively across the block
+    const uint32_t own = hist[kOrderBuckets - 1 - tid];
+    uint32_t x = own;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t before = 0u;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    __syncthreads();
+    hist[kOrderBuckets - 1 - tid] = before + x - own;   // now the bucket's next free slot
+    __syncthreads();
+    for (int64_t t = tid; t < tiles; t += 1024) {
+        const uint32_t c = cost ? cost[t] : offsets[t + 1] - offsets[t];
+        order[atomicAdd(&hist[cost_bucket(c)], 1u)] = (uint32_t)t;
+    }
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n)
@@ -235,9 +288,17 @@ hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s)
 {
     const int64_t T = a.tiles;
     if (T <= 0) return hipSuccess;
-    const int blocks = blend_blocks(T, a.group);
+    const int blocks = blend_grid(T, a.order, a.group);
     if (a.tile_work) hipLaunchKernelGGL(blend_kernel<true>, dim3(blocks), dim3(256), 0, s, a, capacity);
     else hipLaunchKernelGGL(blend_kernel<false>, dim3(blocks), dim3(256), 0, s, a, capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_order(const uint32_t* cost, const uint32_t* tile_offsets, int64_t tiles, uint32_t* order,
+                              hipStream_t s)
+{
+    if (tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(blend_order_kernel, dim3(1), dim3(1024), 0, s, cost, tile_offsets, tiles, order);
     return hipGetLastError();
 }
 

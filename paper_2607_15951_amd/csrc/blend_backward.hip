@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void b
     __shared__ uint32_t s_item[256];
     __shared__ float s_acc[256][kGrad2d];
     __shared__ uint32_t s_wave_keep[4];
-    const int tile = blend_tile_of_block(a.group);
+    const int tile = blend_tile(a.order, a.group);
     if (tile >= a.tiles) return;
     const ViewParams& vp = a.views[view_of_tile(a.views, a.n_views, (uint32_t)tile)];
     const int width = vp.width, height = vp.height;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void b
 hipError_t launch_blend_backward(const BlendBackArgs& a, uint64_t capacity, hipStream_t s)
 {
     if (a.tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(blend_backward_kernel, dim3(blend_blocks(a.tiles, a.group)), dim3(256), 0, s, a, capacity);
+    hipLaunchKernelGGL(blend_backward_kernel, dim3(blend_grid(a.tiles, a.order, a.group)), dim3(256), 0, s, a, capacity);
     return hipGetLastError();
 }
 

@@ -100,4 +100,17 @@ inline int blend_blocks(int64_t tiles, int group)
     return (int)(8 * group * ((tiles + 8 * group - 1) / (8 * group)));
 }
 
+// Workgroup -> tile when a dispatch order is given (heaviest tiles first,
+// from the previous frame's per-tile work): block b takes order[b]; else the
+// XCD groups above.
+__device__ __forceinline__ int blend_tile(const uint32_t* order, int group)
+{
+    return order ? (int)order[blockIdx.x] : blend_tile_of_block(group);
+}
+
+inline int blend_grid(int64_t tiles, const uint32_t* order, int group)
+{
+    return order ? (int)tiles : blend_blocks(tiles, group);
+}
+
 }  // namespace gsmi

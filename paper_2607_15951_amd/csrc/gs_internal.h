@@ -21,9 +21,10 @@ struct Tuning {
     int sort_items;    // keys per thread of a depth-sort block: 4, 8, 16
     int bin1_items;    // depth-sorted Gaussians per lane of a level-1 binning wave: 4, 8, 16
     int bin2_items;    // row entries per lane of a level-2 binning wave: 8, 16, 32
-    int blend_group;   // consecutive tiles dealt to one XCD by the blend: 1 .. 64
+    int blend_group;   // consecutive tiles dealt to one XCD by the blend: 1 .. 64;
+                       // 0: tiles dispatched heaviest first, by the previous frame's work
 };
-constexpr Tuning kDefaultTuning = {8, 8, 16, 16};
+constexpr Tuning kDefaultTuning = {8, 8, 16, 0};
 bool tuning_supported(const Tuning& t);
 constexpr int kMaxRows = 2048;            // tile rows per image (height <= 32768)
 constexpr int kMaxTotalRows = 16384;      // tile rows over all views of one render
@@ -172,6 +173,8 @@ struct BlendArgs {
     int n_views;
     int64_t tiles;             // global tiles
     int group;                 // tiles per XCD group (Tuning::blend_group)
+    const uint32_t* order;     // [tiles] dispatch order (block b renders order[b]), or null: XCD groups
+    uint32_t* tile_cost;       // [tiles] list entries each tile walked before it finished, or null
     float bg[3];
     // per-tile trace when tracing (else null), [T][kTileWorkFields]: start
     // and end of the tile's workgroup (s_memrealtime, 100 MHz), entries
@@ -181,6 +184,12 @@ struct BlendArgs {
 };
 
 hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s);
+
+// Dispatch order of the blend: all tiles, heaviest first by cost[t] (the
+// previous frame's walked entries), or by list length when cost is null;
+// tiles of (nearly) equal cost in any order.  One workgroup.
+hipError_t launch_blend_order(const uint32_t* cost, const uint32_t* tile_offsets, int64_t tiles, uint32_t* order,
+                              hipStream_t s);
 
 // Backward of the blend: per list entry, dL/d(u, v, A, B, C, opacity, r, g, b)
 // summed over the pixels of every tile into grad2d[item][kGrad2d] (zeroed by
@@ -195,6 +204,7 @@ struct BlendBackArgs {
     int n_views;
     int64_t tiles;
     int group;
+    const uint32_t* order;   // the forward's dispatch order, or null: XCD groups
     float bg[3];
     float* grad2d;
 };

@@ -154,3 +154,47 @@ def check_lists_full(g, o, label="", exclude=()):
     if "keys" in g:
         np.testing.assert_array_equal(g["keys"][keep_g], o["keys"][keep_o], err_msg=f"{label} kept keys")
     return int((~keep_g).sum()), int((~keep_o).sum())
+
+
+def batched_views(renderer, outs, cams, n):
+    """Per-view result dicts (as gpu_render returns) of the last batched
+    render or graph launch on ``renderer``: that view's outputs, its slice of
+    the projection, and its per-tile lists with items v * n + i turned back
+    into Gaussian indices and global tile indices into the view's own."""
+    import torch
+    torch.cuda.synchronize()
+    lists = renderer.lists(keys=True)
+    proj = renderer.projection()
+    torch.cuda.synchronize()
+    values = lists["values"].cpu().numpy().view(np.uint32).astype(np.int64)
+    offsets = lists["tile_offsets"].cpu().numpy().view(np.uint32).astype(np.int64)
+    keys = lists["keys"].cpu().numpy().view(np.uint64)
+    pj = {k: v.cpu().numpy() for k, v in proj.items()}
+    res, tile_base = [], 0
+    for v, (c, o) in enumerate(zip(cams, outs)):
+        T = ((c["width"] + 15) // 16) * ((c["height"] + 15) // 16)
+        off = offsets[tile_base:tile_base + T + 1]
+        vals = values[off[0]:off[-1]] - v * n
+        assert (vals >= 0).all() and (vals < n).all()
+        sl = slice(v * n, (v + 1) * n)
+        res.append(dict(image=o["image"].cpu().numpy().astype(np.float64),
+                        final_T=o["final_T"].cpu().numpy().astype(np.float64),
+                        n_contrib=o["n_contrib"].cpu().numpy(),
+                        values=vals.astype(np.uint32), tile_offsets=(off - off[0]).astype(np.uint32),
+                        keys=keys[off[0]:off[-1]] - (np.uint64(tile_base) << np.uint64(32)),
+                        num_pairs=int(off[-1] - off[0]),
+                        splats=pj["splats"][sl], depth_key=pj["depth_key"][sl].view(np.uint32),
+                        radius=pj["radius"][sl], tiles_touched=pj["tiles_touched"][sl].view(np.uint32),
+                        rect=pj["rect"][sl].view(np.uint16).astype(np.int32)))
+        tile_base += T
+    return res
+
+
+def oracle_view_parity(g, scene, cam, label, background=(0.0, 0.0, 0.0)):
+    """One view's result dict against the oracle: projection, whole lists
+    (radius-ambiguous Gaussians' pairs removed), image."""
+    o = oracle.render(scene, cam, background=background)
+    amb = check_projection(g, o["proj"], label)
+    removed = check_lists_full(g, o, label, exclude=amb)
+    stats = check_image(g, o, label)
+    return dict(K=len(o["keys"]), radius_ambiguous=len(amb), pairs_removed=removed, **stats)

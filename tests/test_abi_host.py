@@ -121,3 +121,20 @@ def test_bf16_storage_rounding_matches_torch():
     ours = scenes.bf16_to_f32(scenes.to_bf16_storage(x))
     ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
     np.testing.assert_array_equal(ours, ref)
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding checks device, dtype, contiguity and shape of every tensor
+    before a pointer reaches the C ABI (which cannot see them)."""
+    torch = pytest.importorskip("torch")
+    import paper_2607_15951_amd as gs
+    n = 10
+    base = {"sh_degree": 1, "attr_dtype": gs.GS_F32,
+            "means": torch.zeros((3, n)), "log_scales": torch.zeros((3, n)), "quats": torch.zeros((4, n)),
+            "opacity_logits": torch.zeros(n), "sh": torch.zeros((4, 3, n))}
+    with pytest.raises(ValueError, match="cuda"):
+        gs.make_gaussians(base)                       # host tensors
+    with pytest.raises(ValueError):
+        gs.make_gaussians(dict(base, means=torch.zeros((2, n))))
+    with pytest.raises(ValueError):
+        gs.make_gaussians(dict(base, sh_degree=7))

@@ -303,3 +303,65 @@ def test_backward_c3_full_size_sampled_tiles(renderer):
     outside[U] = False
     for k in GROUPS:
         assert not np.any(got[k][..., outside]), f"{k}: gradient on a Gaussian listed in no sampled tile"
+
+
+def test_graph_backward_follows_the_launched_views(renderer):
+    """A backward after gs_graph_launch differentiates the cameras and outputs
+    of that launch (after gs_graph_set_views too), equal to the oracle's
+    gradient summed over those views; it leaves the graph's own view table
+    alone, so the next launch still renders the new cameras (against the
+    oracle as well)."""
+    import paper_2607_15951_amd as gs
+    import torch
+    from parity import check_image
+    sc = enlarged(scenes.make_scene("C2", n=300, seed=50, sh_degree=1), by=2.0)
+    cams1 = [scenes.default_camera(64, 48), scenes.look_at_camera([1.5, -0.4, -2.4], 50, 40)]
+    cams2 = [scenes.look_at_camera([-1.2, 0.5, -2.6], 64, 48), scenes.look_at_camera([0.4, 1.6, -2.3], 50, 40)]
+    dev = gs.scene_to_device(sc, 0)
+    r = gs.Renderer(0)
+    try:
+        gr = r.graph(dev, cams1, pair_capacity=200_000)
+        gr.set_views(cams2)
+        outs = gr.launch()
+        torch.cuda.synchronize()
+        ws, wts, want = [], [], {k: 0.0 for k in GROUPS}
+        for v, cam in enumerate(cams2):
+            o = oracle.render(sc, cam)
+            check_image({"image": outs[v]["image"].cpu().numpy().astype(np.float64),
+                         "final_T": outs[v]["final_T"].cpu().numpy().astype(np.float64),
+                         "n_contrib": outs[v]["n_contrib"].cpu().numpy()}, o, f"graph view {v}")
+            w_rgb, w_T = loss_weights(cam, 30 + v, ambiguous=oracle.ambiguous_mask(o))
+            ws.append(w_rgb)
+            wts.append(w_T)
+            g = oracle_grads(sc, cam, w_rgb, w_T, (0.0, 0.0, 0.0), proj=o["proj"])
+            for k in GROUPS:
+                want[k] = want[k] + g[k]
+        got = gpu_grads(r, dev, ws, wts)
+        compare("graph launch, new views", got, want)
+        first = [o["image"].clone() for o in outs]
+        for o in outs:
+            o["image"].fill_(-1.0)
+        gr.launch()
+        torch.cuda.synchronize()
+        for o, f in zip(outs, first):
+            assert torch.equal(o["image"], f), "the launch after a backward rendered other views"
+        gr.close()
+    finally:
+        r.close()
+
+
+def test_autograd_refuses_outputs_modified_in_place(renderer):
+    """The image and final T that the backward reads are saved for backward:
+    editing either in place makes autograd raise instead of returning wrong
+    gradients."""
+    import paper_2607_15951_amd as gs
+    import torch
+    sc = enlarged(scenes.make_scene("C1", n=120, seed=51, sh_degree=0))
+    cam = scenes.default_camera(40, 32)
+    leaves = {k: torch.from_numpy(np.ascontiguousarray(sc[k], np.float32)).cuda().requires_grad_(True)
+              for k in GROUPS}
+    img, T = gs.render_autograd(renderer, leaves["means"], leaves["log_scales"], leaves["quats"],
+                                leaves["opacity_logits"], leaves["sh"], cam, 40, 32)
+    img.clamp_(0.0, 0.5)
+    with pytest.raises(RuntimeError, match="inplace"):
+        img.sum().backward()

@@ -38,6 +38,9 @@ IMAGE_TOL = 1e-4
 # seeded scenes: C3 fp32 2 of 4224, C3 bf16 8 of 3712, C5 bf16 17 of 3584,
 # C5 fp16 11 of 3584; each case is capped at about twice its count.
 MAX_AMBIGUOUS = {"C3/fp32": 4, "C3/bf16": 16, "C5/bf16": 34, "C5/fp16": 22}
+# the batched workload's four views (1920x1080, 640x480, 1280x720, 256x256):
+# 3, 0, 1 and 6 ambiguous sampled pixels
+MAX_AMBIGUOUS_C4 = 12
 
 
 def say(msg):
@@ -78,36 +81,17 @@ def tile_pixels(t: int, tx: int, W: int, H: int):
     return xs.ravel().astype(np.int32), ys.ravel().astype(np.int32)
 
 
-def fullsize_case(renderer, workload: str, dtype: int, n_random: int):
-    import torch
-    import paper_2607_15951_amd as gs
-    label = f"{workload}/{['fp32', 'bf16', 'fp16'][dtype]}"
-    say(f"[fullsize] {label}: generating")
-    scene = scenes.make_scene(workload)
-    cam = scenes.make_cameras(workload)[0]
+def check_view_sampled(label: str, scene, ref_scene, cam, g: dict, offsets, values_dev, image, final_T, n_contrib,
+                       n_random: int, seed: int, master_scene=None, max_ambiguous=None):
+    """One view of a GPU render against the oracle, at any size: every
+    Gaussian's projection, every tile's pair count, and the lists and pixels
+    of sampled tiles.  ``g`` holds the view's projection (items of this view
+    only, indices 0..n-1) and ``values_dev`` its list values as Gaussian
+    indices; ``master_scene`` adds the error against the FP64 render of the
+    float32 master scene."""
     W, H = cam["width"], cam["height"]
     tx, ty = (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
-    dev = gs.scene_to_device(scene, dtype)
-    say(f"[fullsize] {label}: GPU render n={scene['means'].shape[1]} {W}x{H}")
-    out = renderer.render(dev, cam, W, H)
-    torch.cuda.synchronize()
-    lists = renderer.lists(keys=False)
-    projg = renderer.projection()
-    torch.cuda.synchronize()
-    g = dict(splats=projg["splats"].cpu().numpy(),
-             depth_key=projg["depth_key"].cpu().numpy().view(np.uint32),
-             radius=projg["radius"].cpu().numpy(),
-             tiles_touched=projg["tiles_touched"].cpu().numpy().view(np.uint32),
-             rect=projg["rect"].cpu().numpy().view(np.uint16).astype(np.int32))
-    offsets = lists["tile_offsets"].cpu().numpy().view(np.uint32).astype(np.int64)
-    values_dev = lists["values"]
-    image = out["image"].cpu().numpy()
-    final_T = out["final_T"].cpu().numpy()
-    n_contrib = out["n_contrib"].cpu().numpy()
-    del dev
-
     say(f"[fullsize] {label}: oracle projection")
-    ref_scene = dequantised(scene, dtype)
     p = oracle.project(ref_scene, cam)
     amb = check_projection(g, p, label)
     # Gaussians whose 3-sigma radius sits on an integer boundary may bin
@@ -128,15 +112,15 @@ def fullsize_case(renderer, workload: str, dtype: int, n_random: int):
                         bad[yy * tx + r[0]: yy * tx + r[2]] = True
         np.testing.assert_array_equal(np.diff(offsets)[~bad], counts[~bad], err_msg=f"{label} tile counts")
 
-    tiles = sample_tiles(counts, tx, ty, n_random, seed=sum(map(ord, workload)) * 3 + dtype)
-    master = oracle.project(scene, cam) if dtype else None
+    tiles = sample_tiles(counts, tx, ty, n_random, seed=seed)
+    master = oracle.project(master_scene, cam) if master_scene is not None else None
     n_pix = n_amb = 0
     worst = 0.0
     se_master = 0.0
     max_master = 0.0
     for t in tiles:
         s, e = int(offsets[t]), int(offsets[t + 1])
-        got = values_dev[s:e].cpu().numpy().view(np.uint32)
+        got = values_dev(s, e)
         want = oracle.tile_list(p, t)
         if not differ:
             np.testing.assert_array_equal(got, want, err_msg=f"{label} tile {t} list")
@@ -173,8 +157,91 @@ def fullsize_case(renderer, workload: str, dtype: int, n_random: int):
                    psnr_vs_fp64_master_db=(math.inf if mse == 0 else 10 * math.log10(1.0 / mse)))
     say("[fullsize] " + json.dumps(rep))
     assert worst <= IMAGE_TOL, f"{label}: max-abs {worst:.3e} on unambiguous sampled pixels"
-    assert n_amb <= MAX_AMBIGUOUS[label], f"{label}: {n_amb} ambiguous of {n_pix}"
+    cap = MAX_AMBIGUOUS[label] if max_ambiguous is None else max_ambiguous
+    assert n_amb <= cap, f"{label}: {n_amb} ambiguous of {n_pix}"
     return rep
+
+
+def fullsize_case(renderer, workload: str, dtype: int, n_random: int):
+    import torch
+    import paper_2607_15951_amd as gs
+    label = f"{workload}/{['fp32', 'bf16', 'fp16'][dtype]}"
+    say(f"[fullsize] {label}: generating")
+    scene = scenes.make_scene(workload)
+    cam = scenes.make_cameras(workload)[0]
+    W, H = cam["width"], cam["height"]
+    dev = gs.scene_to_device(scene, dtype)
+    say(f"[fullsize] {label}: GPU render n={scene['means'].shape[1]} {W}x{H}")
+    out = renderer.render(dev, cam, W, H)
+    torch.cuda.synchronize()
+    lists = renderer.lists(keys=False)
+    projg = renderer.projection()
+    torch.cuda.synchronize()
+    g = dict(splats=projg["splats"].cpu().numpy(),
+             depth_key=projg["depth_key"].cpu().numpy().view(np.uint32),
+             radius=projg["radius"].cpu().numpy(),
+             tiles_touched=projg["tiles_touched"].cpu().numpy().view(np.uint32),
+             rect=projg["rect"].cpu().numpy().view(np.uint16).astype(np.int32))
+    offsets = lists["tile_offsets"].cpu().numpy().view(np.uint32).astype(np.int64)
+    values = lists["values"]
+    del dev
+    return check_view_sampled(label, scene, dequantised(scene, dtype), cam, g, offsets,
+                              lambda s, e: values[s:e].cpu().numpy().view(np.uint32),
+                              out["image"].cpu().numpy(), out["final_T"].cpu().numpy(),
+                              out["n_contrib"].cpu().numpy(), n_random,
+                              seed=sum(map(ord, workload)) * 3 + dtype,
+                              master_scene=scene if dtype else None)
+
+
+def test_c4_batched_one_view_per_resolution(renderer):
+    """The batched workload's scene (1M Gaussians, SH3) rendered in one
+    gs_render_batched call from the first camera of each of its four
+    resolutions: every view against the oracle like the single renders
+    (projection, tile counts, sampled lists and pixels)."""
+    import torch
+    import paper_2607_15951_amd as gs
+    scene = scenes.make_scene("C4")
+    all_cams = scenes.make_cameras("C4")
+    cams, seen = [], set()
+    for c in all_cams:
+        if (c["width"], c["height"]) not in seen:
+            seen.add((c["width"], c["height"]))
+            cams.append(c)
+    assert len(cams) == 4
+    n = scene["means"].shape[1]
+    dev = gs.scene_to_device(scene, 0)
+    say(f"[fullsize] C4: batched render of {len(cams)} views, n={n}")
+    outs = renderer.render_batched(dev, cams)
+    torch.cuda.synchronize()
+    lists = renderer.lists(keys=False)
+    projg = renderer.projection()
+    torch.cuda.synchronize()
+    offsets_all = lists["tile_offsets"].cpu().numpy().view(np.uint32).astype(np.int64)
+    values = lists["values"]
+    splats = projg["splats"].cpu().numpy()
+    dk = projg["depth_key"].cpu().numpy().view(np.uint32)
+    rad = projg["radius"].cpu().numpy()
+    tt = projg["tiles_touched"].cpu().numpy().view(np.uint32)
+    rect = projg["rect"].cpu().numpy().view(np.uint16).astype(np.int32)
+    del dev
+    tile_base = 0
+    for v, (c, o) in enumerate(zip(cams, outs)):
+        W, H = c["width"], c["height"]
+        T = ((W + TILE - 1) // TILE) * ((H + TILE - 1) // TILE)
+        sl = slice(v * n, (v + 1) * n)
+        g = dict(splats=splats[sl], depth_key=dk[sl], radius=rad[sl], tiles_touched=tt[sl], rect=rect[sl])
+        off = offsets_all[tile_base:tile_base + T + 1]
+        base = int(off[0])
+
+        def view_values(s, e, base=base, v=v):
+            got = values[base + s:base + e].cpu().numpy().view(np.uint32).astype(np.int64) - v * n
+            assert (got >= 0).all() and (got < n).all()
+            return got.astype(np.uint32)
+
+        check_view_sampled(f"C4/view{v} {W}x{H}", scene, scene, c, g, off - base, view_values,
+                           o["image"].cpu().numpy(), o["final_T"].cpu().numpy(), o["n_contrib"].cpu().numpy(),
+                           n_random=4, seed=400 + v, max_ambiguous=MAX_AMBIGUOUS_C4)
+        tile_base += T
 
 
 def test_c3_fp32_full_size(renderer):

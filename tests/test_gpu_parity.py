@@ -13,7 +13,8 @@ import pytest
 
 import oracle
 import scenes
-from parity import (check_image, check_lists_full, check_projection, dequantised, gpu_render)
+from parity import (batched_views, check_image, check_lists_full, check_projection, dequantised, gpu_render,
+                    oracle_view_parity)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
 
@@ -295,6 +296,10 @@ def test_batched_views_equal_single_renders(renderer):
         tile_base += T
     assert tile_base == info["num_tiles"]
     assert info["num_pairs"] == sum(g["num_pairs"] for g in singles)
+    # and every view against the oracle directly
+    for v, (c, gv) in enumerate(zip(cams, batched_views(renderer, outs, cams, n))):
+        st = oracle_view_parity(gv, sc, c, f"batched view {v}")
+        say(f"[batched] view {v} vs oracle: {st}")
 
 
 def test_batched_rejects_bad_views(renderer):
@@ -357,6 +362,10 @@ def test_graph_replays_match_eager_batched_render(renderer):
             for o, w in zip(gr.outs, want):
                 for k in ("image", "final_T", "n_contrib"):
                     assert torch.equal(o[k], w[k]), f"replay {rep} {k}"
+        # the replayed views against the oracle directly
+        n = sc["means"].shape[1]
+        for v, (c, gv) in enumerate(zip(cams, batched_views(r, gr.outs, cams, n))):
+            say(f"[graph] view {v} vs oracle: {oracle_view_parity(gv, sc, c, f'graph view {v}')}")
         gr.set_views(cams2)
         gr.launch()
         torch.cuda.synchronize()
@@ -364,6 +373,8 @@ def test_graph_replays_match_eager_batched_render(renderer):
         for o, w in zip(gr.outs, want2):
             for k in ("image", "final_T", "n_contrib"):
                 assert torch.equal(o[k], w[k]), f"new views {k}"
+        for v, (c, gv) in enumerate(zip(cams2, batched_views(r, gr.outs, cams2, n))):
+            say(f"[graph] new view {v} vs oracle: {oracle_view_parity(gv, sc, c, f'graph new view {v}')}")
         gr.close()
         # the context renders eagerly again once the graph is gone
         r.render(dev, cams[0], cams[0]["width"], cams[0]["height"])

@@ -16,8 +16,8 @@ import scenes
 pytestmark = pytest.mark.gpu
 
 CANDIDATES = {"sort_items": (4, 8, 16), "bin_row_items": (4, 8, 16), "bin_tile_items": (8, 16, 32),
-              "blend_tile_group": (1, 2, 4, 8, 16, 32, 64)}
-DEFAULT = {"sort_items": 8, "bin_row_items": 8, "bin_tile_items": 16, "blend_tile_group": 16}
+              "blend_tile_group": (0, 1, 2, 4, 8, 16, 32, 64)}
+DEFAULT = {"sort_items": 8, "bin_row_items": 8, "bin_tile_items": 16, "blend_tile_group": 0}
 
 
 def say(msg):
@@ -103,7 +103,7 @@ def test_every_shape_gives_identical_results(renderer, case, capacity):
 
 def test_set_tuning_rejects_unsupported_values(renderer):
     renderer.set_tuning(**DEFAULT)
-    for bad in ({"sort_items": 5}, {"bin_row_items": 32}, {"bin_tile_items": 4}, {"blend_tile_group": 0},
+    for bad in ({"sort_items": 5}, {"bin_row_items": 32}, {"bin_tile_items": 4}, {"blend_tile_group": -1},
                 {"blend_tile_group": 65}):
         with pytest.raises(RuntimeError):
             renderer.set_tuning(**bad)
@@ -143,7 +143,7 @@ def test_backward_with_other_tile_groups(renderer):
     gi = torch.from_numpy(rng.uniform(-1, 1, (3, 96, 160)).astype(np.float32)).cuda()
     ref = None
     try:
-        for group in (16, 1, 64):
+        for group in (0, 16, 1, 64):
             renderer.set_tuning(blend_tile_group=group)
             renderer.render(dev, cam, 160, 96)
             g = {k: v.cpu().numpy() for k, v in renderer.backward(dev, [gi]).items()}
@@ -155,3 +155,26 @@ def test_backward_with_other_tile_groups(renderer):
                 assert float(np.abs(g[k] - ref[k]).max()) <= 1e-5 * scale, (group, k)
     finally:
         renderer.set_tuning(**DEFAULT)
+
+
+def test_heaviest_first_order_from_length_then_history(renderer):
+    """blend_tile_group 0 on a fresh context: the first render orders its
+    tiles by list length, the next ones by the previous render's per-tile
+    work, and a render of another size falls back to list length; every one
+    equals the default dispatch bit for bit."""
+    import paper_2607_15951_amd as gs
+    sc = scenes.make_scene("C2", n=40_000, seed=25)
+    dev = gs.scene_to_device(sc)
+    big, small = scenes.default_camera(333, 197), scenes.default_camera(128, 72)
+    renderer.set_tuning(**DEFAULT)
+    want_big = snapshot(renderer, render_all(renderer, dev, [big], 0))
+    want_small = snapshot(renderer, render_all(renderer, dev, [small], 0))
+    fresh = gs.Renderer(0)
+    try:
+        fresh.set_tuning(blend_tile_group=0)
+        for cam, want in ((big, want_big), (big, want_big), (small, want_small), (big, want_big)):
+            got = snapshot(fresh, render_all(fresh, dev, [cam], 0))
+            for k in want:
+                assert np.array_equal(got[k], want[k]), f"{cam['width']}x{cam['height']}: {k} differs"
+    finally:
+        fresh.close()
