@@ -145,6 +145,32 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
                     int32_t width, int32_t height, const gs_render_opts* opts,
                     float* out_rgb, float* out_final_T, uint32_t* out_n_contrib, void* stream);
 
+/* gs_render for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * renders what gs_render renders (same kernels, same bits) but takes every
+ * buffer of the render from one static device array of 64 MiB per device
+ * (held from library load to process end) and calls no hipMalloc, hipFree
+ * or other allocating routine, and never synchronises the host.
+ *   opts->pair_capacity  > 0: the bound on (Gaussian, tile) pairs, as for
+ *                        gs_render; 0: the largest bound whose buffers fit
+ *                        beside the scene's
+ *   GS_ERR_CAPACITY      before any launch when the scene, image and
+ *                        capacity need more than the 64 MiB (the message
+ *                        gives the bytes needed); pairs past the capacity
+ *                        are dropped on the device as for gs_render, which
+ *                        gs_get_list_info reports afterwards
+ * GS_RENDER_REUSE_ORDER and GS_PROFILE_BLEND_WORK are ignored, and the
+ * blend takes no per-tile history (a heaviest-first order, if tuned, comes
+ * from list lengths).  After it, gs_get_list_info and gs_get_stage_times
+ * work; the lists, projection and backward of the render are not kept
+ * (gs_copy_lists, gs_copy_projection and gs_render_backward fail).  Every
+ * call on one device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device (two streams, two threads, two
+ * contexts) race and must be ordered by the caller. */
+gs_status gs_render_noalloc(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam,
+                            int32_t width, int32_t height, const gs_render_opts* opts,
+                            float* out_rgb, float* out_final_T, uint32_t* out_n_contrib, void* stream);
+
 /* One view of a batched render: a camera, its image size and its outputs
  * (device memory owned by the caller, laid out as for gs_render). */
 typedef struct {

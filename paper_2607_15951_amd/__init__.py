@@ -26,7 +26,7 @@ EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_rende
             "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
             "gs_get_blend_stats", "gs_get_blend_tile_work", "gs_render_batched", "gs_graph_create",
             "gs_graph_set_views", "gs_graph_launch", "gs_graph_destroy", "gs_render_backward", "gs_set_tuning",
-            "gs_get_tuning", "gs_autotune", "gs_get_order_reuse"]
+            "gs_get_tuning", "gs_autotune", "gs_get_order_reuse", "gs_render_noalloc"]
 STAGES = ["project", "depth_sort", "bin_row_count", "bin_row_scatter", "bin_tile_count", "bin_tile_scatter",
           "blend"]
 
@@ -102,6 +102,9 @@ def load_library(path: str = LIB_PATH):
     L.gs_render.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(gs_camera), C.c_int32, C.c_int32,
                             C.POINTER(gs_render_opts), P, P, P, P]
     L.gs_render.restype = C.c_int
+    L.gs_render_noalloc.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(gs_camera), C.c_int32, C.c_int32,
+                                    C.POINTER(gs_render_opts), P, P, P, P]
+    L.gs_render_noalloc.restype = C.c_int
     L.gs_render_batched.argtypes = [P, C.POINTER(gs_gaussians), C.POINTER(gs_view), C.c_int32,
                                     C.POINTER(gs_render_opts), P]
     L.gs_render_batched.restype = C.c_int
@@ -315,6 +318,25 @@ class Renderer:
         # the backward reads these outputs: hold them so that the caching
         # allocator does not hand their memory to another tensor meanwhile
         self._last_out = out
+        self.generation += 1
+        return out
+
+    def render_noalloc(self, dev_scene: dict, camera: dict, width: int, height: int, out: dict,
+                       background=(0.0, 0.0, 0.0), pair_capacity: int = 0, stream=None):
+        """gs_render_noalloc into the caller's output tensors (which the
+        caller allocates beforehand: the library allocates nothing here)."""
+        torch = _torch()
+        dev = dev_scene["means"].device
+        _check_outputs(out, int(width), int(height), dev)
+        g = make_gaussians(dev_scene)
+        cam = make_camera(camera)
+        opts = make_opts(background, pair_capacity)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        self._check(self._L.gs_render_noalloc(self._ctx, C.byref(g), C.byref(cam), int(width), int(height),
+                                              C.byref(opts), _ptr(out["image"]), _ptr(out.get("final_T")),
+                                              _ptr(out.get("n_contrib")), C.c_void_p(s)))
+        self._last = (dev, int(g.n))
+        self._last_out = None   # nothing of this render can be differentiated
         self.generation += 1
         return out
 

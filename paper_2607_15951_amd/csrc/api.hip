@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,15 +22,46 @@ thread_local std::string g_thread_error;
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool fixed = false;   // a carve-out of the no-allocation scratch: never freed or grown
 };
 
 constexpr int kMaxViews = 1024;
 
+// Workspace of gs_render_noalloc: every device buffer of such a render is
+// carved out of this array, of which each device that loads the library
+// holds one copy until the process ends.  Host code must never use the
+// array's name as an address: the copy on device d lives at
+// g_scratch_addr[d], taken once per device by gs_create.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mutex;
+std::vector<void*> g_scratch_addr;   // per device: its copy of scratch, null until gs_create ran there
+
+// With `device` current: records the address of that device's scratch.
+hipError_t init_scratch_address(int device, int device_count)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if ((int)g_scratch_addr.size() < device_count) g_scratch_addr.resize((size_t)device_count, nullptr);
+    if (g_scratch_addr[(size_t)device]) return hipSuccess;
+    void* addr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[(size_t)device] = addr;
+    return hipSuccess;
+}
+
+void* scratch_address(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return (size_t)device < g_scratch_addr.size() ? g_scratch_addr[(size_t)device] : nullptr;
+}
+
 }  // namespace
 
-struct gs_context {
-    int device = 0;
-    std::string err;
+// The device buffers of one render.  A context grows its own; a render of
+// gs_render_noalloc carves fixed ones out of the static scratch array.
+struct Workspace {
     DevBuf splats, depth_key, radius, tiles_touched, rect;
     DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist, scan_scratch;
     DevBuf bin_info, counts1, rows_off, row_ent, counts2, partials, sorted_rect, readback;
@@ -38,6 +70,15 @@ struct gs_context {
     DevBuf counters;             // [1] capacity overflow flag
     DevBuf tile_offsets, values;
     DevBuf tile_work;   // per-tile blend trace [T][kTileWorkFields] u64 (GS_PROFILE_BLEND_WORK)
+    DevBuf reuse_words;       // [kReuseWords] outcome of an order-reuse attempt
+    // per-tile blend work of the last render, and the blend's dispatch order
+    DevBuf tile_cost, tile_order;
+};
+
+struct gs_context {
+    int device = 0;
+    std::string err;
+    Workspace ws;                    // buffers of the renders on this context
     uint32_t* host_info = nullptr;   // pinned readback of the per-frame sizes
     uint32_t profiling = 0;   // GS_PROFILE_* flags
     bool timed = false;       // the last render recorded stage events
@@ -66,10 +107,11 @@ struct gs_context {
     Tuning last_tuning = kDefaultTuning;  // launch shapes of the last render
     int64_t order_n = -1;     // items of the depth order the sort buffers hold (one view), -1 if none
     bool last_reuse = false;  // the last render started from the previous order
-    DevBuf reuse_words;       // [kReuseWords] outcome of that attempt
-    // per-tile blend work of the last render, and the blend's dispatch order
-    DevBuf tile_cost, tile_order;
-    std::vector<int> cost_layout;   // tiles_x, tiles_y of every view whose work tile_cost holds
+    std::vector<int> cost_layout;   // tiles_x, tiles_y of every view whose work ws.tile_cost holds
+    // the last render was gs_render_noalloc: its sizes are in noalloc_info
+    // (device words, allocated with the context), its buffers are gone
+    bool last_noalloc = false;
+    uint32_t* noalloc_info = nullptr;
 };
 
 struct gs_graph {
@@ -98,6 +140,9 @@ gs_status ensure(gs_context* ctx, DevBuf& b, size_t bytes)
 {
     if (bytes == 0) bytes = 256;
     if (b.bytes >= bytes) return GS_OK;
+    if (b.fixed)
+        return fail(ctx, GS_ERR_CAPACITY,
+                    "a buffer of " + std::to_string(bytes) + " bytes does not fit its share of the no-allocation scratch");
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
@@ -243,14 +288,22 @@ __global__ void row_table_kernel(const ViewParams* views, int n_views, uint32_t*
 // write_table: upload the view table first (false while a graph is captured:
 // the graph then reads the table its owner writes before each launch).
 gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector<ViewParams>& hv,
-                       const gs_render_opts* opts, hipStream_t s, bool write_table = true)
+                       const gs_render_opts* opts, hipStream_t s, bool write_table = true,
+                       Workspace* fixed_ws = nullptr)
 {
     gs_status st;
     gs_render_opts o{};
     o.tile_size = kTile;
     if (opts) o = *opts;
+    // fixed_ws: the buffers of a no-allocation render (capacity mode, no
+    // order reuse, no work tracing, no per-tile history: the scratch is
+    // shared by every context on the device)
+    Workspace& w = fixed_ws ? *fixed_ws : ctx->ws;
+    const bool noalloc = fixed_ws != nullptr;
+    if (noalloc && o.pair_capacity == 0) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "no-allocation render without a capacity");
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     ctx->have_render = false;
+    ctx->last_noalloc = false;
     const int64_t prev_order_n = ctx->order_n;
     ctx->order_n = -1;   // valid again only once this render has completed its sort
 
@@ -268,34 +321,34 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     const Tuning tu = ctx->tuning;
     const int chunks1 = std::max(bin_level1_chunks(n, tu.bin1_items), 1);
 
-    if ((st = ensure(ctx, ctx->splats, ni * sizeof(Splat))) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->depth_key, ni * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->radius, ni * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->tiles_touched, ni * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->rect, ni * 8)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->sorted_rect, ni * 8)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->sort_ka, ni * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->sort_va, ni * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->sort_kb, ni * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->sort_vb, ni * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->hist, depth_sort_hist_elems(n, V) * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->partials, project_partials_elems(n, V) * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->views, (size_t)V * sizeof(ViewParams))) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->view_counts, (size_t)V * kViewCounters * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->row_tiles_x, (size_t)rows * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->bin_info, bin_info_elems(rows) * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->rows_off, (size_t)(rows + 1) * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->counts1, (size_t)chunks1 * rows * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->counters, 64)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.splats, ni * sizeof(Splat))) != GS_OK) return st;
+    if ((st = ensure(ctx, w.depth_key, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.radius, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.tiles_touched, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.rect, ni * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.sorted_rect, ni * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.sort_ka, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.sort_va, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.sort_kb, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.sort_vb, ni * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.hist, depth_sort_hist_elems(n, V) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.partials, project_partials_elems(n, V) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.views, (size_t)V * sizeof(ViewParams))) != GS_OK) return st;
+    if ((st = ensure(ctx, w.view_counts, (size_t)V * kViewCounters * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.row_tiles_x, (size_t)rows * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.bin_info, bin_info_elems(rows) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.rows_off, (size_t)(rows + 1) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.counts1, (size_t)chunks1 * rows * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.counters, 64)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
 
-    ViewParams* views = static_cast<ViewParams*>(ctx->views.p);
-    uint32_t* counters = static_cast<uint32_t*>(ctx->counters.p);
-    uint32_t* view_counts = static_cast<uint32_t*>(ctx->view_counts.p);
+    ViewParams* views = static_cast<ViewParams*>(w.views.p);
+    uint32_t* counters = static_cast<uint32_t*>(w.counters.p);
+    uint32_t* view_counts = static_cast<uint32_t*>(w.view_counts.p);
     HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
     if (write_table) HIP_TRY(write_view_table(hv, views, s), "view table");
     hipLaunchKernelGGL(row_table_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, (const ViewParams*)views,
-                       V, static_cast<uint32_t*>(ctx->row_tiles_x.p), rows);
+                       V, static_cast<uint32_t*>(w.row_tiles_x.p), rows);
     HIP_TRY(hipGetLastError(), "view table");
     STAGE_MARK(0);
 
@@ -310,24 +363,24 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     pa.sh = g->sh;
     pa.views = views;
     pa.n_views = V;
-    pa.splats = static_cast<Splat*>(ctx->splats.p);
-    pa.depth_key = static_cast<uint32_t*>(ctx->depth_key.p);
-    pa.radius = static_cast<int32_t*>(ctx->radius.p);
-    pa.tiles_touched = static_cast<uint32_t*>(ctx->tiles_touched.p);
-    pa.rect = static_cast<ushort4*>(ctx->rect.p);
+    pa.splats = static_cast<Splat*>(w.splats.p);
+    pa.depth_key = static_cast<uint32_t*>(w.depth_key.p);
+    pa.radius = static_cast<int32_t*>(w.radius.p);
+    pa.tiles_touched = static_cast<uint32_t*>(w.tiles_touched.p);
+    pa.rect = static_cast<ushort4*>(w.rect.p);
     pa.view_counts = view_counts;
-    pa.partials = static_cast<uint32_t*>(ctx->partials.p);
+    pa.partials = static_cast<uint32_t*>(w.partials.p);
     HIP_TRY(launch_project(pa, s), "project");
     STAGE_MARK(1);
 
     BinArgs ba{};
     ba.view_counts = view_counts;
     ba.rect = pa.rect;
-    ba.sorted_rect = static_cast<ushort4*>(ctx->sorted_rect.p);
+    ba.sorted_rect = static_cast<ushort4*>(w.sorted_rect.p);
     ba.n = n;
     ba.n_views = V;
     ba.views = views;
-    ba.row_tiles_x = static_cast<const uint32_t*>(ctx->row_tiles_x.p);
+    ba.row_tiles_x = static_cast<const uint32_t*>(w.row_tiles_x.p);
     ba.rows = rows;
     ba.max_tiles_x = max_tx;
     ba.max_tiles_y = max_ty;
@@ -335,10 +388,10 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ba.items1 = tu.bin1_items;
     ba.items2 = tu.bin2_items;
     ba.chunks1 = chunks1;
-    ba.info = static_cast<uint32_t*>(ctx->bin_info.p);
-    ba.counts1 = static_cast<uint32_t*>(ctx->counts1.p);
-    ba.rows_off = static_cast<uint32_t*>(ctx->rows_off.p);
-    ba.tile_offsets = static_cast<uint32_t*>(ctx->tile_offsets.p);
+    ba.info = static_cast<uint32_t*>(w.bin_info.p);
+    ba.counts1 = static_cast<uint32_t*>(w.counts1.p);
+    ba.rows_off = static_cast<uint32_t*>(w.rows_off.p);
+    ba.tile_offsets = static_cast<uint32_t*>(w.tile_offsets.p);
     ba.overflow = counters + 1;
     uint64_t capacity = o.pair_capacity;
     // pair_capacity > 0: every size below is the bound the capacity implies
@@ -352,26 +405,26 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     // for the level-2 counts after its host read
     int64_t scan_max = std::max<int64_t>(T + 1, (int64_t)rows * chunks1);
     if (capacity) scan_max = std::max<int64_t>(scan_max, (int64_t)ba.counts2_capacity);
-    if ((st = ensure(ctx, ctx->scan_scratch, scan_scratch_elems(scan_max) * 8)) != GS_OK) return st;
-    uint64_t* scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
+    if ((st = ensure(ctx, w.scan_scratch, scan_scratch_elems(scan_max) * 8)) != GS_OK) return st;
+    uint64_t* scan_scratch = static_cast<uint64_t*>(w.scan_scratch.p);
     int in_b = 1;
     // one view of the same Gaussians as the last render: start from its order
-    const bool reuse = (o.flags & GS_RENDER_REUSE_ORDER) && V == 1 && n > 0 && prev_order_n == n;
+    const bool reuse = !noalloc && (o.flags & GS_RENDER_REUSE_ORDER) && V == 1 && n > 0 && prev_order_n == n;
     uint32_t* reuse_words = nullptr;
     if (reuse) {
-        if ((st = ensure(ctx, ctx->reuse_words, order_reuse_words(n) * 4)) != GS_OK) return st;
-        reuse_words = static_cast<uint32_t*>(ctx->reuse_words.p);
-        HIP_TRY(launch_order_reuse(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
-                                   static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
-                                   static_cast<uint32_t*>(ctx->sort_vb.p), n, reuse_words, s),
+        if ((st = ensure(ctx, w.reuse_words, order_reuse_words(n) * 4)) != GS_OK) return st;
+        reuse_words = static_cast<uint32_t*>(w.reuse_words.p);
+        HIP_TRY(launch_order_reuse(pa.depth_key, static_cast<uint32_t*>(w.sort_ka.p),
+                                   static_cast<uint32_t*>(w.sort_va.p), static_cast<uint32_t*>(w.sort_kb.p),
+                                   static_cast<uint32_t*>(w.sort_vb.p), n, reuse_words, s),
                 "order reuse");
     }
-    HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(ctx->sort_ka.p),
-                              static_cast<uint32_t*>(ctx->sort_va.p), static_cast<uint32_t*>(ctx->sort_kb.p),
-                              static_cast<uint32_t*>(ctx->sort_vb.p), static_cast<uint32_t*>(ctx->hist.p), n, V,
+    HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(w.sort_ka.p),
+                              static_cast<uint32_t*>(w.sort_va.p), static_cast<uint32_t*>(w.sort_kb.p),
+                              static_cast<uint32_t*>(w.sort_vb.p), static_cast<uint32_t*>(w.hist.p), n, V,
                               tu.sort_items, reuse_words, &in_b, s),
             "depth sort");
-    ba.sorted_idx = static_cast<const uint32_t*>(in_b ? ctx->sort_vb.p : ctx->sort_va.p);
+    ba.sorted_idx = static_cast<const uint32_t*>(in_b ? w.sort_vb.p : w.sort_va.p);
     STAGE_MARK(2);
     HIP_TRY(launch_bin_rows(ba, scan_scratch, s), "bin rows");
     STAGE_MARK(3);
@@ -382,8 +435,8 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
         // level-2 sizes
         uint32_t* hi = ctx->host_info;
         const int n_vc = V * kViewCounters;
-        if ((st = ensure(ctx, ctx->readback, (size_t)(n_vc + kReadbackTail) * 4)) != GS_OK) return st;
-        uint32_t* rb = static_cast<uint32_t*>(ctx->readback.p);
+        if ((st = ensure(ctx, w.readback, (size_t)(n_vc + kReadbackTail) * 4)) != GS_OK) return st;
+        uint32_t* rb = static_cast<uint32_t*>(w.readback.p);
         hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, s, (const uint32_t*)view_counts, n_vc,
                            (const uint32_t*)counters, (const uint32_t*)(ba.rows_off + rows), (const uint32_t*)ba.info,
                            rb);
@@ -406,17 +459,17 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ba.capacity = capacity;
     // the device is idle here in eager mode (host read above), so growing the
     // scan scratch cannot pull memory from under a queued kernel
-    if ((st = ensure(ctx, ctx->scan_scratch, scan_scratch_elems((int64_t)std::max<uint64_t>(ba.counts2_capacity, 1)) *
+    if ((st = ensure(ctx, w.scan_scratch, scan_scratch_elems((int64_t)std::max<uint64_t>(ba.counts2_capacity, 1)) *
                                                  8)) != GS_OK)
         return st;
-    scan_scratch = static_cast<uint64_t*>(ctx->scan_scratch.p);
+    scan_scratch = static_cast<uint64_t*>(w.scan_scratch.p);
     const size_t rows_cap = (size_t)std::max<uint64_t>(ba.row_capacity, 1);
-    if ((st = ensure(ctx, ctx->row_ent, rows_cap * 8)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->counts2, (size_t)std::max<uint64_t>(ba.counts2_capacity, 1) * 4)) != GS_OK) return st;
-    if ((st = ensure(ctx, ctx->values, (size_t)std::max<uint64_t>(capacity, 1) * 4)) != GS_OK) return st;
-    ba.row_ent = static_cast<uint2*>(ctx->row_ent.p);
-    ba.counts2 = static_cast<uint32_t*>(ctx->counts2.p);
-    ba.values = static_cast<uint32_t*>(ctx->values.p);
+    if ((st = ensure(ctx, w.row_ent, rows_cap * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.counts2, (size_t)std::max<uint64_t>(ba.counts2_capacity, 1) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.values, (size_t)std::max<uint64_t>(capacity, 1) * 4)) != GS_OK) return st;
+    ba.row_ent = static_cast<uint2*>(w.row_ent.p);
+    ba.counts2 = static_cast<uint32_t*>(w.counts2.p);
+    ba.values = static_cast<uint32_t*>(w.values.p);
     STAGE_MARK(4);
     HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
     STAGE_MARK(5);
@@ -437,10 +490,10 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     const float* bg = opts ? o.background : zero_bg;
     for (int k = 0; k < 3; ++k) bl.bg[k] = bg[k];
     bl.tile_work = nullptr;
-    if (ctx->profiling & GS_PROFILE_BLEND_WORK) {
-        if ((st = ensure(ctx, ctx->tile_work, (size_t)std::max<int64_t>(T, 1) * kTileWorkFields * 8)) != GS_OK)
+    if ((ctx->profiling & GS_PROFILE_BLEND_WORK) && !noalloc) {
+        if ((st = ensure(ctx, w.tile_work, (size_t)std::max<int64_t>(T, 1) * kTileWorkFields * 8)) != GS_OK)
             return st;
-        bl.tile_work = static_cast<unsigned long long*>(ctx->tile_work.p);
+        bl.tile_work = static_cast<unsigned long long*>(w.tile_work.p);
     }
     // every blend records its tiles' work; with blend_group 0 it is dispatched
     // heaviest first, by the last render's work when that render had the same
@@ -450,19 +503,42 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
         layout.push_back(v.tiles_x);
         layout.push_back(v.tiles_y);
     }
-    const void* cost_before = ctx->tile_cost.p;
-    if ((st = ensure(ctx, ctx->tile_cost, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
-    const bool history = cost_before == ctx->tile_cost.p && ctx->cost_layout == layout;
-    bl.tile_cost = static_cast<uint32_t*>(ctx->tile_cost.p);
+    const void* cost_before = w.tile_cost.p;
+    if ((st = ensure(ctx, w.tile_cost, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
+    const bool history = !noalloc && cost_before == w.tile_cost.p && ctx->cost_layout == layout;
+    bl.tile_cost = static_cast<uint32_t*>(w.tile_cost.p);
     bl.order = nullptr;
     if (tu.blend_group == 0) {
-        if ((st = ensure(ctx, ctx->tile_order, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
-        uint32_t* order = static_cast<uint32_t*>(ctx->tile_order.p);
+        if ((st = ensure(ctx, w.tile_order, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
+        uint32_t* order = static_cast<uint32_t*>(w.tile_order.p);
         HIP_TRY(launch_blend_order(history ? bl.tile_cost : nullptr, bl.tile_offsets, T, order, s), "blend order");
         bl.order = order;
     }
     HIP_TRY(launch_blend(bl, capacity, s), "blend");
     STAGE_MARK(8);
+    if (noalloc) {
+        // nothing of this render stays with the context but its sizes: the
+        // next render on the device may overwrite the scratch
+        hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, s, (const uint32_t*)view_counts,
+                           kViewCounters, (const uint32_t*)counters, (const uint32_t*)(ba.rows_off + rows),
+                           (const uint32_t*)ba.info, ctx->noalloc_info);
+        HIP_TRY(hipGetLastError(), "pack sizes");
+        ctx->last_noalloc = true;
+        ctx->n = n;
+        ctx->n_views = V;
+        ctx->tiles_x = hv[0].tiles_x;
+        ctx->tiles_y = hv[0].tiles_y;
+        ctx->tiles = T;
+        ctx->rows = rows;
+        ctx->capacity = capacity;
+        ctx->stream = s;
+        ctx->cost_layout.clear();
+        ctx->have_render = false;
+        ctx->order_n = -1;
+        ctx->timed = (ctx->profiling & GS_PROFILE_STAGES) != 0;
+        ctx->traced = false;
+        return GS_OK;
+    }
     ctx->cost_layout = layout;
 
     ctx->have_render = true;
@@ -488,6 +564,64 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
 
 gs_status build_views(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
                       const gs_render_opts* opts, std::vector<ViewParams>& hv);
+
+// Bytes of the buffers a capacity-mode render of the views hv asks for (the
+// sizes render_views requests, each rounded up to 256 bytes).  With w, the
+// buffers are also laid out one after another from base and marked fixed.
+size_t carve_noalloc(Workspace* w, unsigned char* base, int64_t n, const std::vector<ViewParams>& hv, const Tuning& tu,
+                     uint64_t capacity)
+{
+    Workspace dummy;
+    Workspace& ws = w ? *w : dummy;
+    size_t off = 0;
+    auto take = [&](DevBuf& b, size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        bytes = (bytes + 255) & ~size_t(255);
+        if (w) {
+            b.p = base + off;
+            b.bytes = bytes;
+            b.fixed = true;
+        }
+        off += bytes;
+    };
+    const int V = (int)hv.size();
+    const size_t ni = (size_t)std::max<int64_t>(n * V, 1);
+    const int rows = (int)(hv.back().row_base + hv.back().tiles_y);
+    const int64_t T = (int64_t)hv.back().tile_base + (int64_t)hv.back().tiles_x * hv.back().tiles_y;
+    int max_tx = 0;
+    for (const ViewParams& v : hv) max_tx = std::max(max_tx, v.tiles_x);
+    const int chunks1 = std::max(bin_level1_chunks(n, tu.bin1_items), 1);
+    const int max_chunks2 = bin_level2_chunk_bound(capacity, rows, tu.bin2_items);
+    const uint64_t counts2_cap = (uint64_t)max_chunks2 * max_tx;
+    const int64_t scan_max = std::max<int64_t>(std::max<int64_t>(T + 1, (int64_t)rows * chunks1), (int64_t)counts2_cap);
+    take(ws.splats, ni * sizeof(Splat));
+    take(ws.depth_key, ni * 4);
+    take(ws.radius, ni * 4);
+    take(ws.tiles_touched, ni * 4);
+    take(ws.rect, ni * 8);
+    take(ws.sorted_rect, ni * 8);
+    take(ws.sort_ka, ni * 4);
+    take(ws.sort_va, ni * 4);
+    take(ws.sort_kb, ni * 4);
+    take(ws.sort_vb, ni * 4);
+    take(ws.hist, depth_sort_hist_elems(n, V) * 4);
+    take(ws.partials, project_partials_elems(n, V) * 4);
+    take(ws.views, (size_t)V * sizeof(ViewParams));
+    take(ws.view_counts, (size_t)V * kViewCounters * 4);
+    take(ws.row_tiles_x, (size_t)rows * 4);
+    take(ws.bin_info, bin_info_elems(rows) * 4);
+    take(ws.rows_off, (size_t)(rows + 1) * 4);
+    take(ws.counts1, (size_t)chunks1 * rows * 4);
+    take(ws.counters, 64);
+    take(ws.tile_offsets, (size_t)(T + 1) * 4);
+    take(ws.scan_scratch, scan_scratch_elems(scan_max) * 8);
+    take(ws.row_ent, (size_t)std::max<uint64_t>(capacity, 1) * 8);
+    take(ws.counts2, (size_t)std::max<uint64_t>(counts2_cap, 1) * 4);
+    take(ws.values, (size_t)std::max<uint64_t>(capacity, 1) * 4);
+    take(ws.tile_cost, (size_t)std::max<int64_t>(T, 1) * 4);
+    take(ws.tile_order, (size_t)std::max<int64_t>(T, 1) * 4);
+    return off;
+}
 
 // The device-table entry of one view; tile_base / row_base follow the views
 // before it.
@@ -534,7 +668,12 @@ gs_status gs_create(int device, gs_context** out)
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&ctx->host_info),
                           sizeof(uint32_t) * ((size_t)kMaxViews * kViewCounters + 16));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ctx->noalloc_info), 64);
+    // the device's copy of the no-allocation scratch (once per device)
+    if (e == hipSuccess) e = init_scratch_address(device, count);
     if (e != hipSuccess) {
+        if (ctx->host_info) (void)hipHostFree(ctx->host_info);
+        if (ctx->noalloc_info) (void)hipFree(ctx->noalloc_info);
         delete ctx;
         return hip_fail(nullptr, e, "context set-up");
     }
@@ -547,15 +686,16 @@ void gs_destroy(gs_context* ctx)
     if (!ctx) return;
     if (ctx->graph) gs_graph_destroy(ctx->graph);
     (void)hipSetDevice(ctx->device);
-    DevBuf* bufs[] = {&ctx->grad2d, &ctx->back_views, &ctx->splats, &ctx->depth_key, &ctx->radius, &ctx->tiles_touched, &ctx->rect,
-                      &ctx->sort_ka, &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb, &ctx->hist,
-                      &ctx->scan_scratch, &ctx->bin_info, &ctx->counts1, &ctx->rows_off, &ctx->row_ent,
-                      &ctx->counts2, &ctx->partials, &ctx->views, &ctx->row_tiles_x, &ctx->view_counts,
-                      &ctx->counters, &ctx->tile_offsets, &ctx->values, &ctx->tile_work, &ctx->sorted_rect,
-                      &ctx->reuse_words, &ctx->readback, &ctx->tile_cost, &ctx->tile_order};
+    DevBuf* bufs[] = {&ctx->grad2d, &ctx->back_views, &ctx->ws.splats, &ctx->ws.depth_key, &ctx->ws.radius, &ctx->ws.tiles_touched, &ctx->ws.rect,
+                      &ctx->ws.sort_ka, &ctx->ws.sort_va, &ctx->ws.sort_kb, &ctx->ws.sort_vb, &ctx->ws.hist,
+                      &ctx->ws.scan_scratch, &ctx->ws.bin_info, &ctx->ws.counts1, &ctx->ws.rows_off, &ctx->ws.row_ent,
+                      &ctx->ws.counts2, &ctx->ws.partials, &ctx->ws.views, &ctx->ws.row_tiles_x, &ctx->ws.view_counts,
+                      &ctx->ws.counters, &ctx->ws.tile_offsets, &ctx->ws.values, &ctx->ws.tile_work, &ctx->ws.sorted_rect,
+                      &ctx->ws.reuse_words, &ctx->ws.readback, &ctx->ws.tile_cost, &ctx->ws.tile_order};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->host_info) (void)hipHostFree(ctx->host_info);
+    if (ctx->noalloc_info) (void)hipFree(ctx->noalloc_info);
     for (hipEvent_t e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     delete ctx;
@@ -582,6 +722,49 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
     if (st != GS_OK) return st;
     std::vector<ViewParams> hv(1, make_view(cam, width, height, out_rgb, out_final_T, out_n_contrib, 0u, 0u));
     return render_views(ctx, g, hv, opts, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_render_noalloc(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam, int32_t width, int32_t height,
+                            const gs_render_opts* opts, float* out_rgb, float* out_final_T, uint32_t* out_n_contrib,
+                            void* stream)
+{
+    if (!ctx) return fail(nullptr, GS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (ctx->graph) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the context is bound to a render graph");
+    gs_status st = validate(ctx, g, cam, width, height, opts, out_rgb);
+    if (st != GS_OK) return st;
+    unsigned char* base = static_cast<unsigned char*>(scratch_address(ctx->device));
+    if (!base) return fail(ctx, GS_ERR_HIP, "the device's no-allocation scratch has no address");
+    std::vector<ViewParams> hv(1, make_view(cam, width, height, out_rgb, out_final_T, out_n_contrib, 0u, 0u));
+    const Tuning tu = ctx->tuning;
+    uint64_t cap = opts ? opts->pair_capacity : 0;
+    if (cap > 0xFFFFFFFFull) return fail(ctx, GS_ERR_CAPACITY, "pair_capacity must stay below 2^32");
+    if (cap == 0) {
+        // the largest capacity whose buffers fit beside the scene's
+        if (carve_noalloc(nullptr, nullptr, g->n, hv, tu, 1) > kNoallocScratchBytes)
+            return fail(ctx, GS_ERR_CAPACITY,
+                        "the scene's buffers exceed the no-allocation scratch of " +
+                            std::to_string(kNoallocScratchBytes) + " bytes");
+        uint64_t lo = 1, hi = 0xFFFFFFFFull;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo + 1) / 2;
+            if (carve_noalloc(nullptr, nullptr, g->n, hv, tu, mid) <= kNoallocScratchBytes) lo = mid;
+            else hi = mid - 1;
+        }
+        cap = lo;
+    }
+    const size_t need = carve_noalloc(nullptr, nullptr, g->n, hv, tu, cap);
+    if (need > kNoallocScratchBytes)
+        return fail(ctx, GS_ERR_CAPACITY,
+                    "a render of this size needs " + std::to_string(need) + " bytes; the no-allocation scratch holds " +
+                        std::to_string(kNoallocScratchBytes));
+    Workspace fw;
+    carve_noalloc(&fw, base, g->n, hv, tu, cap);
+    gs_render_opts o{};
+    o.tile_size = kTile;
+    if (opts) o = *opts;
+    o.pair_capacity = cap;
+    o.flags &= ~GS_RENDER_REUSE_ORDER;
+    return render_views(ctx, g, hv, &o, static_cast<hipStream_t>(stream), true, &fw);
 }
 
 gs_status gs_render_batched(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
@@ -656,7 +839,7 @@ gs_status gs_graph_set_views(gs_graph* graph, const gs_view* views, int32_t n_vi
                           hv[v].row_base);
     }
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-    HIP_TRY(write_view_table(hv, static_cast<ViewParams*>(ctx->views.p), static_cast<hipStream_t>(stream)),
+    HIP_TRY(write_view_table(hv, static_cast<ViewParams*>(ctx->ws.views.p), static_cast<hipStream_t>(stream)),
             "view table");
     graph->views = hv;
     return GS_OK;
@@ -758,15 +941,15 @@ gs_status gs_render_backward(gs_context* ctx, const gs_gaussians* g, const float
     float* grad2d = static_cast<float*>(ctx->grad2d.p);
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, items * kGrad2d, s), "clear gradients");
     BlendBackArgs bb{};
-    bb.splats = static_cast<const Splat*>(ctx->splats.p);
-    bb.values = static_cast<const uint32_t*>(ctx->values.p);
-    bb.tile_offsets = static_cast<const uint32_t*>(ctx->tile_offsets.p);
+    bb.splats = static_cast<const Splat*>(ctx->ws.splats.p);
+    bb.values = static_cast<const uint32_t*>(ctx->ws.values.p);
+    bb.tile_offsets = static_cast<const uint32_t*>(ctx->ws.tile_offsets.p);
     bb.views = views;
     bb.n_views = V;
     bb.tiles = ctx->tiles;
     bb.group = ctx->last_tuning.blend_group;
     // the forward's dispatch order (its buffer is rewritten only by a forward)
-    bb.order = bb.group == 0 ? static_cast<const uint32_t*>(ctx->tile_order.p) : nullptr;
+    bb.order = bb.group == 0 ? static_cast<const uint32_t*>(ctx->ws.tile_order.p) : nullptr;
     for (int k = 0; k < 3; ++k) bb.bg[k] = ctx->last_bg[k];
     bb.grad2d = grad2d;
     HIP_TRY(launch_blend_backward(bb, ctx->capacity, s), "blend backward");
@@ -782,7 +965,7 @@ gs_status gs_render_backward(gs_context* ctx, const gs_gaussians* g, const float
     pb.views = views;
     pb.n_views = V;
     pb.grad2d = grad2d;
-    pb.tiles_touched = static_cast<const uint32_t*>(ctx->tiles_touched.p);
+    pb.tiles_touched = static_cast<const uint32_t*>(ctx->ws.tiles_touched.p);
     pb.g_means = grads->means;
     pb.g_log_scales = grads->log_scales;
     pb.g_quats = grads->quats;
@@ -800,7 +983,7 @@ gs_status gs_get_order_reuse(gs_context* ctx, uint32_t* out2)
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render did not start from the previous order");
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     uint32_t w[kReuseWords];
-    HIP_TRY(hipMemcpyAsync(w, ctx->reuse_words.p, sizeof w, hipMemcpyDeviceToHost, ctx->stream), "read reuse words");
+    HIP_TRY(hipMemcpyAsync(w, ctx->ws.reuse_words.p, sizeof w, hipMemcpyDeviceToHost, ctx->stream), "read reuse words");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     out2[0] = w[0];
     out2[1] = w[1];
@@ -810,14 +993,33 @@ gs_status gs_get_order_reuse(gs_context* ctx, uint32_t* out2)
 gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out)
 {
     if (!ctx || !out) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (ctx->last_noalloc) {
+        // sizes a no-allocation render packed: view counters, the counters,
+        // R, level-2 sizes
+        HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+        uint32_t w[kViewCounters + 7];
+        HIP_TRY(hipMemcpyAsync(w, ctx->noalloc_info, sizeof w, hipMemcpyDeviceToHost, ctx->stream), "read sizes");
+        HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        const uint64_t K = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+        out->num_pairs = K;
+        out->num_row_entries = w[kViewCounters + 4];
+        out->tiles_x = ctx->tiles_x;
+        out->tiles_y = ctx->tiles_y;
+        out->n_visible = (int64_t)w[0];
+        out->num_tiles = ctx->tiles;
+        out->num_views = ctx->n_views;
+        if (w[kViewCounters + 1] != 0 || K > ctx->capacity)
+            return fail(ctx, GS_ERR_CAPACITY, "the last render produced more pairs than pair_capacity");
+        return GS_OK;
+    }
     if (!ctx->have_render) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "no render on this context yet");
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     std::vector<uint32_t> vc((size_t)ctx->n_views * kViewCounters);
     uint32_t c[4], r32 = 0;
-    HIP_TRY(hipMemcpyAsync(vc.data(), ctx->view_counts.p, vc.size() * 4, hipMemcpyDeviceToHost, ctx->stream),
+    HIP_TRY(hipMemcpyAsync(vc.data(), ctx->ws.view_counts.p, vc.size() * 4, hipMemcpyDeviceToHost, ctx->stream),
             "read view counts");
-    HIP_TRY(hipMemcpyAsync(c, ctx->counters.p, sizeof c, hipMemcpyDeviceToHost, ctx->stream), "read counters");
-    HIP_TRY(hipMemcpyAsync(&r32, static_cast<uint32_t*>(ctx->rows_off.p) + ctx->rows, sizeof r32,
+    HIP_TRY(hipMemcpyAsync(c, ctx->ws.counters.p, sizeof c, hipMemcpyDeviceToHost, ctx->stream), "read counters");
+    HIP_TRY(hipMemcpyAsync(&r32, static_cast<uint32_t*>(ctx->ws.rows_off.p) + ctx->rows, sizeof r32,
                            hipMemcpyDeviceToHost, ctx->stream),
             "read R");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
@@ -841,20 +1043,22 @@ gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out)
 
 gs_status gs_copy_lists(gs_context* ctx, uint32_t* values, uint32_t* tile_offsets, uint64_t* keys, void* stream)
 {
+    if (ctx && ctx->last_noalloc)
+        return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the lists of a no-allocation render are not kept");
     gs_list_info info;
     gs_status st = gs_get_list_info(ctx, &info);
     if (st != GS_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t T = ctx->tiles;
     if (values && info.num_pairs)
-        HIP_TRY(hipMemcpyAsync(values, ctx->values.p, info.num_pairs * 4, hipMemcpyDeviceToDevice, s), "copy values");
+        HIP_TRY(hipMemcpyAsync(values, ctx->ws.values.p, info.num_pairs * 4, hipMemcpyDeviceToDevice, s), "copy values");
     if (tile_offsets)
-        HIP_TRY(hipMemcpyAsync(tile_offsets, ctx->tile_offsets.p, (size_t)(T + 1) * 4, hipMemcpyDeviceToDevice, s),
+        HIP_TRY(hipMemcpyAsync(tile_offsets, ctx->ws.tile_offsets.p, (size_t)(T + 1) * 4, hipMemcpyDeviceToDevice, s),
                 "copy offsets");
     if (keys)
-        HIP_TRY(launch_write_keys(static_cast<const uint32_t*>(ctx->values.p),
-                                  static_cast<const uint32_t*>(ctx->tile_offsets.p),
-                                  static_cast<const uint32_t*>(ctx->depth_key.p), T, keys, s),
+        HIP_TRY(launch_write_keys(static_cast<const uint32_t*>(ctx->ws.values.p),
+                                  static_cast<const uint32_t*>(ctx->ws.tile_offsets.p),
+                                  static_cast<const uint32_t*>(ctx->ws.depth_key.p), T, keys, s),
                 "write keys");
     return GS_OK;
 }
@@ -868,12 +1072,12 @@ gs_status gs_copy_projection(gs_context* ctx, float* splats, uint32_t* depth_key
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t n = (size_t)ctx->n * (size_t)ctx->n_views;
     if (n == 0) return GS_OK;
-    if (splats) HIP_TRY(hipMemcpyAsync(splats, ctx->splats.p, n * sizeof(Splat), hipMemcpyDeviceToDevice, s), "copy");
-    if (depth_key) HIP_TRY(hipMemcpyAsync(depth_key, ctx->depth_key.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
-    if (radius) HIP_TRY(hipMemcpyAsync(radius, ctx->radius.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
+    if (splats) HIP_TRY(hipMemcpyAsync(splats, ctx->ws.splats.p, n * sizeof(Splat), hipMemcpyDeviceToDevice, s), "copy");
+    if (depth_key) HIP_TRY(hipMemcpyAsync(depth_key, ctx->ws.depth_key.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
+    if (radius) HIP_TRY(hipMemcpyAsync(radius, ctx->ws.radius.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
     if (tiles_touched)
-        HIP_TRY(hipMemcpyAsync(tiles_touched, ctx->tiles_touched.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
-    if (rect) HIP_TRY(hipMemcpyAsync(rect, ctx->rect.p, n * 8, hipMemcpyDeviceToDevice, s), "copy");
+        HIP_TRY(hipMemcpyAsync(tiles_touched, ctx->ws.tiles_touched.p, n * 4, hipMemcpyDeviceToDevice, s), "copy");
+    if (rect) HIP_TRY(hipMemcpyAsync(rect, ctx->ws.rect.p, n * 8, hipMemcpyDeviceToDevice, s), "copy");
     return GS_OK;
 }
 
@@ -894,7 +1098,7 @@ gs_status gs_get_stage_times(gs_context* ctx, float* ms, int32_t count)
 {
     if (!ctx || !ms) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
     if (count != GS_NUM_STAGES) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "count must be GS_NUM_STAGES");
-    if (!ctx->have_render || !ctx->timed)
+    if (!(ctx->have_render || ctx->last_noalloc) || !ctx->timed)
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render was not timed (gs_set_profiling)");
     HIP_TRY(hipEventSynchronize(ctx->ev[8]), "hipEventSynchronize");
     const int from[GS_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7};
@@ -1016,7 +1220,7 @@ gs_status read_tile_work(gs_context* ctx, std::vector<uint64_t>& w)
     w.assign(T * kTileWorkFields, 0);
     if (T == 0) return GS_OK;
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-    HIP_TRY(hipMemcpyAsync(w.data(), ctx->tile_work.p, T * kTileWorkFields * 8, hipMemcpyDeviceToHost, ctx->stream),
+    HIP_TRY(hipMemcpyAsync(w.data(), ctx->ws.tile_work.p, T * kTileWorkFields * 8, hipMemcpyDeviceToHost, ctx->stream),
             "read tile work");
     HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     return GS_OK;
