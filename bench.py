@@ -83,42 +83,63 @@ def algorithmic_bytes(stage: str, n: int, n_vis: int, K: int, R: int, deg: int, 
     raise KeyError(stage)
 
 
-def cpu_baseline(scene, cam, band_rows: int = 4) -> dict:
-    """The FP64 oracle on a bounded sample of the same frame.
+def cpu_baseline(scene, cam, band_rows: int = 4, band_rows_1t: int = 1, reps: int = 3) -> dict:
+    """The FP64 oracle, as it is, on a bounded sample of the same frame, per
+    stage, median of ``reps`` runs, with all host cores and with one thread.
 
     Sample: the whole projection and pair emission of the frame, then the sort,
-    tile ranges and compositing of ``band_rows`` tile rows in the middle of
-    the image; the frame time is extrapolated as project + emit +
-    (sort + composite of the band) / (band share of all pairs)."""
+    tile ranges and compositing of the middle ``band_rows`` tile rows (all
+    cores) or ``band_rows_1t`` (one thread).  The frame time extrapolates the
+    sort and composite by the band's share of all pairs."""
+    import statistics
     import numpy as np
     import oracle
     W, H = cam["width"], cam["height"]
     tx, ty = (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
-    t0 = time.perf_counter()
-    proj = oracle.project(scene, cam)
-    t1 = time.perf_counter()
-    _, keys, values = oracle.bin_pairs(proj)
-    t2 = time.perf_counter()
-    r0 = ty // 2 - band_rows // 2
-    lo, hi = np.uint64(r0 * tx) << np.uint64(32), np.uint64((r0 + band_rows) * tx) << np.uint64(32)
-    sel = (keys >= lo) & (keys < hi)
-    bk, bv = oracle.sort_pairs(keys[sel], values[sel])
-    ranges = oracle.tile_ranges(bk, tx * ty)
-    pxs, pys = [], []
-    for tile in range(r0 * tx, (r0 + band_rows) * tx):
-        x0, y0 = (tile % tx) * TILE, (tile // tx) * TILE
-        ys, xs = np.mgrid[y0:min(y0 + TILE, H), x0:min(x0 + TILE, W)]
-        s, e = ranges[tile]
-        oracle.composite_pixels(proj, xs.ravel(), ys.ravel(), bv[s:e])
-    t3 = time.perf_counter()
-    share = float(sel.sum()) / max(1, len(keys))
-    frame_s = (t1 - t0) + (t2 - t1) + (t3 - t2) / max(share, 1e-9)
-    del keys, values
-    return {"value": 1.0 / frame_s, "unit": "frames/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": (f"FP64 oracle: full projection ({t1 - t0:.2f} s) and pair emission ({t2 - t1:.2f} s) "
-                       f"of the frame, then sort + composite of {band_rows} middle tile rows "
-                       f"({t3 - t2:.2f} s, {share * 100:.1f}% of the pairs); frame time extrapolated "
-                       f"to {frame_s:.1f} s")}
+
+    def one_run(rows):
+        t0 = time.perf_counter()
+        proj = oracle.project(scene, cam)
+        t1 = time.perf_counter()
+        _, keys, values = oracle.bin_pairs(proj)
+        t2 = time.perf_counter()
+        r0 = ty // 2 - rows // 2
+        lo, hi = np.uint64(r0 * tx) << np.uint64(32), np.uint64((r0 + rows) * tx) << np.uint64(32)
+        sel = (keys >= lo) & (keys < hi)
+        bk, bv = oracle.sort_pairs(keys[sel], values[sel])
+        ranges = oracle.tile_ranges(bk, tx * ty)
+        t3 = time.perf_counter()
+        for tile in range(r0 * tx, (r0 + rows) * tx):
+            x0, y0 = (tile % tx) * TILE, (tile // tx) * TILE
+            ys, xs = np.mgrid[y0:min(y0 + TILE, H), x0:min(x0 + TILE, W)]
+            s, e = ranges[tile]
+            oracle.composite_pixels(proj, xs.ravel(), ys.ravel(), bv[s:e])
+        t4 = time.perf_counter()
+        share = float(sel.sum()) / max(1, len(keys))
+        return {"project": t1 - t0, "emit_pairs": t2 - t1, "sort_band": t3 - t2, "composite_band": t4 - t3,
+                "share": share}
+
+    out = {}
+    cores = oracle.max_threads()
+    for label, threads, rows in (("all_cores", 0, band_rows), ("one_thread", 1, band_rows_1t)):
+        oracle.set_threads(threads)
+        runs = [one_run(rows) for _ in range(reps)]
+        med = {k: statistics.median(r[k] for r in runs) for k in runs[0]}
+        frame = med["project"] + med["emit_pairs"] + (med["sort_band"] + med["composite_band"]) / max(med["share"],
+                                                                                                      1e-9)
+        out[label] = {"threads": cores if threads == 0 else 1, "band_tile_rows": rows,
+                      "band_pair_share": round(med["share"], 4),
+                      "stage_s": {k: round(v, 3) for k, v in med.items() if k != "share"},
+                      "frame_s_extrapolated": round(frame, 2), "frames_per_s": 1.0 / frame}
+    oracle.set_threads(0)
+    allc = out["all_cores"]
+    return {"value": allc["frames_per_s"], "unit": "frames/s", "cores": allc["threads"], "kind": "oracle",
+            "sample": (f"FP64 oracle, median of {reps} runs per stage: full projection and pair emission of the "
+                       f"frame, then sort + composite of the middle {band_rows} tile rows "
+                       f"({allc['band_pair_share'] * 100:.1f}% of the pairs) with all {allc['threads']} cores, "
+                       f"or of the middle {band_rows_1t} row with one thread; frame time extrapolated by the "
+                       f"band's share of the pairs"),
+            "per_thread_count": out}
 
 
 # kernel -> the sources its code comes from (a counter reading stays valid
@@ -636,7 +657,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (FP64 oracle, bounded sample)")
-        cpu = cpu_baseline(scene, cam, band_rows=16)
+        cpu = cpu_baseline(scene, cam)
 
     res = {
         "metric": METRIC,

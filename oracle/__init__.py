@@ -74,6 +74,8 @@ def _declare(L):
     L.or_composite_pixels.argtypes = [_i64, _p, _p, _p, _i64, _i64, _p, _p, _p, _p, _p, _p, _p]
     L.or_bruteforce.argtypes = [_int, _int, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
     L.or_max_threads.restype = _int
+    L.or_set_threads.argtypes = [_int]
+    L.or_set_threads.restype = None
 
 
 def _ptr(a: np.ndarray):
@@ -91,6 +93,11 @@ def camera_array(cam: dict) -> np.ndarray:
 
 def max_threads() -> int:
     return int(lib().or_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (<= 0: default)."""
+    lib().or_set_threads(int(n))
 
 
 def sh_basis(d) -> np.ndarray:

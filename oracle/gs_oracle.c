@@ -546,6 +546,17 @@ void or_bruteforce(int width, int height, int64_t n, const double* radius_margin
     free(e);
 }
 
+/* Threads the parallel loops use from now on (timing at one thread and at
+ * all cores); n <= 0 restores the default. */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 int or_max_threads(void)
 {
 #ifdef _OPENMP
