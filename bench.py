@@ -405,6 +405,36 @@ def time_backward(r, dev, cam, W: int, H: int, steps: int, out) -> dict:
             "forward_backward_per_s": round(1e3 / ms_step, 1), "steps": bsteps}
 
 
+def time_batched_backward(r, dev, cams, steps: int) -> dict:
+    """One training step's rasterizer work on a batch of views: the batched
+    render of all views, then one backward over them (seeded dL/d(image) and
+    dL/d(final_T) in [0, 1) per view), per step; and the backward alone."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4321)
+    outs = r.render_batched(dev, cams)
+    gi = [torch.rand((3, c["height"], c["width"]), device="cuda", generator=g) for c in cams]
+    gt = [torch.rand((c["height"], c["width"]), device="cuda", generator=g) for c in cams]
+    r.backward(dev, gi, gt)
+    torch.cuda.synchronize()
+    bsteps = max(3, min(steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(bsteps):
+        r.render_batched(dev, cams, outs=outs)
+        r.backward(dev, gi, gt)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / bsteps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(bsteps):
+        r.backward(dev, gi, gt)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_bwd = e0.elapsed_time(e1) / bsteps
+    return {"views": len(cams), "ms_forward_backward": round(ms_step, 3), "ms_backward": round(ms_bwd, 3),
+            "views_per_s_forward_backward": round(len(cams) * 1e3 / ms_step, 1), "steps": bsteps}
+
+
 def time_reuse(r, dev, W: int, H: int, frames: int = 16) -> dict:
     """Orbits of several step sizes around the scene (the camera motions of
     the paper's churn table): frame time with and without
@@ -603,6 +633,10 @@ def main():
             variants["batched_C4_64views"] = time_batched(r, dev4, scenes.make_cameras("C4"), args.steps)
             variants["batched_C4_64views"]["workload"] = scenes.WORKLOAD_NAMES["C4"]
             log("[bench] variant batched_C4_64views: " + json.dumps(variants["batched_C4_64views"]))
+            variants["batched_C4_64views_backward"] = time_batched_backward(r, dev4, scenes.make_cameras("C4"),
+                                                                            args.steps)
+            log("[bench] variant batched_C4_64views_backward: " +
+                json.dumps(variants["batched_C4_64views_backward"]))
             del dev4
 
     K, n_vis, R = info["num_pairs"], info["n_visible"], info["num_row_entries"]

@@ -93,7 +93,11 @@ typedef struct {
  *                  host sync; pairs past the bound are dropped without any
  *                  out-of-bounds write, the image is then unspecified, and
  *                  gs_get_list_info (hence gs_copy_lists) returns
- *                  GS_ERR_CAPACITY for that render
+ *                  GS_ERR_CAPACITY for that render; above 2^32 - 1:
+ *                  GS_ERR_UNSUPPORTED (pair offsets are 32-bit; a render
+ *                  with more pairs returns GS_ERR_CAPACITY after the row
+ *                  counts, before the pair buffers are sized or any output
+ *                  is written)
  *   flags          0 or GS_RENDER_REUSE_ORDER (below); other bits give
  *                  GS_ERR_INVALID_ARGUMENT */
 typedef struct {

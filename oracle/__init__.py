@@ -73,6 +73,7 @@ def _declare(L):
     L.or_composite.argtypes = [_int, _int, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p]
     L.or_composite_pixels.argtypes = [_i64, _p, _p, _p, _i64, _i64, _p, _p, _p, _p, _p, _p, _p]
     L.or_bruteforce.argtypes = [_int, _int, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+    L.or_render_tiles.argtypes = [_int, _int, _i64] + [_p] * 8 + [_p, _i64, _p, _p, _p, _p]
     L.or_max_threads.restype = _int
     L.or_set_threads.argtypes = [_int]
     L.or_set_threads.restype = None
@@ -230,6 +231,27 @@ def composite_pixels(proj: dict, px, py, tile_values: np.ndarray, background=(0.
                               _ptr(proj["rgb"]), _ptr(np.asarray(background, np.float64)),
                               _ptr(out), _ptr(marg))
     return out, marg
+
+
+def render_tiles(proj: dict, tiles=None, background=(0.0, 0.0, 0.0), out: dict | None = None) -> dict:
+    """The given tiles (row-major indices; all when None), each from its own
+    list and composited pixel by pixel, without emitting or sorting every
+    pair of the frame: the same lists and per-pixel walk as ``render``, for
+    whole large frames or for the tiles a change touches.  Writes only those
+    tiles' pixels of ``out`` (new zero arrays when None) and returns it."""
+    W, H, n = proj["width"], proj["height"], proj["n"]
+    T = proj["tiles_x"] * proj["tiles_y"]
+    tl = np.arange(T, dtype=np.int64) if tiles is None else np.ascontiguousarray(tiles, np.int64)
+    if out is None:
+        out = dict(image=np.zeros((3, H, W)), final_T=np.zeros((H, W)), n_contrib=np.zeros((H, W), np.int32),
+                   margin=np.zeros((2, H, W)))
+    if len(tl):
+        lib().or_render_tiles(W, H, n, _ptr(proj["rect"]), _ptr(proj["tiles_touched"]), _ptr(proj["depth_bits"]),
+                              _ptr(proj["mean2d"]), _ptr(proj["conic"]), _ptr(proj["opacity"]), _ptr(proj["rgb"]),
+                              _ptr(np.asarray(background, np.float64)), _ptr(tl), len(tl), _ptr(out["image"]),
+                              _ptr(out["final_T"]), _ptr(out["n_contrib"]), _ptr(out["margin"]))
+    out["margin_alpha"], out["margin_T"] = out["margin"][0], out["margin"][1]
+    return out
 
 
 def bruteforce(proj: dict, background=(0.0, 0.0, 0.0)) -> dict:

@@ -504,6 +504,75 @@ void or_composite_pixels(int64_t count, const int32_t* px, const int32_t* py, co
                         out5 + 5 * k, out_margin2 + 2 * k);
 }
 
+/* Selected tiles of the image, each one on its own: the tile's list (every
+ * Gaussian whose rectangle holds the tile, ordered by (depth_bits, index),
+ * the list of or_tile_list) and every pixel of the tile composited along it
+ * (composite_pixel), tiles in parallel.  The Gaussians of each tile row are
+ * gathered once, in index order, so a tile's list comes from its row's
+ * candidates instead of all n.  tiles[count] are tile indices (row-major);
+ * only their pixels of out_rgb[3][H][W], out_T, out_nc and out_margin[2][H][W]
+ * are written. */
+void or_render_tiles(int width, int height, int64_t n, const int32_t* rect, const uint32_t* tiles_touched,
+                     const uint32_t* depth_bits, const double* mean2d, const double* conic, const double* opacity,
+                     const double* rgb, const double* bg3, const int64_t* tiles, int64_t count, double* out_rgb,
+                     double* out_T, int32_t* out_nc, double* out_margin)
+{
+    int tiles_x = (width + TILE - 1) / TILE, tiles_y = (height + TILE - 1) / TILE;
+    int64_t P = (int64_t)width * height;
+    /* the tile rows the selection needs, and their candidates */
+    char* need = (char*)calloc((size_t)tiles_y, 1);
+    for (int64_t k = 0; k < count; ++k) need[tiles[k] / tiles_x] = 1;
+    int64_t* row_count = (int64_t*)calloc((size_t)tiles_y + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        if (tiles_touched[i] == 0) continue;
+        for (int32_t ty = rect[n + i]; ty < rect[3 * n + i]; ++ty)
+            if (need[ty]) ++row_count[ty + 1];
+    }
+    for (int ty = 0; ty < tiles_y; ++ty) row_count[ty + 1] += row_count[ty];
+    uint32_t* cand = (uint32_t*)malloc((size_t)(row_count[tiles_y] > 0 ? row_count[tiles_y] : 1) * sizeof(uint32_t));
+    int64_t* fill = (int64_t*)malloc((size_t)tiles_y * sizeof(int64_t));
+    for (int ty = 0; ty < tiles_y; ++ty) fill[ty] = row_count[ty];
+    for (int64_t i = 0; i < n; ++i) {
+        if (tiles_touched[i] == 0) continue;
+        for (int32_t ty = rect[n + i]; ty < rect[3 * n + i]; ++ty)
+            if (need[ty]) cand[fill[ty]++] = (uint32_t)i;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < count; ++k) {
+        int64_t tile = tiles[k];
+        int32_t tx = (int32_t)(tile % tiles_x), ty = (int32_t)(tile / tiles_x);
+        int64_t c0 = row_count[ty], c1 = row_count[ty + 1], m = 0;
+        depth_entry_t* e = (depth_entry_t*)malloc((size_t)(c1 > c0 ? c1 - c0 : 1) * sizeof(depth_entry_t));
+        for (int64_t c = c0; c < c1; ++c) {
+            uint32_t i = cand[c];
+            if (tx < rect[i] || tx >= rect[2 * n + i]) continue;
+            e[m].bits = depth_bits[i];
+            e[m].index = i;
+            ++m;
+        }
+        qsort(e, (size_t)m, sizeof(depth_entry_t), cmp_depth_entry);
+        uint32_t* list = (uint32_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint32_t));
+        for (int64_t j = 0; j < m; ++j) list[j] = e[j].index;
+        for (int py = ty * TILE; py < ty * TILE + TILE && py < height; ++py)
+            for (int px = tx * TILE; px < tx * TILE + TILE && px < width; ++px) {
+                double o[5], mg[2];
+                composite_pixel(px, py, list, m, n, mean2d, conic, opacity, rgb, bg3, o, mg);
+                int64_t p = (int64_t)py * width + px;
+                for (int ch = 0; ch < 3; ++ch) out_rgb[ch * P + p] = o[ch];
+                out_T[p] = o[3];
+                out_nc[p] = (int32_t)o[4];
+                out_margin[p] = mg[0];
+                out_margin[P + p] = mg[1];
+            }
+        free(list);
+        free(e);
+    }
+    free(fill);
+    free(cand);
+    free(row_count);
+    free(need);
+}
+
 typedef struct { double depth; uint32_t index; } brute_entry_t;
 
 static int cmp_brute(const void* a, const void* b)

@@ -184,6 +184,8 @@ gs_status validate_opts(gs_context* ctx, const gs_render_opts* opts)
         if (opts->tile_size != kTile) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "tile_size must be 16");
         if (opts->flags & ~GS_RENDER_REUSE_ORDER)
             return fail(ctx, GS_ERR_INVALID_ARGUMENT, "unknown flag in opts->flags");
+        if (opts->pair_capacity > 0xFFFFFFFFull)
+            return fail(ctx, GS_ERR_UNSUPPORTED, "pair_capacity above 2^32-1: pair offsets are 32-bit");
         if (!finite_all(opts->background, 3))
             return fail(ctx, GS_ERR_INVALID_ARGUMENT, "background holds a non-finite value");
     }

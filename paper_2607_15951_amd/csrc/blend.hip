@@ -226,10 +226,26 @@ __device__ __forceinline__ int cost_bucket(uint32_t c)
     return 128 + (e - 7) * 32 + (int)((c >> (e - 5)) & 31u);
 }
 
+// Lanes of the wave holding the same bucket as this lane (ten ballots over the
+// bucket's bits), among the lanes where `active` holds.
+__device__ __forceinline__ uint64_t same_bucket_lanes(int b, bool active)
+{
+    uint64_t m = __ballot(active);
+#pragma unroll
+    for (int bit = 0; bit < 10; ++bit) {
+        const bool on = (b >> bit) & 1;
+        const uint64_t bb = __ballot(on);
+        m &= on ? bb : ~bb;
+    }
+    return m;
+}
+
 // One 1024-thread workgroup: a counting sort of the tiles by descending cost
-// bucket.  Within a bucket the order is whatever the LDS atomics give: the
-// order only decides when each tile's workgroup starts, never what it
-// computes.
+// bucket.  Lanes of a wave that share a bucket (cheap and empty tiles mostly
+// do) count and claim their slots with one LDS atomic per group, led by the
+// group's lowest lane.  Within a bucket the order is whatever the atomics
+// give: the order only decides when each tile's workgroup starts, never what
+// it computes.
 __global__ __launch_bounds__(1024) void blend_order_kernel(const uint32_t* __restrict__ cost,
                                                            const uint32_t* __restrict__ offsets, int64_t tiles,
                                                            uint32_t* __restrict__ order)
@@ -237,11 +253,15 @@ __global__ __launch_bounds__(1024) void blend_order_kernel(const uint32_t* __res
     __shared__ uint32_t hist[kOrderBuckets];
     __shared__ uint32_t wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     hist[tid] = 0u;
     __syncthreads();
-    for (int64_t t = tid; t < tiles; t += 1024) {
-        const uint32_t c = cost ? cost[t] : offsets[t + 1] - offsets[t];
-        atomicAdd(&hist[cost_bucket(c)], 1u);
+    for (int64_t t0 = 0; t0 < tiles; t0 += 1024) {
+        const int64_t t = t0 + tid;
+        const bool in = t < tiles;
+        const int b = in ? cost_bucket(cost ? cost[t] : offsets[t + 1] - offsets[t]) : 0;
+        const uint64_t m = same_bucket_lanes(b, in);
+        if (in && (m & below) == 0) atomicAdd(&hist[b], (uint32_t)__popcll(m));
     }
     __syncthreads();
     // start of each bucket in descending bucket order: thread k holds bucket
@@ -259,9 +279,16 @@ __global__ __launch_bounds__(1024) void blend_order_kernel(const uint32_t* __res
     __syncthreads();
     hist[kOrderBuckets - 1 - tid] = before + x - own;   // now the bucket's next free slot
     __syncthreads();
-    for (int64_t t = tid; t < tiles; t += 1024) {
-        const uint32_t c = cost ? cost[t] : offsets[t + 1] - offsets[t];
-        order[atomicAdd(&hist[cost_bucket(c)], 1u)] = (uint32_t)t;
+    for (int64_t t0 = 0; t0 < tiles; t0 += 1024) {
+        const int64_t t = t0 + tid;
+        const bool in = t < tiles;
+        const int b = in ? cost_bucket(cost ? cost[t] : offsets[t + 1] - offsets[t]) : 0;
+        const uint64_t m = same_bucket_lanes(b, in);
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0u;
+        if (in && lane == leader) base = atomicAdd(&hist[b], (uint32_t)__popcll(m));
+        base = (uint32_t)__shfl((int)base, leader < 0 ? 0 : leader, 64);
+        if (in) order[base + (uint32_t)__popcll(m & below)] = (uint32_t)t;
     }
 }
 

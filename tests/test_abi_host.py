@@ -56,6 +56,15 @@ def test_validate_accepts_good_arguments(lib):
     assert gs.validate(g, cam, 1, 1, opts, C.c_void_p(0x2000)) == gs.GS_OK
 
 
+def test_validate_bounds_the_pair_capacity(lib):
+    """Pair offsets are 32-bit: a capacity above 2^32 - 1 is refused on the host."""
+    g, cam, opts = _valid_args()
+    opts.pair_capacity = (1 << 32) - 1
+    assert gs.validate(g, cam, 64, 48, opts, C.c_void_p(0x2000)) == gs.GS_OK
+    opts.pair_capacity = 1 << 32
+    assert gs.validate(g, cam, 64, 48, opts, C.c_void_p(0x2000)) == gs.GS_ERR_UNSUPPORTED
+
+
 def test_validate_accepts_the_reuse_flag(lib):
     g, cam, opts = _valid_args()
     opts.flags = gs.RENDER_REUSE_ORDER

@@ -180,6 +180,44 @@ def test_huge_gaussian_covers_every_tile(renderer):
     full_parity(renderer, sc, scenes.default_camera(150, 90), "huge")
 
 
+def test_more_than_2_32_pairs_is_refused_before_the_pair_buffers(renderer):
+    """4.9e9 (Gaussian, tile) pairs: 600k Gaussians that each cover all 8160
+    tiles of a 1080p image.  Pair offsets are 32-bit, so the eager render
+    stops after the row counts with GS_ERR_CAPACITY: no output written, and
+    no pair buffer allocated (the device's free memory does not drop by the
+    20 GB it would take)."""
+    import torch
+    import paper_2607_15951_amd as gs
+    n = 600_000
+    rng = np.random.default_rng(14)
+    sc = _tiny(rng.uniform(-0.05, 0.05, (3, n)), np.full((3, n), 0.5), np.tile([[1], [0], [0], [0]], (1, n)),
+               np.zeros(n), rng.uniform(0, 1, (3, n)))
+    cam = scenes.default_camera(1920, 1080)
+    dev = gs.scene_to_device(sc)
+    out = {"image": torch.full((3, 1080, 1920), -2.0, device="cuda"),
+           "final_T": torch.full((1080, 1920), -2.0, device="cuda"),
+           "n_contrib": torch.full((1080, 1920), -2, dtype=torch.int32, device="cuda")}
+    r = gs.Renderer(0)
+    try:
+        torch.cuda.synchronize()
+        free0, _ = torch.cuda.mem_get_info()
+        with pytest.raises(gs.GsError) as e:
+            r.render(dev, cam, 1920, 1080, out=out)
+        assert e.value.status == gs.GS_ERR_CAPACITY, str(e.value)
+        torch.cuda.synchronize()
+        free1, _ = torch.cuda.mem_get_info()
+        say(f"[capacity] {e.value}; device memory taken by the attempt: {(free0 - free1) / 2**30:.2f} GiB")
+        assert free0 - free1 < 4 * 2**30
+        assert bool((out["image"] == -2.0).all()) and bool((out["final_T"] == -2.0).all())
+        assert bool((out["n_contrib"] == -2).all())
+        # the context renders normally afterwards
+        small = gs.scene_to_device(scenes.make_scene("C1"))
+        r.render(small, scenes.default_camera(128, 128), 128, 128)
+        assert r.list_info()["num_pairs"] == 4517
+    finally:
+        r.close()
+
+
 def test_pair_capacity_mode(renderer):
     import paper_2607_15951_amd as gs
     sc = scenes.make_scene("C1", n=1500, seed=13)

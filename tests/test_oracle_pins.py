@@ -444,3 +444,25 @@ def test_composite_pixels_and_tile_list_equal_the_whole_frame_path():
     assert checked == W * H
     assert len(o["keys"]) > 20 * tx * ty   # lists long enough to terminate pixels
     assert (o["n_contrib"] > 0).mean() > 0.5
+
+
+def test_render_tiles_equals_the_whole_frame_path():
+    """render_tiles (each tile's list from its row's candidates) against
+    render (every pair emitted, qsort, composite): bit for bit on every pixel,
+    for all tiles and for a scattered subset (other pixels untouched)."""
+    sc = scenes.make_scene("C3", n=8000, seed=78)
+    cam = scenes.look_at_camera([-0.8, 0.5, -2.9], 237, 141)   # ragged: 15 x 9 tiles
+    o = oracle.render(sc, cam, background=(0.3, 0.1, 0.2))
+    t = oracle.render_tiles(o["proj"], background=(0.3, 0.1, 0.2))
+    for k in ("image", "final_T", "n_contrib", "margin_alpha", "margin_T"):
+        np.testing.assert_array_equal(t[k], o[k], err_msg=k)
+    T = o["proj"]["tiles_x"] * o["proj"]["tiles_y"]
+    pick = np.random.default_rng(5).choice(T, 17, replace=False)
+    sub = oracle.render_tiles(o["proj"], pick, background=(0.3, 0.1, 0.2))
+    mask = np.zeros((141, 237), bool)
+    for tile in pick:
+        x0, y0 = (tile % o["proj"]["tiles_x"]) * 16, (tile // o["proj"]["tiles_x"]) * 16
+        mask[y0:y0 + 16, x0:x0 + 16] = True
+    np.testing.assert_array_equal(sub["image"][:, mask], o["image"][:, mask])
+    np.testing.assert_array_equal(sub["n_contrib"][mask], o["n_contrib"][mask])
+    assert not sub["image"][:, ~mask].any() and not sub["final_T"][~mask].any()
