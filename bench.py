@@ -164,7 +164,7 @@ def stage_kernel(stage: str, dtype: int, deg: int, tuning: dict) -> str:
     if stage == "bin_tile_scatter":
         return f"level2_scatter_kernel<{tuning['bin_tile_items']}>"
     if stage == "blend":
-        return "blend_kernel<false>"
+        return f"blend_kernel<false, {tuning['blend_batch']}>"
     raise KeyError(stage)
 
 
@@ -260,7 +260,7 @@ def _pmc_avg(path: str, counter: str) -> dict:
     acc = {}
     for r in _csv_rows(path):
         # the work-counting blend variant (one launch per bench run) is not the timed kernel
-        if r["Counter_Name"] != counter or "blend_kernel<true>" in kernel_short_name(r["Kernel_Name"]):
+        if r["Counter_Name"] != counter or "blend_kernel<true" in kernel_short_name(r["Kernel_Name"]):
             continue
         k = kernel_short_name(r["Kernel_Name"]).replace(" ", "")
         acc.setdefault(k, []).append(float(r["Counter_Value"]))
@@ -491,9 +491,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--tuning", metavar="SORT,ROW,TILE,GROUP",
+    ap.add_argument("--tuning", metavar="SORT,ROW,TILE,GROUP[,BATCH]",
                     help="launch shapes to use instead of autotuning (sort_items, bin_row_items, bin_tile_items, "
-                         "blend_tile_group)")
+                         "blend_tile_group, blend_batch)")
     ap.add_argument("--frames-only", type=int, metavar="F",
                     help="render F frames of the workload (after one warm-up frame) and nothing else, for "
                          "per-frame counter totals; prints one JSON line")
@@ -540,8 +540,8 @@ def main():
     # same bits), chosen before the timed region like the warm-up
     tune = None
     if args.tuning:
-        vals = [int(v) for v in args.tuning.split(",")]
-        r.set_tuning(sort_items=vals[0], bin_row_items=vals[1], bin_tile_items=vals[2], blend_tile_group=vals[3])
+        names = ("sort_items", "bin_row_items", "bin_tile_items", "blend_tile_group", "blend_batch")
+        r.set_tuning(**dict(zip(names, (int(v) for v in args.tuning.split(",")))))
     elif not args.no_autotune and not args.frames_only:
         log("[bench] autotune")
         tune = r.autotune(dev, [cam], reps=5)

@@ -379,7 +379,10 @@ gs_status gs_get_order_reuse(gs_context* ctx, uint32_t* out2);
  *                     coherence of Sec. 5.7 applied to the load imbalance of
  *                     the per-tile blend (Sec. 6); the backward follows its
  *                     render's order
- * A new context starts at {8, 8, 16, 0}.  gs_set_tuning applies to the
+ *   blend_batch       list entries the blend stages from HBM into on-chip
+ *                     memory per batch: 128, 256 or 512 (the backward
+ *                     stages 256)
+ * A new context starts at {8, 8, 16, 0, 256}.  gs_set_tuning applies to the
  * following renders and backwards (a backward uses its render's shapes; a
  * captured graph keeps those of its capture); GS_ERR_INVALID_ARGUMENT for an
  * unsupported value, leaving the tuning unchanged. */
@@ -388,6 +391,7 @@ typedef struct {
     int32_t bin_row_items;
     int32_t bin_tile_items;
     int32_t blend_tile_group;
+    int32_t blend_batch;
 } gs_tuning;
 
 gs_status gs_set_tuning(gs_context* ctx, const gs_tuning* tuning);
@@ -397,18 +401,20 @@ gs_status gs_get_tuning(gs_context* ctx, gs_tuning* out);
  * it overwrites) with each candidate shape, one parameter at a time from the
  * context's current tuning -- sort_items scored by the depth-sort stage time,
  * bin_row_items and bin_tile_items by the four binning stages,
- * blend_tile_group by the blend -- each candidate once untimed and then reps
+ * blend_tile_group and blend_batch by the blend -- each candidate once
+ * untimed and then reps
  * times timed by the stage events, keeps the fastest value of each parameter
  * before tuning the next, and leaves the result as the context's tuning.
  *   out     the chosen tuning (may be NULL)
  *   out_ms  NULL, or host array [GS_TUNE_CANDIDATES]: the mean scored time
  *           of every candidate in the order sort_items 4, 8, 16;
  *           bin_row_items 4, 8, 16; bin_tile_items 8, 16, 32;
- *           blend_tile_group 0, 1, 2, 4, 8, 16, 32, 64
+ *           blend_tile_group 0, 1, 2, 4, 8, 16, 32, 64; blend_batch 128,
+ *           256, 512
  * Profiling flags are restored afterwards.  Errors as gs_render_batched,
  * GS_ERR_INVALID_ARGUMENT for reps outside [1, 1000] or a context bound to a
  * graph; on error the tuning is left as it was. */
-#define GS_TUNE_CANDIDATES 17
+#define GS_TUNE_CANDIDATES 20
 gs_status gs_autotune(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
                       const gs_render_opts* opts, int32_t reps, void* stream, gs_tuning* out, float* out_ms);
 

@@ -66,11 +66,12 @@ class gs_gradients(C.Structure):
 
 class gs_tuning(C.Structure):
     _fields_ = [("sort_items", C.c_int32), ("bin_row_items", C.c_int32), ("bin_tile_items", C.c_int32),
-                ("blend_tile_group", C.c_int32)]
+                ("blend_tile_group", C.c_int32), ("blend_batch", C.c_int32)]
 
 
 TUNE_CANDIDATES = [("sort_items", v) for v in (4, 8, 16)] + [("bin_row_items", v) for v in (4, 8, 16)] + \
-    [("bin_tile_items", v) for v in (8, 16, 32)] + [("blend_tile_group", v) for v in (0, 1, 2, 4, 8, 16, 32, 64)]
+    [("bin_tile_items", v) for v in (8, 16, 32)] + [("blend_tile_group", v) for v in (0, 1, 2, 4, 8, 16, 32, 64)] + \
+    [("blend_batch", v) for v in (128, 256, 512)]
 
 
 class gs_view(C.Structure):

@@ -488,6 +488,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     bl.n_views = V;
     bl.tiles = T;
     bl.group = tu.blend_group;
+    bl.batch = tu.blend_batch;
     const float zero_bg[3] = {0.f, 0.f, 0.f};
     const float* bg = opts ? o.background : zero_bg;
     for (int k = 0; k < 3; ++k) bl.bg[k] = bg[k];
@@ -1112,7 +1113,10 @@ gs_status gs_get_stage_times(gs_context* ctx, float* ms, int32_t count)
 
 namespace {
 
-Tuning from_abi(const gs_tuning& t) { return Tuning{t.sort_items, t.bin_row_items, t.bin_tile_items, t.blend_tile_group}; }
+Tuning from_abi(const gs_tuning& t)
+{
+    return Tuning{t.sort_items, t.bin_row_items, t.bin_tile_items, t.blend_tile_group, t.blend_batch};
+}
 
 gs_tuning to_abi(const Tuning& t)
 {
@@ -1121,6 +1125,7 @@ gs_tuning to_abi(const Tuning& t)
     o.bin_row_items = t.bin1_items;
     o.bin_tile_items = t.bin2_items;
     o.blend_tile_group = t.blend_group;
+    o.blend_batch = t.blend_batch;
     return o;
 }
 
@@ -1138,6 +1143,7 @@ const TuneParam kTuneParams[] = {
     {&Tuning::bin1_items, {4, 8, 16}, 3, 2, 5},
     {&Tuning::bin2_items, {8, 16, 32}, 3, 2, 5},
     {&Tuning::blend_group, {0, 1, 2, 4, 8, 16, 32, 64}, 8, 6, 6},
+    {&Tuning::blend_batch, {128, 256, 512}, 3, 6, 6},
 };
 
 }  // namespace
@@ -1149,7 +1155,7 @@ gs_status gs_set_tuning(gs_context* ctx, const gs_tuning* tuning)
     if (!tuning_supported(t))
         return fail(ctx, GS_ERR_INVALID_ARGUMENT,
                     "unsupported tuning: sort_items and bin_row_items take 4, 8 or 16, bin_tile_items 8, 16 or 32, "
-                    "blend_tile_group 0..64");
+                    "blend_tile_group 0..64, blend_batch 128, 256 or 512");
     ctx->tuning = t;
     return GS_OK;
 }

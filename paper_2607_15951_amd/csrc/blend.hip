@@ -42,21 +42,34 @@ constexpr int kUnroll = 16;   // entries per unrolled group (a divisor of 64)
 static_assert(64 % kUnroll == 0, "groups do not straddle a 64-entry mask word");
 constexpr uint64_t kGroupMask = kUnroll == 64 ? ~0ull : ((1ull << kUnroll) - 1ull);
 
+// Waves per SIMD the plain kernel asks for, by batch: 7 at 256 entries (at
+// most 72 VGPRs; its batches wait on gathers and barriers, and more resident
+// tiles hide more of that: 5 and 6 waves ran alike, 7 ran 4% faster, 8
+// spilled and ran slower); 6 at 128, which spills at 7 (the half of the
+// lanes that stage carries a predicate); 4 at 512, where each lane carries
+// two entries' gathers (107 VGPRs).
+template <int kBatch>
+constexpr int blend_waves() { return kBatch == 256 ? 7 : (kBatch == 128 ? 6 : 4); }
+
 // kStats: the tracing variant, which also records its work per tile
-// (a.tile_work).  The plain kernel asks for 7 waves per SIMD (at most 72
-// VGPRs; it needs no spills there): its batches wait on gathers and barriers,
-// and more resident tiles hide more of that (measured: 5 and 6 waves ran
-// alike, 7 ran 4% faster, 8 spilled and ran slower).  The tracing kernel keeps
-// the compiler's own budget, where its counters need no spills.
-template <bool kStats>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 : 7))) void blend_kernel(
-    BlendArgs a, uint64_t capacity)
+// (a.tile_work); it keeps the compiler's own register budget, where its
+// counters need no spills.  kBatch: list entries staged per batch (128, 256
+// or 512; an autotuner choice): each lane stages the entries tid, tid + 256
+// of the batch that exist, so 128 leaves half the lanes out of the staging.
+// The image does not depend on it; a smaller batch stages fewer entries past
+// the point where every pixel has terminated, a larger one fewer barriers.
+template <bool kStats, int kBatch>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 : blend_waves<kBatch>()))) void
+blend_kernel(BlendArgs a, uint64_t capacity)
 {
-    __shared__ float4 s0[256 + kUnroll];   // du_hi, dv_hi, du_lo, dv_lo  (centre - tile origin)
-    __shared__ float4 s1[256 + kUnroll];   // A', B', C', opacity  (A' = -0.5 log2(e) A, ...)
-    __shared__ float4 s2[256 + kUnroll];   // r, g, b, list position (int bits)
-    __shared__ uint32_t s_mask[256 + kUnroll];   // quads (waves) the entry can reach
-    __shared__ uint32_t s_wave_keep[4];
+    constexpr int kPer = kBatch > 256 ? kBatch / 256 : 1;   // entries a lane stages per batch
+    constexpr int kWords = kBatch / 64;                     // 64-entry mask words of a batch
+    static_assert(kBatch == 128 || kBatch == 256 || kBatch == 512, "batch of 128, 256 or 512 entries");
+    __shared__ float4 s0[kBatch + kUnroll];   // du_hi, dv_hi, du_lo, dv_lo  (centre - tile origin)
+    __shared__ float4 s1[kBatch + kUnroll];   // A', B', C', opacity  (A' = -0.5 log2(e) A, ...)
+    __shared__ float4 s2[kBatch + kUnroll];   // r, g, b, list position (int bits)
+    __shared__ uint32_t s_mask[kBatch + kUnroll];   // quads (waves) the entry can reach
+    __shared__ uint32_t s_wave_keep[4 * kPer];
     const int tile = blend_tile(a.order, a.group);
     if (tile >= a.tiles) return;
     // the view owning this global tile: its size, tile grid and outputs
@@ -82,52 +95,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 
     uint32_t last = 0, term = 0, composited = 0, staged = 0, bodies = 0;
     bool done = !inside;
     // software pipeline of the gathers: list values two batches ahead, the
-    // 48-byte records one batch ahead, both overlapping the compositing
+    // 48-byte records one batch ahead, both overlapping the compositing.
+    // Lane tid stages the batch entries tid + 256 p (p < kPer) below kBatch.
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    uint32_t g_next = (start + tid < end) ? a.values[start + tid] : 0u;
-    uint32_t g_after = (start + 256 + tid < end) ? a.values[start + 256 + tid] : 0u;
-    float4 na = zero4, nb = zero4, nc = zero4;
-    if (start + tid < end) {
-        const float4* rec = reinterpret_cast<const float4*>(a.splats + g_next);
-        na = rec[0];
-        nb = rec[1];
-        nc = rec[2];
+    uint32_t g_after[kPer];
+    float4 na[kPer], nb[kPer], nc[kPer];
+#pragma unroll
+    for (int p = 0; p < kPer; ++p) {
+        const int slot = p * 256 + tid;
+        const bool act = kBatch >= 256 || slot < kBatch;
+        const uint32_t g_next = (act && start + slot < end) ? a.values[start + slot] : 0u;
+        g_after[p] = (act && start + kBatch + slot < end) ? a.values[start + kBatch + slot] : 0u;
+        na[p] = nb[p] = nc[p] = zero4;
+        if (act && start + slot < end) {
+            const float4* rec = reinterpret_cast<const float4*>(a.splats + g_next);
+            na[p] = rec[0];
+            nb[p] = rec[1];
+            nc[p] = rec[2];
+        }
     }
     uint64_t b0 = start;
-    for (; b0 < end; b0 += 256) {
+    for (; b0 < end; b0 += kBatch) {
         if (__syncthreads_count(!done) == 0) break;
-        const float4 ra = na, rb = nb, rc = nc;
-        if (b0 + 256 + tid < end) {
-            const float4* rec = reinterpret_cast<const float4*>(a.splats + g_after);
-            na = rec[0];
-            nb = rec[1];
-            nc = rec[2];
+        // stage: the lane's entries, each dropped when no pixel of the tile
+        // can reach alpha 1/255 (the per-pixel test would skip it everywhere)
+        bool keep[kPer];
+        uint32_t qmask[kPer];
+        float4 v0[kPer], v1[kPer], v2[kPer];
+#pragma unroll
+        for (int p = 0; p < kPer; ++p) {
+            const int slot = p * 256 + tid;
+            const bool act = kBatch >= 256 || slot < kBatch;
+            const float4 ra = na[p], rb = nb[p], rc = nc[p];
+            if (act && b0 + kBatch + slot < end) {
+                const float4* rec = reinterpret_cast<const float4*>(a.splats + g_after[p]);
+                na[p] = rec[0];
+                nb[p] = rec[1];
+                nc[p] = rec[2];
+            }
+            g_after[p] = (act && b0 + 2 * kBatch + slot < end) ? a.values[b0 + 2 * kBatch + slot] : 0u;
+            const uint64_t e = b0 + slot;
+            keep[p] = false;
+            qmask[p] = 0u;
+            if (act && e < end) {
+                qmask[p] = stage_entry(ra, rb, rc, ox, oy, (uint32_t)(e - start), v0[p], v1[p], v2[p]);
+                keep[p] = qmask[p] != 0u;
+            }
         }
-        g_after = (b0 + 512 + tid < end) ? a.values[b0 + 512 + tid] : 0u;
-        // stage: one entry per lane, dropped when no pixel of the tile can
-        // reach alpha 1/255 (the per-pixel test would skip it everywhere)
-        const uint64_t e = b0 + tid;
-        bool keep = false;
-        uint32_t qmask = 0u;
-        float4 v0, v1, v2;
-        if (e < end) {
-            qmask = stage_entry(ra, rb, rc, ox, oy, (uint32_t)(e - start), v0, v1, v2);
-            keep = qmask != 0u;
+        // order-preserving compaction of the kept entries: list order is
+        // (p, wave, lane)
+        uint64_t km[kPer];
+#pragma unroll
+        for (int p = 0; p < kPer; ++p) {
+            km[p] = __ballot(keep[p]);
+            if (lane == 0) s_wave_keep[p * 4 + wave] = (uint32_t)__popcll(km[p]);
         }
-        // order-preserving compaction of the kept entries
-        const uint64_t km = __ballot(keep);
-        if (lane == 0) s_wave_keep[wave] = (uint32_t)__popcll(km);
-        if (kStats) staged += (end - b0 < 256) ? (uint32_t)(end - b0) : 256u;
+        if (kStats) staged += (end - b0 < (uint64_t)kBatch) ? (uint32_t)(end - b0) : (uint32_t)kBatch;
         __syncthreads();
-        uint32_t slot = (uint32_t)__popcll(km & lt);
-        for (int w = 0; w < wave; ++w) slot += s_wave_keep[w];
-        const int nk = (int)(s_wave_keep[0] + s_wave_keep[1] + s_wave_keep[2] + s_wave_keep[3]);
-        if (keep) {
-            s0[slot] = v0;
-            s1[slot] = v1;
-            s2[slot] = v2;
-            s_mask[slot] = qmask;
+#pragma unroll
+        for (int p = 0; p < kPer; ++p) {
+            uint32_t slot = (uint32_t)__popcll(km[p] & lt);
+            for (int i = 0; i < p * 4 + wave; ++i) slot += s_wave_keep[i];
+            if (keep[p]) {
+                s0[slot] = v0[p];
+                s1[slot] = v1[p];
+                s2[slot] = v2[p];
+                s_mask[slot] = qmask[p];
+            }
         }
+        int nk = 0;
+#pragma unroll
+        for (int i = 0; i < 4 * kPer; ++i) nk += (int)s_wave_keep[i];
         if (tid < kUnroll) {   // padding entries reach no quad
             s0[nk + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
             s1[nk + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -137,9 +175,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 
         __syncthreads();
         // this wave's entries of the batch: bit j of bits[j / 64] when entry j
         // can reach the wave's quad (scalar registers, no per-entry LDS read)
-        uint64_t bits[4];
+        uint64_t bits[kWords];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kWords; ++q) {
             const int jj = q * 64 + lane;
             bits[q] = __ballot(jj < nk && ((s_mask[jj] >> wave) & 1u));
         }
@@ -316,8 +354,13 @@ hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s)
     const int64_t T = a.tiles;
     if (T <= 0) return hipSuccess;
     const int blocks = blend_grid(T, a.order, a.group);
-    if (a.tile_work) hipLaunchKernelGGL(blend_kernel<true>, dim3(blocks), dim3(256), 0, s, a, capacity);
-    else hipLaunchKernelGGL(blend_kernel<false>, dim3(blocks), dim3(256), 0, s, a, capacity);
+    auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, a, capacity); };
+    switch (a.batch) {
+    case 128: a.tile_work ? go(blend_kernel<true, 128>) : go(blend_kernel<false, 128>); break;
+    case 512: a.tile_work ? go(blend_kernel<true, 512>) : go(blend_kernel<false, 512>); break;
+    case 256: a.tile_work ? go(blend_kernel<true, 256>) : go(blend_kernel<false, 256>); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -23,8 +23,9 @@ struct Tuning {
     int bin2_items;    // row entries per lane of a level-2 binning wave: 8, 16, 32
     int blend_group;   // consecutive tiles dealt to one XCD by the blend: 1 .. 64;
                        // 0: tiles dispatched heaviest first, by the previous frame's work
+    int blend_batch;   // list entries the blend stages per batch: 128, 256, 512
 };
-constexpr Tuning kDefaultTuning = {8, 8, 16, 0};
+constexpr Tuning kDefaultTuning = {8, 8, 16, 0, 256};
 bool tuning_supported(const Tuning& t);
 constexpr int kMaxRows = 2048;            // tile rows per image (height <= 32768)
 constexpr int kMaxTotalRows = 16384;      // tile rows over all views of one render
@@ -173,6 +174,7 @@ struct BlendArgs {
     int n_views;
     int64_t tiles;             // global tiles
     int group;                 // tiles per XCD group (Tuning::blend_group)
+    int batch;                 // list entries staged per batch (Tuning::blend_batch)
     const uint32_t* order;     // [tiles] dispatch order (block b renders order[b]), or null: XCD groups
     uint32_t* tile_cost;       // [tiles] list entries each tile walked before it finished, or null
     float bg[3];

@@ -16,8 +16,8 @@ import scenes
 pytestmark = pytest.mark.gpu
 
 CANDIDATES = {"sort_items": (4, 8, 16), "bin_row_items": (4, 8, 16), "bin_tile_items": (8, 16, 32),
-              "blend_tile_group": (0, 1, 2, 4, 8, 16, 32, 64)}
-DEFAULT = {"sort_items": 8, "bin_row_items": 8, "bin_tile_items": 16, "blend_tile_group": 0}
+              "blend_tile_group": (0, 1, 2, 4, 8, 16, 32, 64), "blend_batch": (128, 256, 512)}
+DEFAULT = {"sort_items": 8, "bin_row_items": 8, "bin_tile_items": 16, "blend_tile_group": 0, "blend_batch": 256}
 
 
 def say(msg):
@@ -104,7 +104,7 @@ def test_every_shape_gives_identical_results(renderer, case, capacity):
 def test_set_tuning_rejects_unsupported_values(renderer):
     renderer.set_tuning(**DEFAULT)
     for bad in ({"sort_items": 5}, {"bin_row_items": 32}, {"bin_tile_items": 4}, {"blend_tile_group": -1},
-                {"blend_tile_group": 65}):
+                {"blend_tile_group": 65}, {"blend_batch": 192}):
         with pytest.raises(RuntimeError):
             renderer.set_tuning(**bad)
         assert renderer.tuning() == DEFAULT
