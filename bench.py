@@ -309,8 +309,10 @@ def _pmc_total(path: str, counter: str) -> dict:
     for r in _csv_rows(path):
         if r["Counter_Name"] != counter:
             continue
-        kib += float(r["Counter_Value"])
         name = kernel_short_name(r["Kernel_Name"], templates=False)
+        if name.startswith("__amd_rocclr"):   # the runtime's copies: the scene upload and the size readback
+            continue
+        kib += float(r["Counter_Value"])
         key = r.get("Dispatch_Id") or r.get("Correlation_Id") or id(r)
         if name == "project_kernel" and key not in seen:
             seen.add(key)
