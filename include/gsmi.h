@@ -273,7 +273,14 @@ typedef struct {
 
 gs_status gs_get_list_info(gs_context* ctx, gs_list_info* out);
 
-/* Copies the last render's per-tile lists into caller memory.
+/* Copies the last render's per-tile lists into caller memory: the output of
+ * the duplicate-and-sort stages of Sec. 3.1 (every (Gaussian, tile) pair,
+ * ordered by the 64-bit key tile << 32 | depth), which the blend walks.
+ * Device pointers on the context's device, written on `stream`; the caller
+ * sizes them from gs_get_list_info, and any of them may be NULL (not
+ * copied).  Fails as gs_get_list_info does (no render yet, pairs dropped),
+ * and with GS_ERR_INVALID_ARGUMENT after gs_render_noalloc, whose lists are
+ * not kept.
  *   values        uint32 [K]: Gaussian indices; tile t's list is
  *                 values[offsets[t] .. offsets[t+1]), front to back, i.e.
  *                 all K pairs sorted by key (tile << 32 | depth bits), ties
