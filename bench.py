@@ -43,7 +43,6 @@ FLOPS_COMPOSITE = 9
 # packed-FP32 instruction selection): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x
 # 2.4 GHz
 FP32_VECTOR_NONPACKED_TFLOPS = 78.6
-SORT_PASSES = 4       # 8-bit LSD passes of the depth sort
 
 
 def log(msg):
@@ -52,6 +51,9 @@ def log(msg):
 
 def attr_bytes(dtype: int) -> int:
     return 4 if dtype == 0 else 2
+
+
+PACKED_RECT_TILES = 255   # views at most this many tiles wide and tall carry packed rectangles through the sort
 
 
 def algorithmic_bytes(stage: str, n: int, n_vis: int, K: int, R: int, deg: int, dtype: int, W: int, H: int,
@@ -68,12 +70,23 @@ def algorithmic_bytes(stage: str, n: int, n_vis: int, K: int, R: int, deg: int, 
         per_in = 12 + attr_bytes(dtype) * (3 + 4 + 1 + 3 * (deg + 1) ** 2)
         per_out = 48 + 4 + 4 + 4 + 8
         return n * (per_in + per_out)
-    if stage == "depth_sort":        # per 8-bit pass: keys read for the digit counts, keys + values read and written
-        return SORT_PASSES * n * (4 + 8 + 8)
-    if stage == "bin_row_count":     # sorted index + rectangle per Gaussian; per (row, chunk) count written and scanned
-        return n * (4 + 8) + ty * chunks1 * (4 + 8)
+    packed = tx <= PACKED_RECT_TILES and ty <= PACKED_RECT_TILES
+    if stage == "depth_sort":
+        # four 8-bit passes: each reads the keys for its digit counts, then
+        # reads keys + values (the first pass makes the values) and writes
+        # them (the last pass writes no keys); with the packed rectangles
+        # also 8 B of rectangle read in the first pass, then 4 B per pass
+        # written and read
+        passes = 4 * 4 * n + (4 + 8) * n + (8 + 8) * n * 2 + (8 + 4) * n
+        payload = (8 + 4) * n + (4 + 4) * n * 2 + (4 + 4) * n
+        return passes + (payload if packed else 0)
+    if stage == "bin_row_count":
+        # packed rectangles read in depth order, else sorted index read, the
+        # rectangle gathered and written in depth order; per (row, chunk) a
+        # count written and scanned
+        return (n * 4 if packed else n * (4 + 8 + 8)) + ty * chunks1 * (4 + 8)
     if stage == "bin_row_scatter":   # sorted index + rectangle per visible Gaussian, 8-byte row entries out
-        return n_vis * (4 + 8) + R * 8 + chunks1 * ty * 4
+        return n_vis * (4 + (4 if packed else 8)) + R * 8 + chunks1 * ty * 4
     if stage == "bin_tile_count":    # row entries in; per (chunk, column) count written and scanned; tile offsets
         return R * 8 + chunks2 * tx * (4 + 8) + (tx * ty + 1) * 4
     if stage == "bin_tile_scatter":  # row entries in, chunk prefixes, the values out

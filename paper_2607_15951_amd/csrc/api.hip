@@ -64,6 +64,7 @@ void* scratch_address(int device)
 struct Workspace {
     DevBuf splats, depth_key, radius, tiles_touched, rect;
     DevBuf sort_ka, sort_va, sort_kb, sort_vb, hist, scan_scratch;
+    DevBuf sort_pa, sort_pb;     // packed rectangles carried by the depth sort
     DevBuf bin_info, counts1, rows_off, row_ent, counts2, partials, sorted_rect, readback;
     DevBuf views, row_tiles_x;   // device view table and tiles_x of every global tile row
     DevBuf view_counts;          // [n_views][kViewCounters] visible Gaussians and pairs per view
@@ -333,6 +334,11 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     if ((st = ensure(ctx, w.sort_va, ni * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, w.sort_kb, ni * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, w.sort_vb, ni * 4)) != GS_OK) return st;
+    const bool fits_packed = !noalloc && max_tx <= kPackedRectTiles && max_ty <= kPackedRectTiles;
+    if (fits_packed) {
+        if ((st = ensure(ctx, w.sort_pa, ni * 4)) != GS_OK) return st;
+        if ((st = ensure(ctx, w.sort_pb, ni * 4)) != GS_OK) return st;
+    }
     if ((st = ensure(ctx, w.hist, depth_sort_hist_elems(n, V) * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, w.partials, project_partials_elems(n, V) * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, w.views, (size_t)V * sizeof(ViewParams))) != GS_OK) return st;
@@ -421,12 +427,20 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
                                    static_cast<uint32_t*>(w.sort_vb.p), n, reuse_words, s),
                 "order reuse");
     }
+    // the sort carries each Gaussian's packed rectangle to the binning, which
+    // then reads the rectangles in depth order instead of gathering them;
+    // not when the order may be reused (the radix passes may not run) nor in
+    // a no-allocation render (its scratch is kept small)
+    const bool packed = fits_packed && !reuse;
     HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(w.sort_ka.p),
                               static_cast<uint32_t*>(w.sort_va.p), static_cast<uint32_t*>(w.sort_kb.p),
-                              static_cast<uint32_t*>(w.sort_vb.p), static_cast<uint32_t*>(w.hist.p), n, V,
-                              tu.sort_items, reuse_words, &in_b, s),
+                              static_cast<uint32_t*>(w.sort_vb.p), packed ? pa.rect : nullptr,
+                              static_cast<uint32_t*>(packed ? w.sort_pa.p : nullptr),
+                              static_cast<uint32_t*>(packed ? w.sort_pb.p : nullptr), static_cast<uint32_t*>(w.hist.p),
+                              n, V, tu.sort_items, reuse_words, s),
             "depth sort");
-    ba.sorted_idx = static_cast<const uint32_t*>(in_b ? w.sort_vb.p : w.sort_va.p);
+    ba.sorted_idx = static_cast<const uint32_t*>(w.sort_vb.p);
+    ba.sorted_pack = packed ? static_cast<const uint32_t*>(w.sort_pb.p) : nullptr;
     STAGE_MARK(2);
     HIP_TRY(launch_bin_rows(ba, scan_scratch, s), "bin rows");
     STAGE_MARK(3);
@@ -694,7 +708,8 @@ void gs_destroy(gs_context* ctx)
                       &ctx->ws.scan_scratch, &ctx->ws.bin_info, &ctx->ws.counts1, &ctx->ws.rows_off, &ctx->ws.row_ent,
                       &ctx->ws.counts2, &ctx->ws.partials, &ctx->ws.views, &ctx->ws.row_tiles_x, &ctx->ws.view_counts,
                       &ctx->ws.counters, &ctx->ws.tile_offsets, &ctx->ws.values, &ctx->ws.tile_work, &ctx->ws.sorted_rect,
-                      &ctx->ws.reuse_words, &ctx->ws.readback, &ctx->ws.tile_cost, &ctx->ws.tile_order};
+                      &ctx->ws.reuse_words, &ctx->ws.readback, &ctx->ws.tile_cost, &ctx->ws.tile_order,
+                      &ctx->ws.sort_pa, &ctx->ws.sort_pb};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->host_info) (void)hipHostFree(ctx->host_info);

@@ -278,32 +278,56 @@ __device__ __forceinline__ uint64_t same_bucket_lanes(int b, bool active)
     return m;
 }
 
-// One 1024-thread workgroup: a counting sort of the tiles by descending cost
-// bucket.  Lanes of a wave that share a bucket (cheap and empty tiles mostly
-// do) count and claim their slots with one LDS atomic per group, led by the
-// group's lowest lane.  Within a bucket the order is whatever the atomics
-// give: the order only decides when each tile's workgroup starts, never what
-// it computes.
-__global__ __launch_bounds__(1024) void blend_order_kernel(const uint32_t* __restrict__ cost,
-                                                           const uint32_t* __restrict__ offsets, int64_t tiles,
-                                                           uint32_t* __restrict__ order)
+__device__ __forceinline__ uint32_t tile_cost_of(const uint32_t* cost, const uint32_t* offsets, int64_t t)
 {
-    __shared__ uint32_t hist[kOrderBuckets];
-    __shared__ uint32_t wsum[16];
+    return cost ? cost[t] : offsets[t + 1] - offsets[t];
+}
+
+// One 1024-thread workgroup: a counting sort of the tiles by descending cost
+// bucket.  The first pass loads kOrderPre costs per thread before using any
+// (a load under its own branch is waited for before the next one issues),
+// counts the buckets and keeps each tile's bucket in LDS for the second pass
+// (tiles past kOrderKeptTiles load their cost again).  Lanes of a wave that
+// share a bucket (cheap and empty tiles mostly do) count and claim their
+// slots with one LDS atomic per group, led by the group's lowest lane.
+// Within a bucket the order is whatever the atomics give: the order only
+// decides when each tile's workgroup starts, never what it computes.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderPre = 8;
+constexpr int kOrderKeptTiles = 32768;
+static_assert(kOrderBuckets == kOrderThreads, "one bucket per thread in the scan");
+__global__ __launch_bounds__(kOrderThreads) void blend_order_kernel(const uint32_t* __restrict__ cost,
+                                                                    const uint32_t* __restrict__ offsets,
+                                                                    int64_t tiles, uint32_t* __restrict__ order)
+{
+    __shared__ uint32_t hist[kOrderBuckets];   // counts, then each bucket's next free slot
+    __shared__ uint16_t s_bucket[kOrderKeptTiles];
+    __shared__ uint32_t wsum[kOrderThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     hist[tid] = 0u;
     __syncthreads();
-    for (int64_t t0 = 0; t0 < tiles; t0 += 1024) {
-        const int64_t t = t0 + tid;
-        const bool in = t < tiles;
-        const int b = in ? cost_bucket(cost ? cost[t] : offsets[t + 1] - offsets[t]) : 0;
-        const uint64_t m = same_bucket_lanes(b, in);
-        if (in && (m & below) == 0) atomicAdd(&hist[b], (uint32_t)__popcll(m));
+    constexpr int64_t kStep = (int64_t)kOrderThreads * kOrderPre;
+    for (int64_t t0 = 0; t0 < tiles; t0 += kStep) {
+        uint32_t c[kOrderPre];
+#pragma unroll
+        for (int k = 0; k < kOrderPre; ++k) {
+            const int64_t t = t0 + k * kOrderThreads + tid;
+            c[k] = tile_cost_of(cost, offsets, t < tiles ? t : 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kOrderPre; ++k) {
+            const int64_t t = t0 + k * kOrderThreads + tid;
+            const bool in = t < tiles;
+            const int b = in ? cost_bucket(c[k]) : 0;
+            const uint64_t m = same_bucket_lanes(b, in);
+            if (in && (m & below) == 0) atomicAdd(&hist[b], (uint32_t)__popcll(m));
+            if (in && t < kOrderKeptTiles) s_bucket[t] = (uint16_t)b;
+        }
     }
     __syncthreads();
     // start of each bucket in descending bucket order: thread k holds bucket
-    // 1023 - k, scanned inclusively across the block
+    // 1023 - k, scanned exclusively across the block
     const uint32_t own = hist[kOrderBuckets - 1 - tid];
     uint32_t x = own;
     for (int o = 1; o < 64; o <<= 1) {
@@ -314,19 +338,31 @@ __global__ __launch_bounds__(1024) void blend_order_kernel(const uint32_t* __res
     __syncthreads();
     uint32_t before = 0u;
     for (int w = 0; w < wave; ++w) before += wsum[w];
-    __syncthreads();
     hist[kOrderBuckets - 1 - tid] = before + x - own;   // now the bucket's next free slot
     __syncthreads();
-    for (int64_t t0 = 0; t0 < tiles; t0 += 1024) {
-        const int64_t t = t0 + tid;
-        const bool in = t < tiles;
-        const int b = in ? cost_bucket(cost ? cost[t] : offsets[t + 1] - offsets[t]) : 0;
-        const uint64_t m = same_bucket_lanes(b, in);
-        const int leader = __ffsll((long long)m) - 1;
-        uint32_t base = 0u;
-        if (in && lane == leader) base = atomicAdd(&hist[b], (uint32_t)__popcll(m));
-        base = (uint32_t)__shfl((int)base, leader < 0 ? 0 : leader, 64);
-        if (in) order[base + (uint32_t)__popcll(m & below)] = (uint32_t)t;
+    for (int64_t t0 = 0; t0 < tiles; t0 += kStep) {
+        uint32_t c[kOrderPre];
+        const bool reload = t0 + kStep > kOrderKeptTiles;   // uniform: whole steps past the kept tiles
+        if (reload) {
+#pragma unroll
+            for (int k = 0; k < kOrderPre; ++k) {
+                const int64_t t = t0 + k * kOrderThreads + tid;
+                c[k] = tile_cost_of(cost, offsets, t < tiles ? t : 0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kOrderPre; ++k) {
+            const int64_t t = t0 + k * kOrderThreads + tid;
+            const bool in = t < tiles;
+            int b = 0;
+            if (in) b = reload ? cost_bucket(c[k]) : (int)s_bucket[t];
+            const uint64_t m = same_bucket_lanes(b, in);
+            const int leader = __ffsll((long long)m) - 1;
+            uint32_t base = 0u;
+            if (in && lane == leader) base = atomicAdd(&hist[b], (uint32_t)__popcll(m));
+            base = (uint32_t)__shfl((int)base, leader < 0 ? 0 : leader, 64);
+            if (in) order[base + (uint32_t)__popcll(m & below)] = (uint32_t)t;
+        }
     }
 }
 
@@ -368,7 +404,7 @@ hipError_t launch_blend_order(const uint32_t* cost, const uint32_t* tile_offsets
                               hipStream_t s)
 {
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(blend_order_kernel, dim3(1), dim3(1024), 0, s, cost, tile_offsets, tiles, order);
+    hipLaunchKernelGGL(blend_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, cost, tile_offsets, tiles, order);
     return hipGetLastError();
 }
 

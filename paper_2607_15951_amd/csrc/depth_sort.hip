@@ -156,17 +156,23 @@ __global__ __launch_bounds__(256) void radix_row_scan_kernel(const uint32_t* __r
 // consecutive threads on consecutive positions of each digit's run: item i of
 // digit d goes to base[d] + (i - start[d]).  The global writes come as whole
 // runs instead of one scattered word per lane.
-template <int kItems>
+//
+// With kPay every item also carries a payload word: read from pay_in, or in
+// the first pass (pay_in null) packed from rect_in, and written to pay_out
+// beside its value.  keys_out may be null (the last pass: the sorted keys
+// are not needed).
+template <int kItems, bool kPay>
 __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, int64_t n, int shift, const uint32_t* __restrict__ offsets,
+    uint32_t* __restrict__ vals_out, const ushort4* __restrict__ rect_in, const uint32_t* __restrict__ pay_in,
+    uint32_t* __restrict__ pay_out, int64_t n, int shift, const uint32_t* __restrict__ offsets,
     const uint32_t* __restrict__ totals, int bpv, const uint32_t* skip)
 {
     if (skip && *skip) return;
-    // the block's keys and values in digit order; before that, the 16-bit
-    // ranking counts cnt[k][w][d] (at most kItems * kSortBlock) in the same
-    // bytes, which keeps the block's LDS at 8 bytes per item
-    __shared__ uint32_t s_buf[2 * kItems * kSortBlock];
+    // the block's keys, values (and payloads) in digit order; before that,
+    // the 16-bit ranking counts cnt[k][w][d] (at most kItems * kSortBlock)
+    // in the same bytes, which keeps the block's LDS at 8 (12) bytes per item
+    __shared__ uint32_t s_buf[(kPay ? 3 : 2) * kItems * kSortBlock];
     uint16_t(*cnt)[4][256] = reinterpret_cast<uint16_t(*)[4][256]>(s_buf);
     static_assert(kItems * 4 * 256 * sizeof(uint16_t) <= sizeof(s_buf), "ranking counts fit the key buffer");
     static_assert(kItems * kSortBlock <= 65535, "16-bit ranking offsets");
@@ -179,6 +185,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
     uint32_t key[kItems], val[kItems], digit[kItems], rank[kItems];
+    uint32_t pay[kPay ? kItems : 1];
     // all loads first (see radix_hist_kernel)
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
@@ -186,6 +193,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
         const int64_t ic = idx < end ? idx : begin;
         key[k] = keys_in[ic];
         val[k] = vals_in ? vals_in[ic] : (uint32_t)idx;
+        if constexpr (kPay) pay[k] = pay_in ? pay_in[ic] : pack_rect(rect_in[ic]);
     }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
@@ -251,11 +259,13 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
     __syncthreads();   // cnt is reused below
     uint32_t* s_key = s_buf;
     uint32_t* s_val = s_key + kItems * kSortBlock;
+    uint32_t* s_pay = s_val + kItems * kSortBlock;   // kPay only
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         if (local[k] != ~0u) {
             s_key[local[k]] = key[k];
             s_val[local[k]] = val[k];
+            if constexpr (kPay) s_pay[local[k]] = pay[k];
         }
     }
     __syncthreads();
@@ -264,8 +274,9 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
         const uint32_t kk = s_key[i];
         const uint32_t d = (sort_key(kk) >> shift) & 255u;
         const uint32_t pos = s_base[d] + ((uint32_t)i - s_start[d]);
-        keys_out[pos] = kk;
+        if (keys_out) keys_out[pos] = kk;
         vals_out[pos] = s_val[i];
+        if constexpr (kPay) pay_out[pos] = s_pay[i];
     }
 }
 
@@ -273,9 +284,9 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
 // [n_views][256], the offset table [n_views][256][bpv], the block
 // histograms [nblocks][256].
 template <int kItems>
-void launch_sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* counts,
-                      int64_t n, int n_views, int shift, int bpv, unsigned nblocks, const uint32_t* skip,
-                      hipStream_t s)
+void launch_sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const ushort4* rect,
+                      const uint32_t* pin, uint32_t* pout, uint32_t* counts, int64_t n, int n_views, int shift,
+                      int bpv, unsigned nblocks, const uint32_t* skip, hipStream_t s)
 {
     uint32_t* totals = counts;
     uint32_t* table = counts + (int64_t)256 * n_views;
@@ -284,8 +295,12 @@ void launch_sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
                        skip);
     hipLaunchKernelGGL(radix_row_scan_kernel, dim3(256u * (unsigned)n_views), dim3(256), 0, s,
                        (const uint32_t*)hist, table, totals, bpv, skip);
-    hipLaunchKernelGGL(radix_scatter_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n,
-                       shift, (const uint32_t*)table, (const uint32_t*)totals, bpv, skip);
+    if (pout)
+        hipLaunchKernelGGL((radix_scatter_kernel<kItems, true>), dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout,
+                           vout, rect, pin, pout, n, shift, (const uint32_t*)table, (const uint32_t*)totals, bpv, skip);
+    else
+        hipLaunchKernelGGL((radix_scatter_kernel<kItems, false>), dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout,
+                           vout, rect, pin, pout, n, shift, (const uint32_t*)table, (const uint32_t*)totals, bpv, skip);
 }
 
 // ------------------------------------------------- reuse of the previous order
@@ -488,14 +503,15 @@ hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* 
 
 // Sorts each of the n_views segments keys_in[v * n .. (v + 1) * n) (not
 // modified) with values v * n + i, items keys per thread of a block.  Four
-// passes: in -> a -> b -> a -> b, so the sorted keys/values end in (keys_b,
-// vals_b).  With reuse_words (one view, after launch_order_reuse) every pass
-// reads words[0] on the device and does nothing when the reused order holds.
+// passes: in -> a -> b -> a -> b, so the sorted values (and payloads) end in
+// vals_b (pay_b); the last pass writes no keys.  With reuse_words (one view,
+// after launch_order_reuse) every pass reads words[0] on the device and does
+// nothing when the reused order holds.
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
-                             uint32_t* vals_b, uint32_t* counts, int64_t n, int n_views, int items,
-                             const uint32_t* reuse_words, int* result_in_b, hipStream_t s)
+                             uint32_t* vals_b, const ushort4* rect, uint32_t* pay_a, uint32_t* pay_b,
+                             uint32_t* counts, int64_t n, int n_views, int items, const uint32_t* reuse_words,
+                             hipStream_t s)
 {
-    *result_in_b = 1;
     if (n == 0 || n_views <= 0) return hipSuccess;
     if (!depth_sort_items_supported(items)) return hipErrorInvalidValue;
     const int64_t tile = (int64_t)kSortBlock * items;
@@ -503,25 +519,22 @@ hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t
     const unsigned nblocks = (unsigned)bpv * (unsigned)n_views;
     const uint32_t* kin = keys_in;
     const uint32_t* vin = nullptr;
-    uint32_t* kout = keys_a;
-    uint32_t* vout = vals_a;
+    const uint32_t* pin = nullptr;   // the first pass packs from rect
     const uint32_t* skip = reuse_words;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
+        const bool to_b = pass % 2 == 1;
+        uint32_t* kout = pass == 3 ? nullptr : (to_b ? keys_b : keys_a);
+        uint32_t* vout = to_b ? vals_b : vals_a;
+        uint32_t* pout = rect ? (to_b ? pay_b : pay_a) : nullptr;
         switch (items) {
-        case 4: launch_sort_pass<4>(kin, vin, kout, vout, counts, n, n_views, shift, bpv, nblocks, skip, s); break;
-        case 8: launch_sort_pass<8>(kin, vin, kout, vout, counts, n, n_views, shift, bpv, nblocks, skip, s); break;
-        default: launch_sort_pass<16>(kin, vin, kout, vout, counts, n, n_views, shift, bpv, nblocks, skip, s); break;
+        case 4: launch_sort_pass<4>(kin, vin, kout, vout, rect, pin, pout, counts, n, n_views, shift, bpv, nblocks, skip, s); break;
+        case 8: launch_sort_pass<8>(kin, vin, kout, vout, rect, pin, pout, counts, n, n_views, shift, bpv, nblocks, skip, s); break;
+        default: launch_sort_pass<16>(kin, vin, kout, vout, rect, pin, pout, counts, n, n_views, shift, bpv, nblocks, skip, s); break;
         }
         kin = kout;
         vin = vout;
-        if (pass % 2 == 0) {
-            kout = keys_b;
-            vout = vals_b;
-        } else {
-            kout = keys_a;
-            vout = vals_a;
-        }
+        pin = pout;
     }
     return hipGetLastError();
 }

@@ -97,15 +97,32 @@ struct ProjectArgs {
 size_t project_partials_elems(int64_t n, int n_views);
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
 
+// A tile rectangle (x0, y0, x1, y1; exclusive ends) packed in one word,
+// x0 | x1 << 8 | y0 << 16 | y1 << 24, for views at most kPackedRectTiles
+// tiles wide and tall: the payload the depth sort carries to the binning.
+constexpr int kPackedRectTiles = 255;
+__device__ __forceinline__ uint32_t pack_rect(ushort4 r)
+{
+    return (uint32_t)r.x | ((uint32_t)r.z << 8) | ((uint32_t)r.y << 16) | ((uint32_t)r.w << 24);
+}
+__device__ __forceinline__ ushort4 unpack_rect(uint32_t p)
+{
+    return make_ushort4((unsigned short)(p & 255u), (unsigned short)((p >> 16) & 255u),
+                        (unsigned short)((p >> 8) & 255u), (unsigned short)(p >> 24));
+}
+
 // Stable LSD radix sort of the 32-bit keys of n_views segments of n items
 // each, four 8-bit passes, every segment sorted on its own (values start as
-// the item index v * n + i); *result_in_b tells which ping-pong buffer pair
-// holds the result.
+// the item index v * n + i).  The sorted values end in vals_b; the sorted
+// keys are not written (nothing reads them).  With rect (else null) each
+// item carries its packed rectangle (pack_rect of rect[item]) through the
+// passes, which ends in pay_b in the sorted order.
 bool depth_sort_items_supported(int items);
 size_t depth_sort_hist_elems(int64_t n, int n_views);   // enough for every supported width
 hipError_t launch_depth_sort(const uint32_t* keys_in, uint32_t* keys_a, uint32_t* vals_a,
-                             uint32_t* keys_b, uint32_t* vals_b, uint32_t* counts, int64_t n, int n_views, int items,
-                             const uint32_t* reuse_words, int* result_in_b, hipStream_t s);
+                             uint32_t* keys_b, uint32_t* vals_b, const ushort4* rect, uint32_t* pay_a, uint32_t* pay_b,
+                             uint32_t* counts, int64_t n, int n_views, int items, const uint32_t* reuse_words,
+                             hipStream_t s);
 // Reuse of the previous frame's order (one view, n items): reads the previous
 // order from vals_b and this frame's keys; leaves in vals_b this frame's
 // order when it can reach it cheaply, and in words[kReuseWords]: [0] 1 when
@@ -121,7 +138,11 @@ struct BinArgs {
     const uint32_t* sorted_idx;   // [n_views * n] items (v * n + i), each view's segment in (depth, index) order
     const uint32_t* view_counts;  // device [n_views][kViewCounters]; keyed items sort first in a segment
     const ushort4* rect;          // [n_views * n] tile rectangle of each item in its view
-    ushort4* sorted_rect;         // [n_views * n] the same in depth order (keyed items; written by the row count)
+    // the rectangles in depth order: packed (pack_rect), carried by the
+    // depth sort, when sorted_pack is not null; else gathered from rect by
+    // the row count into sorted_rect
+    const uint32_t* sorted_pack;  // [n_views * n] or null
+    ushort4* sorted_rect;         // [n_views * n] (keyed items; written by the row count)
     int64_t n;                    // Gaussians per view
     int n_views;
     const ViewParams* views;      // device table

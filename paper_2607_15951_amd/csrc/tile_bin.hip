@@ -126,7 +126,7 @@ __device__ __forceinline__ bool load_items1(const BinArgs& a, int c, int lane, I
         uint32_t g = 0;
         if (k < end) {
             g = a.sorted_idx[k];
-            r = a.sorted_rect[k];
+            r = a.sorted_pack ? unpack_rect(a.sorted_pack[k]) : a.sorted_rect[k];
             if (r.w > r.y) {   // an off-screen item spans no row
                 lo = (int)r.y < lo ? (int)r.y : lo;
                 hi = (int)r.w > hi ? (int)r.w : hi;
@@ -196,26 +196,46 @@ __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
     int v2, p2;
     int64_t start = 0, end = 0;
     (void)chunk1_range(a, c, &v2, &p2, &start, &end);
-    // the rectangles in depth order, for the scatter to stream: all index
-    // loads, then all gathers, then the counting (see load_items2)
-    uint32_t idx[kItems];
+    if (a.sorted_pack) {
+        // the rectangles in depth order, carried there by the sort: read in
+        // order, all loads before any counting
+        uint32_t pk[kItems];
 #pragma unroll
-    for (int b = 0; b < kItems; ++b) {
-        const int64_t k = start + b * 64 + lane;
-        idx[b] = k < end ? a.sorted_idx[k] : 0u;
-    }
-    ushort4 rr[kItems];
+        for (int b = 0; b < kItems; ++b) {
+            const int64_t k = start + b * 64 + lane;
+            pk[b] = k < end ? a.sorted_pack[k] : 0u;
+        }
 #pragma unroll
-    for (int b = 0; b < kItems; ++b) rr[b] = a.rect[idx[b]];
-#pragma unroll
-    for (int b = 0; b < kItems; ++b) {
-        const int64_t k = start + b * 64 + lane;
-        if (k < end) {
-            const ushort4 r = rr[b];
-            a.sorted_rect[k] = r;
+        for (int b = 0; b < kItems; ++b) {
+            const ushort4 r = unpack_rect(pk[b]);   // empty for lanes past the end
             if (r.w > r.y) {
                 atomicAdd(diff_slot(diff, r.y, lane), 1u);
                 atomicSub(diff_slot(diff, r.w, lane), 1u);
+            }
+        }
+    } else {
+        // the rectangles gathered in depth order, for the scatter to stream:
+        // all index loads, then all gathers, then the counting (see
+        // load_items2)
+        uint32_t idx[kItems];
+#pragma unroll
+        for (int b = 0; b < kItems; ++b) {
+            const int64_t k = start + b * 64 + lane;
+            idx[b] = k < end ? a.sorted_idx[k] : 0u;
+        }
+        ushort4 rr[kItems];
+#pragma unroll
+        for (int b = 0; b < kItems; ++b) rr[b] = a.rect[idx[b]];
+#pragma unroll
+        for (int b = 0; b < kItems; ++b) {
+            const int64_t k = start + b * 64 + lane;
+            if (k < end) {
+                const ushort4 r = rr[b];
+                a.sorted_rect[k] = r;
+                if (r.w > r.y) {
+                    atomicAdd(diff_slot(diff, r.y, lane), 1u);
+                    atomicSub(diff_slot(diff, r.w, lane), 1u);
+                }
             }
         }
     }
