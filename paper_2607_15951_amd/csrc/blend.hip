@@ -264,20 +264,6 @@ __device__ __forceinline__ int cost_bucket(uint32_t c)
     return 128 + (e - 7) * 32 + (int)((c >> (e - 5)) & 31u);
 }
 
-// Lanes of the wave holding the same bucket as this lane (ten ballots over the
-// bucket's bits), among the lanes where `active` holds.
-__device__ __forceinline__ uint64_t same_bucket_lanes(int b, bool active)
-{
-    uint64_t m = __ballot(active);
-#pragma unroll
-    for (int bit = 0; bit < 10; ++bit) {
-        const bool on = (b >> bit) & 1;
-        const uint64_t bb = __ballot(on);
-        m &= on ? bb : ~bb;
-    }
-    return m;
-}
-
 __device__ __forceinline__ uint32_t tile_cost_of(const uint32_t* cost, const uint32_t* offsets, int64_t t)
 {
     return cost ? cost[t] : offsets[t + 1] - offsets[t];
@@ -286,12 +272,13 @@ __device__ __forceinline__ uint32_t tile_cost_of(const uint32_t* cost, const uin
 // One 1024-thread workgroup: a counting sort of the tiles by descending cost
 // bucket.  The first pass loads kOrderPre costs per thread before using any
 // (a load under its own branch is waited for before the next one issues),
-// counts the buckets and keeps each tile's bucket in LDS for the second pass
-// (tiles past kOrderKeptTiles load their cost again).  Lanes of a wave that
-// share a bucket (cheap and empty tiles mostly do) count and claim their
-// slots with one LDS atomic per group, led by the group's lowest lane.
-// Within a bucket the order is whatever the atomics give: the order only
-// decides when each tile's workgroup starts, never what it computes.
+// counts the buckets with LDS atomics and keeps each tile's bucket in LDS for
+// the second pass (tiles past kOrderKeptTiles load their cost again), which
+// claims each tile's slot with one more atomic.  Within a bucket the order
+// is whatever the atomics give: the order only decides when each tile's
+// workgroup starts, never what it computes.  (The whole sort runs on one CU;
+// plain atomics, colliding where many tiles share a bucket, cost less issue
+// there than grouping the lanes of a bucket with ballots.)
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderPre = 8;
 constexpr int kOrderKeptTiles = 32768;
@@ -304,7 +291,6 @@ __global__ __launch_bounds__(kOrderThreads) void blend_order_kernel(const uint32
     __shared__ uint16_t s_bucket[kOrderKeptTiles];
     __shared__ uint32_t wsum[kOrderThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     hist[tid] = 0u;
     __syncthreads();
     constexpr int64_t kStep = (int64_t)kOrderThreads * kOrderPre;
@@ -318,11 +304,11 @@ __global__ __launch_bounds__(kOrderThreads) void blend_order_kernel(const uint32
 #pragma unroll
         for (int k = 0; k < kOrderPre; ++k) {
             const int64_t t = t0 + k * kOrderThreads + tid;
-            const bool in = t < tiles;
-            const int b = in ? cost_bucket(c[k]) : 0;
-            const uint64_t m = same_bucket_lanes(b, in);
-            if (in && (m & below) == 0) atomicAdd(&hist[b], (uint32_t)__popcll(m));
-            if (in && t < kOrderKeptTiles) s_bucket[t] = (uint16_t)b;
+            if (t < tiles) {
+                const int b = cost_bucket(c[k]);
+                atomicAdd(&hist[b], 1u);
+                if (t < kOrderKeptTiles) s_bucket[t] = (uint16_t)b;
+            }
         }
     }
     __syncthreads();
@@ -353,15 +339,10 @@ __global__ __launch_bounds__(kOrderThreads) void blend_order_kernel(const uint32
 #pragma unroll
         for (int k = 0; k < kOrderPre; ++k) {
             const int64_t t = t0 + k * kOrderThreads + tid;
-            const bool in = t < tiles;
-            int b = 0;
-            if (in) b = reload ? cost_bucket(c[k]) : (int)s_bucket[t];
-            const uint64_t m = same_bucket_lanes(b, in);
-            const int leader = __ffsll((long long)m) - 1;
-            uint32_t base = 0u;
-            if (in && lane == leader) base = atomicAdd(&hist[b], (uint32_t)__popcll(m));
-            base = (uint32_t)__shfl((int)base, leader < 0 ? 0 : leader, 64);
-            if (in) order[base + (uint32_t)__popcll(m & below)] = (uint32_t)t;
+            if (t < tiles) {
+                const int b = reload ? cost_bucket(c[k]) : (int)s_bucket[t];
+                order[atomicAdd(&hist[b], 1u)] = (uint32_t)t;
+            }
         }
     }
 }
