@@ -526,15 +526,24 @@ __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int 
     __syncthreads();   // diff is reused by the next chunk
 }
 
-// The level-2 kernels stride over the device's chunk count, so a grid sized
-// for a bound (pair_capacity mode) costs nothing past the real chunks.
+// The level-2 kernels stride over the device's chunk count c2, so a grid
+// sized for a bound (pair_capacity mode) costs nothing past the real chunks.
+// XCD x (blocks b with b % 8 == x, as the dispatcher deals them) owns the
+// contiguous run of chunks [x * per, (x + 1) * per), per = ceil(c2 / 8), and
+// its blocks take them in turn: every XCD has a share of the work whatever
+// the grid, and each XCD's output pieces are adjacent.  (With the grid of
+// an eager render, 8 ceil(c2 / 8) blocks, each block takes one chunk.)
+#define FOR_LEVEL2_CHUNK(c, c2)                                                        \
+    for (int per_ = ((c2) + 7) / 8, j_ = (int)(blockIdx.x >> 3), c = (int)(blockIdx.x & 7) * per_ + j_; \
+         j_ < per_ && c < (c2); j_ += (int)(gridDim.x >> 3), c += (int)(gridDim.x >> 3))
+
 template <int kItems>
 __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
 {
     extern __shared__ uint32_t diff[];   // [max_tiles_x + 1][kDiffCopies], sized at launch: more waves fit
     const int lane = threadIdx.x;
     const int c2 = (int)a.info[kInfoC2];
-    for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_count_chunk<kItems>(a, c, lane, diff);
+    FOR_LEVEL2_CHUNK(c, c2) level2_count_chunk<kItems>(a, c, lane, diff);
 }
 
 // The walk of one band over the n packed entries in LDS (s_g, s_x): batch
@@ -626,7 +635,7 @@ __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
     __shared__ uint16_t s_x[kItems * 64];
     const int lane = threadIdx.x;
     const int c2 = (int)a.info[kInfoC2];
-    for (int c = chunk_of_block(); c < c2; c += (int)gridDim.x) level2_scatter_chunk<kItems>(a, c, lane, s_g, s_x);
+    FOR_LEVEL2_CHUNK(c, c2) level2_scatter_chunk<kItems>(a, c, lane, s_g, s_x);
 }
 
 // Tile offsets from the scanned level-2 counts: tile (r, x) starts at chunk
