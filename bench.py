@@ -420,6 +420,37 @@ def time_backward(r, dev, cam, W: int, H: int, steps: int, out) -> dict:
             "forward_backward_per_s": round(1e3 / ms_step, 1), "steps": bsteps}
 
 
+def time_capacity(r, dev, cam, W: int, H: int, steps: int, out, K: int) -> dict:
+    """The same frame without the host read of its sizes: with a pair
+    capacity of 1.1 K every size is a device-side bound and nothing inside
+    the frame waits for the host; as back-to-back gs_render calls, and as
+    replays of a captured graph of the render."""
+    import torch
+    cap = int(K * 1.1)
+    bsteps = max(3, min(steps, 50))
+    for _ in range(3):
+        r.render(dev, cam, W, H, out=out, pair_capacity=cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(bsteps):
+        r.render(dev, cam, W, H, out=out, pair_capacity=cap)
+    torch.cuda.synchronize()
+    ms_cap = (time.perf_counter() - t0) * 1e3 / bsteps
+    g = r.graph(dev, [cam], pair_capacity=cap, outs=[out])
+    for _ in range(3):
+        g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(bsteps):
+        g.launch()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / bsteps
+    g.close()
+    return {"pair_capacity": cap, "ms_per_step": round(ms_cap, 4), "frames_per_s": round(1e3 / ms_cap, 2),
+            "ms_per_step_graph": round(ms_graph, 4), "frames_per_s_graph": round(1e3 / ms_graph, 2),
+            "steps": bsteps}
+
+
 def time_batched_backward(r, dev, cams, steps: int) -> dict:
     """One training step's rasterizer work on a batch of views: the batched
     render of all views, then one backward over them (seeded dL/d(image) and
@@ -633,6 +664,8 @@ def main():
         if dtype == gs.GS_F32:
             variants["backward"] = time_backward(r, dev, cam, W, H, args.steps, out)
             log("[bench] variant backward: " + json.dumps(variants["backward"]))
+            variants["capacity"] = time_capacity(r, dev, cam, W, H, args.steps, out, info["num_pairs"])
+            log("[bench] variant capacity: " + json.dumps(variants["capacity"]))
             variants["reuse_order"] = time_reuse(r, dev, W, H)
             log("[bench] variant reuse_order: " + json.dumps(variants["reuse_order"]))
         # batched: the same frame's scene from 8 cameras on a ring (1080p each),
