@@ -98,6 +98,7 @@ struct gs_context {
     uint64_t capacity = 0;
     int sorted_in_b = 1;
     hipStream_t stream = nullptr;
+    hipEvent_t sizes_ev = nullptr;   // the host read of an eager render's sizes
     gs_graph* graph = nullptr;   // a captured render owns the workspace
     std::vector<ViewParams> last_views;   // view table of the last render
     gs_gaussians last_g{};                // scene of the last render
@@ -446,6 +447,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     STAGE_MARK(3);
 
     int grid2 = ba.max_chunks2;
+    bool rows_scattered = false;   // the row scatter ran while the host read the sizes
     if (capacity == 0) {
         // eager: one host read (one copy) of the per-view pairs, R and the
         // level-2 sizes
@@ -457,7 +459,23 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
                            (const uint32_t*)counters, (const uint32_t*)(ba.rows_off + rows), (const uint32_t*)ba.info,
                            rb);
         HIP_TRY(hipMemcpyAsync(hi, rb, (size_t)(n_vc + kReadbackTail) * 4, hipMemcpyDeviceToHost, s), "read sizes");
-        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        // the row scatter needs no size but R, and the row-entry buffer of
+        // earlier renders mostly holds this frame's entries: it runs while
+        // the host reads the sizes, and runs again into a grown buffer when R
+        // exceeds it (its stores past the buffer are dropped)
+        const uint64_t spec = w.row_ent.bytes / 8;
+        if (spec > 0) {
+            HIP_TRY(hipEventRecord(ctx->sizes_ev, s), "hipEventRecord");
+            ba.row_ent = static_cast<uint2*>(w.row_ent.p);
+            ba.row_capacity = spec;
+            STAGE_MARK(4);
+            HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
+            STAGE_MARK(5);
+            rows_scattered = true;
+            HIP_TRY(hipEventSynchronize(ctx->sizes_ev), "hipEventSynchronize");
+        } else {
+            HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        }
         uint32_t* tail = hi + n_vc;
         uint64_t K64 = 0;
         for (int v = 0; v < V; ++v) {
@@ -468,13 +486,18 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
             return fail(ctx, GS_ERR_CAPACITY, "more than 2^32-1 (Gaussian, tile) pairs");
         capacity = K64;
         ba.row_capacity = tail[4];
+        if (rows_scattered && ba.row_capacity > spec) {
+            HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");   // the buffer is grown below
+            rows_scattered = false;
+        }
         grid2 = (int)tail[5];
         ba.max_chunks2 = grid2;
         ba.counts2_capacity = tail[6];
     }
     ba.capacity = capacity;
-    // the device is idle here in eager mode (host read above), so growing the
-    // scan scratch cannot pull memory from under a queued kernel
+    // in eager mode nothing queued uses the buffers grown here (the kernels
+    // before the host read have completed; a row scatter still running uses
+    // the row-entry buffer, which then has room)
     if ((st = ensure(ctx, w.scan_scratch, scan_scratch_elems((int64_t)std::max<uint64_t>(ba.counts2_capacity, 1)) *
                                                  8)) != GS_OK)
         return st;
@@ -486,9 +509,11 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ba.row_ent = static_cast<uint2*>(w.row_ent.p);
     ba.counts2 = static_cast<uint32_t*>(w.counts2.p);
     ba.values = static_cast<uint32_t*>(w.values.p);
-    STAGE_MARK(4);
-    HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
-    STAGE_MARK(5);
+    if (!rows_scattered) {
+        STAGE_MARK(4);
+        HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
+        STAGE_MARK(5);
+    }
     HIP_TRY(launch_bin_tiles(ba, grid2, scan_scratch, s), "bin tile counts");
     STAGE_MARK(6);
     HIP_TRY(launch_bin_tile_scatter(ba, grid2, s), "bin tile scatter");
@@ -688,7 +713,9 @@ gs_status gs_create(int device, gs_context** out)
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ctx->noalloc_info), 64);
     // the device's copy of the no-allocation scratch (once per device)
     if (e == hipSuccess) e = init_scratch_address(device, count);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->sizes_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
+        if (ctx->sizes_ev) (void)hipEventDestroy(ctx->sizes_ev);
         if (ctx->host_info) (void)hipHostFree(ctx->host_info);
         if (ctx->noalloc_info) (void)hipFree(ctx->noalloc_info);
         delete ctx;
@@ -716,6 +743,7 @@ void gs_destroy(gs_context* ctx)
     if (ctx->noalloc_info) (void)hipFree(ctx->noalloc_info);
     for (hipEvent_t e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->sizes_ev) (void)hipEventDestroy(ctx->sizes_ev);
     delete ctx;
 }
 

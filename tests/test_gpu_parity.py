@@ -247,6 +247,38 @@ def test_context_reuse_across_sizes(renderer):
     check_lists_full(gb, o, "small after large")
 
 
+def test_row_entries_outgrowing_the_last_render():
+    """An eager render scatters its row entries into the buffer an earlier
+    render left while the host reads this frame's sizes, and scatters them
+    again into a grown buffer when they do not fit.  A large render after a
+    small one on the same context must equal the same render on a fresh
+    context, and the oracle's lists."""
+    import paper_2607_15951_amd as gs
+    small = scenes.make_scene("C2", n=2_000, seed=71)
+    big = scenes.make_scene("C2", n=40_000, seed=72)
+    cam = scenes.default_camera(333, 197)
+    r1, r2 = gs.Renderer(0), gs.Renderer(0)
+    try:
+        gpu_render(r1, small, cam)
+        r_small = r1.list_info()["num_row_entries"]
+        g1 = gpu_render(r1, big, cam)
+        r_big = r1.list_info()["num_row_entries"]
+        # the second render's entries exceed the buffer sized for the first
+        # (sizes grow by a quarter)
+        assert r_big > 2 * r_small, (r_small, r_big)
+        g2 = gpu_render(r2, big, cam)
+        for k in ("image", "final_T", "n_contrib", "values", "tile_offsets", "keys"):
+            np.testing.assert_array_equal(g1[k], g2[k])
+        o = oracle.render(big, cam)
+        amb = check_projection(g1, o["proj"], "row entries outgrowing the last render")
+        check_lists_full(g1, o, "row entries outgrowing the last render", exclude=amb)
+        g3 = gpu_render(r1, big, cam)   # the same frame again: its entries fit the grown buffer
+        np.testing.assert_array_equal(g3["values"], g2["values"])
+    finally:
+        r1.close()
+        r2.close()
+
+
 def test_permutation_and_repeat_determinism(renderer):
     sc = scenes.make_scene("C2", n=10_000, seed=61)
     cam = scenes.default_camera(200, 150)
