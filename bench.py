@@ -20,6 +20,7 @@ host cores.
 from __future__ import annotations
 
 import argparse
+import functools
 import json
 import math
 import os
@@ -451,6 +452,55 @@ def time_capacity(r, dev, cam, W: int, H: int, steps: int, out, K: int) -> dict:
             "steps": bsteps}
 
 
+@functools.lru_cache(maxsize=1)
+def _workload_scene(workload: str):
+    import scenes
+    return scenes.make_scene(workload)
+
+
+def time_workload(r, workload: str, dtype: int, steps: int, graph: bool = False) -> dict:
+    """Frame time of another workload's default view (launch shapes as
+    autotuned for the main frame), back-to-back gs_render calls, and with
+    ``graph`` as replays of a captured graph of the frame."""
+    import torch
+    import paper_2607_15951_amd as gs
+    import scenes
+    sc = _workload_scene(workload)
+    cam = scenes.make_cameras(workload)[0]
+    W, H = cam["width"], cam["height"]
+    dev = gs.scene_to_device(sc, dtype)
+    out = r.render(dev, cam, W, H)
+    for _ in range(3):
+        r.render(dev, cam, W, H, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.render(dev, cam, W, H, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    info = r.list_info()
+    res = {"workload": scenes.WORKLOAD_NAMES[workload], "attributes": {gs.GS_F32: "fp32", gs.GS_BF16: "bf16",
+                                                                       gs.GS_F16: "fp16"}[dtype],
+           "width": W, "height": H, "pairs": info["num_pairs"], "us_per_frame": round(ms * 1e3, 1),
+           "frames_per_s": round(1e3 / ms, 2), "steps": steps}
+    if graph:
+        # the frame's launches captured once and replayed (pair capacity 25%
+        # above this frame's K): no host read, one launch per frame
+        g = r.graph(dev, [cam], pair_capacity=int(info["num_pairs"] * 1.25) + 1024, outs=[out])
+        for _ in range(3):
+            g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.launch()
+        torch.cuda.synchronize()
+        gms = (time.perf_counter() - t0) * 1e3 / steps
+        g.close()
+        res.update(us_per_frame_graph=round(gms * 1e3, 1), frames_per_s_graph=round(1e3 / gms, 2))
+    del dev, out
+    return res
+
+
 def time_batched_backward(r, dev, cams, steps: int) -> dict:
     """One training step's rasterizer work on a batch of views: the batched
     render of all views, then one backward over them (seeded dL/d(image) and
@@ -616,6 +666,17 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # per-frame device times (HIP events around each render on the render
+    # stream, frames still back to back): median and spread
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record()
+    for k in range(args.steps):
+        r.render(dev, cam, W, H, out=out)
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    per_frame = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps))
+    frame_pct = {f"p{q}": round(per_frame[min(len(per_frame) - 1, int(q / 100 * len(per_frame)))], 4)
+                 for q in (10, 50, 90)}
     # per-stage device times: HIP events the library records on its stream
     prof_steps = min(args.steps, 20)
     r.set_profiling(stages=True)
@@ -686,6 +747,14 @@ def main():
             log("[bench] variant batched_C4_64views_backward: " +
                 json.dumps(variants["batched_C4_64views_backward"]))
             del dev4
+            # the small and the large workloads: C1 (1k Gaussians, 128x128),
+            # bound by launch latency, and C5 (6M Gaussians at 3840x2160) with
+            # BF16 / FP16 attribute storage
+            variants["small_C1"] = time_workload(r, "C1", gs.GS_F32, steps=100, graph=True)
+            log("[bench] variant small_C1: " + json.dumps(variants["small_C1"]))
+            for name, vd in (("C5_4k_bf16", gs.GS_BF16), ("C5_4k_fp16", gs.GS_F16)):
+                variants[name] = time_workload(r, "C5", vd, steps=10)
+                log(f"[bench] variant {name}: " + json.dumps(variants[name]))
 
     K, n_vis, R = info["num_pairs"], info["n_visible"], info["num_row_entries"]
     tuned = main_tuning
@@ -758,6 +827,7 @@ def main():
         "config": {"workload": scenes.WORKLOAD_NAMES[args.workload], "gaussians": n, "width": W, "height": H,
                    "sh_degree": deg, "tile": TILE, "attributes": args.variant, "num_pairs": K,
                    "row_entries": R, "visible": n_vis},
+        "frame_ms_events": frame_pct,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stages_algorithmic_GBps": stage_gbs,
         "frame_hbm": frame,

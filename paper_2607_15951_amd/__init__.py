@@ -9,6 +9,7 @@ raises, there is no fallback path.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -579,6 +580,50 @@ class RenderGraph:
             self.close()
         except Exception:
             pass
+
+
+def scene_from_rows(means, log_scales, quats, opacity_logits, sh, attr_dtype: int = GS_F32) -> dict:
+    """A device scene in the library's channel-major layout from per-Gaussian
+    rows (the common [N, C] layout of 3DGS checkpoints): means [N, 3],
+    log_scales [N, 3], quats [N, 4] (w, x, y, z), opacity_logits [N] and sh
+    [N, (deg+1)^2, 3] CUDA tensors.  Transposes once per scene (one copy);
+    attributes other than the means are stored in ``attr_dtype``."""
+    torch = _torch()
+    tdt = _attr_torch_dtype(attr_dtype)
+    n = means.shape[0]
+    if sh.dim() != 3 or sh.shape[0] != n or sh.shape[2] != 3:
+        raise ValueError("sh must be [N, (deg+1)^2, 3]")
+    deg = int(round(math.sqrt(sh.shape[1]))) - 1
+    if (deg + 1) ** 2 != sh.shape[1]:
+        raise ValueError("sh must hold (deg+1)^2 coefficients per channel")
+    return {"sh_degree": deg, "attr_dtype": attr_dtype,
+            "means": means.to(torch.float32).t().contiguous(),
+            "log_scales": log_scales.to(tdt).t().contiguous(),
+            "quats": quats.to(tdt).t().contiguous(),
+            "opacity_logits": opacity_logits.reshape(n).to(tdt).contiguous(),
+            "sh": sh.to(tdt).permute(1, 2, 0).contiguous()}
+
+
+_DEFAULT_RENDERERS = {}
+
+
+def render(dev_scene: dict, camera: dict, size, background=(0.0, 0.0, 0.0), keys: bool = False,
+           renderer: "Renderer | None" = None):
+    """One frame, gs_render, on a renderer kept per device: returns (image
+    [3, H, W], lists), where lists holds the sorted per-tile lists of the
+    frame (Sec. 3.1) as device tensors: values [K], tile_offsets [T + 1] (tile
+    t's list is values[tile_offsets[t]:tile_offsets[t + 1]]), keys [K] with
+    keys=True, and the sizes of gs_get_list_info."""
+    torch = _torch()
+    width, height = (int(v) for v in size)
+    dev = dev_scene["means"].device
+    if renderer is None:
+        key = dev.index if dev.index is not None else torch.cuda.current_device()
+        renderer = _DEFAULT_RENDERERS.get(key)
+        if renderer is None:
+            renderer = _DEFAULT_RENDERERS[key] = Renderer(key)
+    out = renderer.render(dev_scene, camera, width, height, background=background)
+    return out["image"], renderer.lists(keys=keys)
 
 
 def render_autograd(renderer: Renderer, means, log_scales, quats, opacity_logits, sh, camera: dict, width: int,

@@ -147,3 +147,24 @@ def test_binding_rejects_bad_tensors():
         gs.make_gaussians(dict(base, means=torch.zeros((2, n))))
     with pytest.raises(ValueError):
         gs.make_gaussians(dict(base, sh_degree=7))
+
+
+def test_scene_from_rows_layout():
+    """Rows [N, C] to the channel-major layout the C ABI takes (host tensors:
+    the conversion is layout only), and its shape checks."""
+    torch = pytest.importorskip("torch")
+    import paper_2607_15951_amd as gs
+    n, deg = 7, 2
+    g = torch.Generator().manual_seed(3)
+    means, ls, q = torch.randn(n, 3, generator=g), torch.randn(n, 3, generator=g), torch.randn(n, 4, generator=g)
+    op, sh = torch.randn(n, generator=g), torch.randn(n, (deg + 1) ** 2, 3, generator=g)
+    d = gs.scene_from_rows(means, ls, q, op, sh)
+    assert d["sh_degree"] == deg and d["attr_dtype"] == gs.GS_F32
+    assert d["means"].shape == (3, n) and torch.equal(d["means"][1], means[:, 1])
+    assert d["quats"].shape == (4, n) and torch.equal(d["quats"][0], q[:, 0])
+    assert d["sh"].shape == ((deg + 1) ** 2, 3, n) and torch.equal(d["sh"][4, 2], sh[:, 4, 2])
+    assert all(d[k].is_contiguous() for k in ("means", "log_scales", "quats", "opacity_logits", "sh"))
+    b = gs.scene_from_rows(means, ls, q, op, sh, gs.GS_BF16)
+    assert b["sh"].dtype == torch.bfloat16 and b["means"].dtype == torch.float32
+    with pytest.raises(ValueError):
+        gs.scene_from_rows(means, ls, q, op, torch.randn(n, 5, 3))

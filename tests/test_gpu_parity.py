@@ -279,6 +279,29 @@ def test_row_entries_outgrowing_the_last_render():
         r2.close()
 
 
+def test_module_render_from_rows(renderer):
+    """The module-level render() of a scene given as per-Gaussian rows
+    ([N, C], transposed once by scene_from_rows) equals Renderer.render of
+    the channel-major scene, image and lists."""
+    import torch
+    import paper_2607_15951_amd as gs
+    sc = scenes.make_scene("C2", n=5_000, seed=81)
+    cam = scenes.default_camera(200, 120)
+    dev = gs.scene_to_device(sc)
+    rows = gs.scene_from_rows(dev["means"].t(), dev["log_scales"].t(), dev["quats"].t(), dev["opacity_logits"],
+                              dev["sh"].permute(2, 0, 1))
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        assert torch.equal(rows[k], dev[k]), k
+    img, lists = gs.render(rows, cam, (cam["width"], cam["height"]), keys=True)
+    torch.cuda.synchronize()
+    ref = gpu_render(renderer, sc, cam)
+    np.testing.assert_array_equal(img.cpu().numpy().astype(np.float64), ref["image"])
+    np.testing.assert_array_equal(lists["values"].cpu().numpy().view(np.uint32), ref["values"])
+    np.testing.assert_array_equal(lists["tile_offsets"].cpu().numpy().view(np.uint32), ref["tile_offsets"])
+    np.testing.assert_array_equal(lists["keys"].cpu().numpy().view(np.uint64), ref["keys"])
+    assert lists["num_pairs"] == ref["num_pairs"]
+
+
 def test_permutation_and_repeat_determinism(renderer):
     sc = scenes.make_scene("C2", n=10_000, seed=61)
     cam = scenes.default_camera(200, 150)
