@@ -90,6 +90,14 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2607_15951_amd.build`")
+    # PyTorch brings its own HIP runtime under the same soname as the system
+    # one the library is linked against: load it first, so that the process
+    # has one runtime (the library loaded first would bind PyTorch to the
+    # system runtime, where PyTorch then finds no GPU)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     P = C.c_void_p
     L.gs_create.argtypes = [C.c_int, C.POINTER(P)]

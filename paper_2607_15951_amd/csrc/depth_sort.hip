@@ -22,6 +22,8 @@
 // depths as numbers (negative ones, behind the camera, first); keys of
 // Gaussians without a finite depth are 0xFFFFFFFF and sink to the end.
 // Values start as the Gaussian index, so ties in depth stay in index order.
+// A segment that fits one block takes one launch per pass: the scatter
+// counts its block's digits itself (no histogram, no offset table).
 #include "gs_internal.h"
 
 namespace gsmi {
@@ -219,7 +221,6 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
         // and the block's digit start (exclusive prefix of the totals); then
         // the segment's start of digit d (exclusive prefix of its totals)
         const int v = (int)(blockIdx.x / (unsigned)bpv);
-        const uint32_t seg_total = totals[v * 256 + tid];
         uint32_t run = 0u;
 #pragma unroll
         for (int k = 0; k < kItems; ++k)
@@ -229,6 +230,9 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
                 cnt[k][w][tid] = (uint16_t)run;
                 run += c;
             }
+        // the segment's count of digit d: from the digit totals, or, when the
+        // block is the whole segment (no totals), the block's own count
+        const uint32_t seg_total = totals ? totals[v * 256 + tid] : run;
         uint32_t incl = run, seg_incl = seg_total;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(
             seg_before += s_ssum[w];
         }
         s_start[tid] = before + incl - run;
-        s_base[tid] = seg_before + seg_incl - seg_total + offsets[row + (int64_t)tid * bpv];
+        s_base[tid] = seg_before + seg_incl - seg_total + (offsets ? offsets[row + (int64_t)tid * bpv] : 0u);
     }
     __syncthreads();
     uint32_t local[kItems];
@@ -291,10 +295,15 @@ void launch_sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
     uint32_t* totals = counts;
     uint32_t* table = counts + (int64_t)256 * n_views;
     uint32_t* hist = table + (int64_t)256 * nblocks;
-    hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, hist, bpv,
-                       skip);
-    hipLaunchKernelGGL(radix_row_scan_kernel, dim3(256u * (unsigned)n_views), dim3(256), 0, s,
-                       (const uint32_t*)hist, table, totals, bpv, skip);
+    if (bpv > 1) {
+        hipLaunchKernelGGL(radix_hist_kernel<kItems>, dim3(nblocks), dim3(kSortBlock), 0, s, kin, n, shift, hist,
+                           bpv, skip);
+        hipLaunchKernelGGL(radix_row_scan_kernel, dim3(256u * (unsigned)n_views), dim3(256), 0, s,
+                           (const uint32_t*)hist, table, totals, bpv, skip);
+    } else {
+        // one block per segment: the scatter counts the digits itself
+        totals = table = nullptr;
+    }
     if (pout)
         hipLaunchKernelGGL((radix_scatter_kernel<kItems, true>), dim3(nblocks), dim3(kSortBlock), 0, s, kin, vin, kout,
                            vout, rect, pin, pout, n, shift, (const uint32_t*)table, (const uint32_t*)totals, bpv, skip);

@@ -195,7 +195,9 @@ hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scra
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     const unsigned grid = (unsigned)std::min<int64_t>(nb, kScanMaxGrid);
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch);
+    // one tile: the down-sweep reads no tile sums (none precede tile 0)
+    if (nb > 1)
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch);
     hipLaunchKernelGGL(scan_down_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch,
                        total64, total32, overflow);
     return hipGetLastError();

@@ -180,6 +180,22 @@ def test_huge_gaussian_covers_every_tile(renderer):
     full_parity(renderer, sc, scenes.default_camera(150, 90), "huge")
 
 
+def test_grid_wider_than_packed_rectangles(renderer):
+    """263 tile columns: past the 255 of the rectangles packed into one word,
+    so the depth sort carries no rectangles and the row counts gather them."""
+    sc = scenes.make_scene("C2", n=20_000, seed=91)
+    full_parity(renderer, sc, scenes.default_camera(4200, 120), "4200x120 (263 tile columns)")
+
+
+@pytest.mark.parametrize("size", [(32768, 32), (32, 32768)], ids=["max_width", "max_height"])
+def test_largest_image_dimensions(renderer, size):
+    """The widest and the tallest image the library accepts: 2048 tile
+    columns, or 2048 tile rows (the LDS difference arrays of the binning are
+    sized by them)."""
+    sc = scenes.make_scene("C1", n=400, seed=92)
+    full_parity(renderer, sc, scenes.default_camera(*size), f"{size[0]}x{size[1]}")
+
+
 def test_more_than_2_32_pairs_is_refused_before_the_pair_buffers(renderer):
     """4.9e9 (Gaussian, tile) pairs: 600k Gaussians that each cover all 8160
     tiles of a 1080p image.  Pair offsets are 32-bit, so the eager render
