@@ -249,6 +249,26 @@ __global__ void write_views_kernel(ViewBatch b, int count, ViewParams* dst)
     for (int k = threadIdx.x; k < words; k += blockDim.x) out[k] = src[k];
 }
 
+// The start of a frame of at most kViewsPerLaunch views in one launch: the
+// overflow counters cleared, the view table written (when `write`) and the
+// tiles_x of every global tile row, all from the views in the arguments.
+__global__ void frame_setup_kernel(ViewBatch b, int count, ViewParams* dst, int write, uint32_t* counters,
+                                   uint32_t* row_tiles_x, int rows)
+{
+    if (threadIdx.x < 16) counters[threadIdx.x] = 0u;
+    if (write) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&b.v[0]);
+        uint32_t* out = reinterpret_cast<uint32_t*>(dst);
+        const int words = count * (int)(sizeof(ViewParams) / 4);
+        for (int k = threadIdx.x; k < words; k += blockDim.x) out[k] = src[k];
+    }
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        int v = 0;
+        while (v + 1 < count && (int)b.v[v + 1].row_base <= r) ++v;
+        row_tiles_x[r] = (uint32_t)b.v[v].tiles_x;
+    }
+}
+
 hipError_t write_view_table(const std::vector<ViewParams>& hv, ViewParams* dst, hipStream_t s)
 {
     for (size_t v0 = 0; v0 < hv.size(); v0 += kViewsPerLaunch) {
@@ -354,11 +374,18 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ViewParams* views = static_cast<ViewParams*>(w.views.p);
     uint32_t* counters = static_cast<uint32_t*>(w.counters.p);
     uint32_t* view_counts = static_cast<uint32_t*>(w.view_counts.p);
-    HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
-    if (write_table) HIP_TRY(write_view_table(hv, views, s), "view table");
-    hipLaunchKernelGGL(row_table_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, (const ViewParams*)views,
-                       V, static_cast<uint32_t*>(w.row_tiles_x.p), rows);
-    HIP_TRY(hipGetLastError(), "view table");
+    if (V <= kViewsPerLaunch) {
+        ViewBatch b;
+        std::memcpy(b.v, hv.data(), (size_t)V * sizeof(ViewParams));
+        hipLaunchKernelGGL(frame_setup_kernel, dim3(1), dim3(256), 0, s, b, V, views, write_table ? 1 : 0, counters,
+                           static_cast<uint32_t*>(w.row_tiles_x.p), rows);
+    } else {
+        HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
+        if (write_table) HIP_TRY(write_view_table(hv, views, s), "view table");
+        hipLaunchKernelGGL(row_table_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s,
+                           (const ViewParams*)views, V, static_cast<uint32_t*>(w.row_tiles_x.p), rows);
+    }
+    HIP_TRY(hipGetLastError(), "frame set-up");
     STAGE_MARK(0);
 
     ProjectArgs pa{};
