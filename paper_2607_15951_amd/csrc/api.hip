@@ -81,6 +81,7 @@ struct gs_context {
     std::string err;
     Workspace ws;                    // buffers of the renders on this context
     uint32_t* host_info = nullptr;   // pinned readback of the per-frame sizes
+    uint32_t* host_info_dev = nullptr;   // its device address: the size kernel writes there directly
     uint32_t profiling = 0;   // GS_PROFILE_* flags
     bool timed = false;       // the last render recorded stage events
     bool traced = false;      // the last render counted blend work
@@ -292,6 +293,7 @@ __global__ void pack_readback_kernel(const uint32_t* view_counts, int n_vc, cons
         const int t = i - n_vc;
         out[i] = i < n_vc ? view_counts[i] : (t < 4 ? counters[t] : (t == 4 ? *r_total : info[t - 5]));
     }
+    __threadfence_system();   // out may be pinned host memory, read by the host after the frame's event
 }
 
 __global__ void row_table_kernel(const ViewParams* views, int n_views, uint32_t* row_tiles_x, int rows)
@@ -480,12 +482,12 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
         // level-2 sizes
         uint32_t* hi = ctx->host_info;
         const int n_vc = V * kViewCounters;
-        if ((st = ensure(ctx, w.readback, (size_t)(n_vc + kReadbackTail) * 4)) != GS_OK) return st;
-        uint32_t* rb = static_cast<uint32_t*>(w.readback.p);
+        // the sizes go straight into the pinned host buffer (its device
+        // address); the event below marks their arrival
         hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, s, (const uint32_t*)view_counts, n_vc,
                            (const uint32_t*)counters, (const uint32_t*)(ba.rows_off + rows), (const uint32_t*)ba.info,
-                           rb);
-        HIP_TRY(hipMemcpyAsync(hi, rb, (size_t)(n_vc + kReadbackTail) * 4, hipMemcpyDeviceToHost, s), "read sizes");
+                           ctx->host_info_dev);
+        HIP_TRY(hipGetLastError(), "read sizes");
         // the row scatter needs no size but R, and the row-entry buffer of
         // earlier renders mostly holds this frame's entries: it runs while
         // the host reads the sizes, and runs again into a grown buffer when R
@@ -737,6 +739,9 @@ gs_status gs_create(int device, gs_context** out)
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&ctx->host_info),
                           sizeof(uint32_t) * ((size_t)kMaxViews * kViewCounters + 16));
+    // the pinned buffer is mapped into the device's address space: the
+    // kernel that packs the frame's sizes writes them there, with no copy
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->host_info_dev), ctx->host_info, 0);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ctx->noalloc_info), 64);
     // the device's copy of the no-allocation scratch (once per device)
     if (e == hipSuccess) e = init_scratch_address(device, count);

@@ -58,7 +58,9 @@ __device__ __forceinline__ uint32_t stage_entry(const float4& ra, const float4& 
     const double dv = ((double)ra.y + (double)ra.w) - oy;
     const float du_hi = (float)du, dv_hi = (float)dv;
     uint32_t qmask = 0u;
-    const float bc = rb.y / rb.z, ba = rb.y / rb.x;
+    // the minimisers' slopes need no correct rounding (see quad_min_over_box):
+    // a hardware reciprocal, not two divisions
+    const float bc = rb.y * __builtin_amdgcn_rcpf(rb.z), ba = rb.y * __builtin_amdgcn_rcpf(rb.x);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const float qmin = quad_min_over_box(du_hi - (float)((q & 1) * 8 + 7), dv_hi - (float)((q >> 1) * 8 + 7), rb.x,
