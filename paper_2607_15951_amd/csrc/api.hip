@@ -372,6 +372,21 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     if ((st = ensure(ctx, w.counts1, (size_t)chunks1 * rows * 4)) != GS_OK) return st;
     if ((st = ensure(ctx, w.counters, 64)) != GS_OK) return st;
     if ((st = ensure(ctx, w.tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
+    // every blend records its tiles' work; with blend_group 0 it is dispatched
+    // heaviest first, by the last render's work when that render had the same
+    // tile layout (the history: ordered by one extra workgroup of the
+    // projection launch), else by list length (ordered before the blend)
+    std::vector<int> layout;
+    for (const ViewParams& v : hv) {
+        layout.push_back(v.tiles_x);
+        layout.push_back(v.tiles_y);
+    }
+    const void* cost_before = w.tile_cost.p;
+    if ((st = ensure(ctx, w.tile_cost, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
+    const bool history = !noalloc && cost_before == w.tile_cost.p && ctx->cost_layout == layout;
+    if (tu.blend_group == 0)
+        if ((st = ensure(ctx, w.tile_order, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
+    const bool order_in_project = tu.blend_group == 0 && history && n > 0;
 
     ViewParams* views = static_cast<ViewParams*>(w.views.p);
     uint32_t* counters = static_cast<uint32_t*>(w.counters.p);
@@ -408,6 +423,11 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     pa.rect = static_cast<ushort4*>(w.rect.p);
     pa.view_counts = view_counts;
     pa.partials = static_cast<uint32_t*>(w.partials.p);
+    if (order_in_project) {
+        pa.order_cost = static_cast<const uint32_t*>(w.tile_cost.p);
+        pa.order = static_cast<uint32_t*>(w.tile_order.p);
+        pa.order_tiles = T;
+    }
     HIP_TRY(launch_project(pa, s), "project");
     STAGE_MARK(1);
 
@@ -566,23 +586,13 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
             return st;
         bl.tile_work = static_cast<unsigned long long*>(w.tile_work.p);
     }
-    // every blend records its tiles' work; with blend_group 0 it is dispatched
-    // heaviest first, by the last render's work when that render had the same
-    // tile layout, else by list length
-    std::vector<int> layout;
-    for (const ViewParams& v : hv) {
-        layout.push_back(v.tiles_x);
-        layout.push_back(v.tiles_y);
-    }
-    const void* cost_before = w.tile_cost.p;
-    if ((st = ensure(ctx, w.tile_cost, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
-    const bool history = !noalloc && cost_before == w.tile_cost.p && ctx->cost_layout == layout;
     bl.tile_cost = static_cast<uint32_t*>(w.tile_cost.p);
     bl.order = nullptr;
     if (tu.blend_group == 0) {
-        if ((st = ensure(ctx, w.tile_order, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
         uint32_t* order = static_cast<uint32_t*>(w.tile_order.p);
-        HIP_TRY(launch_blend_order(history ? bl.tile_cost : nullptr, bl.tile_offsets, T, order, s), "blend order");
+        // ordered by the projection's extra workgroup, or here by list length
+        if (!order_in_project)
+            HIP_TRY(launch_blend_order(nullptr, bl.tile_offsets, T, order, s), "blend order");
         bl.order = order;
     }
     HIP_TRY(launch_blend(bl, capacity, s), "blend");

@@ -34,6 +34,7 @@
 // the XCDs with the heavy bands running long after the others finish.
 #include "gs_internal.h"
 #include "blend_stage.h"
+#include "tile_order.h"
 
 namespace gsmi {
 namespace {
@@ -254,97 +255,19 @@ blend_kernel(BlendArgs a, uint64_t capacity)
     if (vp.out_nc) vp.out_nc[p] = last;
 }
 
-// Log-scale bucket of a tile's cost: exact below 128, then 32 buckets per
-// octave (costs within about 3% share one); 0 .. 927.
-constexpr int kOrderBuckets = 1024;
-__device__ __forceinline__ int cost_bucket(uint32_t c)
-{
-    if (c < 128u) return (int)c;
-    const int e = 31 - __clz(c);   // 7 .. 31
-    return 128 + (e - 7) * 32 + (int)((c >> (e - 5)) & 31u);
-}
-
-__device__ __forceinline__ uint32_t tile_cost_of(const uint32_t* cost, const uint32_t* offsets, int64_t t)
-{
-    return cost ? cost[t] : offsets[t + 1] - offsets[t];
-}
-
-// One 1024-thread workgroup: a counting sort of the tiles by descending cost
-// bucket.  The first pass loads kOrderPre costs per thread before using any
-// (a load under its own branch is waited for before the next one issues),
-// counts the buckets with LDS atomics and keeps each tile's bucket in LDS for
-// the second pass (tiles past kOrderKeptTiles load their cost again), which
-// claims each tile's slot with one more atomic.  Within a bucket the order
-// is whatever the atomics give: the order only decides when each tile's
-// workgroup starts, never what it computes.  (The whole sort runs on one CU;
-// plain atomics, colliding where many tiles share a bucket, cost less issue
-// there than grouping the lanes of a bucket with ballots.)
+// The order of a layout's first frame (by list length; later frames take the
+// previous frame's walked entries, ordered beside the projection): one
+// 1024-thread workgroup, each tile's bucket kept in LDS between the passes.
 constexpr int kOrderThreads = 1024;
-constexpr int kOrderPre = 8;
 constexpr int kOrderKeptTiles = 32768;
-static_assert(kOrderBuckets == kOrderThreads, "one bucket per thread in the scan");
 __global__ __launch_bounds__(kOrderThreads) void blend_order_kernel(const uint32_t* __restrict__ cost,
                                                                     const uint32_t* __restrict__ offsets,
                                                                     int64_t tiles, uint32_t* __restrict__ order)
 {
-    __shared__ uint32_t hist[kOrderBuckets];   // counts, then each bucket's next free slot
+    __shared__ uint32_t hist[kOrderBuckets];
     __shared__ uint16_t s_bucket[kOrderKeptTiles];
     __shared__ uint32_t wsum[kOrderThreads / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    hist[tid] = 0u;
-    __syncthreads();
-    constexpr int64_t kStep = (int64_t)kOrderThreads * kOrderPre;
-    for (int64_t t0 = 0; t0 < tiles; t0 += kStep) {
-        uint32_t c[kOrderPre];
-#pragma unroll
-        for (int k = 0; k < kOrderPre; ++k) {
-            const int64_t t = t0 + k * kOrderThreads + tid;
-            c[k] = tile_cost_of(cost, offsets, t < tiles ? t : 0);
-        }
-#pragma unroll
-        for (int k = 0; k < kOrderPre; ++k) {
-            const int64_t t = t0 + k * kOrderThreads + tid;
-            if (t < tiles) {
-                const int b = cost_bucket(c[k]);
-                atomicAdd(&hist[b], 1u);
-                if (t < kOrderKeptTiles) s_bucket[t] = (uint16_t)b;
-            }
-        }
-    }
-    __syncthreads();
-    // start of each bucket in descending bucket order: thread k holds bucket
-    // 1023 - k, scanned exclusively across the block
-    const uint32_t own = hist[kOrderBuckets - 1 - tid];
-    uint32_t x = own;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[wave] = x;
-    __syncthreads();
-    uint32_t before = 0u;
-    for (int w = 0; w < wave; ++w) before += wsum[w];
-    hist[kOrderBuckets - 1 - tid] = before + x - own;   // now the bucket's next free slot
-    __syncthreads();
-    for (int64_t t0 = 0; t0 < tiles; t0 += kStep) {
-        uint32_t c[kOrderPre];
-        const bool reload = t0 + kStep > kOrderKeptTiles;   // uniform: whole steps past the kept tiles
-        if (reload) {
-#pragma unroll
-            for (int k = 0; k < kOrderPre; ++k) {
-                const int64_t t = t0 + k * kOrderThreads + tid;
-                c[k] = tile_cost_of(cost, offsets, t < tiles ? t : 0);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kOrderPre; ++k) {
-            const int64_t t = t0 + k * kOrderThreads + tid;
-            if (t < tiles) {
-                const int b = reload ? cost_bucket(c[k]) : (int)s_bucket[t];
-                order[atomicAdd(&hist[b], 1u)] = (uint32_t)t;
-            }
-        }
-    }
+    order_heaviest_first<kOrderThreads>(cost, offsets, tiles, order, hist, wsum, s_bucket, kOrderKeptTiles);
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n)

@@ -92,6 +92,12 @@ struct ProjectArgs {
     ushort4* rect;
     uint32_t* view_counts;        // [n_views][kViewCounters]
     uint32_t* partials;           // [blocks][n_views][4] per-block counts: on screen, pairs, keyed
+    // when order is not null, one extra workgroup of the launch writes the
+    // blend's dispatch order of order_tiles tiles, heaviest first by
+    // order_cost (the previous frame's walked entries)
+    const uint32_t* order_cost;
+    uint32_t* order;
+    int64_t order_tiles;
 };
 
 size_t project_partials_elems(int64_t n, int n_views);

@@ -13,6 +13,7 @@
 // this kernel is bound by HBM reads (up to 236 B per Gaussian), so the double
 // arithmetic costs no frame time.  Colour and opacity are FP32.
 #include "gs_internal.h"
+#include "tile_order.h"
 
 #include <hip/hip_fp16.h>
 
@@ -192,8 +193,20 @@ template <int DT, int DEG, bool kOneView>
 __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
 {
     constexpr int ncoef = (DEG + 1) * (DEG + 1);
+    // the blend's dispatch order, when asked for, is workgroup 0's work: it
+    // needs only the previous frame's per-tile costs, so it runs beside the
+    // projection; the Gaussians go to workgroups 1 and up
+    int64_t blk = blockIdx.x;
+    if (a.order) {
+        if (blockIdx.x == 0) {
+            __shared__ uint32_t s_hist[kOrderBuckets], s_wsum[4];
+            order_heaviest_first<256>(a.order_cost, nullptr, a.order_tiles, a.order, s_hist, s_wsum, nullptr, 0);
+            return;
+        }
+        blk -= 1;
+    }
     // lanes past n stay active (reading Gaussian 0) until the wave reduction
-    const int64_t i_raw = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i_raw = blk * 256 + threadIdx.x;
     const bool valid = i_raw < a.n;
     const int64_t i = valid ? i_raw : 0;
     const int64_t n = a.n;
@@ -301,7 +314,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            uint32_t* pp = a.partials + 4 * ((int64_t)blockIdx.x * a.n_views + v);
+            uint32_t* pp = a.partials + 4 * (blk * a.n_views + v);
             pp[0] = s_vis[0] + s_vis[1] + s_vis[2] + s_vis[3];
             pp[1] = s_pairs[0] + s_pairs[1] + s_pairs[2] + s_pairs[3];
             pp[2] = s_front[0] + s_front[1] + s_front[2] + s_front[3];
@@ -645,10 +658,11 @@ hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
     if (a.n_views <= 0) return hipSuccess;
     if (a.n == 0) return launch_fill_u32(a.view_counts, 0u, (int64_t)kViewCounters * a.n_views, s);
     const unsigned blocks = (unsigned)((a.n + 255) / 256);
+    const unsigned grid = blocks + (a.order ? 1u : 0u);   // the order's workgroup first
     switch (a.dtype) {
-    case 0: launch_project_views<0>(a, blocks, s); break;
-    case 1: launch_project_views<1>(a, blocks, s); break;
-    default: launch_project_views<2>(a, blocks, s); break;
+    case 0: launch_project_views<0>(a, grid, s); break;
+    case 1: launch_project_views<1>(a, grid, s); break;
+    default: launch_project_views<2>(a, grid, s); break;
     }
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)a.n_views), dim3(1024), 0, s,
                        (const uint32_t*)a.partials, (int)blocks, a.n_views, a.view_counts);
