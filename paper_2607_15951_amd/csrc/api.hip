@@ -503,11 +503,20 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
         uint32_t* hi = ctx->host_info;
         const int n_vc = V * kViewCounters;
         // the sizes go straight into the pinned host buffer (its device
-        // address); the event below marks their arrival
+        // address), else through a device buffer and a copy; the event below
+        // marks their arrival
+        uint32_t* rb = ctx->host_info_dev;
+        if (!rb) {
+            if ((st = ensure(ctx, w.readback, (size_t)(n_vc + kReadbackTail) * 4)) != GS_OK) return st;
+            rb = static_cast<uint32_t*>(w.readback.p);
+        }
         hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, s, (const uint32_t*)view_counts, n_vc,
                            (const uint32_t*)counters, (const uint32_t*)(ba.rows_off + rows), (const uint32_t*)ba.info,
-                           ctx->host_info_dev);
+                           rb);
         HIP_TRY(hipGetLastError(), "read sizes");
+        if (!ctx->host_info_dev)
+            HIP_TRY(hipMemcpyAsync(hi, rb, (size_t)(n_vc + kReadbackTail) * 4, hipMemcpyDeviceToHost, s),
+                    "read sizes");
         // the row scatter needs no size but R, and the row-entry buffer of
         // earlier renders mostly holds this frame's entries: it runs while
         // the host reads the sizes, and runs again into a grown buffer when R
@@ -751,7 +760,13 @@ gs_status gs_create(int device, gs_context** out)
                           sizeof(uint32_t) * ((size_t)kMaxViews * kViewCounters + 16));
     // the pinned buffer is mapped into the device's address space: the
     // kernel that packs the frame's sizes writes them there, with no copy
-    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->host_info_dev), ctx->host_info, 0);
+    // (where it is not mapped, the sizes go through a device buffer and a
+    // copy)
+    if (e == hipSuccess &&
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->host_info_dev), ctx->host_info, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->host_info_dev = nullptr;
+    }
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ctx->noalloc_info), 64);
     // the device's copy of the no-allocation scratch (once per device)
     if (e == hipSuccess) e = init_scratch_address(device, count);
