@@ -501,6 +501,40 @@ def time_workload(r, workload: str, dtype: int, steps: int, graph: bool = False)
     return res
 
 
+def time_two_streams(dev, cam, W: int, H: int, steps: int, K: int, tuning: dict) -> dict:
+    """Frames of the same scene on two contexts and two streams in turn, so
+    that one frame's blend (bound by VALU issue) can overlap the next frame's
+    projection and sort (bound by memory): the throughput of a stream of
+    frames with two in flight, beside the single-stream frame time.  Pair
+    capacity 1.1 K, so that no frame waits for the host."""
+    import torch
+    import paper_2607_15951_amd as gs
+    cap = int(K * 1.1)
+    rs = [gs.Renderer(0), gs.Renderer(0)]
+    sts = [torch.cuda.Stream(), torch.cuda.Stream()]   # default priority
+    outs = []
+    for r, st in zip(rs, sts):
+        r.set_tuning(**tuning)
+        with torch.cuda.stream(st):
+            o = r.render(dev, cam, W, H, pair_capacity=cap)
+            for _ in range(3):
+                r.render(dev, cam, W, H, out=o, pair_capacity=cap)
+        outs.append(o)
+    torch.cuda.synchronize()
+    frames = max(4, steps - steps % 2)
+    t0 = time.perf_counter()
+    for k in range(frames):
+        i = k % 2
+        with torch.cuda.stream(sts[i]):
+            rs[i].render(dev, cam, W, H, out=outs[i], pair_capacity=cap)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / frames
+    for r in rs:
+        r.close()
+    return {"frames": frames, "ms_per_frame": round(ms, 4), "frames_per_s": round(1e3 / ms, 2),
+            "pair_capacity": cap}
+
+
 def time_batched_backward(r, dev, cams, steps: int) -> dict:
     """One training step's rasterizer work on a batch of views: the batched
     render of all views, then one backward over them (seeded dL/d(image) and
@@ -727,6 +761,8 @@ def main():
             log("[bench] variant backward: " + json.dumps(variants["backward"]))
             variants["capacity"] = time_capacity(r, dev, cam, W, H, args.steps, out, info["num_pairs"])
             log("[bench] variant capacity: " + json.dumps(variants["capacity"]))
+            variants["two_streams"] = time_two_streams(dev, cam, W, H, args.steps, info["num_pairs"], r.tuning())
+            log("[bench] variant two_streams: " + json.dumps(variants["two_streams"]))
             variants["reuse_order"] = time_reuse(r, dev, W, H)
             log("[bench] variant reuse_order: " + json.dumps(variants["reuse_order"]))
         # batched: the same frame's scene from 8 cameras on a ring (1080p each),
