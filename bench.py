@@ -609,6 +609,49 @@ def time_reuse(r, dev, W: int, H: int, frames: int = 16) -> dict:
     return out
 
 
+def time_list_reuse(r, dev, cam, W: int, H: int, frames: int = 20) -> dict:
+    """A static camera over frames whose colours change (the SH coefficients
+    alternate between two sets, the geometry stays): frame time with
+    GS_RENDER_REUSE_LISTS, which keeps the lists when no depth key or tile
+    rectangle changed, against plain renders of the same frames, and how many
+    frames kept their lists.  Then one orbit step per frame, where the lists
+    cannot hold: the cost of the comparison and of its host wait."""
+    import torch
+    import scenes
+    dev_b = dict(dev)
+    dev_b["sh"] = (dev["sh"].float() * 0.9).to(dev["sh"].dtype)
+    scenes_ab = [dev, dev_b]
+    o = r.render(dev, cam, W, H)
+    res = {}
+    for reuse in (True, False):
+        r.render(dev, cam, W, H, out=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(frames):
+            r.render(scenes_ab[(f + 1) % 2], cam, W, H, out=o, reuse_lists=reuse)
+        torch.cuda.synchronize()
+        res["ms_per_frame_reuse" if reuse else "ms_per_frame_plain"] = round((time.perf_counter() - t0) * 1e3 / frames,
+                                                                            4)
+    kept = 0
+    r.render(dev, cam, W, H, out=o)
+    for f in range(frames):
+        r.render(scenes_ab[(f + 1) % 2], cam, W, H, out=o, reuse_lists=True)
+        kept += r.list_reuse()["reused"]
+    res["frames_kept"] = int(kept)
+    res["frames"] = frames
+    cams = [scenes.orbit_camera(0.01 * f, W, H) for f in range(frames + 1)]
+    for reuse in (True, False):
+        r.render(dev, cams[0], W, H, out=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in cams[1:]:
+            r.render(dev, c, W, H, out=o, reuse_lists=reuse)
+        torch.cuda.synchronize()
+        key = "orbit_ms_per_frame_reuse" if reuse else "orbit_ms_per_frame_plain"
+        res[key] = round((time.perf_counter() - t0) * 1e3 / frames, 4)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -765,6 +808,8 @@ def main():
             log("[bench] variant two_streams: " + json.dumps(variants["two_streams"]))
             variants["reuse_order"] = time_reuse(r, dev, W, H)
             log("[bench] variant reuse_order: " + json.dumps(variants["reuse_order"]))
+            variants["reuse_lists"] = time_list_reuse(r, dev, cam, W, H)
+            log("[bench] variant reuse_lists: " + json.dumps(variants["reuse_lists"]))
         # batched: the same frame's scene from 8 cameras on a ring (1080p each),
         # and the 64-camera mixed-resolution workload, each one
         # gs_render_batched call per step, against the same views rendered one

@@ -98,8 +98,8 @@ typedef struct {
  *                  with more pairs returns GS_ERR_CAPACITY after the row
  *                  counts, before the pair buffers are sized or any output
  *                  is written)
- *   flags          0 or GS_RENDER_REUSE_ORDER (below); other bits give
- *                  GS_ERR_INVALID_ARGUMENT */
+ *   flags          0, GS_RENDER_REUSE_ORDER or GS_RENDER_REUSE_LISTS
+ *                  (below), or both; other bits give GS_ERR_INVALID_ARGUMENT */
 typedef struct {
     float background[3];
     int32_t tile_size;
@@ -119,6 +119,22 @@ typedef struct {
  * output, is the same as without the flag; only the time differs.  Ignored
  * for batched renders and for the first render on a context. */
 #define GS_RENDER_REUSE_ORDER 1u
+
+/* GS_RENDER_REUSE_LISTS: frame-to-frame reuse of the whole tile lists, the
+ * case of Sec. 5.7 (Table 5) where no Gaussian changes its tiles.  The lists
+ * of Sec. 3.1 depend only on the depth keys, the tile rectangles and the
+ * image size.  When the previous render on the context was a single view of
+ * as many Gaussians at the same width and height without a pair capacity,
+ * the projection compares each Gaussian's depth key and rectangle with that
+ * render's, and the host reads the number that differ (one wait on the
+ * stream after the projection).  None (a static camera; colour or SH edits):
+ * the depth sort and the binning are skipped and the blend reads the lists
+ * kept in the context, which are the ones this frame would build.  Otherwise
+ * the render goes on as usual (with GS_RENDER_REUSE_ORDER, trying the
+ * order).  Every output is the same as without the flag.  Ignored with a pair
+ * capacity (graphs included), for batched renders and for the first render
+ * on a context; gs_get_list_reuse reports the outcome. */
+#define GS_RENDER_REUSE_LISTS 2u
 
 /* Creates a context on HIP device `device`; *out receives it. */
 gs_status gs_create(int device, gs_context** out);
@@ -163,8 +179,8 @@ gs_status gs_render(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam
  *                        gives the bytes needed); pairs past the capacity
  *                        are dropped on the device as for gs_render, which
  *                        gs_get_list_info reports afterwards
- * GS_RENDER_REUSE_ORDER and GS_PROFILE_BLEND_WORK are ignored, and the
- * blend takes no per-tile history (a heaviest-first order, if tuned, comes
+ * GS_RENDER_REUSE_ORDER, GS_RENDER_REUSE_LISTS and GS_PROFILE_BLEND_WORK
+ * are ignored, and the blend takes no per-tile history (a heaviest-first order, if tuned, comes
  * from list lengths).  After it, gs_get_list_info and gs_get_stage_times
  * work; the lists, projection and backward of the render are not kept
  * (gs_copy_lists, gs_copy_projection and gs_render_backward fail).  Every
@@ -366,6 +382,14 @@ gs_status gs_get_blend_tile_work(gs_context* ctx, uint64_t* work, int64_t tiles)
  * churn between the two frames).  GS_ERR_INVALID_ARGUMENT if the last render
  * did not start from a previous order. */
 gs_status gs_get_order_reuse(gs_context* ctx, uint32_t* out2);
+
+/* Outcome of the last render's GS_RENDER_REUSE_LISTS comparison (host array
+ * of 2; the render already waited for it): [0] 1 if no Gaussian's depth key
+ * or tile rectangle had changed and the previous lists were kept (sort and
+ * binning skipped), else 0; [1] the number of Gaussians whose key or
+ * rectangle changed.  GS_ERR_INVALID_ARGUMENT if the last render made no
+ * comparison (flag absent, or a render the flag is ignored for). */
+gs_status gs_get_list_reuse(gs_context* ctx, uint32_t* out2);
 
 /* Launch shapes of the render, chosen per workload: the tile size (16, which
  * the keys of Sec. 3.1 and the lists depend on) is fixed, but how many items

@@ -20,14 +20,15 @@ LIB_PATH = os.path.join(_PKG, "libgsmi.so")
 GS_OK, GS_ERR_INVALID_ARGUMENT, GS_ERR_OUT_OF_MEMORY, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = range(6)
 GS_F32, GS_BF16, GS_F16 = 0, 1, 2
 PROFILE_STAGES, PROFILE_BLEND_WORK = 1, 2
-RENDER_REUSE_ORDER = 1
+RENDER_REUSE_ORDER, RENDER_REUSE_LISTS = 1, 2
 TILE = 16
 
 EXPORTED = ["gs_create", "gs_destroy", "gs_last_error", "gs_validate", "gs_render", "gs_get_list_info",
             "gs_copy_lists", "gs_copy_projection", "gs_set_profiling", "gs_get_stage_times",
             "gs_get_blend_stats", "gs_get_blend_tile_work", "gs_render_batched", "gs_graph_create",
             "gs_graph_set_views", "gs_graph_launch", "gs_graph_destroy", "gs_render_backward", "gs_set_tuning",
-            "gs_get_tuning", "gs_autotune", "gs_get_order_reuse", "gs_render_noalloc"]
+            "gs_get_tuning", "gs_autotune", "gs_get_order_reuse", "gs_render_noalloc",
+            "gs_get_list_reuse"]
 STAGES = ["project", "depth_sort", "bin_row_count", "bin_row_scatter", "bin_tile_count", "bin_tile_scatter",
           "blend"]
 
@@ -132,6 +133,8 @@ def load_library(path: str = LIB_PATH):
     L.gs_render_backward.restype = C.c_int
     L.gs_get_order_reuse.argtypes = [P, C.POINTER(C.c_uint32)]
     L.gs_get_order_reuse.restype = C.c_int
+    L.gs_get_list_reuse.argtypes = [P, C.POINTER(C.c_uint32)]
+    L.gs_get_list_reuse.restype = C.c_int
     L.gs_set_tuning.argtypes = [P, C.POINTER(gs_tuning)]
     L.gs_set_tuning.restype = C.c_int
     L.gs_get_tuning.argtypes = [P, C.POINTER(gs_tuning)]
@@ -303,10 +306,13 @@ class Renderer:
 
     def render(self, dev_scene: dict, camera: dict, width: int, height: int, background=(0.0, 0.0, 0.0),
                pair_capacity: int = 0, out=None, want_T: bool = True, want_n_contrib: bool = True,
-               stream=None, reuse_order: bool = False):
+               stream=None, reuse_order: bool = False, reuse_lists: bool = False):
         """Renders into (new or given) tensors: rgb [3,H,W], final_T [H,W], n_contrib [H,W].
         reuse_order: start the depth sort from the previous render's order
-        (GS_RENDER_REUSE_ORDER; same results, less work between nearby frames)."""
+        (GS_RENDER_REUSE_ORDER; same results, less work between nearby frames).
+        reuse_lists: keep the previous render's tile lists when no Gaussian's
+        depth key or tile rectangle changed (GS_RENDER_REUSE_LISTS; same
+        results, no sort and no binning for a static camera)."""
         torch = _torch()
         dev = dev_scene["means"].device
         if out is None:
@@ -318,7 +324,8 @@ class Renderer:
             _check_outputs(out, int(width), int(height), dev)
         g = make_gaussians(dev_scene)
         cam = make_camera(camera)
-        opts = make_opts(background, pair_capacity, RENDER_REUSE_ORDER if reuse_order else 0)
+        flags = (RENDER_REUSE_ORDER if reuse_order else 0) | (RENDER_REUSE_LISTS if reuse_lists else 0)
+        opts = make_opts(background, pair_capacity, flags)
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         st = self._L.gs_render(self._ctx, C.byref(g), C.byref(cam), int(width), int(height), C.byref(opts),
                                _ptr(out["image"]), _ptr(out.get("final_T")), _ptr(out.get("n_contrib")),
@@ -417,6 +424,14 @@ class Renderer:
         w = (C.c_uint32 * 2)()
         self._check(self._L.gs_get_order_reuse(self._ctx, w))
         return {"reused": bool(w[0]), "descents": int(w[1])}
+
+    def list_reuse(self) -> dict:
+        """Outcome of the last render's comparison with the previous lists
+        (gs_get_list_reuse): whether the lists were kept (sort and binning
+        skipped), and the Gaussians whose depth key or tile rectangle changed."""
+        w = (C.c_uint32 * 2)()
+        self._check(self._L.gs_get_list_reuse(self._ctx, w))
+        return {"reused": bool(w[0]), "changed": int(w[1])}
 
     def tuning(self) -> dict:
         t = gs_tuning()

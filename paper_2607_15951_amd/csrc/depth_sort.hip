@@ -467,7 +467,26 @@ __global__ __launch_bounds__(256) void order_check_kernel(const uint32_t* __rest
     }
 }
 
+// The rectangles in a reused order (see launch_order_pack).
+__global__ __launch_bounds__(256) void order_pack_kernel(const uint32_t* __restrict__ order,
+                                                         const ushort4* __restrict__ rect, int64_t n,
+                                                         const uint32_t* words, uint32_t* __restrict__ pay)
+{
+    if (!words[0]) return;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < n) pay[j] = pack_rect(rect[order[j]]);
+}
+
 }  // namespace
+
+hipError_t launch_order_pack(const uint32_t* vals_b, const ushort4* rect, int64_t n, const uint32_t* words,
+                             uint32_t* pay_b, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(order_pack_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vals_b, rect, n, words,
+                       pay_b);
+    return hipGetLastError();
+}
 
 bool depth_sort_items_supported(int items) { return items == 4 || items == 8 || items == 16; }
 

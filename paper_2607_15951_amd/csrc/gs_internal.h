@@ -98,6 +98,10 @@ struct ProjectArgs {
     const uint32_t* order_cost;
     uint32_t* order;
     int64_t order_tiles;
+    // when not null (one view): before its own stores each item compares its
+    // depth key and rectangle with the values the buffers hold (the last
+    // render's), and *changed receives the number that differ
+    uint32_t* changed;
 };
 
 size_t project_partials_elems(int64_t n, int n_views);
@@ -139,6 +143,12 @@ constexpr int kReuseWords = 3;
 size_t order_reuse_words(int64_t n);   // words and the gather's per-block counts
 hipError_t launch_order_reuse(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
                               uint32_t* vals_b, int64_t n, uint32_t* words, hipStream_t s);
+// After launch_depth_sort with reuse words and rect: when the reused order
+// held (words[0] = 1, so the passes did not run) writes pay_b[j] =
+// pack_rect(rect[vals_b[j]]), the rectangles the passes would have carried;
+// otherwise the passes wrote them and nothing is done.
+hipError_t launch_order_pack(const uint32_t* vals_b, const ushort4* rect, int64_t n, const uint32_t* words,
+                             uint32_t* pay_b, hipStream_t s);
 
 struct BinArgs {
     const uint32_t* sorted_idx;   // [n_views * n] items (v * n + i), each view's segment in (depth, index) order

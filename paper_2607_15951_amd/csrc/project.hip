@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
     // sigmoid in double, rounded once: the opacity carries one float rounding
     // whatever the logit (a float exp of -logit would carry about |logit| of them)
     const float opacity = (float)(1.0 / (1.0 + exp(-(double)logit)));
-    __shared__ uint32_t s_vis[4], s_pairs[4], s_front[4];
+    __shared__ uint32_t s_vis[4], s_pairs[4], s_front[4], s_changed[4];
 
     const int n_views = kOneView ? 1 : a.n_views;
     for (int v = 0; v < n_views; ++v) {
@@ -288,13 +288,20 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
             }
             sp.c = make_float4(col[0], col[1], col[2], (float)g.tz);
         }
+        bool changed = false;
         if (valid) {
             const int64_t o = (int64_t)v * n + i;
             float4* dst = reinterpret_cast<float4*>(a.splats + o);
             dst[0] = sp.a;
             dst[1] = sp.b;
             dst[2] = sp.c;
-            a.depth_key[o] = keyed ? __float_as_uint((float)tz_key) : 0xFFFFFFFFu;
+            const uint32_t key = keyed ? __float_as_uint((float)tz_key) : 0xFFFFFFFFu;
+            if (a.changed) {
+                const uint32_t key0 = a.depth_key[o];
+                const ushort4 rc0 = a.rect[o];
+                changed = key0 != key || rc0.x != rc.x || rc0.y != rc.y || rc0.z != rc.z || rc0.w != rc.w;
+            }
+            a.depth_key[o] = key;
             a.radius[o] = tiles > 0 ? g.radius : 0;
             a.tiles_touched[o] = tiles;
             a.rect[o] = rc;
@@ -305,12 +312,14 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
         // sums them
         const uint64_t vis = __ballot(tiles > 0);
         const uint64_t front = __ballot(valid && keyed);
+        const uint64_t moved = __ballot(changed);
         uint32_t wave_pairs = tiles;
         for (int o = 32; o > 0; o >>= 1) wave_pairs += __shfl_xor(wave_pairs, o, 64);
         if ((threadIdx.x & 63) == 0) {
             s_vis[threadIdx.x >> 6] = (uint32_t)__popcll(vis);
             s_pairs[threadIdx.x >> 6] = wave_pairs;
             s_front[threadIdx.x >> 6] = (uint32_t)__popcll(front);
+            s_changed[threadIdx.x >> 6] = (uint32_t)__popcll(moved);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -318,6 +327,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a)
             pp[0] = s_vis[0] + s_vis[1] + s_vis[2] + s_vis[3];
             pp[1] = s_pairs[0] + s_pairs[1] + s_pairs[2] + s_pairs[3];
             pp[2] = s_front[0] + s_front[1] + s_front[2] + s_front[3];
+            pp[3] = s_changed[0] + s_changed[1] + s_changed[2] + s_changed[3];
         }
         __syncthreads();   // s_vis / s_pairs are reused by the next view
     }
@@ -582,44 +592,51 @@ void launch_project_backward_dt(const ProjectBackArgs& a, unsigned blocks, hipSt
 
 // Per view (one block each): Gaussians on screen, pairs and Gaussians with a
 // depth key (past the culls), summed over the projection blocks' partials.
+// With changed (one view), also the items whose key or rectangle changed,
+// clamped to 2^32 - 1.
 __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* __restrict__ partials, int blocks,
-                                                               int n_views, uint32_t* view_counts)
+                                                               int n_views, uint32_t* view_counts, uint32_t* changed)
 {
     // 64-bit sums: in each thread over a stride of blocks, in each wave by
     // shuffles, then over the 16 waves in LDS
-    __shared__ unsigned long long sv[16], sp[16], sf[16];
+    __shared__ unsigned long long sv[16], sp[16], sf[16], sc[16];
     const int v = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned long long vis = 0, pairs = 0, front = 0;
+    unsigned long long vis = 0, pairs = 0, front = 0, moved = 0;
 #pragma unroll 4
     for (int b = threadIdx.x; b < blocks; b += 1024) {
         const uint4 pp = *reinterpret_cast<const uint4*>(partials + 4 * ((int64_t)b * n_views + v));
         vis += pp.x;
         pairs += pp.y;
         front += pp.z;
+        moved += changed ? pp.w : 0u;
     }
     for (int o = 32; o > 0; o >>= 1) {
         vis += __shfl_xor(vis, o, 64);
         pairs += __shfl_xor(pairs, o, 64);
         front += __shfl_xor(front, o, 64);
+        moved += __shfl_xor(moved, o, 64);
     }
     if (lane == 0) {
         sv[wave] = vis;
         sp[wave] = pairs;
         sf[wave] = front;
+        sc[wave] = moved;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long tv = 0, tp = 0, tf = 0;
+        unsigned long long tv = 0, tp = 0, tf = 0, tc = 0;
         for (int w = 0; w < 16; ++w) {
             tv += sv[w];
             tp += sp[w];
             tf += sf[w];
+            tc += sc[w];
         }
         uint32_t* c = view_counts + (int64_t)kViewCounters * v;
         c[0] = (uint32_t)tv;
         c[1] = (uint32_t)tf;
         c[2] = (uint32_t)tp;
         c[3] = (uint32_t)(tp >> 32);
+        if (changed) *changed = tc > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tc;
     }
 }
 
@@ -665,7 +682,8 @@ hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
     default: launch_project_views<2>(a, grid, s); break;
     }
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)a.n_views), dim3(1024), 0, s,
-                       (const uint32_t*)a.partials, (int)blocks, a.n_views, a.view_counts);
+                       (const uint32_t*)a.partials, (int)blocks, a.n_views, a.view_counts,
+                       a.n_views == 1 ? a.changed : nullptr);
     return hipGetLastError();
 }
 

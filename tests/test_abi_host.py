@@ -65,10 +65,11 @@ def test_validate_bounds_the_pair_capacity(lib):
     assert gs.validate(g, cam, 64, 48, opts, C.c_void_p(0x2000)) == gs.GS_ERR_UNSUPPORTED
 
 
-def test_validate_accepts_the_reuse_flag(lib):
+def test_validate_accepts_the_reuse_flags(lib):
     g, cam, opts = _valid_args()
-    opts.flags = gs.RENDER_REUSE_ORDER
-    assert gs.validate(g, cam, 64, 48, opts, C.c_void_p(0x2000)) == gs.GS_OK
+    for flags in (gs.RENDER_REUSE_ORDER, gs.RENDER_REUSE_LISTS, gs.RENDER_REUSE_ORDER | gs.RENDER_REUSE_LISTS):
+        opts.flags = flags
+        assert gs.validate(g, cam, 64, 48, opts, C.c_void_p(0x2000)) == gs.GS_OK, flags
 
 
 @pytest.mark.parametrize("case", ["null_out", "neg_n", "huge_n", "deg4", "deg_neg", "dtype", "null_attr",
@@ -109,7 +110,7 @@ def test_validate_rejects(lib, case):
     elif case == "tile8":
         opts.tile_size = 8
     elif case == "flags":
-        opts.flags = 2          # only GS_RENDER_REUSE_ORDER (1) is defined
+        opts.flags = 4          # only GS_RENDER_REUSE_ORDER (1) and GS_RENDER_REUSE_LISTS (2) are defined
     elif case == "nan_bg":
         opts.background[1] = float("nan")
     st = gs.validate(g, cam, W, H, opts, out)
