@@ -285,7 +285,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_writ
                   variant: str, tuning: str | None = None) -> str:
     """HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
     each scaled by the reading of a plain copy of known size."""
-    copy_bytes = 1 << 30
+    copy_bytes = COPY_CALIBRATION_BYTES
     cf = max(_pmc_avg(copy_fetch_csv, "FETCH_SIZE").items(), key=lambda kv: kv[1])
     cw = max(_pmc_avg(copy_write_csv, "WRITE_SIZE").items(), key=lambda kv: kv[1])
     f_fac = copy_bytes / (cf[1] * 1024.0)
@@ -334,7 +334,12 @@ def _pmc_total(path: str, counter: str) -> dict:
     return {"kib": kib, "frames": max(frames, 1)}
 
 
-def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
+# the plain copy that calibrates the byte counters: 4 GiB read and written,
+# far past the 256 MB last-level cache
+COPY_CALIBRATION_BYTES = 1 << 32
+
+
+def copy_calibration(nbytes: int = COPY_CALIBRATION_BYTES, reps: int = 3):
     """A plain device-to-device copy of known size: reads and writes nbytes
     per launch.  Profiled with the same FETCH_SIZE / WRITE_SIZE counters, it
     gives the factor between counter readings and bytes moved."""
@@ -663,7 +668,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the BF16/FP16 storage variants")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a 1 GiB device copy (reference for the HBM byte counters)")
+                    help="only run a 4 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--tuning", metavar="SORT,ROW,TILE,GROUP[,BATCH]",
                     help="launch shapes to use instead of autotuning (sort_items, bin_row_items, bin_tile_items, "
                          "blend_tile_group, blend_batch)")
