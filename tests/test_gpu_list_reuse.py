@@ -92,6 +92,22 @@ def test_static_camera_and_colour_edits_keep_the_lists(renderer):
         assert renderer.list_reuse()["reused"], k
 
 
+@pytest.mark.parametrize("dtype_name", ["GS_BF16", "GS_F16"])
+def test_kept_lists_with_reduced_storage(renderer, dtype_name):
+    """BF16 and FP16 attribute storage: an SH edit keeps the lists, and the
+    frame is the plain render's."""
+    import paper_2607_15951_amd as gs
+    W, H = 224, 160
+    sc = scenes.make_scene("C3", n=30_000, seed=77)
+    dev = gs.scene_to_device(sc, getattr(gs, dtype_name))
+    cam = scenes.default_camera(W, H)
+    renderer.render(dev, cam, W, H)
+    dev["sh"].mul_(-0.75)
+    got = snapshot(renderer, renderer.render(dev, cam, W, H, reuse_lists=True))
+    assert renderer.list_reuse() == {"reused": True, "changed": 0}
+    same(got, plain(dev, cam, W, H), f"{dtype_name} SH edit")
+
+
 def test_moving_geometry_rebuilds_the_lists(renderer):
     """A camera step, or a few moved Gaussians: the comparison counts them,
     the lists are rebuilt, and the frame is the plain render's."""
