@@ -400,14 +400,15 @@ class Renderer:
         return views, outs
 
     def graph(self, dev_scene: dict, cameras: list, pair_capacity: int, background=(0.0, 0.0, 0.0), outs=None,
-              stream=None, reuse_order: bool = False) -> "RenderGraph":
+              stream=None, reuse_order: bool = False, reuse_lists: bool = False) -> "RenderGraph":
         """Captures a batched render of ``cameras`` into a replayable graph
         (gs_graph_create); the renderer belongs to it until it is closed."""
         torch = _torch()
         dev = dev_scene["means"].device
         views, outs = self._views(cameras, outs, dev)
         g = make_gaussians(dev_scene)
-        opts = make_opts(background, pair_capacity, RENDER_REUSE_ORDER if reuse_order else 0)
+        flags = (RENDER_REUSE_ORDER if reuse_order else 0) | (RENDER_REUSE_LISTS if reuse_lists else 0)
+        opts = make_opts(background, pair_capacity, flags)
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         h = C.c_void_p()
         self._check(self._L.gs_graph_create(self._ctx, C.byref(g), views, len(cameras), C.byref(opts),

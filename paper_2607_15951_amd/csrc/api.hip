@@ -110,14 +110,12 @@ struct gs_context {
     Tuning last_tuning = kDefaultTuning;  // launch shapes of the last render
     int64_t order_n = -1;     // items of the depth order the sort buffers hold (one view), -1 if none
     bool last_reuse = false;  // the last render started from the previous order
-    // the tile lists in the workspace: those of an eager one-view render of
-    // lists_n Gaussians at lists_w x lists_h with lists_k pairs (-1: none)
+    // the tile lists in the workspace: those of a one-view render of lists_n
+    // Gaussians at lists_w x lists_h with pair capacity lists_cap (0: eager)
     int64_t lists_n = -1;
     int lists_w = 0, lists_h = 0;
-    uint64_t lists_k = 0;
-    bool lists_compared = false;    // the last render compared keys and rectangles with its predecessor's
-    bool lists_reused = false;      // ... found none changed and kept the lists
-    uint32_t lists_changed = 0;     // ... the Gaussians whose key or rectangle changed
+    uint64_t lists_cap = 0;
+    bool lists_compared = false;   // the last render compared keys and rectangles with its predecessor's
     std::vector<int> cost_layout;   // tiles_x, tiles_y of every view whose work ws.tile_cost holds
     // the last render was gs_render_noalloc: its sizes are in noalloc_info
     // (device words, allocated with the context), its buffers are gone
@@ -304,15 +302,9 @@ __global__ void pack_readback_kernel(const uint32_t* view_counts, int n_vc, cons
     __threadfence_system();   // out may be pinned host memory, read by the host after the frame's event
 }
 
-// One word to the host readback (pinned memory, or the device buffer copied to it).
-__global__ void read_word_kernel(const uint32_t* src, uint32_t* out)
-{
-    if (threadIdx.x == 0) out[0] = src[0];
-    __threadfence_system();
-}
-
 // counters[kCounterChanged]: the projection's count of Gaussians whose depth
-// key or rectangle differ from the last render's (list reuse)
+// key or rectangle differ from the last render's (list reuse), and after it
+// the flag that none did
 constexpr int kCounterChanged = 2;
 
 __global__ void row_table_kernel(const ViewParams* views, int n_views, uint32_t* row_tiles_x, int rows)
@@ -353,7 +345,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ctx->order_n = -1;   // valid again only once this render has completed its sort
     const int64_t prev_lists_n = ctx->lists_n;
     ctx->lists_n = -1;   // valid again only once this render has completed its lists
-    ctx->lists_compared = ctx->lists_reused = false;
+    ctx->lists_compared = false;
 
     const int V = (int)hv.size();
     const int64_t n = g->n;
@@ -427,12 +419,15 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     HIP_TRY(hipGetLastError(), "frame set-up");
     STAGE_MARK(0);
 
-    // list reuse: the workspace holds the lists of an eager one-view render of
-    // as many Gaussians at the same size; the projection counts the Gaussians
-    // whose depth key or rectangle changed since, and when none did those
-    // lists are this frame's (they depend on nothing else)
-    const bool try_lists = !noalloc && o.pair_capacity == 0 && (o.flags & GS_RENDER_REUSE_LISTS) && V == 1 &&
-                           n > 0 && prev_lists_n == n && ctx->lists_w == hv[0].width && ctx->lists_h == hv[0].height;
+    // list reuse: the workspace holds the lists of a one-view render of as
+    // many Gaussians at the same size and pair capacity (a capacity that
+    // truncated them truncates an identical frame's the same way); the
+    // projection counts the Gaussians whose depth key or rectangle changed
+    // since, and when none did those lists are this frame's (they depend on
+    // nothing else): the sort and the binning then skip on the device
+    const bool try_lists = !noalloc && (o.flags & GS_RENDER_REUSE_LISTS) && V == 1 && n > 0 && prev_lists_n == n &&
+                           ctx->lists_w == hv[0].width && ctx->lists_h == hv[0].height &&
+                           ctx->lists_cap == o.pair_capacity;
 
     ProjectArgs pa{};
     pa.n = n;
@@ -457,27 +452,13 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
         pa.order = static_cast<uint32_t*>(w.tile_order.p);
         pa.order_tiles = T;
     }
+    // counters[kCounterChanged]: the changed count, then the flag that the
+    // previous lists hold, which every kernel of the sort and the binning
+    // reads on the device
     pa.changed = try_lists ? counters + kCounterChanged : nullptr;
     HIP_TRY(launch_project(pa, s), "project");
     STAGE_MARK(1);
-    bool lists_hold = false;
-    if (try_lists) {
-        // one word read back decides whether the sort and the binning run
-        uint32_t* rb = ctx->host_info_dev;
-        if (!rb) {
-            if ((st = ensure(ctx, w.readback, (size_t)(kViewCounters + kReadbackTail) * 4)) != GS_OK) return st;
-            rb = static_cast<uint32_t*>(w.readback.p);
-        }
-        hipLaunchKernelGGL(read_word_kernel, dim3(1), dim3(64), 0, s, (const uint32_t*)(counters + kCounterChanged),
-                           rb);
-        HIP_TRY(hipGetLastError(), "read change count");
-        if (!ctx->host_info_dev)
-            HIP_TRY(hipMemcpyAsync(ctx->host_info, rb, 4, hipMemcpyDeviceToHost, s), "read change count");
-        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-        ctx->lists_compared = true;
-        ctx->lists_changed = ctx->host_info[0];
-        lists_hold = ctx->lists_changed == 0;
-    }
+    ctx->lists_compared = try_lists;
 
     BinArgs ba{};
     ba.view_counts = view_counts;
@@ -501,144 +482,140 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ba.overflow = counters + 1;
     uint64_t capacity = o.pair_capacity;
     int in_b = 1;
-    bool reuse = false;
-    if (lists_hold) {
-        // the last render's lists, offsets and pair count are this frame's
-        capacity = ctx->lists_k;
-        in_b = ctx->sorted_in_b;
-        ba.values = static_cast<uint32_t*>(w.values.p);
-        for (int k = 2; k <= 7; ++k) STAGE_MARK(k);
-    } else {
-        // pair_capacity > 0: every size below is the bound the capacity implies
-        // (row entries <= pairs); else the host reads K, R and the level-2 sizes
-        // once
-        ba.row_capacity = capacity ? capacity : ~0ull;
-        ba.max_chunks2 = capacity ? bin_level2_chunk_bound(capacity, rows, tu.bin2_items) : (1 << 30);
-        ba.counts2_capacity = capacity ? (uint64_t)ba.max_chunks2 * max_tx : ~0ull;
-        // scan lengths: level-1 counts, tile offsets and
-        // (pair_capacity > 0) the level-2 counts; the eager path grows the scratch
-        // for the level-2 counts after its host read
-        int64_t scan_max = std::max<int64_t>(T + 1, (int64_t)rows * chunks1);
-        if (capacity) scan_max = std::max<int64_t>(scan_max, (int64_t)ba.counts2_capacity);
-        if ((st = ensure(ctx, w.scan_scratch, scan_scratch_elems(scan_max) * 8)) != GS_OK) return st;
-        uint64_t* scan_scratch = static_cast<uint64_t*>(w.scan_scratch.p);
-        // one view of the same Gaussians as the last render: start from its order
-        reuse = !noalloc && (o.flags & GS_RENDER_REUSE_ORDER) && V == 1 && n > 0 && prev_order_n == n;
-        uint32_t* reuse_words = nullptr;
-        if (reuse) {
-            if ((st = ensure(ctx, w.reuse_words, order_reuse_words(n) * 4)) != GS_OK) return st;
-            reuse_words = static_cast<uint32_t*>(w.reuse_words.p);
-            HIP_TRY(launch_order_reuse(pa.depth_key, static_cast<uint32_t*>(w.sort_ka.p),
-                                       static_cast<uint32_t*>(w.sort_va.p), static_cast<uint32_t*>(w.sort_kb.p),
-                                       static_cast<uint32_t*>(w.sort_vb.p), n, reuse_words, s),
-                    "order reuse");
-        }
-        // the sort carries each Gaussian's packed rectangle to the binning, which
-        // then reads the rectangles in depth order instead of gathering them (not
-        // in a no-allocation render: its scratch is kept small); when a reused
-        // order skips the radix passes, one gather in that order writes them
-        const bool packed = fits_packed;
-        HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(w.sort_ka.p),
-                                  static_cast<uint32_t*>(w.sort_va.p), static_cast<uint32_t*>(w.sort_kb.p),
-                                  static_cast<uint32_t*>(w.sort_vb.p), packed ? pa.rect : nullptr,
-                                  static_cast<uint32_t*>(packed ? w.sort_pa.p : nullptr),
-                                  static_cast<uint32_t*>(packed ? w.sort_pb.p : nullptr),
-                                  static_cast<uint32_t*>(w.hist.p),
-                                  n, V, tu.sort_items, reuse_words, s),
-                "depth sort");
-        if (reuse && packed)
-            HIP_TRY(launch_order_pack(static_cast<const uint32_t*>(w.sort_vb.p), pa.rect, n, reuse_words,
-                                      static_cast<uint32_t*>(w.sort_pb.p), s),
-                    "reused order's rectangles");
-        ba.sorted_idx = static_cast<const uint32_t*>(w.sort_vb.p);
-        ba.sorted_pack = packed ? static_cast<const uint32_t*>(w.sort_pb.p) : nullptr;
-        STAGE_MARK(2);
-        HIP_TRY(launch_bin_rows(ba, scan_scratch, s), "bin rows");
-        STAGE_MARK(3);
+    ba.skip = try_lists ? counters + kCounterChanged + 1 : nullptr;
+    // pair_capacity > 0: every size below is the bound the capacity implies
+    // (row entries <= pairs); else the host reads K, R and the level-2 sizes
+    // once
+    ba.row_capacity = capacity ? capacity : ~0ull;
+    ba.max_chunks2 = capacity ? bin_level2_chunk_bound(capacity, rows, tu.bin2_items) : (1 << 30);
+    ba.counts2_capacity = capacity ? (uint64_t)ba.max_chunks2 * max_tx : ~0ull;
+    // scan lengths: level-1 counts, tile offsets and
+    // (pair_capacity > 0) the level-2 counts; the eager path grows the scratch
+    // for the level-2 counts after its host read
+    int64_t scan_max = std::max<int64_t>(T + 1, (int64_t)rows * chunks1);
+    if (capacity) scan_max = std::max<int64_t>(scan_max, (int64_t)ba.counts2_capacity);
+    if ((st = ensure(ctx, w.scan_scratch, scan_scratch_elems(scan_max) * 8)) != GS_OK) return st;
+    uint64_t* scan_scratch = static_cast<uint64_t*>(w.scan_scratch.p);
+    // one view of the same Gaussians as the last render: start from its order
+    const bool reuse = !noalloc && (o.flags & GS_RENDER_REUSE_ORDER) && V == 1 && n > 0 && prev_order_n == n;
+    uint32_t* reuse_words = nullptr;
+    if (reuse) {
+        if ((st = ensure(ctx, w.reuse_words, order_reuse_words(n) * 4)) != GS_OK) return st;
+        reuse_words = static_cast<uint32_t*>(w.reuse_words.p);
+        HIP_TRY(launch_order_reuse(pa.depth_key, static_cast<uint32_t*>(w.sort_ka.p),
+                                   static_cast<uint32_t*>(w.sort_va.p), static_cast<uint32_t*>(w.sort_kb.p),
+                                   static_cast<uint32_t*>(w.sort_vb.p), n, reuse_words, s),
+                "order reuse");
+    }
+    // the sort carries each Gaussian's packed rectangle to the binning, which
+    // then reads the rectangles in depth order instead of gathering them (not
+    // in a no-allocation render: its scratch is kept small); when a reused
+    // order skips the radix passes, one gather in that order writes them
+    const bool packed = fits_packed;
+    HIP_TRY(launch_depth_sort(pa.depth_key, static_cast<uint32_t*>(w.sort_ka.p),
+                              static_cast<uint32_t*>(w.sort_va.p), static_cast<uint32_t*>(w.sort_kb.p),
+                              static_cast<uint32_t*>(w.sort_vb.p), packed ? pa.rect : nullptr,
+                              static_cast<uint32_t*>(packed ? w.sort_pa.p : nullptr),
+                              static_cast<uint32_t*>(packed ? w.sort_pb.p : nullptr),
+                              static_cast<uint32_t*>(w.hist.p),
+                              n, V, tu.sort_items, reuse ? reuse_words : ba.skip, s),
+            "depth sort");
+    if (reuse && packed)
+        HIP_TRY(launch_order_pack(static_cast<const uint32_t*>(w.sort_vb.p), pa.rect, n, reuse_words,
+                                  static_cast<uint32_t*>(w.sort_pb.p), s),
+                "reused order's rectangles");
+    ba.sorted_idx = static_cast<const uint32_t*>(w.sort_vb.p);
+    ba.sorted_pack = packed ? static_cast<const uint32_t*>(w.sort_pb.p) : nullptr;
+    STAGE_MARK(2);
+    HIP_TRY(launch_bin_rows(ba, scan_scratch, s), "bin rows");
+    STAGE_MARK(3);
 
-        int grid2 = ba.max_chunks2;
-        bool rows_scattered = false;   // the row scatter ran while the host read the sizes
-        if (capacity == 0) {
-            // eager: one host read (one copy) of the per-view pairs, R and the
-            // level-2 sizes
-            uint32_t* hi = ctx->host_info;
-            const int n_vc = V * kViewCounters;
-            // the sizes go straight into the pinned host buffer (its device
-            // address), else through a device buffer and a copy; the event below
-            // marks their arrival
-            uint32_t* rb = ctx->host_info_dev;
-            if (!rb) {
-                if ((st = ensure(ctx, w.readback, (size_t)(n_vc + kReadbackTail) * 4)) != GS_OK) return st;
-                rb = static_cast<uint32_t*>(w.readback.p);
-            }
-            hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, s, (const uint32_t*)view_counts, n_vc,
-                               (const uint32_t*)counters, (const uint32_t*)(ba.rows_off + rows),
-                               (const uint32_t*)ba.info,
-                               rb);
-            HIP_TRY(hipGetLastError(), "read sizes");
-            if (!ctx->host_info_dev)
-                HIP_TRY(hipMemcpyAsync(hi, rb, (size_t)(n_vc + kReadbackTail) * 4, hipMemcpyDeviceToHost, s),
-                        "read sizes");
-            // the row scatter needs no size but R, and the row-entry buffer of
-            // earlier renders mostly holds this frame's entries: it runs while
-            // the host reads the sizes, and runs again into a grown buffer when R
-            // exceeds it (its stores past the buffer are dropped)
-            const uint64_t spec = w.row_ent.bytes / 8;
-            if (spec > 0) {
-                HIP_TRY(hipEventRecord(ctx->sizes_ev, s), "hipEventRecord");
-                ba.row_ent = static_cast<uint2*>(w.row_ent.p);
-                ba.row_capacity = spec;
-                STAGE_MARK(4);
-                HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
-                STAGE_MARK(5);
-                rows_scattered = true;
-                HIP_TRY(hipEventSynchronize(ctx->sizes_ev), "hipEventSynchronize");
-            } else {
-                HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-            }
-            uint32_t* tail = hi + n_vc;
-            uint64_t K64 = 0;
-            for (int v = 0; v < V; ++v) {
-                const uint32_t* c = hi + (size_t)v * kViewCounters;
-                K64 += (uint64_t)c[2] | ((uint64_t)c[3] << 32);
-            }
-            if (K64 > 0xFFFFFFFFull || tail[1] != 0u)
-                return fail(ctx, GS_ERR_CAPACITY, "more than 2^32-1 (Gaussian, tile) pairs");
-            capacity = K64;
-            ba.row_capacity = tail[4];
-            if (rows_scattered && ba.row_capacity > spec) {
-                HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");   // the buffer is grown below
-                rows_scattered = false;
-            }
-            grid2 = (int)tail[5];
-            ba.max_chunks2 = grid2;
-            ba.counts2_capacity = tail[6];
+    int grid2 = ba.max_chunks2;
+    bool rows_scattered = false;   // the row scatter ran while the host read the sizes
+    bool lists_held = false;       // the host read that the previous lists hold (eager)
+    if (capacity == 0) {
+        // eager: one host read (one copy) of the per-view pairs, R and the
+        // level-2 sizes
+        uint32_t* hi = ctx->host_info;
+        const int n_vc = V * kViewCounters;
+        // the sizes go straight into the pinned host buffer (its device
+        // address), else through a device buffer and a copy; the event below
+        // marks their arrival
+        uint32_t* rb = ctx->host_info_dev;
+        if (!rb) {
+            if ((st = ensure(ctx, w.readback, (size_t)(n_vc + kReadbackTail) * 4)) != GS_OK) return st;
+            rb = static_cast<uint32_t*>(w.readback.p);
         }
-        ba.capacity = capacity;
-        // in eager mode nothing queued uses the buffers grown here (the kernels
-        // before the host read have completed; a row scatter still running uses
-        // the row-entry buffer, which then has room)
-        if ((st = ensure(ctx, w.scan_scratch, scan_scratch_elems((int64_t)std::max<uint64_t>(ba.counts2_capacity, 1)) *
-                                                     8)) != GS_OK)
-            return st;
-        scan_scratch = static_cast<uint64_t*>(w.scan_scratch.p);
-        const size_t rows_cap = (size_t)std::max<uint64_t>(ba.row_capacity, 1);
-        if ((st = ensure(ctx, w.row_ent, rows_cap * 8)) != GS_OK) return st;
-        if ((st = ensure(ctx, w.counts2, (size_t)std::max<uint64_t>(ba.counts2_capacity, 1) * 4)) != GS_OK) return st;
-        if ((st = ensure(ctx, w.values, (size_t)std::max<uint64_t>(capacity, 1) * 4)) != GS_OK) return st;
-        ba.row_ent = static_cast<uint2*>(w.row_ent.p);
-        ba.counts2 = static_cast<uint32_t*>(w.counts2.p);
-        ba.values = static_cast<uint32_t*>(w.values.p);
-        if (!rows_scattered) {
+        hipLaunchKernelGGL(pack_readback_kernel, dim3(1), dim3(256), 0, s, (const uint32_t*)view_counts, n_vc,
+                           (const uint32_t*)counters, (const uint32_t*)(ba.rows_off + rows),
+                           (const uint32_t*)ba.info,
+                           rb);
+        HIP_TRY(hipGetLastError(), "read sizes");
+        if (!ctx->host_info_dev)
+            HIP_TRY(hipMemcpyAsync(hi, rb, (size_t)(n_vc + kReadbackTail) * 4, hipMemcpyDeviceToHost, s),
+                    "read sizes");
+        // the row scatter needs no size but R, and the row-entry buffer of
+        // earlier renders mostly holds this frame's entries: it runs while
+        // the host reads the sizes, and runs again into a grown buffer when R
+        // exceeds it (its stores past the buffer are dropped)
+        const uint64_t spec = w.row_ent.bytes / 8;
+        if (spec > 0) {
+            HIP_TRY(hipEventRecord(ctx->sizes_ev, s), "hipEventRecord");
+            ba.row_ent = static_cast<uint2*>(w.row_ent.p);
+            ba.row_capacity = spec;
             STAGE_MARK(4);
             HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
             STAGE_MARK(5);
+            rows_scattered = true;
+            HIP_TRY(hipEventSynchronize(ctx->sizes_ev), "hipEventSynchronize");
+        } else {
+            HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         }
-        HIP_TRY(launch_bin_tiles(ba, grid2, scan_scratch, s), "bin tile counts");
-        STAGE_MARK(6);
-        HIP_TRY(launch_bin_tile_scatter(ba, grid2, s), "bin tile scatter");
-        STAGE_MARK(7);
+        uint32_t* tail = hi + n_vc;
+        uint64_t K64 = 0;
+        for (int v = 0; v < V; ++v) {
+            const uint32_t* c = hi + (size_t)v * kViewCounters;
+            K64 += (uint64_t)c[2] | ((uint64_t)c[3] << 32);
+        }
+        if (K64 > 0xFFFFFFFFull || tail[1] != 0u)
+            return fail(ctx, GS_ERR_CAPACITY, "more than 2^32-1 (Gaussian, tile) pairs");
+        capacity = K64;
+        ba.row_capacity = tail[4];
+        if (rows_scattered && ba.row_capacity > spec) {
+            HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");   // the buffer is grown below
+            rows_scattered = false;
+        }
+        grid2 = (int)tail[5];
+        ba.max_chunks2 = grid2;
+        ba.counts2_capacity = tail[6];
+        // counters[kCounterChanged + 1] came with the sizes: when the lists
+        // hold, the tile-level launches (which would skip) are not made
+        lists_held = try_lists && tail[kCounterChanged + 1] != 0u;
     }
+    ba.capacity = capacity;
+    // in eager mode nothing queued uses the buffers grown here (the kernels
+    // before the host read have completed; a row scatter still running uses
+    // the row-entry buffer, which then has room)
+    if ((st = ensure(ctx, w.scan_scratch, scan_scratch_elems((int64_t)std::max<uint64_t>(ba.counts2_capacity, 1)) *
+                                                 8)) != GS_OK)
+        return st;
+    scan_scratch = static_cast<uint64_t*>(w.scan_scratch.p);
+    const size_t rows_cap = (size_t)std::max<uint64_t>(ba.row_capacity, 1);
+    if ((st = ensure(ctx, w.row_ent, rows_cap * 8)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.counts2, (size_t)std::max<uint64_t>(ba.counts2_capacity, 1) * 4)) != GS_OK) return st;
+    if ((st = ensure(ctx, w.values, (size_t)std::max<uint64_t>(capacity, 1) * 4)) != GS_OK) return st;
+    ba.row_ent = static_cast<uint2*>(w.row_ent.p);
+    ba.counts2 = static_cast<uint32_t*>(w.counts2.p);
+    ba.values = static_cast<uint32_t*>(w.values.p);
+    if (!rows_scattered) {
+        STAGE_MARK(4);
+        HIP_TRY(launch_bin_row_scatter(ba, s), "bin row scatter");
+        STAGE_MARK(5);
+    }
+    if (!lists_held) HIP_TRY(launch_bin_tiles(ba, grid2, scan_scratch, s), "bin tile counts");
+    STAGE_MARK(6);
+    if (!lists_held) HIP_TRY(launch_bin_tile_scatter(ba, grid2, s), "bin tile scatter");
+    STAGE_MARK(7);
 
     BlendArgs bl{};
     bl.splats = pa.splats;
@@ -696,14 +673,13 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
 
     ctx->have_render = true;
     ctx->last_tuning = tu;
-    ctx->order_n = lists_hold ? prev_order_n : ((V == 1 && in_b) ? n : -1);
+    ctx->order_n = (V == 1 && in_b) ? n : -1;
     ctx->last_reuse = reuse;
-    ctx->lists_reused = lists_hold;
-    if (V == 1 && o.pair_capacity == 0) {
+    if (V == 1) {
         ctx->lists_n = n;
         ctx->lists_w = hv[0].width;
         ctx->lists_h = hv[0].height;
-        ctx->lists_k = capacity;
+        ctx->lists_cap = o.pair_capacity;
     }
     ctx->last_views = hv;
     ctx->last_g = *g;
@@ -1168,8 +1144,14 @@ gs_status gs_get_list_reuse(gs_context* ctx, uint32_t* out2)
     if (!ctx || !out2) return fail(ctx, GS_ERR_INVALID_ARGUMENT, "NULL argument");
     if (!ctx->have_render || !ctx->lists_compared)
         return fail(ctx, GS_ERR_INVALID_ARGUMENT, "the last render did not compare its keys and rectangles");
-    out2[0] = ctx->lists_reused ? 1u : 0u;
-    out2[1] = ctx->lists_changed;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    uint32_t w[2];
+    HIP_TRY(hipMemcpyAsync(w, static_cast<uint32_t*>(ctx->ws.counters.p) + kCounterChanged, sizeof w,
+                           hipMemcpyDeviceToHost, ctx->stream),
+            "read list reuse words");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    out2[0] = w[1];
+    out2[1] = w[0];
     return GS_OK;
 }
 

@@ -100,7 +100,9 @@ struct ProjectArgs {
     int64_t order_tiles;
     // when not null (one view): before its own stores each item compares its
     // depth key and rectangle with the values the buffers hold (the last
-    // render's), and *changed receives the number that differ
+    // render's); changed[0] receives the number that differ and changed[1]
+    // is 1 when none did (the previous lists hold: the skip flag of the sort
+    // and the binning), else 0
     uint32_t* changed;
 };
 
@@ -180,6 +182,10 @@ struct BinArgs {
     uint64_t capacity;
     int max_chunks2;
     uint32_t* overflow;           // set to 1 when a capacity is exceeded
+    // when not null, every binning kernel (and scan) reads *skip on the
+    // device and does nothing when it is set: the lists, offsets and sizes of
+    // the last render stay, because they are this render's
+    const uint32_t* skip;
 };
 
 size_t bin_info_elems(int rows);
@@ -199,9 +205,11 @@ constexpr int kInfoC2Elems = 1;
 // *total64 and/or *total32 (either may be null), overflow flag when the total
 // does not fit 32 bits.  block_scratch holds scan_scratch_elems(n) u64.
 size_t scan_scratch_elems(int64_t n);
+// With skip (else null) every kernel of the scan reads *skip on the device
+// and does nothing when it is set.
 hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scratch, uint64_t* total64,
                                  uint32_t* total32, uint32_t* overflow, hipStream_t s,
-                                 const uint32_t* n_dev = nullptr);
+                                 const uint32_t* n_dev = nullptr, const uint32_t* skip = nullptr);
 
 struct BlendArgs {
     const Splat* splats;

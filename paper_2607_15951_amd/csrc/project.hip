@@ -593,7 +593,7 @@ void launch_project_backward_dt(const ProjectBackArgs& a, unsigned blocks, hipSt
 // Per view (one block each): Gaussians on screen, pairs and Gaussians with a
 // depth key (past the culls), summed over the projection blocks' partials.
 // With changed (one view), also the items whose key or rectangle changed,
-// clamped to 2^32 - 1.
+// clamped to 2^32 - 1, and whether none did.
 __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* __restrict__ partials, int blocks,
                                                                int n_views, uint32_t* view_counts, uint32_t* changed)
 {
@@ -636,7 +636,10 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* _
         c[1] = (uint32_t)tf;
         c[2] = (uint32_t)tp;
         c[3] = (uint32_t)(tp >> 32);
-        if (changed) *changed = tc > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tc;
+        if (changed) {
+            changed[0] = tc > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tc;
+            changed[1] = tc == 0 ? 1u : 0u;
+        }
     }
 }
 

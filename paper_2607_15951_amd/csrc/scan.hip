@@ -49,8 +49,10 @@ __device__ __forceinline__ int64_t scan_length(int64_t n, const uint32_t* n_dev)
 // length (a grid sized for a bound then costs nothing past the real length).
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n_max,
                                                                     const uint32_t* n_dev,
-                                                                    uint64_t* __restrict__ block_sums)
+                                                                    uint64_t* __restrict__ block_sums,
+                                                                    const uint32_t* skip)
 {
+    if (skip && *skip) return;
     const int64_t n = scan_length(n_max, n_dev);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     __shared__ uint64_t sh[kScanThreads / 64];
@@ -78,8 +80,10 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_
 // exclusive scan of the tiles' sums by one block; writes the 64-bit total
 __global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(uint64_t* __restrict__ sums, int64_t n_max,
                                                                    const uint32_t* n_dev, uint64_t* total_out,
-                                                                   uint32_t* total32, uint32_t* overflow)
+                                                                   uint32_t* total32, uint32_t* overflow,
+                                                                   const uint32_t* skip)
 {
+    if (skip && *skip) return;
     __shared__ uint64_t sh[kScanThreads / 64];
     const int64_t n = scan_length(n_max, n_dev);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
@@ -109,8 +113,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* __res
                                                                  const uint32_t* n_dev,
                                                                  const uint64_t* __restrict__ tile_sums,
                                                                  uint64_t* total_out, uint32_t* total32,
-                                                                 uint32_t* overflow)
+                                                                 uint32_t* overflow, const uint32_t* skip)
 {
+    if (skip && *skip) return;
     const int64_t n = scan_length(n_max, n_dev);
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     __shared__ uint64_t sh[kScanThreads / 64];
@@ -184,12 +189,13 @@ size_t scan_scratch_elems(int64_t n)
 }
 
 hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scratch, uint64_t* total64,
-                                 uint32_t* total32, uint32_t* overflow, hipStream_t s, const uint32_t* n_dev)
+                                 uint32_t* total32, uint32_t* overflow, hipStream_t s, const uint32_t* n_dev,
+                                 const uint32_t* skip)
 {
     if (n <= 0) {
         if (total64 || total32) {
             hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, block_scratch, (int64_t)0,
-                               (const uint32_t*)nullptr, total64, total32, overflow);
+                               (const uint32_t*)nullptr, total64, total32, overflow, skip);
         }
         return hipGetLastError();
     }
@@ -197,9 +203,10 @@ hipError_t launch_scan_exclusive(uint32_t* data, int64_t n, uint64_t* block_scra
     const unsigned grid = (unsigned)std::min<int64_t>(nb, kScanMaxGrid);
     // one tile: the down-sweep reads no tile sums (none precede tile 0)
     if (nb > 1)
-        hipLaunchKernelGGL(scan_reduce_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch);
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch,
+                           skip);
     hipLaunchKernelGGL(scan_down_kernel, dim3(grid), dim3(kScanThreads), 0, s, data, n, n_dev, block_scratch,
-                       total64, total32, overflow);
+                       total64, total32, overflow, skip);
     return hipGetLastError();
 }
 

@@ -186,6 +186,7 @@ __device__ __forceinline__ void counts_from_diff(const uint32_t* diff, int m, ui
 template <int kItems>
 __global__ __launch_bounds__(64) void level1_count_kernel(BinArgs a)
 {
+    if (a.skip && *a.skip) return;   // the last render's lists hold
     extern __shared__ uint32_t diff[];   // [max_tiles_y + 1][kDiffCopies], sized at launch
     const int lane = threadIdx.x, c = chunk_of_block();
     const int view = c / a.chunks1, part = c % a.chunks1;
@@ -288,6 +289,7 @@ __device__ __forceinline__ void walk_row_band(const uint2* s_p, const uint8_t* s
 template <int kItems>
 __global__ __launch_bounds__(64) void level1_scatter_kernel(BinArgs a)
 {
+    if (a.skip && *a.skip) return;   // the last render's lists hold
     __shared__ uint2 s_p[kItems * 64];
     __shared__ uint8_t s_r[kItems * 64];
     const int lane = threadIdx.x, c = chunk_of_block();
@@ -340,6 +342,7 @@ static_assert(kMaxTotalRows % 1024 == 0, "rows per thread of the chunk table");
 
 __global__ __launch_bounds__(1024) void level2_table_kernel(BinArgs a)
 {
+    if (a.skip && *a.skip) return;   // the last render's lists hold
     __shared__ uint32_t wave_c[16], wave_e[16];
     __shared__ uint32_t s_total_c, s_total_e;
     const int tid = threadIdx.x, rows = a.rows, lane = tid & 63, wave = tid >> 6;
@@ -540,6 +543,7 @@ __device__ __forceinline__ void level2_count_chunk(const BinArgs& a, int c, int 
 template <int kItems>
 __global__ __launch_bounds__(64) void level2_count_kernel(BinArgs a)
 {
+    if (a.skip && *a.skip) return;   // the last render's lists hold
     extern __shared__ uint32_t diff[];   // [max_tiles_x + 1][kDiffCopies], sized at launch: more waves fit
     const int lane = threadIdx.x;
     const int c2 = (int)a.info[kInfoC2];
@@ -631,6 +635,7 @@ __device__ __forceinline__ void level2_scatter_chunk(const BinArgs& a, int c, in
 template <int kItems>
 __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
 {
+    if (a.skip && *a.skip) return;   // the last render's lists hold
     __shared__ uint32_t s_g[kItems * 64];
     __shared__ uint16_t s_x[kItems * 64];
     const int lane = threadIdx.x;
@@ -644,6 +649,7 @@ __global__ __launch_bounds__(64) void level2_scatter_kernel(BinArgs a)
 // K when it is the last.
 __global__ __launch_bounds__(256) void tile_offsets_kernel(BinArgs a)
 {
+    if (a.skip && *a.skip) return;   // the last render's lists hold
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= a.tiles) return;
     const ViewParams& vp = a.views[view_of_tile(a.views, a.n_views, (uint32_t)t)];
@@ -719,7 +725,7 @@ hipError_t launch_bin_rows(const BinArgs& a, uint64_t* scan_scratch, hipStream_t
                            (a.max_tiles_y + 1) * kDiffCopies * sizeof(uint32_t), s, a);
     });
     hipError_t e = launch_scan_exclusive(a.counts1, (int64_t)a.rows * a.chunks1, scan_scratch, nullptr,
-                                         a.rows_off + a.rows, a.overflow, s);
+                                         a.rows_off + a.rows, a.overflow, s, nullptr, a.skip);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(level2_table_kernel, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
@@ -747,7 +753,7 @@ hipError_t launch_bin_tiles(const BinArgs& a, int grid2, uint64_t* scan_scratch,
         });
     // the scan's length E2 is read on the device (info[1])
     hipError_t e = launch_scan_exclusive(a.counts2, (int64_t)a.counts2_capacity, scan_scratch, nullptr,
-                                         a.tile_offsets + a.tiles, a.overflow, s, a.info + kInfoC2Elems);
+                                         a.tile_offsets + a.tiles, a.overflow, s, a.info + kInfoC2Elems, a.skip);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(tile_offsets_kernel, dim3((unsigned)((a.tiles + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -198,10 +198,57 @@ def test_backward_after_kept_lists(renderer):
         assert err < 1e-5, (k, err)
 
 
+def test_graph_replays_keep_the_lists(renderer):
+    """A captured render with the flag: replays of a static camera keep the
+    lists (the decision is taken on the device), a camera change rebuilds
+    them, and every replay matches the eager render of its camera."""
+    import paper_2607_15951_amd as gs
+    import torch
+    W, H = 256, 144
+    sc = scenes.make_scene("C3", n=60_000, seed=78)
+    dev = gs.scene_to_device(sc)
+    cams = [scenes.orbit_camera(a, W, H) for a in (0.0, 0.0, 0.2, 0.2, 0.2)]
+    renderer.render(dev, cams[0], W, H)
+    cap = int(renderer.list_info()["num_pairs"] * 1.5) + 4096
+    gr = renderer.graph(dev, [cams[0]], pair_capacity=cap, reuse_lists=True)
+    outcomes = []
+    try:
+        for k, c in enumerate(cams):
+            gr.set_views([c])
+            if k == 3:
+                dev["sh"].mul_(0.5)   # a colour edit between two replays of one camera
+            gr.launch()
+            torch.cuda.synchronize()
+            outcomes.append(renderer.list_reuse())
+            img = gr.outs[0]["image"].cpu().numpy().view(np.uint32).copy()
+            want = plain(dev, c, W, H)["image"]
+            assert np.array_equal(img, want), f"replay {k}"
+    finally:
+        gr.close()
+    say(f"[lists] graph replays: {outcomes}")
+    assert [o["reused"] for o in outcomes] == [True, True, False, True, True], outcomes
+
+
+def test_capacity_renders_keep_the_lists(renderer):
+    """Renders with one pair capacity compare with each other; the frame of
+    kept lists matches the plain capacity render."""
+    import paper_2607_15951_amd as gs
+    W, H = 200, 120
+    sc = scenes.make_scene("C3", n=30_000, seed=79)
+    dev = gs.scene_to_device(sc)
+    cam = scenes.default_camera(W, H)
+    renderer.render(dev, cam, W, H)
+    cap = int(renderer.list_info()["num_pairs"] * 1.2) + 1024
+    renderer.render(dev, cam, W, H, pair_capacity=cap)
+    got = snapshot(renderer, renderer.render(dev, cam, W, H, pair_capacity=cap, reuse_lists=True))
+    assert renderer.list_reuse() == {"reused": True, "changed": 0}
+    same(got, plain(dev, cam, W, H), "capacity render")
+
+
 def test_list_reuse_is_ignored_when_it_cannot_apply(renderer):
-    """First render of a context, another image size or Gaussian count, a
-    batched render or a pair capacity in between, a pair capacity on the
-    render itself: no comparison is made, and the result is unchanged."""
+    """First render of a context, another image size, Gaussian count or pair
+    capacity, or a batched render in between: no comparison is made, and the
+    result is unchanged."""
     import paper_2607_15951_amd as gs
     W, H = 160, 96
     cam = scenes.default_camera(W, H)
@@ -228,13 +275,11 @@ def test_list_reuse_is_ignored_when_it_cannot_apply(renderer):
     not_compared(renderer.render(b, cam, W, H, reuse_lists=True), b, cam, W, H, "after a batched render")
     cap = int(renderer.list_info()["num_pairs"] * 2) + 4096
     renderer.render(b, cam, W, H, pair_capacity=cap)
-    not_compared(renderer.render(b, cam, W, H, reuse_lists=True), b, cam, W, H, "after a capacity render")
+    not_compared(renderer.render(b, cam, W, H, reuse_lists=True), b, cam, W, H, "capacity lists, then eager")
     renderer.render(b, cam, W, H)
-    out = renderer.render(b, cam, W, H, reuse_lists=True, pair_capacity=cap)
-    with pytest.raises(RuntimeError):
-        renderer.list_reuse()
+    not_compared(renderer.render(b, cam, W, H, reuse_lists=True, pair_capacity=cap), b, cam, W, H,
+                 "eager lists, then a pair capacity")
     # and once the conditions hold again, the lists are kept
     renderer.render(b, cam, W, H)
     renderer.render(b, cam, W, H, reuse_lists=True)
     assert renderer.list_reuse() == {"reused": True, "changed": 0}
-    del out
