@@ -123,18 +123,19 @@ typedef struct {
 /* GS_RENDER_REUSE_LISTS: frame-to-frame reuse of the whole tile lists, the
  * case of Sec. 5.7 (Table 5) where no Gaussian changes its tiles.  The lists
  * of Sec. 3.1 depend only on the depth keys, the tile rectangles and the
- * image size.  When the previous render on the context was a single view of
- * as many Gaussians at the same width, height and pair_capacity (0 included),
- * the projection compares each Gaussian's depth key and rectangle with that
- * render's and counts those that differ.  None (a static camera; colour, SH
+ * image size.  When the previous render on the context rendered as many
+ * Gaussians in as many views of the same widths and heights, with the same
+ * pair_capacity (0 included), the projection compares each (view, Gaussian)
+ * item's depth key and rectangle with that render's and counts those that
+ * differ.  None (a static camera; colour, SH
  * or opacity edits): every kernel of the depth sort and the binning finds
  * that on the device and does nothing, and the blend reads the lists kept
  * in the context, which are the ones this frame would build.  Otherwise the
  * render goes on as usual (with GS_RENDER_REUSE_ORDER, trying the order).
  * The decision needs no host read, so a captured graph can carry the flag.
- * Every output is the same as without the flag.  Ignored for batched renders
- * and for the first render on a context; gs_get_list_reuse reports the
- * outcome. */
+ * Every output is the same as without the flag.  Applies to gs_render,
+ * gs_render_batched and graphs alike; ignored for the first render on a
+ * context; gs_get_list_reuse reports the outcome. */
 #define GS_RENDER_REUSE_LISTS 2u
 
 /* Creates a context on HIP device `device`; *out receives it. */
@@ -387,8 +388,9 @@ gs_status gs_get_order_reuse(gs_context* ctx, uint32_t* out2);
 /* Outcome of the last render's GS_RENDER_REUSE_LISTS comparison (host array
  * of 2, synchronises with that render or graph replay): [0] 1 if no
  * Gaussian's depth key or tile rectangle had changed and the previous lists
- * were kept (sort and binning skipped), else 0; [1] the number of Gaussians
- * whose key or rectangle changed.  GS_ERR_INVALID_ARGUMENT if the last
+ * were kept (sort and binning skipped), else 0; [1] the number of (view,
+ * Gaussian) items whose key or rectangle changed (each view's share
+ * saturating at 2^32 - 1).  GS_ERR_INVALID_ARGUMENT if the last
  * render made no comparison (flag absent, or a render the flag is ignored
  * for). */
 gs_status gs_get_list_reuse(gs_context* ctx, uint32_t* out2);

@@ -358,15 +358,16 @@ class Renderer:
         return out
 
     def render_batched(self, dev_scene: dict, cameras: list, background=(0.0, 0.0, 0.0), pair_capacity: int = 0,
-                       outs=None, want_T: bool = True, want_n_contrib: bool = True, stream=None):
+                       outs=None, want_T: bool = True, want_n_contrib: bool = True, stream=None,
+                       reuse_lists: bool = False):
         """Renders every camera dict of ``cameras`` (each with its own
         width/height) in one gs_render_batched call; returns one output dict
-        per view, as render() does."""
+        per view, as render() does.  reuse_lists: GS_RENDER_REUSE_LISTS."""
         torch = _torch()
         dev = dev_scene["means"].device
         views, outs = self._views(cameras, outs, dev, want_T, want_n_contrib)
         g = make_gaussians(dev_scene)
-        opts = make_opts(background, pair_capacity)
+        opts = make_opts(background, pair_capacity, RENDER_REUSE_LISTS if reuse_lists else 0)
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         self._check(self._L.gs_render_batched(self._ctx, C.byref(g), views, len(cameras), C.byref(opts),
                                               C.c_void_p(s)))

@@ -110,10 +110,11 @@ struct gs_context {
     Tuning last_tuning = kDefaultTuning;  // launch shapes of the last render
     int64_t order_n = -1;     // items of the depth order the sort buffers hold (one view), -1 if none
     bool last_reuse = false;  // the last render started from the previous order
-    // the tile lists in the workspace: those of a one-view render of lists_n
-    // Gaussians at lists_w x lists_h with pair capacity lists_cap (0: eager)
+    // the tile lists in the workspace: those of a render of lists_n Gaussians
+    // in views of the sizes lists_sizes (width, height per view) with pair
+    // capacity lists_cap (0: eager)
     int64_t lists_n = -1;
-    int lists_w = 0, lists_h = 0;
+    std::vector<int> lists_sizes;
     uint64_t lists_cap = 0;
     bool lists_compared = false;   // the last render compared keys and rectangles with its predecessor's
     std::vector<int> cost_layout;   // tiles_x, tiles_y of every view whose work ws.tile_cost holds
@@ -243,6 +244,12 @@ gs_status validate(gs_context* ctx, const gs_gaussians* g, const gs_camera* cam,
 // kViewsPerLaunch views (kernel arguments are copied at launch, so the host
 // array can be reused at once and the upload stays on the compute queue).
 constexpr int kViewsPerLaunch = 16;
+// counters[kCounterChanged]: the projection's count of (view, Gaussian)
+// items whose depth key or rectangle differ from the last render's (list
+// reuse), and after it the flag that none did: set to 1 at frame set-up when
+// the comparison runs, cleared by any view that finds a change
+constexpr int kCounterChanged = 2;
+
 struct ViewBatch {
     ViewParams v[kViewsPerLaunch];
 };
@@ -260,9 +267,9 @@ __global__ void write_views_kernel(ViewBatch b, int count, ViewParams* dst)
 // overflow counters cleared, the view table written (when `write`) and the
 // tiles_x of every global tile row, all from the views in the arguments.
 __global__ void frame_setup_kernel(ViewBatch b, int count, ViewParams* dst, int write, uint32_t* counters,
-                                   uint32_t* row_tiles_x, int rows)
+                                   uint32_t* row_tiles_x, int rows, uint32_t hold_init)
 {
-    if (threadIdx.x < 16) counters[threadIdx.x] = 0u;
+    if (threadIdx.x < 16) counters[threadIdx.x] = threadIdx.x == kCounterChanged + 1 ? hold_init : 0u;
     if (write) {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(&b.v[0]);
         uint32_t* out = reinterpret_cast<uint32_t*>(dst);
@@ -301,11 +308,6 @@ __global__ void pack_readback_kernel(const uint32_t* view_counts, int n_vc, cons
     }
     __threadfence_system();   // out may be pinned host memory, read by the host after the frame's event
 }
-
-// counters[kCounterChanged]: the projection's count of Gaussians whose depth
-// key or rectangle differ from the last render's (list reuse), and after it
-// the flag that none did
-constexpr int kCounterChanged = 2;
 
 __global__ void row_table_kernel(const ViewParams* views, int n_views, uint32_t* row_tiles_x, int rows)
 {
@@ -401,6 +403,20 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     if (tu.blend_group == 0)
         if ((st = ensure(ctx, w.tile_order, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
     const bool order_in_project = tu.blend_group == 0 && history && n > 0;
+    // list reuse: the workspace holds the lists of a render of as many
+    // Gaussians in views of the same sizes, with the same pair capacity (a
+    // capacity that truncated them truncates an identical frame's the same
+    // way); the projection counts the items whose depth key or rectangle
+    // changed since, and when none did those lists are this frame's (they
+    // depend on nothing else): the sort and the binning then skip on the
+    // device
+    std::vector<int> sizes;
+    for (const ViewParams& v : hv) {
+        sizes.push_back(v.width);
+        sizes.push_back(v.height);
+    }
+    const bool try_lists = !noalloc && (o.flags & GS_RENDER_REUSE_LISTS) && n > 0 && prev_lists_n == n &&
+                           ctx->lists_sizes == sizes && ctx->lists_cap == o.pair_capacity;
 
     ViewParams* views = static_cast<ViewParams*>(w.views.p);
     uint32_t* counters = static_cast<uint32_t*>(w.counters.p);
@@ -409,9 +425,10 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
         ViewBatch b;
         std::memcpy(b.v, hv.data(), (size_t)V * sizeof(ViewParams));
         hipLaunchKernelGGL(frame_setup_kernel, dim3(1), dim3(256), 0, s, b, V, views, write_table ? 1 : 0, counters,
-                           static_cast<uint32_t*>(w.row_tiles_x.p), rows);
+                           static_cast<uint32_t*>(w.row_tiles_x.p), rows, try_lists ? 1u : 0u);
     } else {
         HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
+        if (try_lists) HIP_TRY(launch_fill_u32(counters + kCounterChanged + 1, 1u, 1, s), "list reuse flag");
         if (write_table) HIP_TRY(write_view_table(hv, views, s), "view table");
         hipLaunchKernelGGL(row_table_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s,
                            (const ViewParams*)views, V, static_cast<uint32_t*>(w.row_tiles_x.p), rows);
@@ -425,9 +442,6 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     // projection counts the Gaussians whose depth key or rectangle changed
     // since, and when none did those lists are this frame's (they depend on
     // nothing else): the sort and the binning then skip on the device
-    const bool try_lists = !noalloc && (o.flags & GS_RENDER_REUSE_LISTS) && V == 1 && n > 0 && prev_lists_n == n &&
-                           ctx->lists_w == hv[0].width && ctx->lists_h == hv[0].height &&
-                           ctx->lists_cap == o.pair_capacity;
 
     ProjectArgs pa{};
     pa.n = n;
@@ -675,12 +689,9 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     ctx->last_tuning = tu;
     ctx->order_n = (V == 1 && in_b) ? n : -1;
     ctx->last_reuse = reuse;
-    if (V == 1) {
-        ctx->lists_n = n;
-        ctx->lists_w = hv[0].width;
-        ctx->lists_h = hv[0].height;
-        ctx->lists_cap = o.pair_capacity;
-    }
+    ctx->lists_n = n;
+    ctx->lists_sizes = sizes;
+    ctx->lists_cap = o.pair_capacity;
     ctx->last_views = hv;
     ctx->last_g = *g;
     for (int k = 0; k < 3; ++k) ctx->last_bg[k] = bl.bg[k];

@@ -98,11 +98,11 @@ struct ProjectArgs {
     const uint32_t* order_cost;
     uint32_t* order;
     int64_t order_tiles;
-    // when not null (one view): before its own stores each item compares its
-    // depth key and rectangle with the values the buffers hold (the last
-    // render's); changed[0] receives the number that differ and changed[1]
-    // is 1 when none did (the previous lists hold: the skip flag of the sort
-    // and the binning), else 0
+    // when not null: before its own stores each item compares its depth key
+    // and rectangle with the values the buffers hold (the last render's);
+    // the number that differ is added to changed[0] (zero before the launch)
+    // and any difference clears changed[1] (one before the launch: the skip
+    // flag of the sort and the binning while the previous lists hold)
     uint32_t* changed;
 };
 

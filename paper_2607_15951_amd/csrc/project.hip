@@ -592,8 +592,9 @@ void launch_project_backward_dt(const ProjectBackArgs& a, unsigned blocks, hipSt
 
 // Per view (one block each): Gaussians on screen, pairs and Gaussians with a
 // depth key (past the culls), summed over the projection blocks' partials.
-// With changed (one view), also the items whose key or rectangle changed,
-// clamped to 2^32 - 1, and whether none did.
+// With changed, also the items whose key or rectangle changed (added over
+// the views; each view's share clamped to 2^32 - 1), clearing the flag that
+// none did when any did.
 __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* __restrict__ partials, int blocks,
                                                                int n_views, uint32_t* view_counts, uint32_t* changed)
 {
@@ -636,9 +637,11 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const uint32_t* _
         c[1] = (uint32_t)tf;
         c[2] = (uint32_t)tp;
         c[3] = (uint32_t)(tp >> 32);
-        if (changed) {
-            changed[0] = tc > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tc;
-            changed[1] = tc == 0 ? 1u : 0u;
+        if (changed && tc > 0) {
+            // views add their counts; any change clears the flag (all
+            // writers store the same 0)
+            atomicAdd(&changed[0], tc > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tc);
+            changed[1] = 0u;
         }
     }
 }
@@ -686,7 +689,7 @@ hipError_t launch_project(const ProjectArgs& a, hipStream_t s)
     }
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)a.n_views), dim3(1024), 0, s,
                        (const uint32_t*)a.partials, (int)blocks, a.n_views, a.view_counts,
-                       a.n_views == 1 ? a.changed : nullptr);
+                       a.changed);
     return hipGetLastError();
 }
 

@@ -229,6 +229,36 @@ def test_graph_replays_keep_the_lists(renderer):
     assert [o["reused"] for o in outcomes] == [True, True, False, True, True], outcomes
 
 
+def test_batched_views_keep_the_lists(renderer):
+    """A batched render of three views of different sizes: unchanged views
+    keep all lists, one moved camera rebuilds them, and every view matches its
+    plain single render."""
+    import paper_2607_15951_amd as gs
+    sc = scenes.make_scene("C3", n=40_000, seed=80)
+    dev = gs.scene_to_device(sc)
+    sizes = [(160, 96), (256, 144), (96, 200)]
+    cams = [scenes.orbit_camera(20.0 * k, w, h) for k, (w, h) in enumerate(sizes)]
+    renderer.render_batched(dev, cams)
+    outcomes = []
+    for step, moved in ((0, False), (1, True), (2, False)):
+        if moved:
+            w, h = sizes[1]
+            cams[1] = scenes.orbit_camera(20.5, w, h)
+        dev["sh"].mul_(0.9)
+        outs = renderer.render_batched(dev, cams, reuse_lists=True)
+        outcomes.append(renderer.list_reuse())
+        for k, (c, o) in enumerate(zip(cams, outs)):
+            w, h = sizes[k]
+            want = plain(dev, c, w, h)
+            got = o["image"].cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, want["image"]), f"step {step} view {k}: image"
+            assert np.array_equal(o["n_contrib"].cpu().numpy(), want["nc"]), f"step {step} view {k}: n_contrib"
+    say(f"[lists] batched: {outcomes}")
+    assert outcomes[0] == {"reused": True, "changed": 0}
+    assert not outcomes[1]["reused"] and outcomes[1]["changed"] > 0
+    assert outcomes[2] == {"reused": True, "changed": 0}
+
+
 def test_capacity_renders_keep_the_lists(renderer):
     """Renders with one pair capacity compare with each other; the frame of
     kept lists matches the plain capacity render."""
@@ -246,9 +276,9 @@ def test_capacity_renders_keep_the_lists(renderer):
 
 
 def test_list_reuse_is_ignored_when_it_cannot_apply(renderer):
-    """First render of a context, another image size, Gaussian count or pair
-    capacity, or a batched render in between: no comparison is made, and the
-    result is unchanged."""
+    """First render of a context, another image size, Gaussian count, pair
+    capacity or view count in between: no comparison is made, and the result
+    is unchanged."""
     import paper_2607_15951_amd as gs
     W, H = 160, 96
     cam = scenes.default_camera(W, H)
