@@ -672,6 +672,9 @@ def main():
     ap.add_argument("--tuning", metavar="SORT,ROW,TILE,GROUP[,BATCH]",
                     help="launch shapes to use instead of autotuning (sort_items, bin_row_items, bin_tile_items, "
                          "blend_tile_group, blend_batch)")
+    ap.add_argument("--reuse-lists", action="store_true",
+                    help="with --frames-only: render with GS_RENDER_REUSE_LISTS (the first frame builds the lists, "
+                         "the others keep them)")
     ap.add_argument("--frames-only", type=int, metavar="F",
                     help="render F frames of the workload (after one warm-up frame) and nothing else, for "
                          "per-frame counter totals; prints one JSON line")
@@ -727,7 +730,7 @@ def main():
     main_tuning = r.tuning()   # the shapes of the timed frames (later variants retune)
     if args.frames_only:
         for _ in range(args.frames_only + 1):
-            r.render(dev, cam, W, H, out=out)
+            r.render(dev, cam, W, H, out=out, reuse_lists=args.reuse_lists)
         torch.cuda.synchronize()
         r.close()
         print(json.dumps({"frames": args.frames_only + 1, "workload": args.workload, "tuning": main_tuning}),
