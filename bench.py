@@ -566,8 +566,28 @@ def time_batched_backward(r, dev, cams, steps: int) -> dict:
     e1.record()
     torch.cuda.synchronize()
     ms_bwd = e0.elapsed_time(e1) / bsteps
+    # the same step, render (with a pair capacity 25% above this batch's K)
+    # and backward, captured into one graph and replayed: one launch per step
+    cap = int(r.list_info()["num_pairs"] * 1.25) + 1024
+    o2 = r.render_batched(dev, cams, pair_capacity=cap)
+    r.backward(dev, gi, gt)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        r.render_batched(dev, cams, pair_capacity=cap, outs=o2)
+        r.backward(dev, gi, gt)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(bsteps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / bsteps
+    del graph
     return {"views": len(cams), "ms_forward_backward": round(ms_step, 3), "ms_backward": round(ms_bwd, 3),
-            "views_per_s_forward_backward": round(len(cams) * 1e3 / ms_step, 1), "steps": bsteps}
+            "views_per_s_forward_backward": round(len(cams) * 1e3 / ms_step, 1),
+            "ms_forward_backward_graph": round(ms_graph, 3),
+            "views_per_s_forward_backward_graph": round(len(cams) * 1e3 / ms_graph, 1), "steps": bsteps}
 
 
 def time_reuse(r, dev, W: int, H: int, frames: int = 16) -> dict:
