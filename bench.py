@@ -639,8 +639,8 @@ def time_list_reuse(r, dev, cam, W: int, H: int, frames: int = 20) -> dict:
     alternate between two sets, the geometry stays): frame time with
     GS_RENDER_REUSE_LISTS, which keeps the lists when no depth key or tile
     rectangle changed, against plain renders of the same frames, and how many
-    frames kept their lists.  Then one orbit step per frame, where the lists
-    cannot hold: the cost of the comparison and of its host wait."""
+    frames kept their lists; the same from a captured graph.  Then one orbit
+    step per frame, where the lists cannot hold: the cost of the comparison."""
     import torch
     import scenes
     dev_b = dict(dev)
@@ -664,6 +664,21 @@ def time_list_reuse(r, dev, cam, W: int, H: int, frames: int = 20) -> dict:
         kept += r.list_reuse()["reused"]
     res["frames_kept"] = int(kept)
     res["frames"] = frames
+    # the same static camera replayed from a captured graph (pair capacity
+    # 1.1 K), with and without the flag: the decision is taken on the device
+    cap = int(r.list_info()["num_pairs"] * 1.1)
+    for reuse in (True, False):
+        gr = r.graph(dev, [cam], pair_capacity=cap, reuse_lists=reuse)
+        gr.launch()
+        gr.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(frames):
+            gr.launch()
+        torch.cuda.synchronize()
+        res["graph_ms_per_frame_reuse" if reuse else "graph_ms_per_frame_plain"] = round(
+            (time.perf_counter() - t0) * 1e3 / frames, 4)
+        gr.close()
     cams = [scenes.orbit_camera(0.01 * f, W, H) for f in range(frames + 1)]
     for reuse in (True, False):
         r.render(dev, cams[0], W, H, out=o)

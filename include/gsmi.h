@@ -236,7 +236,10 @@ gs_status gs_render_batched(gs_context* ctx, const gs_gaussians* g, const gs_vie
  * and sizes as at creation) by a small upload on `stream`; the next launch
  * renders them.
  * gs_graph_launch enqueues one render on `stream`; an overflow of
- * pair_capacity is reported by gs_get_list_info after it.
+ * pair_capacity is reported by gs_get_list_info after it.  The flags of
+ * opts act in every replay (their decisions are taken on the device):
+ * GS_RENDER_REUSE_LISTS keeps the lists of the previous replay when no depth
+ * key or rectangle changed.
  * gs_graph_destroy releases the graph and frees the context (NULL-safe). */
 typedef struct gs_graph gs_graph;
 gs_status gs_graph_create(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
