@@ -707,6 +707,9 @@ def main():
     ap.add_argument("--tuning", metavar="SORT,ROW,TILE,GROUP[,BATCH]",
                     help="launch shapes to use instead of autotuning (sort_items, bin_row_items, bin_tile_items, "
                          "blend_tile_group, blend_batch)")
+    ap.add_argument("--batched", action="store_true",
+                    help="with --frames-only: render all cameras of the workload in one gs_render_batched call "
+                         "per frame (C4: 64 views)")
     ap.add_argument("--reuse-lists", action="store_true",
                     help="with --frames-only: render with GS_RENDER_REUSE_LISTS (the first frame builds the lists, "
                          "the others keep them)")
@@ -764,8 +767,13 @@ def main():
         log("[bench] tuning " + json.dumps(tune["tuning"]))
     main_tuning = r.tuning()   # the shapes of the timed frames (later variants retune)
     if args.frames_only:
+        cams_all = scenes.make_cameras(args.workload) if args.batched else None
+        outs = r.render_batched(dev, cams_all) if args.batched else None
         for _ in range(args.frames_only + 1):
-            r.render(dev, cam, W, H, out=out, reuse_lists=args.reuse_lists)
+            if args.batched:
+                r.render_batched(dev, cams_all, outs=outs, reuse_lists=args.reuse_lists)
+            else:
+                r.render(dev, cam, W, H, out=out, reuse_lists=args.reuse_lists)
         torch.cuda.synchronize()
         r.close()
         print(json.dumps({"frames": args.frames_only + 1, "workload": args.workload, "tuning": main_tuning}),
