@@ -186,18 +186,23 @@ blend_kernel(BlendArgs a, uint64_t capacity)
             if (__ballot(!done) == 0) break;   // whole wave finished
             const uint64_t word = bits[j0 >> 6] >> (j0 & 63);
             if ((word & kGroupMask) == 0) continue;   // none of the next kUnroll reaches the quad
+            // the group's LDS byte offset in a VGPR: every entry below reads
+            // at a constant offset from it (no per-entry address move)
+            uint32_t gofs = (uint32_t)j0 * (uint32_t)sizeof(float4);
+            __asm__ volatile("" : "+v"(gofs));
+            const char* g0 = reinterpret_cast<const char*>(s0) + gofs;
+            const char* g1 = reinterpret_cast<const char*>(s1) + gofs;
+            const char* g2 = reinterpret_cast<const char*>(s2) + gofs;
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int j = j0 + u;
                 // an entry out of this quad's reach is skipped by the whole wave
                 if (!((word >> u) & 1u)) continue;
                 if (kStats) ++bodies;
-                const float4 e0 = s0[j];
-                const float4 e1 = s1[j];
-                const float4 e2 = s2[j];
+                const float4 e0 = reinterpret_cast<const float4*>(g0)[u];
+                const float4 e1 = reinterpret_cast<const float4*>(g1)[u];
+                const float4 e2 = reinterpret_cast<const float4*>(g2)[u];
                 float dx, dy, E;
                 const float al = entry_alpha(e0, e1, fx, fy, dx, dy, E);
-                const float wt = al * Tr;
                 const float tn = fmaf(-al, Tr, Tr);   // Tr (1 - al), rounded once
                 const bool pass = al >= 1.0f / 255.0f;
                 const bool stop = pass && tn < 1e-4f && !done;
@@ -205,12 +210,14 @@ blend_kernel(BlendArgs a, uint64_t capacity)
                 const uint32_t pos1 = (uint32_t)__float_as_int(e2.w);   // list position + 1
                 if (kStats) term = stop ? pos1 : term;
                 done = done || stop;
-                const float wgt = take ? wt : 0.0f;
-                c0 = fmaf(wgt, e2.x, c0);
-                c1 = fmaf(wgt, e2.y, c1);
-                c2 = fmaf(wgt, e2.z, c2);
-                Tr = take ? tn : Tr;
-                last = take ? pos1 : last;
+                if (take) {   // under the lane mask: no selects
+                    const float wt = al * Tr;
+                    c0 = fmaf(wt, e2.x, c0);
+                    c1 = fmaf(wt, e2.y, c1);
+                    c2 = fmaf(wt, e2.z, c2);
+                    Tr = tn;
+                    last = pos1;
+                }
                 if (kStats) composited += take ? 1u : 0u;
             }
         }
