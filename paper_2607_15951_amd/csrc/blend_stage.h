@@ -26,14 +26,16 @@ __device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, 
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         const float xe = xs[e];
-        const float y = fminf(y1, fmaxf(y0, -bc * xe));
+        // clamp to [y0, y1] as one median-of-three (finite operands: the
+        // same value as min(y1, max(y0, .)))
+        const float y = __builtin_amdgcn_fmed3f(-bc * xe, y0, y1);
         const float qe = A * xe * xe + 2.0f * B * xe * y + C * y * y;
         if (qe < q) {
             q = qe;
             S = A * xe * xe + 2.0f * fabsf(B * xe * y) + C * y * y;
         }
         const float ye = ys[e];
-        const float x = fminf(x1, fmaxf(x0, -ba * ye));
+        const float x = __builtin_amdgcn_fmed3f(-ba * ye, x0, x1);
         const float qf = A * x * x + 2.0f * B * x * ye + C * ye * ye;
         if (qf < q) {
             q = qf;
