@@ -11,17 +11,19 @@ constexpr float kLog2e = 1.4426950408889634f;
 
 // Smallest value of the quadratic form A x^2 + 2 B x y + C y^2 (positive
 // definite) over the box [x0, x0 + 7] x [y0, y0 + 7] of pixel offsets, made a
-// lower bound by subtracting 1e-5 of the size of its terms.  The form is
-// convex, so its minimum is 0 when the origin lies in the box and on an edge
-// otherwise; on an edge it is a 1D quadratic minimised in closed form, at
-// y = -(B / C) x or x = -(B / A) y (bc = B / C and ba = B / A, computed once
-// per entry: the rounding of the minimiser moves the value by a term
-// quadratic in that rounding, far inside the margin).
+// lower bound by subtracting 1e-5 of a bound on the size of its terms over
+// the box (2 |B x y| <= |B| (x^2 + y^2)), which covers the float rounding of
+// every evaluation.  The form is convex, so its minimum is 0 when the origin
+// lies in the box and on an edge otherwise; on an edge it is a 1D quadratic
+// minimised in closed form, at y = -(B / C) x or x = -(B / A) y (bc = B / C
+// and ba = B / A, computed once per entry: the rounding of the minimiser
+// moves the value by a term quadratic in that rounding, far inside the
+// margin).
 __device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, float B, float C, float bc, float ba)
 {
     const float x1 = x0 + 7.0f, y1 = y0 + 7.0f;
     if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return 0.0f;
-    float q = INFINITY, S = 0.0f;
+    float q = INFINITY;
     const float xs[2] = {x0, x1}, ys[2] = {y0, y1};
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -29,19 +31,13 @@ __device__ __forceinline__ float quad_min_over_box(float x0, float y0, float A, 
         // clamp to [y0, y1] as one median-of-three (finite operands: the
         // same value as min(y1, max(y0, .)))
         const float y = __builtin_amdgcn_fmed3f(-bc * xe, y0, y1);
-        const float qe = A * xe * xe + 2.0f * B * xe * y + C * y * y;
-        if (qe < q) {
-            q = qe;
-            S = A * xe * xe + 2.0f * fabsf(B * xe * y) + C * y * y;
-        }
+        q = fminf(q, A * xe * xe + 2.0f * B * xe * y + C * y * y);
         const float ye = ys[e];
         const float x = __builtin_amdgcn_fmed3f(-ba * ye, x0, x1);
-        const float qf = A * x * x + 2.0f * B * x * ye + C * ye * ye;
-        if (qf < q) {
-            q = qf;
-            S = A * x * x + 2.0f * fabsf(B * x * ye) + C * ye * ye;
-        }
+        q = fminf(q, A * x * x + 2.0f * B * x * ye + C * ye * ye);
     }
+    const float ab = fabsf(B);
+    const float S = (A + ab) * fmaxf(x0 * x0, x1 * x1) + (C + ab) * fmaxf(y0 * y0, y1 * y1);
     return q - 1e-5f * (S + 1.0f);
 }
 
@@ -63,11 +59,18 @@ __device__ __forceinline__ uint32_t stage_entry(const float4& ra, const float4& 
     // the minimisers' slopes need no correct rounding (see quad_min_over_box):
     // a hardware reciprocal, not two divisions
     const float bc = rb.y * __builtin_amdgcn_rcpf(rb.z), ba = rb.y * __builtin_amdgcn_rcpf(rb.x);
+    // opacity * exp(-q / 2) >= 1/255 where q <= 2 ln(255 opacity): one log
+    // per entry instead of an exp per quad, with a margin (1e-4 of the
+    // threshold's size) that covers the 1e-5 relative margin on alpha, the
+    // fast log's error and the per-pixel exp2's, so no quad a pixel reaches
+    // is dropped
+    const float lt = 2.0f * __logf(255.0f * rb.w);
+    const float thr = lt + 1e-4f * (1.0f + fabsf(lt));
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const float qmin = quad_min_over_box(du_hi - (float)((q & 1) * 8 + 7), dv_hi - (float)((q >> 1) * 8 + 7), rb.x,
                                              rb.y, rb.z, bc, ba);
-        if (rb.w * __expf(-0.5f * qmin) >= (1.0f / 255.0f) * (1.0f - 1e-5f)) qmask |= 1u << q;
+        if (qmin <= thr) qmask |= 1u << q;
     }
     v0 = make_float4(du_hi, dv_hi, (float)(du - (double)du_hi), (float)(dv - (double)dv_hi));
     v1 = make_float4(-0.5f * kLog2e * rb.x, -kLog2e * rb.y, -0.5f * kLog2e * rb.z, rb.w);
