@@ -163,6 +163,7 @@ KERNEL_SOURCES = {
     "level1_scatter_kernel": ["tile_bin.hip", "gs_internal.h"],
     "level2_scatter_kernel": ["tile_bin.hip", "gs_internal.h"],
     "blend_kernel": ["blend.hip", "blend_stage.h", "gs_internal.h"],
+    "blend_queue_kernel": ["blend.hip", "blend_stage.h", "gs_internal.h"],
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt")
 
@@ -178,6 +179,8 @@ def stage_kernel(stage: str, dtype: int, deg: int, tuning: dict) -> str:
     if stage == "bin_tile_scatter":
         return f"level2_scatter_kernel<{tuning['bin_tile_items']}>"
     if stage == "blend":
+        if tuning["blend_tile_group"] < 0:   # the persistent grid over the work queue
+            return f"blend_queue_kernel<{tuning['blend_batch']}>"
         return f"blend_kernel<false, {tuning['blend_batch']}>"
     raise KeyError(stage)
 

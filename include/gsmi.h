@@ -415,8 +415,12 @@ gs_status gs_get_list_reuse(gs_context* ctx, uint32_t* out2);
  *                     render on the context when it had the same tile
  *                     layout, else by list length -- the frame-to-frame
  *                     coherence of Sec. 5.7 applied to the load imbalance of
- *                     the per-tile blend (Sec. 6); the backward follows its
- *                     render's order
+ *                     the per-tile blend (Sec. 6); or -1: the same order
+ *                     as a work queue over the (view, tile) items of all
+ *                     views, drained by a persistent grid of as many
+ *                     workgroups as the device holds at once, each taking
+ *                     the next item from an atomic head when it finishes
+ *                     one; the backward follows its render's order
  *   blend_batch       list entries the blend stages from HBM into on-chip
  *                     memory per batch: 128, 256 or 512 (the backward
  *                     stages 256)
@@ -447,12 +451,12 @@ gs_status gs_get_tuning(gs_context* ctx, gs_tuning* out);
  *   out_ms  NULL, or host array [GS_TUNE_CANDIDATES]: the mean scored time
  *           of every candidate in the order sort_items 4, 8, 16;
  *           bin_row_items 4, 8, 16; bin_tile_items 8, 16, 32;
- *           blend_tile_group 0, 1, 2, 4, 8, 16, 32, 64; blend_batch 128,
+ *           blend_tile_group -1, 0, 1, 2, 4, 8, 16, 32, 64; blend_batch 128,
  *           256, 512
  * Profiling flags are restored afterwards.  Errors as gs_render_batched,
  * GS_ERR_INVALID_ARGUMENT for reps outside [1, 1000] or a context bound to a
  * graph; on error the tuning is left as it was. */
-#define GS_TUNE_CANDIDATES 20
+#define GS_TUNE_CANDIDATES 21
 gs_status gs_autotune(gs_context* ctx, const gs_gaussians* g, const gs_view* views, int32_t n_views,
                       const gs_render_opts* opts, int32_t reps, void* stream, gs_tuning* out, float* out_ms);
 

@@ -72,7 +72,7 @@ class gs_tuning(C.Structure):
 
 
 TUNE_CANDIDATES = [("sort_items", v) for v in (4, 8, 16)] + [("bin_row_items", v) for v in (4, 8, 16)] + \
-    [("bin_tile_items", v) for v in (8, 16, 32)] + [("blend_tile_group", v) for v in (0, 1, 2, 4, 8, 16, 32, 64)] + \
+    [("bin_tile_items", v) for v in (8, 16, 32)] + [("blend_tile_group", v) for v in (-1, 0, 1, 2, 4, 8, 16, 32, 64)] + \
     [("blend_batch", v) for v in (128, 256, 512)]
 
 

@@ -249,6 +249,8 @@ constexpr int kViewsPerLaunch = 16;
 // reuse), and after it the flag that none did: set to 1 at frame set-up when
 // the comparison runs, cleared by any view that finds a change
 constexpr int kCounterChanged = 2;
+// counters[kCounterBlendQueue]: head of the blend's work queue (blend_group -1)
+constexpr int kCounterBlendQueue = 4;
 
 struct ViewBatch {
     ViewParams v[kViewsPerLaunch];
@@ -389,7 +391,7 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     if ((st = ensure(ctx, w.counters, 64)) != GS_OK) return st;
     if ((st = ensure(ctx, w.tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
     // every blend records its tiles' work; with blend_group 0 it is dispatched
-    // heaviest first, by the last render's work when that render had the same
+    // (with -1 queued for a persistent grid) heaviest first, by the last render's work when that render had the same
     // tile layout (the history: ordered by one extra workgroup of the
     // projection launch), else by list length (ordered before the blend)
     std::vector<int> layout;
@@ -400,9 +402,9 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     const void* cost_before = w.tile_cost.p;
     if ((st = ensure(ctx, w.tile_cost, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
     const bool history = !noalloc && cost_before == w.tile_cost.p && ctx->cost_layout == layout;
-    if (tu.blend_group == 0)
+    if (tu.blend_group <= 0)
         if ((st = ensure(ctx, w.tile_order, (size_t)std::max<int64_t>(T, 1) * 4)) != GS_OK) return st;
-    const bool order_in_project = tu.blend_group == 0 && history && n > 0;
+    const bool order_in_project = tu.blend_group <= 0 && history && n > 0;
     // list reuse: the workspace holds the lists of a render of as many
     // Gaussians in views of the same sizes, with the same pair capacity (a
     // capacity that truncated them truncates an identical frame's the same
@@ -651,12 +653,15 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     }
     bl.tile_cost = static_cast<uint32_t*>(w.tile_cost.p);
     bl.order = nullptr;
-    if (tu.blend_group == 0) {
+    bl.queue = nullptr;
+    if (tu.blend_group <= 0) {
         uint32_t* order = static_cast<uint32_t*>(w.tile_order.p);
         // ordered by the projection's extra workgroup, or here by list length
         if (!order_in_project)
             HIP_TRY(launch_blend_order(nullptr, bl.tile_offsets, T, order, s), "blend order");
         bl.order = order;
+        // the queue head was cleared with the frame's counters
+        if (tu.blend_group < 0) bl.queue = counters + kCounterBlendQueue;
     }
     HIP_TRY(launch_blend(bl, capacity, s), "blend");
     STAGE_MARK(8);
@@ -1109,7 +1114,7 @@ gs_status gs_render_backward(gs_context* ctx, const gs_gaussians* g, const float
     bb.tiles = ctx->tiles;
     bb.group = ctx->last_tuning.blend_group;
     // the forward's dispatch order (its buffer is rewritten only by a forward)
-    bb.order = bb.group == 0 ? static_cast<const uint32_t*>(ctx->ws.tile_order.p) : nullptr;
+    bb.order = bb.group <= 0 ? static_cast<const uint32_t*>(ctx->ws.tile_order.p) : nullptr;
     for (int k = 0; k < 3; ++k) bb.bg[k] = ctx->last_bg[k];
     bb.grad2d = grad2d;
     HIP_TRY(launch_blend_backward(bb, ctx->capacity, s), "blend backward");
@@ -1307,7 +1312,7 @@ gs_tuning to_abi(const Tuning& t)
 // into the GS_NUM_STAGES stage times).
 struct TuneParam {
     int Tuning::*field;
-    int values[8];
+    int values[9];
     int count;
     int stage_lo, stage_hi;   // stages [lo, hi]
 };
@@ -1315,7 +1320,7 @@ const TuneParam kTuneParams[] = {
     {&Tuning::sort_items, {4, 8, 16}, 3, 1, 1},
     {&Tuning::bin1_items, {4, 8, 16}, 3, 2, 5},
     {&Tuning::bin2_items, {8, 16, 32}, 3, 2, 5},
-    {&Tuning::blend_group, {0, 1, 2, 4, 8, 16, 32, 64}, 8, 6, 6},
+    {&Tuning::blend_group, {-1, 0, 1, 2, 4, 8, 16, 32, 64}, 9, 6, 6},
     {&Tuning::blend_batch, {128, 256, 512}, 3, 6, 6},
 };
 
@@ -1328,7 +1333,7 @@ gs_status gs_set_tuning(gs_context* ctx, const gs_tuning* tuning)
     if (!tuning_supported(t))
         return fail(ctx, GS_ERR_INVALID_ARGUMENT,
                     "unsupported tuning: sort_items and bin_row_items take 4, 8 or 16, bin_tile_items 8, 16 or 32, "
-                    "blend_tile_group 0..64, blend_batch 128, 256 or 512");
+                    "blend_tile_group -1..64, blend_batch 128, 256 or 512");
     ctx->tuning = t;
     return GS_OK;
 }

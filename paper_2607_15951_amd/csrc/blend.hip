@@ -52,26 +52,37 @@ constexpr uint64_t kGroupMask = kUnroll == 64 ? ~0ull : ((1ull << kUnroll) - 1ul
 template <int kBatch>
 constexpr int blend_waves() { return kBatch == 256 ? 7 : (kBatch == 128 ? 6 : 4); }
 
+// The LDS of one tile's walk (one instance per workgroup).
+template <int kBatch>
+struct BlendLds {
+    float4 s0[kBatch + kUnroll];   // du_hi, dv_hi, du_lo, dv_lo  (centre - tile origin)
+    float4 s1[kBatch + kUnroll];   // A', B', C', opacity  (A' = -0.5 log2(e) A, ...)
+    float4 s2[kBatch + kUnroll];   // r, g, b, list position (int bits)
+    uint32_t s_mask[kBatch + kUnroll];   // quads (waves) the entry can reach
+    uint32_t s_wave_keep[4 * (kBatch > 256 ? kBatch / 256 : 1)];
+    unsigned long long s_ev[4], s_co[4];   // tracing only
+    uint32_t s_bodies[4];
+};
+
 // kStats: the tracing variant, which also records its work per tile
-// (a.tile_work); it keeps the compiler's own register budget, where its
-// counters need no spills.  kBatch: list entries staged per batch (128, 256
-// or 512; an autotuner choice): each lane stages the entries tid, tid + 256
-// of the batch that exist, so 128 leaves half the lanes out of the staging.
-// The image does not depend on it; a smaller batch stages fewer entries past
-// the point where every pixel has terminated, a larger one fewer barriers.
+// (a.tile_work).  kBatch: list entries staged per batch (128, 256 or 512; an
+// autotuner choice): each lane stages the entries tid, tid + 256 of the batch
+// that exist, so 128 leaves half the lanes out of the staging.  The image
+// does not depend on it; a smaller batch stages fewer entries past the point
+// where every pixel has terminated, a larger one fewer barriers.  Called by
+// all 256 threads of the workgroup with the same tile; the LDS is free again
+// once every thread has returned.
 template <bool kStats, int kBatch>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 : blend_waves<kBatch>()))) void
-blend_kernel(BlendArgs a, uint64_t capacity)
+__device__ __forceinline__ void blend_tile_walk(const BlendArgs& a, uint64_t capacity, int tile, BlendLds<kBatch>& L)
 {
     constexpr int kPer = kBatch > 256 ? kBatch / 256 : 1;   // entries a lane stages per batch
     constexpr int kWords = kBatch / 64;                     // 64-entry mask words of a batch
     static_assert(kBatch == 128 || kBatch == 256 || kBatch == 512, "batch of 128, 256 or 512 entries");
-    __shared__ float4 s0[kBatch + kUnroll];   // du_hi, dv_hi, du_lo, dv_lo  (centre - tile origin)
-    __shared__ float4 s1[kBatch + kUnroll];   // A', B', C', opacity  (A' = -0.5 log2(e) A, ...)
-    __shared__ float4 s2[kBatch + kUnroll];   // r, g, b, list position (int bits)
-    __shared__ uint32_t s_mask[kBatch + kUnroll];   // quads (waves) the entry can reach
-    __shared__ uint32_t s_wave_keep[4 * kPer];
-    const int tile = blend_tile(a.order, a.group);
+    float4* s0 = L.s0;
+    float4* s1 = L.s1;
+    float4* s2 = L.s2;
+    uint32_t* s_mask = L.s_mask;
+    uint32_t* s_wave_keep = L.s_wave_keep;
     if (tile >= a.tiles) return;
     // the view owning this global tile: its size, tile grid and outputs
     const ViewParams& vp = a.views[view_of_tile(a.views, a.n_views, (uint32_t)tile)];
@@ -230,12 +241,10 @@ blend_kernel(BlendArgs a, uint64_t capacity)
             ev += __shfl_xor(ev, o, 64);
             co += __shfl_xor(co, o, 64);
         }
-        __shared__ unsigned long long s_ev[4], s_co[4];
-        __shared__ uint32_t s_bodies[4];
         if (lane == 0) {
-            s_ev[wave] = ev;
-            s_co[wave] = co;
-            s_bodies[wave] = bodies;
+            L.s_ev[wave] = ev;
+            L.s_co[wave] = co;
+            L.s_bodies[wave] = bodies;
         }
         __syncthreads();
         if (tid == 0) {
@@ -243,9 +252,9 @@ blend_kernel(BlendArgs a, uint64_t capacity)
             w[0] = t_start;
             w[1] = wall_clock64();
             w[2] = staged;
-            w[3] = (unsigned long long)s_bodies[0] + s_bodies[1] + s_bodies[2] + s_bodies[3];
-            w[4] = s_ev[0] + s_ev[1] + s_ev[2] + s_ev[3];
-            w[5] = s_co[0] + s_co[1] + s_co[2] + s_co[3];
+            w[3] = (unsigned long long)L.s_bodies[0] + L.s_bodies[1] + L.s_bodies[2] + L.s_bodies[3];
+            w[4] = L.s_ev[0] + L.s_ev[1] + L.s_ev[2] + L.s_ev[3];
+            w[5] = L.s_co[0] + L.s_co[1] + L.s_co[2] + L.s_co[3];
         }
     }
     // the work of this tile, for the next frame's dispatch order: list
@@ -260,6 +269,47 @@ blend_kernel(BlendArgs a, uint64_t capacity)
     out_rgb[2 * P + p] = fmaf(Tr, a.bg[2], c2);
     if (vp.out_T) vp.out_T[p] = Tr;
     if (vp.out_nc) vp.out_nc[p] = last;
+}
+
+// One workgroup per tile: workgroup b walks tile order[b] (heaviest first)
+// or, without an order, the tile its XCD group assigns.  kStats keeps the
+// compiler's own register budget, where the tracing counters need no spills.
+template <bool kStats, int kBatch>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kStats ? 1 : blend_waves<kBatch>()))) void
+blend_kernel(BlendArgs a, uint64_t capacity)
+{
+    __shared__ BlendLds<kBatch> lds;
+    blend_tile_walk<kStats, kBatch>(a, capacity, blend_tile(a.order, a.group), lds);
+}
+
+// Persistent form: a grid of at most as many workgroups as the chip holds at
+// once, each taking the next position of the heaviest-first order from an
+// atomic head (a.queue, zero at the start of the frame) until the order is
+// used up.  The work queue runs over the global tiles of every view, so the
+// (view, tile) items of uneven cameras share one pool: a workgroup that
+// finishes early takes the next heaviest item instead of idling while the
+// dispatcher drains.  Every workgroup leaves once the head passes the tile
+// count, so the grid always drains.  It asks for one wave per SIMD fewer
+// than the plain kernel: the loop's own state spills at the plain count.
+// Measured at 3M Gaussians / 1080p and on the 64-view batch it is slower
+// than the dispatcher walking the same order one workgroup per tile
+// (blend_group 0: 0.23 against 0.20 ms at 1080p), so the autotuner keeps it
+// as a candidate only; claiming the next item before walking the current one
+// needs a register across the walk and was slower still.
+template <int kBatch>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(blend_waves<kBatch>() - 1))) void
+blend_queue_kernel(BlendArgs a, uint64_t capacity)
+{
+    __shared__ BlendLds<kBatch> lds;
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();   // every thread has read s_item before thread 0 writes the next
+        if ((int64_t)item >= a.tiles) break;
+        blend_tile_walk<false, kBatch>(a, capacity, (int)a.order[item], lds);
+    }
 }
 
 // The order of a layout's first frame (by list length; later frames take the
@@ -294,12 +344,47 @@ __global__ __launch_bounds__(256) void write_keys_kernel(const uint32_t* __restr
     for (uint32_t j = s + threadIdx.x; j < e; j += 256) keys[j] = (t << 32) | depth_key[values[j]];
 }
 
+// Workgroups of a 256-thread kernel that the current device holds at once
+// (resident per compute unit times compute units), cached per device and
+// batch; 0 when the runtime cannot say.
+template <typename K>
+int64_t resident_blocks(K kernel, int batch)
+{
+    constexpr int kDevices = 64;
+    static int64_t cache[kDevices][3];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) return 0;
+    const int slot = batch == 128 ? 0 : (batch == 256 ? 1 : 2);
+    if (cache[dev][slot] > 0) return cache[dev][slot];
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
+        cus <= 0)
+        return 0;
+    cache[dev][slot] = (int64_t)per_cu * cus;
+    return cache[dev][slot];
+}
+
 }  // namespace
 
 hipError_t launch_blend(const BlendArgs& a, uint64_t capacity, hipStream_t s)
 {
     const int64_t T = a.tiles;
     if (T <= 0) return hipSuccess;
+    if (a.queue && a.order && !a.tile_work) {   // persistent grid over the heaviest-first queue
+        auto go = [&](auto kernel) {
+            const int64_t r = resident_blocks(kernel, a.batch);   // 0: one workgroup per tile
+            const int blocks = (int)(r > 0 ? std::min<int64_t>(T, r) : T);
+            hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, a, capacity);
+        };
+        switch (a.batch) {
+        case 128: go(blend_queue_kernel<128>); break;
+        case 512: go(blend_queue_kernel<512>); break;
+        case 256: go(blend_queue_kernel<256>); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int blocks = blend_grid(T, a.order, a.group);
     auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, a, capacity); };
     switch (a.batch) {

@@ -22,7 +22,8 @@ struct Tuning {
     int bin1_items;    // depth-sorted Gaussians per lane of a level-1 binning wave: 4, 8, 16
     int bin2_items;    // row entries per lane of a level-2 binning wave: 8, 16, 32
     int blend_group;   // consecutive tiles dealt to one XCD by the blend: 1 .. 64;
-                       // 0: tiles dispatched heaviest first, by the previous frame's work
+                       // 0: tiles dispatched heaviest first, by the previous frame's work;
+                       // -1: the same order as a work queue that a persistent grid drains
     int blend_batch;   // list entries the blend stages per batch: 128, 256, 512
 };
 constexpr Tuning kDefaultTuning = {8, 8, 16, 0, 256};
@@ -221,6 +222,8 @@ struct BlendArgs {
     int group;                 // tiles per XCD group (Tuning::blend_group)
     int batch;                 // list entries staged per batch (Tuning::blend_batch)
     const uint32_t* order;     // [tiles] dispatch order (block b renders order[b]), or null: XCD groups
+    uint32_t* queue;           // with order: head of the work queue over order (zero before the launch),
+                               // drained by a persistent grid; else null
     uint32_t* tile_cost;       // [tiles] list entries each tile walked before it finished, or null
     float bg[3];
     // per-tile trace when tracing (else null), [T][kTileWorkFields]: start

@@ -679,7 +679,7 @@ bool bin_items_supported(int items1, int items2)
 bool tuning_supported(const Tuning& t)
 {
     return depth_sort_items_supported(t.sort_items) && bin_items_supported(t.bin1_items, t.bin2_items) &&
-           t.blend_group >= 0 && t.blend_group <= 64 &&
+           t.blend_group >= -1 && t.blend_group <= 64 &&
            (t.blend_batch == 128 || t.blend_batch == 256 || t.blend_batch == 512);
 }
 int bin_level1_chunks(int64_t n, int items1) { return (int)((n + (int64_t)items1 * 64 - 1) / ((int64_t)items1 * 64)); }

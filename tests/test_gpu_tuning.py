@@ -16,7 +16,7 @@ import scenes
 pytestmark = pytest.mark.gpu
 
 CANDIDATES = {"sort_items": (4, 8, 16), "bin_row_items": (4, 8, 16), "bin_tile_items": (8, 16, 32),
-              "blend_tile_group": (0, 1, 2, 4, 8, 16, 32, 64), "blend_batch": (128, 256, 512)}
+              "blend_tile_group": (-1, 0, 1, 2, 4, 8, 16, 32, 64), "blend_batch": (128, 256, 512)}
 DEFAULT = {"sort_items": 8, "bin_row_items": 8, "bin_tile_items": 16, "blend_tile_group": 0, "blend_batch": 256}
 
 
@@ -103,7 +103,7 @@ def test_every_shape_gives_identical_results(renderer, case, capacity):
 
 def test_set_tuning_rejects_unsupported_values(renderer):
     renderer.set_tuning(**DEFAULT)
-    for bad in ({"sort_items": 5}, {"bin_row_items": 32}, {"bin_tile_items": 4}, {"blend_tile_group": -1},
+    for bad in ({"sort_items": 5}, {"bin_row_items": 32}, {"bin_tile_items": 4}, {"blend_tile_group": -2},
                 {"blend_tile_group": 65}, {"blend_batch": 192}):
         with pytest.raises(RuntimeError):
             renderer.set_tuning(**bad)
@@ -143,7 +143,7 @@ def test_backward_with_other_tile_groups(renderer):
     gi = torch.from_numpy(rng.uniform(-1, 1, (3, 96, 160)).astype(np.float32)).cuda()
     ref = None
     try:
-        for group in (0, 16, 1, 64):
+        for group in (0, 16, 1, 64, -1):
             renderer.set_tuning(blend_tile_group=group)
             renderer.render(dev, cam, 160, 96)
             g = {k: v.cpu().numpy() for k, v in renderer.backward(dev, [gi]).items()}
