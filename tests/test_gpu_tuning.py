@@ -178,3 +178,49 @@ def test_heaviest_first_order_from_length_then_history(renderer):
                 assert np.array_equal(got[k], want[k]), f"{cam['width']}x{cam['height']}: {k} differs"
     finally:
         fresh.close()
+
+
+def test_persistent_queue_in_graph_replays_and_noalloc(renderer):
+    """blend_tile_group -1 (a persistent grid draining the heaviest-first
+    queue, whose head the frame's set-up launch clears): graph replays, with
+    eager work between them, and the no-allocation render each equal the
+    default dispatch bit for bit."""
+    import torch
+    import paper_2607_15951_amd as gs
+    sc = scenes.make_scene("C2", n=30_000, seed=26)
+    dev = gs.scene_to_device(sc)
+    cams = [scenes.default_camera(200, 120), scenes.look_at_camera([1.5, -0.4, -2.4], 96, 64),
+            scenes.look_at_camera([-2.0, 0.3, -2.0], 300, 180)]
+    renderer.set_tuning(**DEFAULT)
+    want = [{k: v.clone() for k, v in o.items()} for o in renderer.render_batched(dev, cams)]
+    cap = int(renderer.list_info()["num_pairs"] * 1.3) + 1024
+    c0 = cams[0]
+    want0 = {k: v.clone() for k, v in renderer.render(dev, c0, c0["width"], c0["height"]).items()}
+    r = gs.Renderer(0)
+    try:
+        r.set_tuning(blend_tile_group=-1)
+        gr = r.graph(dev, cams, pair_capacity=cap)
+        for rep in range(3):
+            for o in gr.outs:
+                o["image"].fill_(-1.0)
+            torch.cuda.synchronize()
+            gr.launch()
+            torch.cuda.synchronize()
+            _ = torch.ones(1024, device="cuda").sum().item()   # eager work between replays
+            for v, (o, w) in enumerate(zip(gr.outs, want)):
+                for k in ("image", "final_T", "n_contrib"):
+                    assert torch.equal(o[k], w[k]), f"replay {rep} view {v} {k}"
+        gr.close()
+        say("[tuning] queue blend: 3 graph replays equal the default dispatch")
+        out = {"image": torch.full((3, c0["height"], c0["width"]), -2.0, device="cuda"),
+               "final_T": torch.full((c0["height"], c0["width"]), -2.0, device="cuda"),
+               "n_contrib": torch.full((c0["height"], c0["width"]), -2, dtype=torch.int32, device="cuda")}
+        for _ in range(2):
+            r.render_noalloc(dev, c0, c0["width"], c0["height"], out)
+            torch.cuda.synchronize()
+            for k in ("image", "final_T", "n_contrib"):
+                assert torch.equal(out[k], want0[k]), f"no-allocation render {k}"
+        say("[tuning] queue blend: no-allocation renders equal the default dispatch")
+    finally:
+        r.close()
+        renderer.set_tuning(**DEFAULT)
