@@ -36,6 +36,8 @@
 #include "blend_stage.h"
 #include "tile_order.h"
 
+#include <atomic>
+
 namespace gsmi {
 namespace {
 
@@ -346,23 +348,26 @@ __global__ __launch_bounds__(256) void write_keys_kernel(const uint32_t* __restr
 
 // Workgroups of a 256-thread kernel that the current device holds at once
 // (resident per compute unit times compute units), cached per device and
-// batch; 0 when the runtime cannot say.
+// batch (contexts on several host threads may fill the cache at once: each
+// writes the same value); 0 when the runtime cannot say.
 template <typename K>
 int64_t resident_blocks(K kernel, int batch)
 {
     constexpr int kDevices = 64;
-    static int64_t cache[kDevices][3];
+    static std::atomic<int64_t> cache[kDevices][3];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) return 0;
     const int slot = batch == 128 ? 0 : (batch == 256 ? 1 : 2);
-    if (cache[dev][slot] > 0) return cache[dev][slot];
+    const int64_t known = cache[dev][slot].load(std::memory_order_relaxed);
+    if (known > 0) return known;
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
         cus <= 0)
         return 0;
-    cache[dev][slot] = (int64_t)per_cu * cus;
-    return cache[dev][slot];
+    const int64_t blocks = (int64_t)per_cu * cus;
+    cache[dev][slot].store(blocks, std::memory_order_relaxed);
+    return blocks;
 }
 
 }  // namespace

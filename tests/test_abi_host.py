@@ -169,3 +169,14 @@ def test_scene_from_rows_layout():
     assert b["sh"].dtype == torch.bfloat16 and b["means"].dtype == torch.float32
     with pytest.raises(ValueError):
         gs.scene_from_rows(means, ls, q, op, torch.randn(n, 5, 3))
+
+
+def test_tune_candidates_match_the_header():
+    """The binding's candidate list is the order of gs_autotune's out_ms
+    array, whose length the header fixes."""
+    text = open(os.path.join(ROOT, "include", "gsmi.h")).read()
+    n = int(re.search(r"#define\s+GS_TUNE_CANDIDATES\s+(\d+)", text).group(1))
+    assert len(gs.TUNE_CANDIDATES) == n
+    listed = re.search(r"of every candidate in the order (.*?)\n \* Profiling", text, flags=re.S).group(1)
+    values = [int(v) for v in re.findall(r"-?\d+", listed)]
+    assert values == [v for _, v in gs.TUNE_CANDIDATES]
