@@ -391,9 +391,10 @@ gs_status render_views(gs_context* ctx, const gs_gaussians* g, const std::vector
     if ((st = ensure(ctx, w.counters, 64)) != GS_OK) return st;
     if ((st = ensure(ctx, w.tile_offsets, (size_t)(T + 1) * 4)) != GS_OK) return st;
     // every blend records its tiles' work; with blend_group 0 it is dispatched
-    // (with -1 queued for a persistent grid) heaviest first, by the last render's work when that render had the same
-    // tile layout (the history: ordered by one extra workgroup of the
-    // projection launch), else by list length (ordered before the blend)
+    // (with -1 queued for a persistent grid) heaviest first, by the last
+    // render's work when that render had the same tile layout (the history:
+    // ordered by one extra workgroup of the projection launch), else by list
+    // length (ordered before the blend)
     std::vector<int> layout;
     for (const ViewParams& v : hv) {
         layout.push_back(v.tiles_x);
